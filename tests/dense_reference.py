@@ -1,0 +1,174 @@
+"""Independent dense numpy construction of the scheme (test helper for the
+brute-force pin of the oracle on tiny grids, and for the energy pins).
+
+Built from the paper's operator definitions with numpy/scipy routines of its
+own (np.interp for every interpolant, dense products, numpy.linalg.solve),
+sharing no code with the oracle.  The hammer of eq. (6) is applied in its
+eliminated form (lumped-mass update substituted into the string equation),
+while the oracle solves the joint system; agreement checks both.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def dmin(N, h):
+    """D_{x-}: N x (N-1), fixed ends."""
+    D = np.zeros((N, N - 1))
+    for i in range(1, N + 1):
+        if i <= N - 1:
+            D[i - 1, i - 1] = 1.0 / h
+        if i >= 2:
+            D[i - 1, i - 2] = -1.0 / h
+    return D
+
+
+def interp_matrix(x_src, x_dst):
+    """Matrix of np.interp (linear, constant beyond the ends)."""
+    M = np.zeros((len(x_dst), len(x_src)))
+    for j in range(len(x_src)):
+        e = np.zeros(len(x_src))
+        e[j] = 1.0
+        M[:, j] = np.interp(x_dst, x_src, e)
+    return M
+
+
+def point_row(x, N):
+    """Row interpolating the interior nodes 1..N-1 at x (end nodes are zero)."""
+    nodes = np.arange(N + 1) / N
+    row = np.zeros(N - 1)
+    for j in range(N - 1):
+        e = np.zeros(N + 1)
+        e[j + 1] = 1.0
+        row[j] = np.interp(x, nodes, e)
+    return row
+
+
+class Dense:
+    def __init__(self, p, g):
+        self.p, self.g = p, g
+        Nt, Nl = g["N_t"], g["N_l"]
+        ht, k, th = g["h_t"], g["k"], g["theta"]
+        self.nt = Nt - 1
+        self.nl = Nl - 1 if Nl > 0 else 0
+        self.Dm_t = dmin(Nt, ht)
+        self.Dp_t = -self.Dm_t.T
+        self.Dxx_t = self.Dp_t @ self.Dm_t
+        Mx = 0.5 * (np.eye(self.nt, k=1) + np.eye(self.nt, k=-1))
+        self.Theta = th * np.eye(self.nt) + (1 - th) * Mx
+        self.S = g["kappa"] ** 2 * k ** 2 * (self.Dxx_t @ self.Dxx_t)
+        if Nl > 0:
+            hl = g["h_l"]
+            self.Dm_l = dmin(Nl, hl)
+            self.Dp_l = -self.Dm_l.T
+            self.Dxx_l = self.Dp_l @ self.Dm_l
+            xt = (np.arange(1, Nt + 1) - 0.5) * ht
+            xl = (np.arange(1, Nl + 1) - 0.5) * hl
+            self.I_lt = interp_matrix(xl, xt)
+            self.I_tl = (ht / hl) * self.I_lt.T
+
+    def blocks(self, u_n, gamma):
+        p, g = self.p, self.g
+        k = g["k"]
+        a2 = p["alpha"] ** 2
+        phi2 = gamma ** 2 * k ** 2 * (a2 - 1) / 4
+        G = gamma ** 2 * k ** 2
+        Lam = np.diag(self.Dm_t @ u_n)
+        V = -phi2 * self.Dp_t @ Lam @ Lam @ self.Dm_t
+        It = np.eye(self.nt)
+        Qp = self.Theta + p["sigma0_t"] * k * It - p["sigma1_t"] * k * self.Dxx_t
+        Qm = self.Theta - p["sigma0_t"] * k * It + p["sigma1_t"] * k * self.Dxx_t
+        Buu = -2 * self.Theta - G * self.Dxx_t + self.S
+        if self.nl == 0:
+            return Qp + V, Buu, Qm + V
+        Il = np.eye(self.nl)
+        Ktl = -phi2 * self.Dp_t @ Lam @ self.I_lt @ self.Dm_l
+        Klt = -phi2 * self.Dp_l @ self.I_tl @ Lam @ self.Dm_t
+        Qlp = (1 + p["sigma0_l"] * k) * Il - p["sigma1_l"] * k * self.Dxx_l
+        Qlm = (1 - p["sigma0_l"] * k) * Il + p["sigma1_l"] * k * self.Dxx_l
+        A = np.block([[Qp + V, Ktl], [Klt, Qlp]])
+        Bm = np.block([[Buu, 2 * Ktl], [np.zeros((self.nl, self.nt)), -2 * Il - a2 * G * self.Dxx_l]])
+        Cm = np.block([[Qm + V, Ktl], [Klt, Qlm]])
+        return A, Bm, Cm
+
+
+def gamma_at(p, n):
+    t = n / p["fs"]
+    f = p["f0"]
+    if p.get("mod_type", 0) == 1:
+        f *= 2.0 ** ((p["mod_depth_cents"] / 1200.0) * np.sin(2 * np.pi * p["mod_rate_hz"] * t))
+    elif p.get("mod_type", 0) == 2:
+        T = p["n_samples"] / p["fs"]
+        f *= 2.0 ** ((p["glide_semitones"] / 12.0) * (t / T))
+    return 2.0 * f
+
+
+def run_dense(p, e, g, n_samples):
+    """Step eq. (7) with dense solves; returns (traj_u, traj_z, u_H)."""
+    D = Dense(p, g)
+    nt, nl = D.nt, D.nl
+    Nt, k = g["N_t"], g["k"]
+    w0 = np.zeros(nt + nl)
+    uH = np.zeros(n_samples)
+    if e["type"] == 1:
+        x = np.arange(1, Nt) / Nt
+        tri = np.where(x <= e["x"], e["c0"] * x / e["x"], e["c0"] * (1 - x) / (1 - e["x"]))
+        w0[:nt] = tri
+    w1 = w0.copy()
+    traj = np.zeros((n_samples, nt + nl))
+    traj[0], traj[1] = w0, w1
+    if e["type"] == 2:
+        uH[1] = k * e["v_H"]
+        Ih = point_row(e["x"], Nt)
+        Jh = Ih / g["h_t"]
+        Mr = e["M_H"] / e["rhoA"]
+        wpow = e["K_H"] / e["M_H"]
+    for n in range(1, n_samples - 1):
+        gam = gamma_at(p, n)
+        A, Bm, Cm = D.blocks(w1[:nt], gam)
+        rhs = -Bm @ w1 - Cm @ w0
+        if e["type"] == 2:
+            eta_n = uH[n] - Ih @ w1[:nt]
+            eta_m = uH[n - 1] - Ih @ w0[:nt]
+            c = 0.5 * wpow * eta_n ** (e["alpha_H"] - 1) if eta_n > 0 else 0.0
+            beta = k * k * Mr * c / (1 + k * k * c)
+            A = A.copy()
+            A[:nt, :nt] += beta * np.outer(Jh, Ih)
+            rhs[:nt] += beta * Jh * (2 * uH[n] - uH[n - 1] + eta_m)
+        w2 = np.linalg.solve(A, rhs)
+        if e["type"] == 2:
+            uH[n + 1] = (2 * uH[n] - uH[n - 1] - k * k * c * (eta_m - Ih @ w2[:nt])) / (1 + k * k * c)
+        traj[n + 1] = w2
+        w0, w1 = w1, w2
+    return traj[:, :nt], traj[:, nt:], uH
+
+
+def energy(p, g, u1, u0, z1, z0, gamma):
+    """H^{n+1/2}: discrete energy of the lossless unforced scheme (string only)."""
+    Nt, Nl = g["N_t"], g["N_l"]
+    ht, k, th, kap = g["h_t"], g["k"], g["theta"], g["kappa"]
+
+    def half_diff(v, h):
+        return np.diff(np.concatenate([[0.0], v, [0.0]])) / h
+
+    def lap(v, h):
+        w = np.concatenate([[0.0], v, [0.0]])
+        return (w[2:] - 2 * w[1:-1] + w[:-2]) / h ** 2
+
+    du = u1 - u0
+    dpad = np.concatenate([[0.0], du, [0.0]])
+    theta_du = th * du + (1 - th) * 0.5 * (dpad[2:] + dpad[:-2])
+    q1, q0 = half_diff(u1, ht), half_diff(u0, ht)
+    H = ht / (2 * k * k) * np.dot(du, theta_du) + gamma ** 2 * ht / 2 * np.dot(q1, q0) \
+        + kap ** 2 * ht / 2 * np.dot(lap(u1, ht), lap(u0, ht))
+    if Nl > 0:
+        hl = g["h_l"]
+        a2 = p["alpha"] ** 2
+        p1, p0 = half_diff(z1, hl), half_diff(z0, hl)
+        xt = (np.arange(1, Nt + 1) - 0.5) * ht
+        xl = (np.arange(1, Nl + 1) - 0.5) * hl
+        pt1, pt0 = np.interp(xt, xl, p1), np.interp(xt, xl, p0)
+        qq = q1 * q0
+        H += hl / (2 * k * k) * np.dot(z1 - z0, z1 - z0) + gamma ** 2 * a2 * hl / 2 * np.dot(p1, p0) \
+            + gamma ** 2 * (a2 - 1) / 2 * ht * np.sum(qq * qq / 4 + qq * (pt1 + pt0) / 2)
+    return H
