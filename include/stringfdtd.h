@@ -1,0 +1,181 @@
+/*
+ * libstringfdtd: MI355X (gfx950) finite-difference time-domain synthesis of
+ * stiff, lossy, nonlinear planar strings (transverse u and longitudinal zeta
+ * coupled), after "String Sound Synthesizer on GPU-Accelerated Finite
+ * Difference Scheme" (Lee, Choi, Lee; arXiv 2311.18505).
+ *
+ * One batch holds `capacity` independent string slots.  Each slot is given
+ * physical and control parameters (Table 1 of the paper), an excitation by
+ * pluck or hammer (Sec. 3.3), and is then advanced by the recursion of
+ * eq. (7) from its initial conditions (Sec. 3.4); the readout of u at x_out is
+ * written to device memory one sample per time step.
+ *
+ * Conventions
+ *  - Every call returns an int status (SB_OK or a negative SB_E* code); no
+ *    exception crosses the boundary.  string_batch_last_error() describes the
+ *    last failure of a handle (pointer valid until the next call on it).
+ *  - Host arrays passed in are copied before the call returns; the caller
+ *    keeps ownership of every pointer it passes.
+ *  - string_batch_step() is asynchronous on the HIP stream given at create
+ *    time; outputs are valid after that stream is synchronised.
+ *    string_batch_read_output() orders itself on the same stream.
+ *  - A handle is not thread-safe: use one handle per host thread.
+ *  - Units: the string has length L = 1 (positions are fractions of L),
+ *    displacements are metres, time is seconds.
+ */
+#ifndef STRINGFDTD_H
+#define STRINGFDTD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SB_OK          0
+#define SB_EINVAL     -1   /* invalid argument (range, NaN/Inf, index)              */
+#define SB_ENOMEM     -2   /* device or host allocation failed                      */
+#define SB_EBUDGET    -3   /* string larger than the per-wavefront budget (N > 1024) */
+#define SB_EUNSTABLE  -4   /* energy monitor flagged a string, or the solve diverged */
+#define SB_ESTATE     -5   /* call out of order (e.g. step before excite)            */
+#define SB_EDEVICE    -6   /* HIP runtime error                                      */
+
+/* precision of a batch */
+#define SB_FP64        0   /* acceleration-form stepping in FP64                      */
+#define SB_FP32C       1   /* FP32 stepping with compensated (Kahan) state updates    */
+#define SB_FP64_PLAIN  2   /* eq. (7) as printed, FP64, serial banded LU per string   */
+
+/* excitation types */
+#define SB_EXC_NONE    0
+#define SB_EXC_PLUCK   1
+#define SB_EXC_HAMMER  2
+
+/* f0 modulation types */
+#define SB_MOD_NONE    0
+#define SB_MOD_VIBRATO 1   /* f0 * 2^{(depth/1200) sin(2 pi rate t)}                  */
+#define SB_MOD_GLIDE   2   /* f0 * 2^{(semitones/12) t/T}, T = n_samples/fs           */
+
+typedef struct sb_batch sb_batch;   /* opaque; owns all device memory of the batch */
+
+/* Physical and control parameters of one string (Table 1; Sec. 3.2, 4.1).
+ * gamma = 2 f0 (Sec. 4.1), kappa = gamma sqrt(B)/pi (inharmonicity
+ * K = (pi kappa/gamma)^2 of Sec. 4.1 read as B).  theta <= 0 selects the
+ * paper's (1+4/pi^2)/2; otherwise 1/2 < theta <= 1.  The grids are sized at
+ * the stability bounds of the theta-scheme (transverse) and h_l >= gamma
+ * alpha k (longitudinal) from the largest f0 the modulation reaches; grid_t /
+ * grid_l > 0 force a size instead (testing).  alpha == 1 omits the
+ * longitudinal grid (the system is then linear and zeta stays zero). */
+typedef struct {
+    double fs;                 /* sample rate [Hz], k = 1/fs                      */
+    double f0;                 /* fundamental of the ideal string [Hz]            */
+    double B;                  /* inharmonicity (>= 0)                            */
+    double alpha;              /* stiffness-to-tension ratio (>= 1)               */
+    double theta;              /* theta-scheme parameter                          */
+    double sigma0_t, sigma1_t; /* transverse losses of eq. (4a) [1/s], [m^2/s]    */
+    double sigma0_l, sigma1_l; /* longitudinal losses of eq. (4b)                 */
+    double x_out;              /* readout position in (0,1)                       */
+    int64_t n_samples;         /* output length (>= 2)                            */
+    int32_t mod_type;          /* SB_MOD_*                                        */
+    int32_t grid_t;            /* 0 or a forced N_t                               */
+    double mod_depth_cents;    /* vibrato depth                                   */
+    double mod_rate_hz;        /* vibrato rate                                    */
+    double glide_semitones;    /* glide interval over the duration                */
+    int32_t grid_l;            /* 0 or a forced N_l                               */
+    int32_t reserved;
+} sb_string_params;
+
+/* Excitation (Sec. 3.3).  Pluck: initial triangle of peak c0 at x, released
+ * from rest.  Hammer (eq. 6): lumped mass M_H [kg] at x with initial velocity
+ * v_H [m/s], felt force K_H max(0, compression)^alpha_H, mass ratio
+ * M_H / (rhoA * 1 m); starts touching the string at rest. */
+typedef struct {
+    int32_t type;              /* SB_EXC_*                                        */
+    int32_t reserved;
+    double x;                  /* position in (0,1)                               */
+    double c0;                 /* pluck peak [m]                                  */
+    double v_H, M_H, K_H, alpha_H, rhoA;
+} sb_excitation;
+
+/* Per-slot information (grid sizes and progress). */
+typedef struct {
+    int32_t N_t, N_l;          /* grid intervals (N_l = 0: no longitudinal grid)  */
+    int64_t n_samples;         /* requested samples                               */
+    int64_t samples_done;      /* samples available in the output                */
+    int32_t flags;             /* 1: unstable (energy monitor), 2: no convergence */
+    int32_t max_sweeps;        /* largest number of coupled-solve sweeps in a step */
+    int64_t total_sweeps;      /* total sweeps                                    */
+} sb_string_info;
+
+/* Create a batch of `capacity` (>= 1) slots computing in `precision`
+ * (SB_FP64, SB_FP32C or SB_FP64_PLAIN), launching on `hip_stream` (a
+ * hipStream_t; NULL = the default stream).  *out receives the handle.
+ * Errors: SB_EINVAL, SB_ENOMEM, SB_EDEVICE. */
+int string_batch_create(int capacity, int precision, void *hip_stream, sb_batch **out);
+
+/* Set the parameters of slots first .. first+count-1 from p[0..count-1]
+ * (host array).  Plans the grids (Sec. 3.2), coefficient and interpolation
+ * tables, and allocates the slots' device state and output (n_samples
+ * samples each).  Resets the slots: excite must follow before step.
+ * Errors: SB_EINVAL (ranges: fs, f0 > 0, B >= 0, alpha >= 1, 1/2 < theta <= 1,
+ * sigmas >= 0, 0 < x_out < 1, n_samples >= 2, finite values), SB_EBUDGET
+ * (N_t or N_l > 1024), SB_ENOMEM. */
+int string_batch_set_params(sb_batch *b, int first, int count, const sb_string_params *p);
+
+/* Excite slots first .. first+count-1 with e[0..count-1] (host array): writes
+ * the initial conditions w^0, w^1 and samples y^0, y^1 (Sec. 3.3-3.4).
+ * Errors: SB_EINVAL (type, 0 < x < 1, hammer M_H, K_H, rhoA > 0,
+ * alpha_H >= 1, finite), SB_ESTATE (slot without parameters). */
+int string_batch_excite(sb_batch *b, int first, int count, const sb_excitation *e);
+
+/* Advance every excited slot by n_steps time steps of eq. (7) (clamped at
+ * its n_samples), asynchronously on the batch stream.  Each step produces one
+ * output sample.  Errors: SB_EINVAL (n_steps < 0), SB_ESTATE (no excited
+ * slot), SB_EDEVICE.  Use string_batch_info() after a synchronisation to see
+ * per-slot flags (the step of a flagged slot stops). */
+int string_batch_step(sb_batch *b, int64_t n_steps);
+
+/* Same as string_batch_step but only for slots first .. first+count-1. */
+int string_batch_step_range(sb_batch *b, int first, int count, int64_t n_steps);
+
+/* Copy samples offset .. offset+count-1 of slot idx to dst (count elements
+ * of the batch precision: float for SB_FP32C, double otherwise), ordered on
+ * the batch stream and synchronous with it when dst_is_device == 0.
+ * Errors: SB_EINVAL (range beyond n_samples), SB_EDEVICE. */
+int string_batch_read_output(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst, int dst_is_device);
+
+/* Device pointer of slot idx's output samples (n_samples elements of the
+ * batch precision); the batch owns the memory. */
+int string_batch_output_ptr(sb_batch *b, int idx, void **dev_ptr);
+
+/* Energy H^{n+1/2} of slot idx at its last monitor check (FP64, computed on
+ * the GPU), and the step n of that check (-1 if none).  Synchronises the
+ * stream.  Errors: SB_EINVAL, SB_EDEVICE. */
+int string_batch_read_energy(sb_batch *b, int idx, double *H_latest, int64_t *step_of_H);
+
+/* Grid sizes and progress of slot idx.  Synchronises the stream. */
+int string_batch_info(sb_batch *b, int idx, sb_string_info *info);
+
+/* Energy monitor period in steps (0 disables; default 480) and relative
+ * growth tolerance (default 1e-9 for FP64, 1e-4 for FP32C). */
+int string_batch_set_monitor(sb_batch *b, int period, double growth_tol);
+
+/* Coupled-solve controls: relative tolerance on the update of the
+ * acceleration (default 1e-15 FP64, 1e-7 FP32C) and the sweep cap (default 64). */
+int string_batch_set_solver(sb_batch *b, double tol, int max_sweeps);
+
+/* Grid sizes the library plans for p (host only, needs no device): N_t from
+ * the stability bound of the theta-scheme, N_l from h_l >= gamma alpha k.
+ * Errors: SB_EINVAL. */
+int string_plan_grid(const sb_string_params *p, int32_t *N_t, int32_t *N_l);
+
+/* Free every resource of the batch (synchronises its stream first). */
+int string_batch_destroy(sb_batch *b);
+
+/* Description of the last error on b (or of the last create failure if b is NULL). */
+const char *string_batch_last_error(const sb_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,520 @@
+// C ABI of libstringfdtd: batch handles, device memory, uploads and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/stringfdtd.h"
+#include "planner.h"
+#include "sfd_types.h"
+
+namespace sfd {
+hipError_t launch_step(int precision, int cls, const LaunchArgs &a, int blocks, hipStream_t st);
+hipError_t launch_zero(int32_t *c, int n, hipStream_t st);
+int max_blocks_per_cu(int precision, int cls);
+hipError_t launch_plain(const Desc *d_desc, Status *d_status, int slot, int64_t n_steps, int mon_period,
+                        double mon_tol, hipStream_t st);
+}  // namespace sfd
+
+using namespace sfd;
+
+namespace {
+
+std::string g_create_error;
+
+// Chunked first-fit allocator over large device allocations.
+class Arena {
+ public:
+  ~Arena() { clear(); }
+  void clear() {
+    for (auto &c : chunks_) (void)hipFree(c.base);
+    chunks_.clear();
+  }
+  void *alloc(size_t n) {
+    n = (n + 255) & ~size_t(255);
+    for (auto &c : chunks_) {
+      for (auto it = c.free.begin(); it != c.free.end(); ++it) {
+        if (it->second >= n) {
+          size_t off = it->first, sz = it->second;
+          c.free.erase(it);
+          if (sz > n) c.free[off + n] = sz - n;
+          return c.base + off;
+        }
+      }
+    }
+    size_t csz = std::max(n, (size_t)256 << 20);
+    void *p = nullptr;
+    if (hipMalloc(&p, csz) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    chunks_.push_back(Chunk{(char *)p, csz, {}});
+    Chunk &c = chunks_.back();
+    if (csz > n) c.free[n] = csz - n;
+    return c.base;
+  }
+  void release(void *p, size_t n) {
+    if (!p) return;
+    n = (n + 255) & ~size_t(255);
+    for (auto &c : chunks_) {
+      char *q = (char *)p;
+      if (q < c.base || q >= c.base + c.size) continue;
+      size_t off = (size_t)(q - c.base);
+      auto it = c.free.emplace(off, n).first;
+      auto nx = std::next(it);
+      if (nx != c.free.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        c.free.erase(nx);
+      }
+      if (it != c.free.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+          pv->second += it->second;
+          c.free.erase(it);
+        }
+      }
+      return;
+    }
+  }
+
+ private:
+  struct Chunk {
+    char *base;
+    size_t size;
+    std::map<size_t, size_t> free;
+  };
+  std::vector<Chunk> chunks_;
+};
+
+struct Slot {
+  bool planned = false, excited = false;
+  Plan plan;
+  char *dmem = nullptr;
+  size_t dsize = 0;
+  int64_t samples_host = 0;   // samples expected after the launches issued so far
+  bool flagged = false;       // a flag was observed on the device
+};
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct sb_batch {
+  int capacity = 0, precision = 0;
+  size_t esz = 8;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<Slot> slots;
+  Arena arena;
+  Desc *d_desc = nullptr;
+  Status *d_status = nullptr;
+  int32_t *d_work = nullptr;
+  int32_t *d_counters = nullptr;
+  std::vector<int32_t> h_work;
+  bool work_dirty = true;
+  int mon_period = 480;
+  double mon_tol = 1e-9;
+  double tol = 1e-13;
+  int max_sweeps = 64;
+  int num_cu = 256;
+};
+
+static int fail(sb_batch *b, int code, const std::string &msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+static int hip_fail(sb_batch *b, hipError_t e, const char *where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  (void)hipGetLastError();
+  return fail(b, SB_EDEVICE, m);
+}
+
+extern "C" int string_batch_create(int capacity, int precision, void *hip_stream, sb_batch **out) {
+  g_create_error.clear();
+  if (!out || capacity < 1 || (precision != SB_FP64 && precision != SB_FP32C && precision != SB_FP64_PLAIN)) {
+    g_create_error = "bad capacity, precision or output pointer";
+    return SB_EINVAL;
+  }
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    g_create_error = "no HIP device";
+    return SB_EDEVICE;
+  }
+  sb_batch *b = new (std::nothrow) sb_batch();
+  if (!b) return SB_ENOMEM;
+  b->capacity = capacity;
+  b->precision = precision;
+  b->esz = precision == SB_FP32C ? 4 : 8;
+  b->stream = (hipStream_t)hip_stream;
+  b->mon_tol = precision == SB_FP32C ? 1e-4 : 1e-9;
+  b->tol = precision == SB_FP32C ? 1e-6 : 1e-13;
+  b->slots.resize(capacity);
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    b->num_cu = prop.multiProcessorCount;
+  hipError_t e;
+  if ((e = hipMalloc(&b->d_desc, sizeof(Desc) * capacity)) != hipSuccess ||
+      (e = hipMalloc(&b->d_status, sizeof(Status) * capacity)) != hipSuccess ||
+      (e = hipMalloc(&b->d_work, sizeof(int32_t) * capacity)) != hipSuccess ||
+      (e = hipMalloc(&b->d_counters, sizeof(int32_t) * 16)) != hipSuccess) {
+    g_create_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+    (void)hipGetLastError();
+    hipFree(b->d_desc);
+    hipFree(b->d_status);
+    hipFree(b->d_work);
+    hipFree(b->d_counters);
+    delete b;
+    return SB_ENOMEM;
+  }
+  if ((e = hipMemset(b->d_status, 0, sizeof(Status) * capacity)) != hipSuccess) {
+    g_create_error = std::string("hipMemset: ") + hipGetErrorString(e);
+    delete b;
+    return SB_EDEVICE;
+  }
+  *out = b;
+  return SB_OK;
+}
+
+extern "C" int string_batch_destroy(sb_batch *b) {
+  if (!b) return SB_EINVAL;
+  (void)hipStreamSynchronize(b->stream);
+  b->arena.clear();
+  hipFree(b->d_desc);
+  hipFree(b->d_status);
+  hipFree(b->d_work);
+  hipFree(b->d_counters);
+  delete b;
+  return SB_OK;
+}
+
+extern "C" const char *string_batch_last_error(const sb_batch *b) {
+  return b ? b->err.c_str() : g_create_error.c_str();
+}
+
+static bool range_ok(const sb_batch *b, int first, int count) {
+  return first >= 0 && count >= 0 && (int64_t)first + count <= b->capacity;
+}
+
+// Device region of one slot: state | real tables | output | integer tables.
+static size_t region_size(const sb_batch *b, const Desc &D, size_t *off_tabf, size_t *off_out, size_t *off_tab) {
+  const size_t st = align256(b->esz * (size_t)kWave * 4 * (D.mt + D.ml));
+  const size_t tf = align256(b->esz * (size_t)kWave * (3 * D.mt + D.ml));
+  const size_t ou = align256(b->esz * (size_t)(D.n_samples + kWave));
+  const size_t tb = align256(sizeof(uint32_t) * (size_t)kWave * (D.mt + 2 * D.ml));
+  *off_tabf = st;
+  *off_out = st + tf;
+  *off_tab = st + tf + ou;
+  return st + tf + ou + tb;
+}
+
+extern "C" int string_batch_set_params(sb_batch *b, int first, int count, const sb_string_params *p) {
+  if (!b) return SB_EINVAL;
+  if (!p || !range_ok(b, first, count)) return fail(b, SB_EINVAL, "bad slot range or null params");
+  std::vector<Plan> plans(count);
+  for (int i = 0; i < count; ++i) {
+    std::string err;
+    int st = plan_string(p[i], plans[i], err);
+    if (st) return fail(b, st, "slot " + std::to_string(first + i) + ": " + err);
+  }
+  if (b->precision == SB_FP64_PLAIN)
+    for (int i = 0; i < count; ++i)
+      if (plans[i].desc.nt + plans[i].desc.nl + 1 > 2048)
+        return fail(b, SB_EBUDGET, "plain FP64 path holds at most 2048 unknowns");
+  for (int i = 0; i < count; ++i) {
+    Slot &s = b->slots[first + i];
+    if (s.dmem) {
+      b->arena.release(s.dmem, s.dsize);
+      s.dmem = nullptr;
+    }
+    size_t a, o, t;
+    s.plan = std::move(plans[i]);
+    s.dsize = region_size(b, s.plan.desc, &a, &o, &t);
+    s.dmem = (char *)b->arena.alloc(s.dsize);
+    if (!s.dmem) {
+      s.planned = false;
+      return fail(b, SB_ENOMEM, "device memory exhausted");
+    }
+    s.planned = true;
+    s.excited = false;
+    s.flagged = false;
+    s.samples_host = 0;
+  }
+  b->work_dirty = true;
+  // mark the slots idle on the device until they are excited
+  std::vector<Status> zs(count);
+  for (auto &z : zs) {
+    std::memset(&z, 0, sizeof(z));
+    z.H_step = -1;
+  }
+  hipError_t e = hipMemcpyAsync(b->d_status + first, zs.data(), sizeof(Status) * count, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(b, e, "set_params upload");
+  return SB_OK;
+}
+
+template <typename T>
+static void to_prec(const std::vector<double> &src, std::vector<char> &dst) {
+  dst.resize(src.size() * sizeof(T));
+  T *d = (T *)dst.data();
+  for (size_t i = 0; i < src.size(); ++i) d[i] = (T)src[i];
+}
+
+extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_excitation *e) {
+  if (!b) return SB_EINVAL;
+  if (!e || !range_ok(b, first, count)) return fail(b, SB_EINVAL, "bad slot range or null excitation");
+  for (int i = 0; i < count; ++i)
+    if (!b->slots[first + i].planned) return fail(b, SB_ESTATE, "slot " + std::to_string(first + i) + " has no parameters");
+  // validate everything before touching any slot
+  for (int i = 0; i < count; ++i) {
+    Plan tmp = b->slots[first + i].plan;
+    std::string err;
+    int st = plan_excitation(e[i], tmp, err);
+    if (st) return fail(b, st, "slot " + std::to_string(first + i) + ": " + err);
+  }
+  std::vector<std::vector<char>> keep;   // host buffers alive until the stream sync below
+  std::vector<Desc> descs(count);
+  std::vector<Status> stats(count);
+  hipError_t err = hipSuccess;
+  for (int i = 0; i < count && err == hipSuccess; ++i) {
+    Slot &s = b->slots[first + i];
+    std::string msg;
+    plan_excitation(e[i], s.plan, msg);
+    Desc &D = s.plan.desc;
+    size_t otf, oout, otab;
+    region_size(b, D, &otf, &oout, &otab);
+    D.st = s.dmem;
+    D.tabf = s.dmem + otf;
+    D.out = s.dmem + oout;
+    D.tab = (const uint32_t *)(s.dmem + otab);
+    // initial state, lane-major: u, v, cu, cv (transverse), same for zeta
+    std::vector<double> u0;
+    double uH0, uH1;
+    initial_state(e[i], s.plan, u0, uH0, uH1);
+    std::vector<double> state((size_t)kWave * 4 * (D.mt + D.ml), 0.0);
+    for (int lane = 0; lane < kWave; ++lane)
+      for (int r = 0; r < D.mt; ++r) {
+        const int node = lane * D.mt + r + 1;
+        if (node <= D.nt) state[(size_t)r * kWave + lane] = u0[node];
+      }
+    double y0 = 0.0;
+    if (D.on0) y0 += D.ow0 * u0[D.on0];
+    if (D.on1) y0 += D.ow1 * u0[D.on1];
+    std::vector<double> head = {y0, y0};   // y^0 = y^1 (w^1 = w^0)
+    keep.emplace_back();
+    keep.emplace_back();
+    keep.emplace_back();
+    std::vector<char> &bs = keep[keep.size() - 3], &bt = keep[keep.size() - 2], &bh = keep[keep.size() - 1];
+    if (b->precision == SB_FP32C) {
+      to_prec<float>(state, bs);
+      to_prec<float>(s.plan.tabf, bt);
+      to_prec<float>(head, bh);
+    } else {
+      to_prec<double>(state, bs);
+      to_prec<double>(s.plan.tabf, bt);
+      to_prec<double>(head, bh);
+    }
+    err = hipMemcpyAsync(s.dmem, bs.data(), bs.size(), hipMemcpyHostToDevice, b->stream);
+    if (err == hipSuccess) err = hipMemcpyAsync(s.dmem + otf, bt.data(), bt.size(), hipMemcpyHostToDevice, b->stream);
+    if (err == hipSuccess) err = hipMemcpyAsync(s.dmem + oout, bh.data(), bh.size(), hipMemcpyHostToDevice, b->stream);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(s.dmem + otab, s.plan.tab.data(), s.plan.tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           b->stream);
+    descs[i] = D;
+    Status &S = stats[i];
+    std::memset(&S, 0, sizeof(S));
+    S.samples_done = std::min<int64_t>(2, D.n_samples);
+    S.H_step = -1;
+    S.uH_n = uH1;
+    S.uH_nm1 = uH0;
+    S.eta_nm1 = uH0;   // eta^0 = u_H^0 - I u^0, the string starts at rest under the hammer
+    s.excited = true;
+    s.flagged = false;
+    s.samples_host = S.samples_done;
+  }
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(b->d_desc + first, descs.data(), sizeof(Desc) * count, hipMemcpyHostToDevice, b->stream);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(b->d_status + first, stats.data(), sizeof(Status) * count, hipMemcpyHostToDevice, b->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(b->stream);
+  if (err != hipSuccess) return hip_fail(b, err, "excite upload");
+  b->work_dirty = true;
+  return SB_OK;
+}
+
+static int do_step(sb_batch *b, int first, int count, int64_t n_steps) {
+  if (n_steps < 0) return fail(b, SB_EINVAL, "n_steps < 0");
+  if (!range_ok(b, first, count)) return fail(b, SB_EINVAL, "bad slot range");
+  if (n_steps == 0) return SB_OK;
+  // active slots per size class, longest remaining work first
+  std::vector<std::vector<std::pair<double, int>>> cls(kNumClasses);
+  bool any = false;
+  for (int i = first; i < first + count; ++i) {
+    Slot &s = b->slots[i];
+    if (!s.excited) continue;
+    any = true;
+    if (s.flagged || s.samples_host >= s.plan.desc.n_samples) continue;
+    const int64_t st = std::min<int64_t>(n_steps, s.plan.desc.n_samples - s.samples_host);
+    const double cost = (double)st * (double)(s.plan.desc.nt + s.plan.desc.nl + 8);
+    const int c = b->precision == SB_FP64_PLAIN ? 0 : s.plan.desc.cls;
+    cls[c].push_back({cost, i});
+  }
+  if (!any) return fail(b, SB_ESTATE, "no excited slot");
+  std::vector<int32_t> work;
+  std::vector<int> off(kNumClasses + 1, 0);
+  for (int c = 0; c < kNumClasses; ++c) {
+    std::stable_sort(cls[c].begin(), cls[c].end(), [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
+      return x.first > y.first;
+    });
+    off[c] = (int)work.size();
+    for (auto &w : cls[c]) work.push_back(w.second);
+  }
+  off[kNumClasses] = (int)work.size();
+  if (work.empty()) return SB_OK;
+  hipError_t e = hipSuccess;
+  if (b->precision == SB_FP64_PLAIN) {
+    // one string per launch, in order
+    for (int32_t i : work) {
+      e = launch_plain(b->d_desc, b->d_status, i, n_steps, b->mon_period, b->mon_tol, b->stream);
+      if (e != hipSuccess) return hip_fail(b, e, "plain launch");
+    }
+  } else {
+    if (work != b->h_work || b->work_dirty) {
+      // the previous upload may still be read by queued launches: order the
+      // host buffer's reuse after them
+      e = hipStreamSynchronize(b->stream);
+      if (e != hipSuccess) return hip_fail(b, e, "sync");
+      b->h_work = work;
+      e = hipMemcpyAsync(b->d_work, b->h_work.data(), sizeof(int32_t) * work.size(), hipMemcpyHostToDevice, b->stream);
+      if (e != hipSuccess) return hip_fail(b, e, "work upload");
+      b->work_dirty = false;
+    }
+    e = launch_zero(b->d_counters, kNumClasses, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "counter reset");
+    for (int c = 0; c < kNumClasses; ++c) {
+      const int nw = off[c + 1] - off[c];
+      if (nw == 0) continue;
+      LaunchArgs a;
+      a.desc = b->d_desc;
+      a.status = b->d_status;
+      a.work = b->d_work + off[c];
+      a.n_work = nw;
+      a.counter = b->d_counters + c;
+      a.n_steps = n_steps;
+      a.mon_period = b->mon_period;
+      a.max_sweeps = b->max_sweeps;
+      a.tol = b->tol;
+      a.mon_tol = b->mon_tol;
+      const int per_cu = std::max(1, max_blocks_per_cu(b->precision, c));
+      const int blocks = std::min(nw, b->num_cu * per_cu);
+      e = launch_step(b->precision, c, a, blocks, b->stream);
+      if (e != hipSuccess) return hip_fail(b, e, "step launch");
+    }
+  }
+  for (int c = 0; c < kNumClasses; ++c)
+    for (auto &w : cls[c]) {
+      Slot &s = b->slots[w.second];
+      s.samples_host = std::min<int64_t>(s.samples_host + n_steps, s.plan.desc.n_samples);
+    }
+  return SB_OK;
+}
+
+extern "C" int string_batch_step(sb_batch *b, int64_t n_steps) {
+  if (!b) return SB_EINVAL;
+  return do_step(b, 0, b->capacity, n_steps);
+}
+
+extern "C" int string_batch_step_range(sb_batch *b, int first, int count, int64_t n_steps) {
+  if (!b) return SB_EINVAL;
+  return do_step(b, first, count, n_steps);
+}
+
+extern "C" int string_batch_read_output(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst, int dst_is_device) {
+  if (!b) return SB_EINVAL;
+  if (idx < 0 || idx >= b->capacity || !dst || offset < 0 || count < 0) return fail(b, SB_EINVAL, "bad arguments");
+  Slot &s = b->slots[idx];
+  if (!s.excited) return fail(b, SB_ESTATE, "slot not excited");
+  if (offset + count > s.plan.desc.n_samples) return fail(b, SB_EINVAL, "range beyond n_samples");
+  if (count == 0) return SB_OK;
+  const char *src = (const char *)s.plan.desc.out + offset * b->esz;
+  hipError_t e = hipMemcpyAsync(dst, src, count * b->esz, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                b->stream);
+  if (e == hipSuccess && !dst_is_device) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(b, e, "read_output");
+  return SB_OK;
+}
+
+extern "C" int string_batch_output_ptr(sb_batch *b, int idx, void **dev_ptr) {
+  if (!b) return SB_EINVAL;
+  if (idx < 0 || idx >= b->capacity || !dev_ptr) return fail(b, SB_EINVAL, "bad arguments");
+  if (!b->slots[idx].excited) return fail(b, SB_ESTATE, "slot not excited");
+  *dev_ptr = b->slots[idx].plan.desc.out;
+  return SB_OK;
+}
+
+static int read_status(sb_batch *b, int idx, Status *S) {
+  if (idx < 0 || idx >= b->capacity) return fail(b, SB_EINVAL, "bad slot");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess) e = hipMemcpy(S, b->d_status + idx, sizeof(Status), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(b, e, "status read");
+  if (S->flags) b->slots[idx].flagged = true;
+  return SB_OK;
+}
+
+extern "C" int string_batch_read_energy(sb_batch *b, int idx, double *H_latest, int64_t *step_of_H) {
+  if (!b) return SB_EINVAL;
+  Status S;
+  int st = read_status(b, idx, &S);
+  if (st) return st;
+  if (H_latest) *H_latest = S.H_latest;
+  if (step_of_H) *step_of_H = S.H_step;
+  return SB_OK;
+}
+
+extern "C" int string_batch_info(sb_batch *b, int idx, sb_string_info *info) {
+  if (!b) return SB_EINVAL;
+  if (!info) return fail(b, SB_EINVAL, "null info");
+  if (idx < 0 || idx >= b->capacity) return fail(b, SB_EINVAL, "bad slot");
+  Slot &s = b->slots[idx];
+  std::memset(info, 0, sizeof(*info));
+  if (!s.planned) return fail(b, SB_ESTATE, "slot has no parameters");
+  info->N_t = s.plan.desc.Nt;
+  info->N_l = s.plan.desc.Nl;
+  info->n_samples = s.plan.desc.n_samples;
+  if (!s.excited) return SB_OK;
+  Status S;
+  int st = read_status(b, idx, &S);
+  if (st) return st;
+  info->samples_done = S.samples_done;
+  info->flags = S.flags;
+  info->max_sweeps = S.max_sweeps;
+  info->total_sweeps = S.total_sweeps;
+  s.samples_host = S.samples_done;
+  return SB_OK;
+}
+
+extern "C" int string_batch_set_monitor(sb_batch *b, int period, double growth_tol) {
+  if (!b) return SB_EINVAL;
+  if (period < 0 || !(growth_tol >= 0) || !std::isfinite(growth_tol)) return fail(b, SB_EINVAL, "bad monitor settings");
+  b->mon_period = period;
+  b->mon_tol = growth_tol;
+  return SB_OK;
+}
+
+extern "C" int string_batch_set_solver(sb_batch *b, double tol, int max_sweeps) {
+  if (!b) return SB_EINVAL;
+  if (!(tol >= 0) || !std::isfinite(tol) || max_sweeps < 1 || max_sweeps > 100000)
+    return fail(b, SB_EINVAL, "bad solver settings");
+  b->tol = tol;
+  b->max_sweeps = max_sweeps;
+  return SB_OK;
+}

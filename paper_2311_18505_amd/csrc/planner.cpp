@@ -1,0 +1,339 @@
+// Host planner of libstringfdtd: grid sizing, coefficients and per-string
+// tables for the GPU stepping kernel (FP64 on the host, rounded once to the
+// kernel precision on upload).
+#include "planner.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+
+namespace sfd {
+
+static bool finite_all(std::initializer_list<double> xs) {
+  for (double x : xs)
+    if (!std::isfinite(x)) return false;
+  return true;
+}
+
+double theta_of(const sb_string_params &p) {
+  // Sec. 3.2: theta = (1 + 4/pi^2)/2 unless given
+  return p.theta > 0.0 ? p.theta : 0.5 * (1.0 + 4.0 / (M_PI * M_PI));
+}
+
+int plan_grid(const sb_string_params &p, GridPlan &g, std::string &err) {
+  if (!finite_all({p.fs, p.f0, p.B, p.alpha, p.theta, p.sigma0_t, p.sigma1_t, p.sigma0_l, p.sigma1_l,
+                   p.x_out, p.mod_depth_cents, p.mod_rate_hz, p.glide_semitones})) {
+    err = "non-finite parameter";
+    return SB_EINVAL;
+  }
+  if (!(p.fs > 0) || !(p.f0 > 0) || !(p.B >= 0) || !(p.alpha >= 1)) {
+    err = "need fs > 0, f0 > 0, B >= 0, alpha >= 1";
+    return SB_EINVAL;
+  }
+  const double th = theta_of(p);
+  if (!(th > 0.5) || !(th <= 1.0)) {
+    err = "need 1/2 < theta <= 1";
+    return SB_EINVAL;
+  }
+  if (!(p.sigma0_t >= 0) || !(p.sigma1_t >= 0) || !(p.sigma0_l >= 0) || !(p.sigma1_l >= 0)) {
+    err = "losses must be >= 0";
+    return SB_EINVAL;
+  }
+  if (!(p.x_out > 0 && p.x_out < 1)) {
+    err = "x_out must lie in (0,1)";
+    return SB_EINVAL;
+  }
+  if (p.n_samples < 2) {
+    err = "n_samples must be >= 2";
+    return SB_EINVAL;
+  }
+  if (p.mod_type < 0 || p.mod_type > 2 || p.grid_t < 0 || p.grid_l < 0) {
+    err = "bad mod_type or grid override";
+    return SB_EINVAL;
+  }
+  const double k = 1.0 / p.fs;
+  const double gamma0 = 2.0 * p.f0;                      // Sec. 4.1: f0 = gamma/2
+  const double kappa = gamma0 * std::sqrt(p.B) / M_PI;    // Sec. 4.1: K = (pi kappa/gamma)^2, K := B
+  double gmax = gamma0;                                   // largest gamma the modulation reaches
+  if (p.mod_type == 1) gmax = gamma0 * std::exp2(std::fabs(p.mod_depth_cents) / 1200.0);
+  if (p.mod_type == 2) gmax = gamma0 * std::exp2((p.glide_semitones > 0.0 ? p.glide_semitones : 0.0) / 12.0);
+  // Transverse spacing: stability of the theta-scheme requires
+  // lambda^2 + 4 nu^2 <= 2 theta - 1 (Von Neumann), which gives Sec. 3.2's
+  // h^(t) at theta = 1.
+  const double gk2 = gmax * gmax * k * k;
+  const double h2 = (gk2 + std::sqrt(gk2 * gk2 + 16.0 * (2.0 * th - 1.0) * kappa * kappa * k * k)) /
+                    (2.0 * (2.0 * th - 1.0));
+  const int Nt = p.grid_t > 0 ? p.grid_t : (int)std::floor(1.0 / std::sqrt(h2));
+  int Nl = 0;
+  if (p.alpha != 1.0) Nl = p.grid_l > 0 ? p.grid_l : (int)std::floor(1.0 / (gmax * p.alpha * k));
+  if (Nt < 2 || (p.alpha != 1.0 && Nl < 2)) {
+    err = "grid has fewer than 2 intervals";
+    return SB_EINVAL;
+  }
+  g.Nt = Nt;
+  g.Nl = Nl;
+  g.k = k;
+  g.theta = th;
+  g.gamma0 = gamma0;
+  g.gamma_max = gmax;
+  g.kappa = kappa;
+  return SB_OK;
+}
+
+// Factor of the symmetric Toeplitz tridiagonal (c, d, c) = kT (1 + rho S-)(1 + rho S+)
+static void toeplitz_factor(double d, double c, double &rho, double &kT) {
+  if (c == 0.0) {
+    rho = 0.0;
+    kT = d;
+    return;
+  }
+  rho = 2.0 * c / (d + std::sqrt(d * d - 4.0 * c * c));
+  kT = d / (1.0 + rho * rho);
+}
+
+// Weights of the boundary value z_0 = sum_m w_m b_m of the forward
+// recurrence on the odd 2N-periodic extension of a Dirichlet system.
+static void boundary_weights(double rho, double kT, int N, std::vector<double> &w) {
+  w.assign(N + 1, 0.0);
+  if (rho == 0.0) return;
+  const double mr = -rho;
+  const double r2N = std::pow(rho, 2.0 * N);
+  const double scale = 1.0 / (kT * (1.0 - r2N));
+  for (int m = 1; m <= N - 1; ++m) {
+    double a = std::pow(mr, (double)m);
+    double b = std::pow(mr, (double)(2 * N - m));
+    w[m] = (-a + b) * scale;
+  }
+}
+
+// Linear interpolation row on the nodes 1..N-1 at x (end nodes are fixed).
+static void point_interp(double x, int N, int &n0, int &n1, double &w0, double &w1) {
+  int l = (int)std::floor(x * N);
+  double w = x * N - l;
+  n0 = (l >= 1 && l <= N - 1) ? l : 0;
+  n1 = (l + 1 >= 1 && l + 1 <= N - 1) ? l + 1 : 0;
+  w0 = n0 ? 1.0 - w : 0.0;
+  w1 = n1 ? w : 0.0;
+}
+
+int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
+  GridPlan g;
+  int st = plan_grid(p, g, err);
+  if (st) return st;
+  if (g.Nt > kMaxN || g.Nl > kMaxN) {
+    err = "grid larger than 1024 intervals";
+    return SB_EBUDGET;
+  }
+  P = Plan();
+  P.grid = g;
+  Desc &D = P.desc;
+  const int Nt = g.Nt, Nl = g.Nl;
+  D.Nt = Nt;
+  D.Nl = Nl;
+  D.nt = Nt - 1;
+  D.nl = Nl > 0 ? Nl - 1 : 0;
+  D.mt = (Nt + kWave - 1) / kWave;     // slots per lane cover the half points 1..Nt
+  D.ml = Nl > 0 ? (Nl + kWave - 1) / kWave : 0;
+  const int need = std::max(D.mt, D.ml);
+  D.cls = -1;
+  for (int c = 0; c < kNumClasses; ++c)
+    if (need <= kClassSlots[c]) {
+      D.cls = c;
+      break;
+    }
+  if (D.cls < 0) {
+    err = "string exceeds the largest size class";
+    return SB_EBUDGET;
+  }
+  D.mon_check = p.mod_type == 0 ? 1 : 0;
+  D.n_samples = p.n_samples;
+  const double k = g.k, th = g.theta;
+  D.k = k;
+  D.Ntd = Nt;
+  D.Nld = Nl;
+  D.theta = th;
+  D.g2k2_0 = g.gamma0 * g.gamma0 * k * k;
+  D.a2 = p.alpha * p.alpha;
+  D.a2m1_4 = (p.alpha * p.alpha - 1.0) / 4.0;
+  D.cS = g.kappa * g.kappa * k * k * (double)Nt * (double)Nt;
+  D.s0k_t = p.sigma0_t * k;
+  D.s1k_t = p.sigma1_t * k * (double)Nt * (double)Nt;
+  D.s0k_l = p.sigma0_l * k;
+  D.s1k_l = Nl > 0 ? p.sigma1_l * k * (double)Nl * (double)Nl : 0.0;
+  D.ratio_lt = Nl > 0 ? (double)Nl / (double)Nt : 0.0;
+
+  // T_u0 = Theta + sigma0 k I - sigma1 k D_xx (constant part of the
+  // transverse block of A); T_z = (1 + sigma0 k) I - sigma1 k D_xx.
+  const double dt = th + D.s0k_t + 2.0 * D.s1k_t, ct = 0.5 * (1.0 - th) - D.s1k_t;
+  double kTt;
+  toeplitz_factor(dt, ct, D.rho_t, kTt);
+  D.itk_t = 1.0 / kTt;
+  D.gt_t = std::pow(-D.rho_t, (double)D.mt);
+  std::vector<double> wbt, wbl;
+  boundary_weights(D.rho_t, kTt, Nt, wbt);
+  double kTl = 1.0;
+  if (Nl > 0) {
+    const double dl = 1.0 + D.s0k_l + 2.0 * D.s1k_l, cl = -D.s1k_l;
+    toeplitz_factor(dl, cl, D.rho_l, kTl);
+    D.itk_l = 1.0 / kTl;
+    D.gt_l = std::pow(-D.rho_l, (double)D.ml);
+    boundary_weights(D.rho_l, kTl, Nl, wbl);
+  }
+
+  D.mod_type = p.mod_type;
+  D.f0 = p.f0;
+  D.fs = p.fs;
+  if (p.mod_type == 1) {
+    D.mod_a = p.mod_depth_cents / 1200.0;
+    D.mod_b = p.mod_rate_hz;
+  } else if (p.mod_type == 2) {
+    D.mod_a = p.glide_semitones / 12.0;
+    D.mod_b = (double)p.n_samples / p.fs;   // duration T
+  }
+  point_interp(p.x_out, Nt, D.on0, D.on1, D.ow0, D.ow1);
+
+  // tables, lane-major [slot][lane]
+  const int mt = D.mt, ml = D.ml;
+  P.tab.assign((size_t)kWave * (mt + 2 * ml), 0u);
+  P.tabf.assign((size_t)kWave * (3 * mt + ml), 0.0);
+  uint32_t *jab = P.tab.data();
+  uint32_t *rga = jab + (size_t)kWave * mt;
+  uint32_t *rgb = rga + (size_t)kWave * ml;
+  double *wi = P.tabf.data();
+  double *wbu = wi + (size_t)kWave * mt;
+  double *wbz = wbu + (size_t)kWave * mt;
+  double *sm = wbz + (size_t)kWave * ml;
+  P.ja.assign(Nt + 1, 1);
+  P.jb.assign(Nt + 1, 1);
+  P.w.assign(Nt + 1, 0.0);
+  for (int lane = 0; lane < kWave; ++lane)
+    for (int r = 0; r < mt; ++r) {
+      const int i = lane * mt + r + 1;   // half point i / node i
+      uint32_t a = 1, b = 1;
+      double w = 0.0;
+      if (i <= Nt && Nl > 0) {
+        // I_(l)->(t): half point (i-1/2) h_t in units of l-half points:
+        // xi = ((2i-1) Nl + Nt) / (2 Nt), linear weights, ends held constant
+        const long long num = (long long)(2 * i - 1) * Nl + Nt, den = 2LL * Nt;
+        const int j0 = (int)(num / den);
+        w = (double)(num % den) / (double)den;
+        a = (uint32_t)std::min(std::max(j0, 1), Nl);
+        b = (uint32_t)std::min(std::max(j0 + 1, 1), Nl);
+        P.ja[i] = (int)a;
+        P.jb[i] = (int)b;
+        P.w[i] = w;
+      }
+      jab[(size_t)r * kWave + lane] = a | (b << 16);
+      wi[(size_t)r * kWave + lane] = w;
+      if (i <= Nt - 1) wbu[(size_t)r * kWave + lane] = wbt[i];
+    }
+  if (Nl > 0) {
+    // ranges of t-half points whose first (second) tap lands on l-half j
+    std::vector<int> sa(Nl + 2, 0), na(Nl + 2, 0), sb(Nl + 2, 0), nb(Nl + 2, 0);
+    for (int i = Nt; i >= 1; --i) {
+      sa[P.ja[i]] = i - 1;
+      na[P.ja[i]]++;
+      sb[P.jb[i]] = i - 1;
+      nb[P.jb[i]]++;
+    }
+    D.gmax = 0;
+    for (int j = 1; j <= Nl; ++j) D.gmax = std::max(D.gmax, std::max(na[j], nb[j]));
+    for (int lane = 0; lane < kWave; ++lane)
+      for (int r = 0; r < ml; ++r) {
+        const int j = lane * ml + r + 1;
+        if (j <= Nl) {
+          rga[(size_t)r * kWave + lane] = (uint32_t)sa[j] | ((uint32_t)na[j] << 16);
+          rgb[(size_t)r * kWave + lane] = (uint32_t)sb[j] | ((uint32_t)nb[j] << 16);
+        }
+        if (j <= Nl - 1) wbz[(size_t)r * kWave + lane] = wbl[j];
+      }
+  }
+  (void)sm;
+  return SB_OK;
+}
+
+int plan_excitation(const sb_excitation &e, Plan &P, std::string &err) {
+  Desc &D = P.desc;
+  if (e.type < 0 || e.type > 2) {
+    err = "bad excitation type";
+    return SB_EINVAL;
+  }
+  if (!finite_all({e.x, e.c0, e.v_H, e.M_H, e.K_H, e.alpha_H})) {
+    err = "non-finite excitation parameter";
+    return SB_EINVAL;
+  }
+  if (e.type != 0 && !(e.x > 0 && e.x < 1)) {
+    err = "excitation position must lie in (0,1)";
+    return SB_EINVAL;
+  }
+  if (e.type == 2 && (!(e.M_H > 0) || !(e.K_H > 0) || !(e.alpha_H >= 1) || !(e.rhoA > 0))) {
+    err = "hammer needs M_H, K_H, rhoA > 0 and alpha_H >= 1";
+    return SB_EINVAL;
+  }
+  const int Nt = D.Nt, mt = D.mt, ml = D.ml, nt = D.nt;
+  D.ham_on = e.type == 2;
+  D.hn0 = D.hn1 = 0;
+  D.hw0 = D.hw1 = 0.0;
+  D.omega_pow = D.alpha_H = D.Mr = D.IHs = 0.0;
+  double *sm = P.tabf.data() + (size_t)kWave * (2 * mt + ml);
+  std::fill(sm, sm + (size_t)kWave * mt, 0.0);
+  if (e.type == 2) {
+    point_interp(e.x, Nt, D.hn0, D.hn1, D.hw0, D.hw1);
+    D.omega_pow = e.K_H / e.M_H;       // omega_H^{1 + alpha_H}
+    D.alpha_H = e.alpha_H;
+    D.Mr = e.M_H / e.rhoA;             // mass ratio for a string of length 1
+    // s = T_u0^{-1} J_H, J_H = I_H^T / h_t (Thomas algorithm, FP64)
+    const double th = D.theta;
+    const double d = th + D.s0k_t + 2.0 * D.s1k_t, c = 0.5 * (1.0 - th) - D.s1k_t;
+    std::vector<double> rhs(nt + 1, 0.0), cp(nt + 1, 0.0), x(nt + 2, 0.0);
+    if (D.hn0) rhs[D.hn0] += D.hw0 * Nt;
+    if (D.hn1) rhs[D.hn1] += D.hw1 * Nt;
+    double den = d;
+    std::vector<double> dp(nt + 1, 0.0);
+    cp[1] = c / d;
+    dp[1] = rhs[1] / d;
+    for (int i = 2; i <= nt; ++i) {
+      den = d - c * cp[i - 1];
+      cp[i] = c / den;
+      dp[i] = (rhs[i] - c * dp[i - 1]) / den;
+    }
+    x[nt] = dp[nt];
+    for (int i = nt - 1; i >= 1; --i) x[i] = dp[i] - cp[i] * x[i + 1];
+    D.IHs = (D.hn0 ? D.hw0 * x[D.hn0] : 0.0) + (D.hn1 ? D.hw1 * x[D.hn1] : 0.0);
+    for (int lane = 0; lane < kWave; ++lane)
+      for (int r = 0; r < mt; ++r) {
+        const int i = lane * mt + r + 1;
+        if (i <= nt) sm[(size_t)r * kWave + lane] = x[i];
+      }
+  }
+  return SB_OK;
+}
+
+// Initial state (Sec. 3.3): pluck = triangle of peak c0 at x released from
+// rest; hammer = string at rest, hammer touching it with velocity v_H.
+void initial_state(const sb_excitation &e, const Plan &P, std::vector<double> &u0, double &uH0, double &uH1) {
+  const Desc &D = P.desc;
+  u0.assign(D.nt + 1, 0.0);
+  uH0 = uH1 = 0.0;
+  if (e.type == 1) {
+    for (int i = 1; i <= D.nt; ++i) {
+      const double x = (double)i / D.Nt;
+      u0[i] = x <= e.x ? e.c0 * x / e.x : e.c0 * (1.0 - x) / (1.0 - e.x);
+    }
+  } else if (e.type == 2) {
+    uH1 = D.k * e.v_H;
+  }
+}
+
+}  // namespace sfd
+
+extern "C" int string_plan_grid(const sb_string_params *p, int32_t *N_t, int32_t *N_l) {
+  if (!p) return SB_EINVAL;
+  sfd::GridPlan g;
+  std::string err;
+  int st = sfd::plan_grid(*p, g, err);
+  if (st) return st;
+  if (N_t) *N_t = g.Nt;
+  if (N_l) *N_l = g.Nl;
+  return SB_OK;
+}

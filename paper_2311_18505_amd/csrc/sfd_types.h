@@ -1,0 +1,93 @@
+// Internal types shared by the host planner, the C ABI and the HIP kernels of
+// libstringfdtd (private to the library).
+#pragma once
+#include <stdint.h>
+
+namespace sfd {
+
+constexpr int kWave = 64;          // lanes per wavefront on CDNA4
+constexpr int kMaxSlots = 16;      // grid points per lane per grid: N_t, N_l <= 1024
+constexpr int kMaxN = kWave * kMaxSlots;
+
+// Size classes of the stepping kernel: every lane owns up to MM consecutive
+// points of each grid.  A string runs in the smallest class whose MM covers
+// both ceil(N_t/64) and ceil(N_l/64).
+constexpr int kNumClasses = 4;
+constexpr int kClassSlots[kNumClasses] = {2, 4, 8, 16};
+
+enum : int32_t {
+  kFlagUnstable = 1,      // energy monitor: non-finite or growing energy
+  kFlagNoConverge = 2,    // coupled solve did not converge within the sweep cap
+};
+
+// Per-string plan, computed once on the host in FP64 and uploaded.  All
+// offsets are in elements of the respective arena.
+struct Desc {
+  int32_t Nt, Nl;             // intervals of the transverse / longitudinal grids (Nl = 0: no zeta)
+  int32_t nt, nl;             // unknowns: Nt-1, Nl-1 (0)
+  int32_t mt, ml;             // points per lane: ceil(Nt/64), ceil(Nl/64)
+  int32_t cls;                // size class index
+  int32_t mon_check;          // 1: energy must not grow (unforced, constant f0)
+  int64_t n_samples;          // samples to produce
+  void *st;                   // state block, kernel precision, lane-major [array][slot][lane]
+  void *out;                  // output samples, kernel precision
+  const uint32_t *tab;        // integer tables: ja|jb<<16 per t-slot, sa|na<<16 and sb|nb<<16 per l-slot
+  const void *tabf;           // real tables (kernel precision): w per t-slot, boundary weights, SM vector
+  double k;                   // time step
+  double Ntd, Nld;            // 1/h_t, 1/h_l
+  double theta;
+  double g2k2_0;              // (gamma0 k)^2
+  double a2;                  // alpha^2
+  double a2m1_4;              // (alpha^2 - 1) / 4
+  double cS;                  // kappa^2 k^2 Nt^2
+  double s0k_t, s1k_t;        // sigma0_t k, sigma1_t k Nt^2
+  double s0k_l, s1k_l;        // sigma0_l k, sigma1_l k Nl^2
+  double ratio_lt;            // h_t / h_l = Nl / Nt
+  double rho_t, itk_t;        // Toeplitz factor of T_u0: rho, 1/kappa_T
+  double rho_l, itk_l;        // same for T_z
+  double gt_t, gt_l;          // (-rho)^mt, (-rho)^ml: lane-to-lane carry factors
+  // f0 modulation
+  int32_t mod_type, pad0;     // 0 none, 1 vibrato, 2 glide
+  double f0, fs, mod_a, mod_b;   // vibrato: a = depth/1200, b = rate; glide: a = semis/12, b = 1/T
+  // hammer
+  int32_t ham_on;             // 1 if the excitation is a hammer
+  int32_t hn0, hn1;           // nodes of I_H (1-based; 0 = absent)
+  int32_t pad1;
+  double hw0, hw1;            // weights of I_H
+  double omega_pow, alpha_H, Mr, IHs;   // K_H/M_H, exponent, M_H/(rho A), I_H T_u0^{-1} J_H
+  // readout
+  int32_t on0, on1;           // nodes of I(x_out)
+  double ow0, ow1;
+  int32_t gmax;               // longest t-half range gathered by one l-half point
+  int32_t pad2;
+};
+
+// Per-string dynamic status (device memory, updated by the kernel).
+struct Status {
+  int64_t samples_done;       // samples y^0..y^{samples_done-1} are valid
+  int32_t flags;              // kFlag*
+  int32_t max_sweeps;         // largest number of solver sweeps taken in one step
+  int64_t total_sweeps;       // sum of sweeps (for statistics)
+  double H_latest;            // energy H^{n+1/2} of the last monitor check
+  int64_t H_step;             // n of that check (-1: none)
+  double H_ref;               // reference for the growth check
+  int32_t touched;            // hammer in contact since the last check
+  int32_t pad0;
+  double uH_n, uH_nm1, eta_nm1;  // hammer lumped state (FP64)
+};
+
+// Arguments of one launch of the stepping kernel.
+struct LaunchArgs {
+  const Desc *desc;
+  Status *status;
+  const int32_t *work;        // string indices of this class, longest first
+  int32_t n_work;
+  int32_t *counter;           // work-queue head (zeroed before the launch)
+  int64_t n_steps;            // steps to advance each string (clamped at n_samples)
+  int32_t mon_period;         // steps between energy checks (0: off)
+  int32_t max_sweeps;         // cap of solver sweeps per step
+  double tol;                 // relative convergence tolerance of the coupled solve
+  double mon_tol;             // relative growth tolerance of the energy check
+};
+
+}  // namespace sfd
