@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Benchmark of batched FP32 string synthesis on one MI355X.
+
+One bench step synthesises a whole batch of strings from their excitation to
+their last sample through the C ABI (rewind on the device, then
+string_batch_step over the longest duration), with every input already in
+device memory.  Prints one JSON line: grid-point updates per second (the sum
+over strings of (N_t - 1 + N_l - 1) per time step), audio seconds per second,
+the kernel's roofline position and the FP64 CPU oracle timed on a sample of
+the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point updates/s & audio-s/s, batched FP32 vs plain FP64; p99 latency"
+PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 2.4 GHz x 256)
+
+WORKLOADS = {
+    # 16384 nonlinear strings, durations U(0.5, 4) s, vibrato or glide, FP32
+    "uneven16384": lambda W: W.uneven_batch_16384(),
+    # 4096 nonlinear strings of 2 s
+    "uniform4096": lambda W: W.uniform_batch_4096(),
+}
+
+
+def unknowns(info):
+    return (info["N_t"] - 1) + max(info["N_l"] - 1, 0)
+
+
+def cpu_baseline(items, seconds_cap, threads):
+    """The FP64 oracle on a bounded sample of the workload, one string per
+    host thread.  Returns the baseline record and the oracle's arithmetic per
+    grid-point update (its RHS matvecs and banded LU)."""
+    import oracle
+    sample = []
+    for p, e in items[:threads * 4]:
+        q = dict(p, n_samples=min(p["n_samples"], int(seconds_cap * p["fs"])))
+        sample.append((q, e))
+    t0 = time.perf_counter()
+    res = oracle.run_many(sample, threads=threads)
+    dt = time.perf_counter() - t0
+    upd = 0
+    flops = 0.0
+    for r in res:
+        g = r["grid"]
+        n = (g["N_t"] - 1) + max(g["N_l"] - 1, 0)
+        upd += n * r["steps_done"]
+        flops += r["flops"]
+    rec = {"value": upd / dt, "unit": "grid-point updates/s", "cores": threads, "kind": "oracle",
+           "sample": "first %d strings of the workload, each cut to %.2f s (%d updates), FP64, "
+                     "one string per thread" % (len(sample), seconds_cap, upd),
+           "seconds": dt}
+    return rec, flops / upd
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="uneven16384", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=0.25, help="duration cap of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the strings are independent and this build has no "
+              "multi-GPU path (got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2311_18505_amd import binding, hiptime, workloads as W
+
+    t_setup = time.perf_counter()
+    items = WORKLOADS[args.workload](W)
+    params = [p for p, _ in items]
+    excs = [e for _, e in items]
+    b = binding.StringBatch(len(items), "fp32c")
+    b.set_params(0, params)
+    b.excite(0, excs)
+    infos = [b.info(i) for i in range(len(items))]
+    n_max = max(p["n_samples"] for p in params)
+    updates = sum(unknowns(inf) * (inf["n_samples"] - 2) for inf in infos)
+    audio_s = sum(p["n_samples"] / p["fs"] for p in params)
+    print("[bench] %s: %d strings, %.3e grid-point updates per step, %.0f audio-s, setup %.1f s"
+          % (args.workload, len(items), updates, audio_s, time.perf_counter() - t_setup), file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        b.rewind()
+        b.step(n_max)
+        hiptime.synchronize()
+        print("[bench] warmup %d done" % w, file=sys.stderr, flush=True)
+
+    ev0, ev1 = hiptime.Event(), hiptime.Event()
+    hiptime.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(0)
+    for k in range(args.steps):
+        b.rewind()
+        b.step(n_max)
+    ev1.record(0)
+    ev1.synchronize()
+    hiptime.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_ms(ev1)
+    print("[bench] %d steps: wall %.3f s, events %.3f ms" % (args.steps, wall, gpu_ms), file=sys.stderr, flush=True)
+
+    # every string must have finished cleanly
+    bad = 0
+    sweeps = 0
+    for i in range(len(items)):
+        inf = b.info(i)
+        sweeps += inf["total_sweeps"]
+        if inf["flags"] != 0 or inf["samples_done"] != inf["n_samples"]:
+            bad += 1
+    b.close()
+    if bad:
+        print("[bench] %d strings did not finish cleanly" % bad, file=sys.stderr, flush=True)
+
+    sec_per_step = wall / args.steps
+    value = updates / sec_per_step
+    kernel_s = gpu_ms / 1e3 / args.steps
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_per_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "strings": len(items), "fs": 48000,
+                   "updates_per_step": updates, "audio_seconds_per_step": audio_s,
+                   "precision": "FP32 with compensated state updates, FP64 energy monitor"},
+        "audio_s_per_s": audio_s / sec_per_step,
+        "sweeps_per_step_mean": sweeps / max(1, sum(inf["n_samples"] - 2 for inf in infos)),
+        "strings_not_finished": bad,
+    }
+    if not args.no_cpu:
+        threads = min(16, os.cpu_count() or 1)
+        rec, flops_per_update = cpu_baseline(items, args.cpu_seconds, threads)
+        out["cpu_baseline"] = {k: v for k, v in rec.items() if k != "seconds"}
+        achieved = flops_per_update * updates / kernel_s
+        out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                           "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                           "flops_per_update": flops_per_update,
+                           "kernel_ms_per_launch": kernel_s * 1e3}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -138,6 +138,12 @@ int string_batch_step(sb_batch *b, int64_t n_steps);
 /* Same as string_batch_step but only for slots first .. first+count-1. */
 int string_batch_step_range(sb_batch *b, int first, int count, int64_t n_steps);
 
+/* Return slots first .. first+count-1 to their state right after
+ * string_batch_excite (samples_done = 2, flags cleared) without host work:
+ * a device copy of the excited state is kept for this.  Asynchronous on the
+ * batch stream.  Errors: SB_EINVAL, SB_EDEVICE. */
+int string_batch_rewind(sb_batch *b, int first, int count);
+
 /* Copy samples offset .. offset+count-1 of slot idx to dst (count elements
  * of the batch precision: float for SB_FP32C, double otherwise), ordered on
  * the batch stream and synchronous with it when dst_is_device == 0.

@@ -58,6 +58,7 @@ SIGNATURES = [
     ("string_batch_excite", C.c_int, [_P, C.c_int, C.c_int, C.POINTER(SbExcitation)]),
     ("string_batch_step", C.c_int, [_P, C.c_int64]),
     ("string_batch_step_range", C.c_int, [_P, C.c_int, C.c_int, C.c_int64]),
+    ("string_batch_rewind", C.c_int, [_P, C.c_int, C.c_int]),
     ("string_batch_read_output", C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, _P, C.c_int]),
     ("string_batch_output_ptr", C.c_int, [_P, C.c_int, C.POINTER(_P)]),
     ("string_batch_read_energy", C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -183,6 +184,10 @@ class StringBatch:
         if first is None:
             return self._check(self.lib.string_batch_step(self.h, n_steps), "step")
         return self._check(self.lib.string_batch_step_range(self.h, first, count, n_steps), "step_range")
+
+    def rewind(self, first: int = 0, count: int | None = None):
+        count = self.capacity - first if count is None else count
+        self._check(self.lib.string_batch_rewind(self.h, first, count), "rewind")
 
     def read_output(self, idx: int, offset: int = 0, count: int | None = None) -> np.ndarray:
         if count is None:

@@ -18,6 +18,8 @@ namespace sfd {
 hipError_t launch_step(int precision, int cls, const LaunchArgs &a, int blocks, hipStream_t st);
 hipError_t launch_zero(int32_t *c, int n, hipStream_t st);
 int max_blocks_per_cu(int precision, int cls);
+hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
+                         hipStream_t st);
 hipError_t launch_plain(const Desc *d_desc, Status *d_status, int slot, int64_t n_steps, int mon_period,
                         double mon_tol, hipStream_t st);
 }  // namespace sfd
@@ -114,6 +116,7 @@ struct sb_batch {
   Arena arena;
   Desc *d_desc = nullptr;
   Status *d_status = nullptr;
+  Status *d_status0 = nullptr;   // status right after excitation (for rewind)
   int32_t *d_work = nullptr;
   int32_t *d_counters = nullptr;
   std::vector<int32_t> h_work;
@@ -165,18 +168,22 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
   hipError_t e;
   if ((e = hipMalloc(&b->d_desc, sizeof(Desc) * capacity)) != hipSuccess ||
       (e = hipMalloc(&b->d_status, sizeof(Status) * capacity)) != hipSuccess ||
+      (e = hipMalloc(&b->d_status0, sizeof(Status) * capacity)) != hipSuccess ||
       (e = hipMalloc(&b->d_work, sizeof(int32_t) * capacity)) != hipSuccess ||
       (e = hipMalloc(&b->d_counters, sizeof(int32_t) * 16)) != hipSuccess) {
     g_create_error = std::string("hipMalloc: ") + hipGetErrorString(e);
     (void)hipGetLastError();
     hipFree(b->d_desc);
     hipFree(b->d_status);
+    hipFree(b->d_status0);
     hipFree(b->d_work);
     hipFree(b->d_counters);
     delete b;
     return SB_ENOMEM;
   }
-  if ((e = hipMemset(b->d_status, 0, sizeof(Status) * capacity)) != hipSuccess) {
+  // zeroed descriptors: a slot without an excitation has null state pointers
+  if ((e = hipMemset(b->d_desc, 0, sizeof(Desc) * capacity)) != hipSuccess ||
+      (e = hipMemset(b->d_status, 0, sizeof(Status) * capacity)) != hipSuccess) {
     g_create_error = std::string("hipMemset: ") + hipGetErrorString(e);
     delete b;
     return SB_EDEVICE;
@@ -191,6 +198,7 @@ extern "C" int string_batch_destroy(sb_batch *b) {
   b->arena.clear();
   hipFree(b->d_desc);
   hipFree(b->d_status);
+  hipFree(b->d_status0);
   hipFree(b->d_work);
   hipFree(b->d_counters);
   delete b;
@@ -205,16 +213,18 @@ static bool range_ok(const sb_batch *b, int first, int count) {
   return first >= 0 && count >= 0 && (int64_t)first + count <= b->capacity;
 }
 
-// Device region of one slot: state | real tables | output | integer tables.
-static size_t region_size(const sb_batch *b, const Desc &D, size_t *off_tabf, size_t *off_out, size_t *off_tab) {
+// Device region of one slot: state | initial state | real tables | output | integer tables.
+static size_t region_size(const sb_batch *b, const Desc &D, size_t *off_st0, size_t *off_tabf, size_t *off_out,
+                          size_t *off_tab) {
   const size_t st = align256(b->esz * (size_t)kWave * 4 * (D.mt + D.ml));
   const size_t tf = align256(b->esz * (size_t)kWave * (3 * D.mt + D.ml));
   const size_t ou = align256(b->esz * (size_t)(D.n_samples + kWave));
   const size_t tb = align256(sizeof(uint32_t) * (size_t)kWave * (D.mt + 2 * D.ml));
-  *off_tabf = st;
-  *off_out = st + tf;
-  *off_tab = st + tf + ou;
-  return st + tf + ou + tb;
+  *off_st0 = st;
+  *off_tabf = 2 * st;
+  *off_out = 2 * st + tf;
+  *off_tab = 2 * st + tf + ou;
+  return 2 * st + tf + ou + tb;
 }
 
 extern "C" int string_batch_set_params(sb_batch *b, int first, int count, const sb_string_params *p) {
@@ -230,15 +240,18 @@ extern "C" int string_batch_set_params(sb_batch *b, int first, int count, const 
     for (int i = 0; i < count; ++i)
       if (plans[i].desc.nt + plans[i].desc.nl + 1 > 2048)
         return fail(b, SB_EBUDGET, "plain FP64 path holds at most 2048 unknowns");
+  // queued launches may still read the memory released below
+  hipError_t es = hipStreamSynchronize(b->stream);
+  if (es != hipSuccess) return hip_fail(b, es, "sync");
   for (int i = 0; i < count; ++i) {
     Slot &s = b->slots[first + i];
     if (s.dmem) {
       b->arena.release(s.dmem, s.dsize);
       s.dmem = nullptr;
     }
-    size_t a, o, t;
+    size_t a0, a, o, t;
     s.plan = std::move(plans[i]);
-    s.dsize = region_size(b, s.plan.desc, &a, &o, &t);
+    s.dsize = region_size(b, s.plan.desc, &a0, &a, &o, &t);
     s.dmem = (char *)b->arena.alloc(s.dsize);
     if (!s.dmem) {
       s.planned = false;
@@ -256,7 +269,12 @@ extern "C" int string_batch_set_params(sb_batch *b, int first, int count, const 
     std::memset(&z, 0, sizeof(z));
     z.H_step = -1;
   }
+  // and null descriptors (the previous state memory of these slots is released)
+  std::vector<Desc> zd(count);
+  std::memset(zd.data(), 0, sizeof(Desc) * count);
   hipError_t e = hipMemcpyAsync(b->d_status + first, zs.data(), sizeof(Status) * count, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_desc + first, zd.data(), sizeof(Desc) * count, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(b, e, "set_params upload");
   return SB_OK;
@@ -281,6 +299,9 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     int st = plan_excitation(e[i], tmp, err);
     if (st) return fail(b, st, "slot " + std::to_string(first + i) + ": " + err);
   }
+  // queued launches may still step these slots
+  hipError_t es = hipStreamSynchronize(b->stream);
+  if (es != hipSuccess) return hip_fail(b, es, "sync");
   std::vector<std::vector<char>> keep;   // host buffers alive until the stream sync below
   std::vector<Desc> descs(count);
   std::vector<Status> stats(count);
@@ -290,9 +311,11 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     std::string msg;
     plan_excitation(e[i], s.plan, msg);
     Desc &D = s.plan.desc;
-    size_t otf, oout, otab;
-    region_size(b, D, &otf, &oout, &otab);
+    size_t ost0, otf, oout, otab;
+    region_size(b, D, &ost0, &otf, &oout, &otab);
     D.st = s.dmem;
+    D.st0 = s.dmem + ost0;
+    D.st_elems = kWave * 4 * (D.mt + D.ml);
     D.tabf = s.dmem + otf;
     D.out = s.dmem + oout;
     D.tab = (const uint32_t *)(s.dmem + otab);
@@ -324,6 +347,7 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
       to_prec<double>(head, bh);
     }
     err = hipMemcpyAsync(s.dmem, bs.data(), bs.size(), hipMemcpyHostToDevice, b->stream);
+    if (err == hipSuccess) err = hipMemcpyAsync(s.dmem + ost0, bs.data(), bs.size(), hipMemcpyHostToDevice, b->stream);
     if (err == hipSuccess) err = hipMemcpyAsync(s.dmem + otf, bt.data(), bt.size(), hipMemcpyHostToDevice, b->stream);
     if (err == hipSuccess) err = hipMemcpyAsync(s.dmem + oout, bh.data(), bh.size(), hipMemcpyHostToDevice, b->stream);
     if (err == hipSuccess)
@@ -345,6 +369,8 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     err = hipMemcpyAsync(b->d_desc + first, descs.data(), sizeof(Desc) * count, hipMemcpyHostToDevice, b->stream);
   if (err == hipSuccess)
     err = hipMemcpyAsync(b->d_status + first, stats.data(), sizeof(Status) * count, hipMemcpyHostToDevice, b->stream);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(b->d_status0 + first, stats.data(), sizeof(Status) * count, hipMemcpyHostToDevice, b->stream);
   if (err == hipSuccess) err = hipStreamSynchronize(b->stream);
   if (err != hipSuccess) return hip_fail(b, err, "excite upload");
   b->work_dirty = true;
@@ -516,5 +542,19 @@ extern "C" int string_batch_set_solver(sb_batch *b, double tol, int max_sweeps) 
     return fail(b, SB_EINVAL, "bad solver settings");
   b->tol = tol;
   b->max_sweeps = max_sweeps;
+  return SB_OK;
+}
+
+extern "C" int string_batch_rewind(sb_batch *b, int first, int count) {
+  if (!b) return SB_EINVAL;
+  if (!range_ok(b, first, count)) return fail(b, SB_EINVAL, "bad slot range");
+  for (int i = first; i < first + count; ++i) {
+    Slot &s = b->slots[i];
+    if (!s.excited) continue;
+    s.samples_host = std::min<int64_t>(2, s.plan.desc.n_samples);
+    s.flagged = false;
+  }
+  hipError_t e = launch_rewind(b->precision, b->d_desc, b->d_status, b->d_status0, first, count, b->stream);
+  if (e != hipSuccess) return hip_fail(b, e, "rewind");
   return SB_OK;
 }

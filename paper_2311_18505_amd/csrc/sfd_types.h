@@ -59,7 +59,8 @@ struct Desc {
   int32_t on0, on1;           // nodes of I(x_out)
   double ow0, ow1;
   int32_t gmax;               // longest t-half range gathered by one l-half point
-  int32_t pad2;
+  int32_t st_elems;           // elements of the state block
+  void *st0;                  // copy of the state block right after excitation
 };
 
 // Per-string dynamic status (device memory, updated by the kernel).

@@ -829,6 +829,30 @@ __global__ __launch_bounds__(64) void step_kernel(LaunchArgs a) {
   }
 }
 
+// Restores slots first..first+count-1 to their state right after excitation:
+// one block per slot copies the saved state block and the saved status.
+template <typename T>
+__global__ void rewind_kernel(const Desc *desc, Status *status, const Status *status0, int first, int count) {
+  const int s = first + (int)blockIdx.x;
+  if ((int)blockIdx.x >= count) return;
+  const Desc &D = desc[s];
+  if (!D.st0) return;
+  T *dst = (T *)D.st;
+  const T *src = (const T *)D.st0;
+  for (int i = (int)threadIdx.x; i < D.st_elems; i += (int)blockDim.x) dst[i] = src[i];
+  if (threadIdx.x == 0) status[s] = status0[s];
+}
+
+hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
+                         hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (precision == 1)
+    hipLaunchKernelGGL(rewind_kernel<float>, dim3(count), dim3(256), 0, st, desc, status, status0, first, count);
+  else
+    hipLaunchKernelGGL(rewind_kernel<double>, dim3(count), dim3(256), 0, st, desc, status, status0, first, count);
+  return hipGetLastError();
+}
+
 __global__ void zero_counters(int32_t *c, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) c[i] = 0;
