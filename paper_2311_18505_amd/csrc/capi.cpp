@@ -111,14 +111,21 @@ struct sb_batch {
   int capacity = 0, precision = 0;
   size_t esz = 8;
   hipStream_t stream = nullptr;
+  // size classes run concurrently on streams of their own, forked from and
+  // joined back into `stream` through events (default priority)
+  hipStream_t cls_stream[kNumClasses] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kNumClasses] = {};
   std::string err;
   std::vector<Slot> slots;
   Arena arena;
   Desc *d_desc = nullptr;
   Status *d_status = nullptr;
   Status *d_status0 = nullptr;   // status right after excitation (for rewind)
-  int32_t *d_work = nullptr;
+  int32_t *d_work = nullptr;     // wavefront tasks: 64/G slot indices each (-1: empty group)
   int32_t *d_counters = nullptr;
+  void *d_trash = nullptr;        // write target of empty groups and unused slots
+  Status *d_trash_status = nullptr;
   std::vector<int32_t> h_work;
   bool work_dirty = true;
   int mon_period = 480;
@@ -138,6 +145,8 @@ static int hip_fail(sb_batch *b, hipError_t e, const char *where) {
   (void)hipGetLastError();
   return fail(b, SB_EDEVICE, m);
 }
+
+static size_t work_capacity(int capacity);
 
 extern "C" int string_batch_create(int capacity, int precision, void *hip_stream, sb_batch **out) {
   g_create_error.clear();
@@ -169,8 +178,10 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
   if ((e = hipMalloc(&b->d_desc, sizeof(Desc) * capacity)) != hipSuccess ||
       (e = hipMalloc(&b->d_status, sizeof(Status) * capacity)) != hipSuccess ||
       (e = hipMalloc(&b->d_status0, sizeof(Status) * capacity)) != hipSuccess ||
-      (e = hipMalloc(&b->d_work, sizeof(int32_t) * capacity)) != hipSuccess ||
-      (e = hipMalloc(&b->d_counters, sizeof(int32_t) * 16)) != hipSuccess) {
+      (e = hipMalloc(&b->d_work, sizeof(int32_t) * work_capacity(capacity))) != hipSuccess ||
+      (e = hipMalloc(&b->d_counters, sizeof(int32_t) * 16)) != hipSuccess ||
+      (e = hipMalloc(&b->d_trash, kMaxTrash)) != hipSuccess ||
+      (e = hipMalloc(&b->d_trash_status, sizeof(Status))) != hipSuccess) {
     g_create_error = std::string("hipMalloc: ") + hipGetErrorString(e);
     (void)hipGetLastError();
     hipFree(b->d_desc);
@@ -178,6 +189,8 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
     hipFree(b->d_status0);
     hipFree(b->d_work);
     hipFree(b->d_counters);
+    hipFree(b->d_trash);
+    hipFree(b->d_trash_status);
     delete b;
     return SB_ENOMEM;
   }
@@ -188,6 +201,17 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
     delete b;
     return SB_EDEVICE;
   }
+  for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
+    e = hipStreamCreateWithFlags(&b->cls_stream[c], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    g_create_error = std::string("stream/event creation: ") + hipGetErrorString(e);
+    (void)hipGetLastError();
+    string_batch_destroy(b);
+    return SB_EDEVICE;
+  }
   *out = b;
   return SB_OK;
 }
@@ -195,12 +219,22 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
 extern "C" int string_batch_destroy(sb_batch *b) {
   if (!b) return SB_EINVAL;
   (void)hipStreamSynchronize(b->stream);
+  for (int c = 0; c < kNumClasses; ++c) {
+    if (b->cls_stream[c]) {
+      (void)hipStreamSynchronize(b->cls_stream[c]);
+      (void)hipStreamDestroy(b->cls_stream[c]);
+    }
+    if (b->ev_join[c]) (void)hipEventDestroy(b->ev_join[c]);
+  }
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   b->arena.clear();
   hipFree(b->d_desc);
   hipFree(b->d_status);
   hipFree(b->d_status0);
   hipFree(b->d_work);
   hipFree(b->d_counters);
+  hipFree(b->d_trash);
+  hipFree(b->d_trash_status);
   delete b;
   return SB_OK;
 }
@@ -209,17 +243,23 @@ extern "C" const char *string_batch_last_error(const sb_batch *b) {
   return b ? b->err.c_str() : g_create_error.c_str();
 }
 
+// Entries of the task array: every class pads its last task with at most 64/G - 1 empty groups.
+static size_t work_capacity(int capacity) { return (size_t)capacity + (size_t)kNumClasses * kWave; }
+
 static bool range_ok(const sb_batch *b, int first, int count) {
   return first >= 0 && count >= 0 && (int64_t)first + count <= b->capacity;
 }
 
 // Device region of one slot: state | initial state | real tables | output | integer tables.
+// State and tables are lane-major over the G lanes of the string's class; the
+// output has 64 samples of padding that absorb the stores of idle lanes.
 static size_t region_size(const sb_batch *b, const Desc &D, size_t *off_st0, size_t *off_tabf, size_t *off_out,
                           size_t *off_tab) {
-  const size_t st = align256(b->esz * (size_t)kWave * 4 * (D.mt + D.ml));
-  const size_t tf = align256(b->esz * (size_t)kWave * (3 * D.mt + D.ml));
+  const size_t G = (size_t)kClassLanes[D.cls];
+  const size_t st = align256(b->esz * G * 4 * (D.mt + D.ml));
+  const size_t tf = align256(b->esz * G * (3 * D.mt + D.ml));
   const size_t ou = align256(b->esz * (size_t)(D.n_samples + kWave));
-  const size_t tb = align256(sizeof(uint32_t) * (size_t)kWave * (D.mt + 2 * D.ml));
+  const size_t tb = align256(sizeof(uint32_t) * G * (D.mt + 2 * D.ml));
   *off_st0 = st;
   *off_tabf = 2 * st;
   *off_out = 2 * st + tf;
@@ -315,7 +355,8 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     region_size(b, D, &ost0, &otf, &oout, &otab);
     D.st = s.dmem;
     D.st0 = s.dmem + ost0;
-    D.st_elems = kWave * 4 * (D.mt + D.ml);
+    const int G = kClassLanes[D.cls];
+    D.st_elems = G * 4 * (D.mt + D.ml);
     D.tabf = s.dmem + otf;
     D.out = s.dmem + oout;
     D.tab = (const uint32_t *)(s.dmem + otab);
@@ -323,11 +364,11 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     std::vector<double> u0;
     double uH0, uH1;
     initial_state(e[i], s.plan, u0, uH0, uH1);
-    std::vector<double> state((size_t)kWave * 4 * (D.mt + D.ml), 0.0);
-    for (int lane = 0; lane < kWave; ++lane)
+    std::vector<double> state((size_t)G * 4 * (D.mt + D.ml), 0.0);
+    for (int lane = 0; lane < G; ++lane)
       for (int r = 0; r < D.mt; ++r) {
         const int node = lane * D.mt + r + 1;
-        if (node <= D.nt) state[(size_t)r * kWave + lane] = u0[node];
+        if (node <= D.nt) state[(size_t)r * G + lane] = u0[node];
       }
     double y0 = 0.0;
     if (D.on0) y0 += D.ow0 * u0[D.on0];
@@ -395,6 +436,9 @@ static int do_step(sb_batch *b, int first, int count, int64_t n_steps) {
     cls[c].push_back({cost, i});
   }
   if (!any) return fail(b, SB_ESTATE, "no excited slot");
+  // Tasks of 64/G strings per class, strings of similar remaining work side by
+  // side (a wavefront runs as long as its longest string); tasks are queued
+  // longest first.
   std::vector<int32_t> work;
   std::vector<int> off(kNumClasses + 1, 0);
   for (int c = 0; c < kNumClasses; ++c) {
@@ -402,7 +446,9 @@ static int do_step(sb_batch *b, int first, int count, int64_t n_steps) {
       return x.first > y.first;
     });
     off[c] = (int)work.size();
-    for (auto &w : cls[c]) work.push_back(w.second);
+    const int groups = b->precision == SB_FP64_PLAIN ? 1 : kWave / kClassLanes[c];
+    for (size_t i = 0; i < cls[c].size(); i += groups)
+      for (int g = 0; g < groups; ++g) work.push_back(i + g < cls[c].size() ? cls[c][i + g].second : -1);
   }
   off[kNumClasses] = (int)work.size();
   if (work.empty()) return SB_OK;
@@ -410,6 +456,7 @@ static int do_step(sb_batch *b, int first, int count, int64_t n_steps) {
   if (b->precision == SB_FP64_PLAIN) {
     // one string per launch, in order
     for (int32_t i : work) {
+      if (i < 0) continue;
       e = launch_plain(b->d_desc, b->d_status, i, n_steps, b->mon_period, b->mon_tol, b->stream);
       if (e != hipSuccess) return hip_fail(b, e, "plain launch");
     }
@@ -426,8 +473,11 @@ static int do_step(sb_batch *b, int first, int count, int64_t n_steps) {
     }
     e = launch_zero(b->d_counters, kNumClasses, b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "counter reset");
-    for (int c = 0; c < kNumClasses; ++c) {
-      const int nw = off[c + 1] - off[c];
+    e = hipEventRecord(b->ev_fork, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "fork event");
+    // largest strings first: their classes hold the longest per-step latency
+    for (int c = kNumClasses - 1; c >= 0; --c) {
+      const int nw = (off[c + 1] - off[c]) / (kWave / kClassLanes[c]);   // tasks of this class
       if (nw == 0) continue;
       LaunchArgs a;
       a.desc = b->d_desc;
@@ -440,9 +490,15 @@ static int do_step(sb_batch *b, int first, int count, int64_t n_steps) {
       a.max_sweeps = b->max_sweeps;
       a.tol = b->tol;
       a.mon_tol = b->mon_tol;
+      a.trash_st = b->d_trash;
+      a.trash_status = b->d_trash_status;
       const int per_cu = std::max(1, max_blocks_per_cu(b->precision, c));
       const int blocks = std::min(nw, b->num_cu * per_cu);
-      e = launch_step(b->precision, c, a, blocks, b->stream);
+      hipStream_t cs = b->cls_stream[c];
+      e = hipStreamWaitEvent(cs, b->ev_fork, 0);
+      if (e == hipSuccess) e = launch_step(b->precision, c, a, blocks, cs);
+      if (e == hipSuccess) e = hipEventRecord(b->ev_join[c], cs);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_join[c], 0);
       if (e != hipSuccess) return hip_fail(b, e, "step launch");
     }
   }

@@ -132,12 +132,10 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
   D.Nl = Nl;
   D.nt = Nt - 1;
   D.nl = Nl > 0 ? Nl - 1 : 0;
-  D.mt = (Nt + kWave - 1) / kWave;     // slots per lane cover the half points 1..Nt
-  D.ml = Nl > 0 ? (Nl + kWave - 1) / kWave : 0;
-  const int need = std::max(D.mt, D.ml);
+  const int need = std::max(Nt, Nl);   // slots must cover the half points 1..N of both grids
   D.cls = -1;
   for (int c = 0; c < kNumClasses; ++c)
-    if (need <= kClassSlots[c]) {
+    if (need <= kClassLanes[c] * kClassSlots[c]) {
       D.cls = c;
       break;
     }
@@ -145,6 +143,9 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
     err = "string exceeds the largest size class";
     return SB_EBUDGET;
   }
+  const int G = kClassLanes[D.cls];
+  D.mt = (Nt + G - 1) / G;
+  D.ml = Nl > 0 ? (Nl + G - 1) / G : 0;
   D.mon_check = p.mod_type == 0 ? 1 : 0;
   D.n_samples = p.n_samples;
   const double k = g.k, th = g.theta;
@@ -194,19 +195,19 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
 
   // tables, lane-major [slot][lane]
   const int mt = D.mt, ml = D.ml;
-  P.tab.assign((size_t)kWave * (mt + 2 * ml), 0u);
-  P.tabf.assign((size_t)kWave * (3 * mt + ml), 0.0);
+  P.tab.assign((size_t)G * (mt + 2 * ml), 0u);
+  P.tabf.assign((size_t)G * (3 * mt + ml), 0.0);
   uint32_t *jab = P.tab.data();
-  uint32_t *rga = jab + (size_t)kWave * mt;
-  uint32_t *rgb = rga + (size_t)kWave * ml;
+  uint32_t *rga = jab + (size_t)G * mt;
+  uint32_t *rgb = rga + (size_t)G * ml;
   double *wi = P.tabf.data();
-  double *wbu = wi + (size_t)kWave * mt;
-  double *wbz = wbu + (size_t)kWave * mt;
-  double *sm = wbz + (size_t)kWave * ml;
+  double *wbu = wi + (size_t)G * mt;
+  double *wbz = wbu + (size_t)G * mt;
+  double *sm = wbz + (size_t)G * ml;
   P.ja.assign(Nt + 1, 1);
   P.jb.assign(Nt + 1, 1);
   P.w.assign(Nt + 1, 0.0);
-  for (int lane = 0; lane < kWave; ++lane)
+  for (int lane = 0; lane < G; ++lane)
     for (int r = 0; r < mt; ++r) {
       const int i = lane * mt + r + 1;   // half point i / node i
       uint32_t a = 1, b = 1;
@@ -223,9 +224,9 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
         P.jb[i] = (int)b;
         P.w[i] = w;
       }
-      jab[(size_t)r * kWave + lane] = a | (b << 16);
-      wi[(size_t)r * kWave + lane] = w;
-      if (i <= Nt - 1) wbu[(size_t)r * kWave + lane] = wbt[i];
+      jab[(size_t)r * G + lane] = a | (b << 16);
+      wi[(size_t)r * G + lane] = w;
+      if (i <= Nt - 1) wbu[(size_t)r * G + lane] = wbt[i];
     }
   if (Nl > 0) {
     // ranges of t-half points whose first (second) tap lands on l-half j
@@ -238,14 +239,14 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
     }
     D.gmax = 0;
     for (int j = 1; j <= Nl; ++j) D.gmax = std::max(D.gmax, std::max(na[j], nb[j]));
-    for (int lane = 0; lane < kWave; ++lane)
+    for (int lane = 0; lane < G; ++lane)
       for (int r = 0; r < ml; ++r) {
         const int j = lane * ml + r + 1;
         if (j <= Nl) {
-          rga[(size_t)r * kWave + lane] = (uint32_t)sa[j] | ((uint32_t)na[j] << 16);
-          rgb[(size_t)r * kWave + lane] = (uint32_t)sb[j] | ((uint32_t)nb[j] << 16);
+          rga[(size_t)r * G + lane] = (uint32_t)sa[j] | ((uint32_t)na[j] << 16);
+          rgb[(size_t)r * G + lane] = (uint32_t)sb[j] | ((uint32_t)nb[j] << 16);
         }
-        if (j <= Nl - 1) wbz[(size_t)r * kWave + lane] = wbl[j];
+        if (j <= Nl - 1) wbz[(size_t)r * G + lane] = wbl[j];
       }
   }
   (void)sm;
@@ -271,12 +272,13 @@ int plan_excitation(const sb_excitation &e, Plan &P, std::string &err) {
     return SB_EINVAL;
   }
   const int Nt = D.Nt, mt = D.mt, ml = D.ml, nt = D.nt;
+  const int G = kClassLanes[D.cls];
   D.ham_on = e.type == 2;
   D.hn0 = D.hn1 = 0;
   D.hw0 = D.hw1 = 0.0;
   D.omega_pow = D.alpha_H = D.Mr = D.IHs = 0.0;
-  double *sm = P.tabf.data() + (size_t)kWave * (2 * mt + ml);
-  std::fill(sm, sm + (size_t)kWave * mt, 0.0);
+  double *sm = P.tabf.data() + (size_t)G * (2 * mt + ml);
+  std::fill(sm, sm + (size_t)G * mt, 0.0);
   if (e.type == 2) {
     point_interp(e.x, Nt, D.hn0, D.hn1, D.hw0, D.hw1);
     D.omega_pow = e.K_H / e.M_H;       // omega_H^{1 + alpha_H}
@@ -300,10 +302,10 @@ int plan_excitation(const sb_excitation &e, Plan &P, std::string &err) {
     x[nt] = dp[nt];
     for (int i = nt - 1; i >= 1; --i) x[i] = dp[i] - cp[i] * x[i + 1];
     D.IHs = (D.hn0 ? D.hw0 * x[D.hn0] : 0.0) + (D.hn1 ? D.hw1 * x[D.hn1] : 0.0);
-    for (int lane = 0; lane < kWave; ++lane)
+    for (int lane = 0; lane < G; ++lane)
       for (int r = 0; r < mt; ++r) {
         const int i = lane * mt + r + 1;
-        if (i <= nt) sm[(size_t)r * kWave + lane] = x[i];
+        if (i <= nt) sm[(size_t)r * G + lane] = x[i];
       }
   }
   return SB_OK;

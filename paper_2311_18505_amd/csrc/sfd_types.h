@@ -6,14 +6,16 @@
 namespace sfd {
 
 constexpr int kWave = 64;          // lanes per wavefront on CDNA4
-constexpr int kMaxSlots = 16;      // grid points per lane per grid: N_t, N_l <= 1024
-constexpr int kMaxN = kWave * kMaxSlots;
+constexpr int kMaxSlots = 16;      // grid points per lane per grid
+constexpr int kMaxN = kWave * kMaxSlots;   // N_t, N_l <= 1024
 
-// Size classes of the stepping kernel: every lane owns up to MM consecutive
-// points of each grid.  A string runs in the smallest class whose MM covers
-// both ceil(N_t/64) and ceil(N_l/64).
-constexpr int kNumClasses = 4;
-constexpr int kClassSlots[kNumClasses] = {2, 4, 8, 16};
+// Size classes of the stepping kernel.  A string occupies a group of G lanes
+// (a wavefront holds 64/G strings) and every lane owns up to MM consecutive
+// points of each grid; a string runs in the smallest class with
+// G * MM >= max(N_t, N_l).
+constexpr int kNumClasses = 6;
+constexpr int kClassLanes[kNumClasses] = {16, 16, 32, 64, 64, 64};
+constexpr int kClassSlots[kNumClasses] = {2, 4, 4, 4, 8, 16};
 
 enum : int32_t {
   kFlagUnstable = 1,      // energy monitor: non-finite or growing energy
@@ -25,7 +27,7 @@ enum : int32_t {
 struct Desc {
   int32_t Nt, Nl;             // intervals of the transverse / longitudinal grids (Nl = 0: no zeta)
   int32_t nt, nl;             // unknowns: Nt-1, Nl-1 (0)
-  int32_t mt, ml;             // points per lane: ceil(Nt/64), ceil(Nl/64)
+  int32_t mt, ml;             // points per lane: ceil(Nt/G), ceil(Nl/G)
   int32_t cls;                // size class index
   int32_t mon_check;          // 1: energy must not grow (unforced, constant f0)
   int64_t n_samples;          // samples to produce
@@ -81,14 +83,18 @@ struct Status {
 struct LaunchArgs {
   const Desc *desc;
   Status *status;
-  const int32_t *work;        // string indices of this class, longest first
-  int32_t n_work;
+  const int32_t *work;        // 64/G string indices per wavefront task (-1: empty group)
+  int32_t n_work;             // number of wavefront tasks
   int32_t *counter;           // work-queue head (zeroed before the launch)
   int64_t n_steps;            // steps to advance each string (clamped at n_samples)
   int32_t mon_period;         // steps between energy checks (0: off)
   int32_t max_sweeps;         // cap of solver sweeps per step
   double tol;                 // relative convergence tolerance of the coupled solve
   double mon_tol;             // relative growth tolerance of the energy check
+  void *trash_st;             // write target of empty groups (kMaxTrash bytes)
+  Status *trash_status;
 };
+
+constexpr int kMaxTrash = 4 * 2 * kMaxSlots * kWave * 8;   // largest state block in FP64
 
 }  // namespace sfd

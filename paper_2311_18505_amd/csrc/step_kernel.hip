@@ -1,19 +1,24 @@
 // Batched stepping kernel of libstringfdtd for gfx950.
 //
-// One wavefront owns one string for a whole launch: every lane holds a
-// contiguous run of grid points of both grids in registers (lane l owns the
-// transverse points l*mt+1 .. l*mt+mt and the longitudinal points
-// l*ml+1 .. l*ml+ml), neighbours come from the adjacent lanes, and the two
-// grids exchange interpolated values through LDS.  The scheme is eq. (7) of
-// the paper written for the acceleration a = w^{n+1} - 2 w^n + w^{n-1}:
+// A wavefront steps 64/G strings at once: each string owns a group of G
+// lanes, and lane l of a group holds the transverse points l*mt+1 .. l*mt+mt
+// and the longitudinal points l*ml+1 .. l*ml+ml of its string in registers
+// for a whole launch.  Neighbours come from the adjacent lanes through DPP
+// moves, the two grids exchange interpolated values through LDS, and every
+// loop has a wave-uniform trip count with per-group differences expressed as
+// selects (writes that a group must not make go to a trash slot), so the
+// control flow of the persistent loop never diverges.
+//
+// The scheme is eq. (7) of the paper written for the acceleration
+// a = w^{n+1} - 2 w^n + w^{n-1}:
 //     (A^n + beta J I) a = -(A^n + B^n + C^n) w^n - (A^n - C^n) v + 2 beta J eta^n,
-// v = w^n - w^{n-1}, whose right-hand side is O(k^2 force) (the O(1) Theta
-// terms cancel), which is what makes FP32 stepping accurate.  The linear
-// system is solved by block Gauss-Seidel between the two grids around the
-// constant Toeplitz blocks T_u0 = Theta + sigma0 k - sigma1 k D_xx and
+// v = w^n - w^{n-1}; its right-hand side is O(k^2 force) (the O(1) Theta
+// terms cancel), which is what makes FP32 stepping accurate.  The system is
+// solved by block Gauss-Seidel between the two grids around the constant
+// Toeplitz blocks T_u0 = Theta + sigma0 k - sigma1 k D_xx and
 // T_z = (1 + sigma0 k) - sigma1 k D_xx, each inverted exactly through its
 // factorisation kT (1 + rho S-)(1 + rho S+) on the odd periodic extension of
-// the fixed-end grid (two first-order recurrences per lane plus lane scans);
+// the fixed-end grid (two first-order recurrences per lane plus group scans);
 // the hammer's rank-one term is removed exactly by Sherman-Morrison.
 #include <hip/hip_runtime.h>
 
@@ -23,183 +28,248 @@ namespace sfd {
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
-// Wave-uniform copies (scalar registers) of values every lane holds equally.
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
-__device__ __forceinline__ float uni(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
-}
+// ---------------------------------------------------------------------------
+// Wave-uniform values and cross-lane moves
+// ---------------------------------------------------------------------------
+
 __device__ __forceinline__ int64_t uni(int64_t x) {
   const uint64_t b = (uint64_t)x;
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
-__device__ __forceinline__ double uni(double x) {
-  return __builtin_bit_cast(double, uni(__builtin_bit_cast(int64_t, x)));
+
+// DPP move of a 32-bit value; lanes whose source lies outside the row / wave read 0.
+template <int CTRL>
+__device__ __forceinline__ int dpp32(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, true);
 }
-template <typename P>
-__device__ __forceinline__ P *uni(P *x) {
-  return (P *)(uintptr_t)uni((int64_t)(uintptr_t)x);
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __builtin_bit_cast(float, dpp32<CTRL>(__builtin_bit_cast(int, x)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)dpp32<CTRL>((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)dpp32<CTRL>((int)(uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-template <typename T>
-__device__ __forceinline__ T lane_prev(T v) {  // value of lane-1 (0 for lane 0)
-  T r = __shfl_up(v, 1, kWave);
-  return lane_id() == 0 ? T(0) : r;
+// value of lane l (a constant) for every lane
+__device__ __forceinline__ float lane_read(float x, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+}
+__device__ __forceinline__ double lane_read(double x, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-template <typename T>
-__device__ __forceinline__ T lane_next(T v) {  // value of lane+1 (0 for the last lane)
-  T r = __shfl_down(v, 1, kWave);
-  return lane_id() == kWave - 1 ? T(0) : r;
+constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108;
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138;
+
+// value of the previous / next lane of the same group (0 at the group edge)
+template <int G, typename T>
+__device__ __forceinline__ T grp_prev(T x) {
+  const T v = dpp<kWaveShr1>(x);
+  return (lane_id() & (G - 1)) == 0 ? T(0) : v;
+}
+template <int G, typename T>
+__device__ __forceinline__ T grp_next(T x) {
+  const T v = dpp<kWaveShl1>(x);
+  return (lane_id() & (G - 1)) == G - 1 ? T(0) : v;
 }
 
-// Deterministic wave sum: butterfly, then lane 0's value for everyone.
+// Sum (or max, of non-negative inputs) over the lanes of each group, returned
+// to every lane of the group, in a fixed association order.
+template <int G, bool MAX, typename T>
+__device__ __forceinline__ T grp_reduce(T x) {
+  auto op = [](T a, T b) { return MAX ? fmax(a, b) : a + b; };
+  x = op(x, dpp<kRowShr1>(x));
+  x = op(x, dpp<kRowShr2>(x));
+  x = op(x, dpp<kRowShr4>(x));
+  x = op(x, dpp<kRowShr8>(x));
+  // lane 15 of a row now holds the row total
+  const T r0 = lane_read(x, 15), r1 = lane_read(x, 31), r2 = lane_read(x, 47), r3 = lane_read(x, 63);
+  const int row = lane_id() >> 4;
+  if (G == 16) return row == 0 ? r0 : row == 1 ? r1 : row == 2 ? r2 : r3;
+  if (G == 32) return row < 2 ? op(r0, r1) : op(r2, r3);
+  return op(op(r0, r1), op(r2, r3));
+}
+
+// Powers of the lane-to-lane carry factor g used by the group scans.
 template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
+struct ScanPow {
+  T g1, g2, g4, g8, g16;
+  T gl;   // g^{(lane & 15) + 1}
+  T gr;   // g^{16 - (lane & 15)}
+};
+
+template <typename T>
+__device__ __forceinline__ T ipow(T g, int e) {   // 0 <= e <= 31
+  T r = T(1), b = g;
 #pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
-  return __shfl(v, 0, kWave);
+  for (int k = 0; k < 5; ++k) {
+    r = (e & (1 << k)) ? r * b : r;
+    b = b * b;
+  }
+  return r;
 }
 
 template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-  return __shfl(v, 0, kWave);
+__device__ __forceinline__ ScanPow<T> scan_pow(T g) {
+  ScanPow<T> p;
+  p.g1 = g;
+  p.g2 = g * g;
+  p.g4 = p.g2 * p.g2;
+  p.g8 = p.g4 * p.g4;
+  p.g16 = p.g8 * p.g8;
+  const int j = lane_id() & 15;
+  p.gl = ipow(g, j + 1);
+  p.gr = ipow(g, 16 - j);
+  return p;
 }
 
-// Inclusive scan of x_l = e_l + g x_{l-1} over the lanes (x_{-1} = 0).
-template <typename T>
-__device__ __forceinline__ T scan_fwd(T e, T g) {
-  T t = e, gp = g;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    T o = __shfl_up(t, d, kWave);
-    if (lane_id() >= d) t = fma(gp, o, t);
-    gp = gp * gp;
+// Inclusive scan x_l = e_l + g x_{l-1} over the lanes of each group (x_{-1} = 0):
+// Kogge-Stone inside rows of 16 lanes, then carries across rows.
+template <int G, typename T>
+__device__ __forceinline__ T grp_scan_fwd(T e, const ScanPow<T> &p) {
+  T t = e;
+  t = fma(p.g1, dpp<kRowShr1>(t), t);
+  t = fma(p.g2, dpp<kRowShr2>(t), t);
+  t = fma(p.g4, dpp<kRowShr4>(t), t);
+  t = fma(p.g8, dpp<kRowShr8>(t), t);
+  if (G >= 32) {
+    const T R0 = lane_read(t, 15), R1 = lane_read(t, 31), R2 = lane_read(t, 47);
+    const int row = lane_id() >> 4;
+    T C;
+    if (G == 32) {
+      C = row == 1 ? R0 : row == 3 ? R2 : T(0);
+    } else {
+      const T C1 = R0, C2 = fma(p.g16, C1, R1), C3 = fma(p.g16, C2, R2);
+      C = row == 1 ? C1 : row == 2 ? C2 : row == 3 ? C3 : T(0);
+    }
+    t = fma(p.gl, C, t);
   }
   return t;
 }
 
-// Inclusive scan of x_l = e_l + g x_{l+1} over the lanes (x_64 = 0).
-template <typename T>
-__device__ __forceinline__ T scan_bwd(T e, T g) {
-  T t = e, gp = g;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    T o = __shfl_down(t, d, kWave);
-    if (lane_id() + d < kWave) t = fma(gp, o, t);
-    gp = gp * gp;
+// Inclusive scan x_l = e_l + g x_{l+1} over the lanes of each group (x_G = 0).
+template <int G, typename T>
+__device__ __forceinline__ T grp_scan_bwd(T e, const ScanPow<T> &p) {
+  T t = e;
+  t = fma(p.g1, dpp<kRowShl1>(t), t);
+  t = fma(p.g2, dpp<kRowShl2>(t), t);
+  t = fma(p.g4, dpp<kRowShl4>(t), t);
+  t = fma(p.g8, dpp<kRowShl8>(t), t);
+  if (G >= 32) {
+    const T R1 = lane_read(t, 16), R2 = lane_read(t, 32), R3 = lane_read(t, 48);
+    const int row = lane_id() >> 4;
+    T C;
+    if (G == 32) {
+      C = row == 0 ? R1 : row == 2 ? R3 : T(0);
+    } else {
+      const T C3 = R3, C2 = fma(p.g16, C3, R2), C1 = fma(p.g16, C2, R1);
+      C = row == 0 ? C1 : row == 1 ? C2 : row == 2 ? C3 : T(0);
+    }
+    t = fma(p.gr, C, t);
   }
   return t;
 }
 
-// x[m-1] for a wave-uniform m >= 1 (no runtime register indexing).
+// p[idx] where ok, else 0; the load itself is unconditional (p[0] is valid).
+template <typename T, typename P>
+__device__ __forceinline__ T ld_if(const P *p, int idx, bool ok) {
+  const P v = p[ok ? idx : 0];
+  return ok ? (T)v : T(0);
+}
+
+// p[idx] = v where ok, else the value goes to trash[tidx]: every lane stores.
+template <typename T>
+__device__ __forceinline__ void st_if(T *p, int idx, bool ok, T *trash, int tidx, T v) {
+  T *q = ok ? p + idx : trash + tidx;
+  *q = v;
+}
+
+// x[m-1] for a per-lane m >= 1 (no runtime register indexing).
 template <typename T, int MM>
 __device__ __forceinline__ T last_of(const T (&x)[MM], int m) {
   T v = x[0];
 #pragma unroll
-  for (int j = 1; j < MM; ++j)
-    if (j < m) v = x[j];
+  for (int j = 1; j < MM; ++j) v = (j < m) ? x[j] : v;
   return v;
 }
 
-// Point evaluation w0 x(n0) + w1 x(n1) of a lane-blocked array (m slots per
-// lane, nodes 1-based, node 0 = absent), returned to every lane in FP64.
-template <typename T, int MM>
+// Point evaluation w0 x(n0) + w1 x(n1) (FP64) of a lane-blocked array of the
+// calling lane's group (m slots per lane, nodes 1-based, 0 = absent).
+template <int G, typename T, int MM>
 __device__ __forceinline__ double point_eval(const T (&x)[MM], const T (&c)[MM], int m, int n0, double w0, int n1,
                                              double w1) {
-  const int base = lane_id() * m;
+  const int li = lane_id() & (G - 1), base = lane_id() & ~(G - 1);
   double part = 0.0;
 #pragma unroll
   for (int r = 0; r < MM; ++r) {
-    if (r >= m) continue;
-    const int i = base + r + 1;
+    const int i = li * m + r + 1;
     const double v = (double)x[r] - (double)c[r];
-    if (i == n0) part += w0 * v;
-    if (i == n1) part += w1 * v;
+    part += (r < m && i == n0) ? w0 * v : 0.0;
+    part += (r < m && i == n1) ? w1 * v : 0.0;
   }
   const int l0 = n0 ? (n0 - 1) / m : 0, l1 = n1 ? (n1 - 1) / m : 0;
-  double y = __shfl(part, l0, kWave);
-  if (n1 && l1 != l0) y += __shfl(part, l1, kWave);
-  return y;
+  const double y0 = __shfl(part, base + l0, kWave);
+  const double y1 = __shfl(part, base + l1, kWave);
+  return (n1 && l1 != l0) ? y0 + y1 : y0;
 }
 
-template <typename T, int MM>
-struct Toep {
-  T rho, itk, g;      // factor, 1/kT, (-rho)^m
-  T pr[MM];           // (-rho)^{r+1}
-  T qr[MM];           // (-rho)^{m-r}
-};
+// ---------------------------------------------------------------------------
+// Exact Toeplitz solve (per group)
+// ---------------------------------------------------------------------------
 
-template <typename T, int MM>
-__device__ __forceinline__ void toep_init(Toep<T, MM> &tp, double rho, double itk, int m) {
-  tp.rho = (T)rho;
-  tp.itk = (T)itk;
-  T pw = T(1);
-#pragma unroll
-  for (int r = 0; r < MM; ++r) {
-    pw = pw * (-tp.rho);
-    tp.pr[r] = pw;
-  }
-  pw = T(1);
-#pragma unroll
-  for (int r = MM - 1; r >= 0; --r) {
-    if (r < m) pw = pw * (-tp.rho);
-    tp.qr[r] = pw;
-  }
-  tp.g = pw;   // (-rho)^m
-}
-
-// Exact solve of the fixed-end symmetric Toeplitz tridiagonal system
-// kT (1 + rho S-)(1 + rho S+) x = b on nodes 1..n (n = N-1), m slots per lane.
-//   forward:  z_i = b_i / kT - rho z_{i-1},  z_0 = sum_m wb_m b_m  (odd extension)
+// kT (1 + rho S-)(1 + rho S+) x = b on nodes 1..n of each group's string
+// (m slots per lane; this lane's first `valid` slots hold nodes <= n):
+//   forward:  z_i = b_i / kT - rho z_{i-1},  z_0 = sum_i wb_i b_i  (odd extension)
 //   backward: x_i = z_i - rho x_{i+1},       x_N = 0
-// valid: number of this lane's slots holding nodes <= n.
-template <typename T, int MM>
+template <int G, typename T, int MM>
 __device__ __forceinline__ void toeplitz_solve(T (&x)[MM], const T (&b)[MM], const T (&wb)[MM], int m, int valid,
-                                               const Toep<T, MM> &tp) {
+                                               T rho, T itk, const ScanPow<T> &sp) {
   T part = T(0);
 #pragma unroll
-  for (int r = 0; r < MM; ++r)
-    if (r < m) part = fma(wb[r], b[r], part);
-  const T z0 = wave_sum(part);
+  for (int r = 0; r < MM; ++r) part = (r < m) ? fma(wb[r], b[r], part) : part;
+  const T z0 = grp_reduce<G, false>(part);
   T z[MM];
   T prev = T(0);
 #pragma unroll
-  for (int r = 0; r < MM; ++r)
-    if (r < m) {
-      z[r] = fma(-tp.rho, prev, b[r] * tp.itk);
-      prev = z[r];
-    }
-  T e = prev;
-  if (lane_id() == 0) e = fma(tp.g, z0, e);
-  const T Z = scan_fwd(e, tp.g);
-  T C = lane_prev(Z);
-  if (lane_id() == 0) C = z0;
+  for (int r = 0; r < MM; ++r) {
+    z[r] = fma(-rho, prev, b[r] * itk);
+    prev = (r < m) ? z[r] : prev;
+  }
+  const bool first = (lane_id() & (G - 1)) == 0;
+  const T e = first ? fma(sp.g1, z0, prev) : prev;
+  const T Z = grp_scan_fwd<G>(e, sp);
+  const T Zp = grp_prev<G>(Z);   // every lane takes part in the move
+  const T C = first ? z0 : Zp;
+  T pw = -rho;
 #pragma unroll
-  for (int r = 0; r < MM; ++r)
-    if (r < m) {
-      z[r] = fma(tp.pr[r], C, z[r]);
-      if (r >= valid) z[r] = T(0);
-    }
+  for (int r = 0; r < MM; ++r) {
+    z[r] = (r < valid) ? fma(pw, C, z[r]) : T(0);
+    pw = pw * (-rho);
+  }
   prev = T(0);
 #pragma unroll
-  for (int r = MM - 1; r >= 0; --r)
-    if (r < m) {
-      x[r] = fma(-tp.rho, prev, z[r]);
-      prev = x[r];
-    }
-  const T X = scan_bwd(prev, tp.g);
-  const T Dn = lane_next(X);
+  for (int r = MM - 1; r >= 0; --r) {
+    x[r] = fma(-rho, prev, z[r]);
+    prev = (r < m) ? x[r] : prev;
+  }
+  const T X = grp_scan_bwd<G>(prev, sp);
+  const T Dn = grp_next<G>(X);
+  pw = T(1);
 #pragma unroll
-  for (int r = 0; r < MM; ++r)
-    if (r < m) {
-      x[r] = fma(tp.qr[r], Dn, x[r]);
-      if (r >= valid) x[r] = T(0);
-    }
+  for (int r = MM - 1; r >= 0; --r) {
+    pw = (r < m) ? pw * (-rho) : pw;
+    x[r] = (r < valid) ? fma(pw, Dn, x[r]) : T(0);
+  }
 }
 
 // x += (v - cv) with compensation: the stored pairs represent x - c and v - cv.
@@ -228,10 +298,9 @@ __device__ __forceinline__ void kahan_add(T &s, T &c, T y) {
   }
 }
 
-// (gamma^n k)^2 with gamma^n = 2 f0(nk), f0 modulated by vibrato or glide.
-// Out of line: evaluated once per 64 steps (one step per lane), its FP64
-// transcendental code stays out of the stepping loop's registers.
-__device__ __attribute__((noinline)) double gamma2k2_at(const Desc &D, int64_t n) {
+// (gamma^n k)^2 with gamma^n = 2 f0(nk), f0 modulated by vibrato or glide
+// (evaluated once per G steps, one step per lane).
+__device__ __forceinline__ double gamma2k2_at(const Desc &D, int64_t n) {
   const double t = (double)n / D.fs;
   double f = D.f0;
   if (D.mod_type == 1)
@@ -243,137 +312,14 @@ __device__ __attribute__((noinline)) double gamma2k2_at(const Desc &D, int64_t n
 }
 
 // Contact coefficient c = omega^{1+alpha_H} (eta^+)^{alpha_H - 1} / 2 of eq. (6)
-// (power factor at time n); out of line, used only while the hammer touches.
-__device__ __attribute__((noinline)) double contact_coef(double eta, double omega_pow, double alpha_H) {
-  return eta > 0.0 ? 0.5 * omega_pow * pow(eta, alpha_H - 1.0) : 0.0;
+// (power factor at time n), used only while a hammer touches.
+__device__ __forceinline__ double contact_coef(double eta, double omega_pow, double alpha_H) {
+  return eta > 0.0 ? 0.5 * omega_pow * pow(eta > 0.0 ? eta : 1.0, alpha_H - 1.0) : 0.0;
 }
 
 template <typename T>
 __device__ __forceinline__ double to_d(T hi, T c) {
   return (double)hi - (double)c;
-}
-
-// Discrete energy H^{n+1/2} (FP64) from w^{n+1} = (u - cu, z - cz) and
-// w^n = w^{n+1} - v, read from the string's state block in global memory:
-// kinetic and linear potential of both grids plus the nonlinear potential
-// (gamma^2 (alpha^2-1)/2)(p q^2/2 + q^4/8) in the time-paired form of the
-// scheme.  Not inlined: it runs once per monitor period and keeps its FP64
-// temporaries out of the stepping loop's registers.
-template <typename T, int MM>
-__device__ __attribute__((noinline)) double energy_fp64(const Desc &D, double g2k2, double *sD) {
-  const int lane = lane_id();
-  const int mt = D.mt, ml = D.ml, nt = D.nt, Nt = D.Nt, Nl = D.Nl, nl = D.nl;
-  const double k = D.k, th = D.theta;
-  const T *st = (const T *)D.st;
-  const T *tf = (const T *)D.tabf;
-  double U1[MM], U0[MM], DU[MM];
-#pragma unroll
-  for (int r = 0; r < MM; ++r) {
-    const bool ok = r < mt;
-    U1[r] = ok ? to_d(st[(0 * mt + r) * kWave + lane], st[(2 * mt + r) * kWave + lane]) : 0.0;
-    DU[r] = ok ? to_d(st[(1 * mt + r) * kWave + lane], st[(3 * mt + r) * kWave + lane]) : 0.0;
-    U0[r] = U1[r] - DU[r];
-  }
-  const double dul = lane_prev(last_of<double, MM>(DU, mt)), dur = lane_next(DU[0]);
-  const double u1l = lane_prev(last_of<double, MM>(U1, mt)), u0l = lane_prev(last_of<double, MM>(U0, mt));
-  double q1[MM], q0[MM];
-#pragma unroll
-  for (int r = 0; r < MM; ++r) {
-    const double a1 = r == 0 ? u1l : U1[r > 0 ? r - 1 : 0];
-    const double a0 = r == 0 ? u0l : U0[r > 0 ? r - 1 : 0];
-    q1[r] = (U1[r] - a1) * D.Ntd;
-    q0[r] = (U0[r] - a0) * D.Ntd;
-  }
-  const double q1r = lane_next(q1[0]), q0r = lane_next(q0[0]);
-  double kin = 0.0, pot = 0.0, stf = 0.0;
-  const int base = lane * mt;
-#pragma unroll
-  for (int r = 0; r < MM; ++r) {
-    if (r >= mt) continue;
-    const int i = base + r + 1;
-    const bool nx = r + 1 < mt && r + 1 < MM;
-    const double n1 = nx ? q1[r + 1 < MM ? r + 1 : r] : q1r;
-    const double n0 = nx ? q0[r + 1 < MM ? r + 1 : r] : q0r;
-    const double c1 = (n1 - q1[r]) * D.Ntd, c0 = (n0 - q0[r]) * D.Ntd;
-    const double dl = r == 0 ? dul : DU[r > 0 ? r - 1 : 0];
-    const double dr = nx ? DU[r + 1 < MM ? r + 1 : r] : dur;
-    if (i <= nt) {
-      kin += DU[r] * (th * DU[r] + 0.5 * (1.0 - th) * (dl + dr));
-      stf += c1 * c0;
-    }
-    if (i <= Nt) pot += q1[r] * q0[r];
-  }
-  const double gam2 = g2k2 / (k * k);
-  const double kap2 = D.cS / (k * k * D.Ntd * D.Ntd);
-  double H = (1.0 / D.Ntd) / (2.0 * k * k) * kin + gam2 / D.Ntd / 2.0 * pot + kap2 / D.Ntd / 2.0 * stf;
-  if (nl > 0) {
-    const int zo = 4 * mt * kWave;
-    double Z1[MM], Z0[MM], DZ[MM];
-#pragma unroll
-    for (int r = 0; r < MM; ++r) {
-      const bool ok = r < ml;
-      Z1[r] = ok ? to_d(st[zo + (0 * ml + r) * kWave + lane], st[zo + (2 * ml + r) * kWave + lane]) : 0.0;
-      DZ[r] = ok ? to_d(st[zo + (1 * ml + r) * kWave + lane], st[zo + (3 * ml + r) * kWave + lane]) : 0.0;
-      Z0[r] = Z1[r] - DZ[r];
-    }
-    const double z1l = lane_prev(last_of<double, MM>(Z1, ml)), z0l = lane_prev(last_of<double, MM>(Z0, ml));
-    double kz = 0.0, pz = 0.0;
-    const int lb = lane * ml;
-#pragma unroll
-    for (int r = 0; r < MM; ++r) {
-      if (r >= ml) continue;
-      const double a1 = r == 0 ? z1l : Z1[r > 0 ? r - 1 : 0];
-      const double a0 = r == 0 ? z0l : Z0[r > 0 ? r - 1 : 0];
-      const double p1 = (Z1[r] - a1) * D.Nld, p0 = (Z0[r] - a0) * D.Nld;
-      const int j = lb + r + 1;
-      if (j <= nl) kz += DZ[r] * DZ[r];
-      if (j <= Nl) pz += p1 * p0;
-      sD[2 * (lb + r)] = p1;
-      sD[2 * (lb + r) + 1] = p0;
-    }
-    __syncthreads();
-    // p^{n+1}, p^n interpolated to the transverse half points
-    double nlt = 0.0;
-#pragma unroll
-    for (int r = 0; r < MM; ++r) {
-      if (r >= mt) continue;
-      const int i = base + r + 1;
-      if (i > Nt) continue;
-      const uint32_t jab = D.tab[r * kWave + lane];
-      const int ja = (int)(jab & 0xffffu), jb = (int)(jab >> 16);
-      const double w = (double)tf[r * kWave + lane];
-      const double pt1 = (1.0 - w) * sD[2 * (ja - 1)] + w * sD[2 * (jb - 1)];
-      const double pt0 = (1.0 - w) * sD[2 * (ja - 1) + 1] + w * sD[2 * (jb - 1) + 1];
-      const double qq = q1[r] * q0[r];
-      nlt += qq * qq / 4.0 + qq * (pt1 + pt0) / 2.0;
-    }
-    __syncthreads();
-    const double a2 = D.a2;
-    H += (1.0 / D.Nld) / (2.0 * k * k) * kz + gam2 * a2 / D.Nld / 2.0 * pz + gam2 * (a2 - 1.0) / 2.0 / D.Ntd * nlt;
-  }
-  return wave_sum(H);
-}
-
-template <typename T, int MM>
-__device__ __forceinline__ void store_state(T *st, const T (&u)[MM], const T (&vu)[MM], const T (&cu)[MM],
-                                            const T (&cvu)[MM], const T (&z)[MM], const T (&vz)[MM],
-                                            const T (&cz)[MM], const T (&cvz)[MM], int mt, int ml, int lane) {
-  const int zo = 4 * mt * kWave;
-#pragma unroll
-  for (int r = 0; r < MM; ++r) {
-    if (r < mt) {
-      st[(0 * mt + r) * kWave + lane] = u[r];
-      st[(1 * mt + r) * kWave + lane] = vu[r];
-      st[(2 * mt + r) * kWave + lane] = cu[r];
-      st[(3 * mt + r) * kWave + lane] = cvu[r];
-    }
-    if (r < ml) {
-      st[zo + (0 * ml + r) * kWave + lane] = z[r];
-      st[zo + (1 * ml + r) * kWave + lane] = vz[r];
-      st[zo + (2 * ml + r) * kWave + lane] = cz[r];
-      st[zo + (3 * ml + r) * kWave + lane] = cvz[r];
-    }
-  }
 }
 
 // I_(t)->(l) gather for one longitudinal half point: the sums of the two
@@ -392,179 +338,309 @@ __device__ __forceinline__ T range_gather(const T *sA, const T *sB, uint32_t ra,
   return acc;
 }
 
-template <typename T, int MM, bool KAHAN>
-__device__ __forceinline__ void run_steps(const LaunchArgs &a, const Desc &D, Status *S, const int64_t done,
-                                          const int64_t nsteps, T *sP, T *sA, T *sB);
+// LDS scratch of the energy monitor per group: u^{n+1}, u^n, zeta^{n+1},
+// zeta^n (FP64) on nodes 0 .. MM*G, each followed by a trash entry.
+template <int G, int MM>
+struct EnergyLds {
+  static constexpr int kArr = MM * G + 2;
+  static constexpr int kTrash = MM * G + 1;
+  static constexpr int kStride = 4 * kArr;
+};
 
-template <typename T, int MM, bool KAHAN>
-__device__ void run_string(const LaunchArgs &a, int s, T *sP, T *sA, T *sB) {
-  const Desc &D = a.desc[s];
-  Status *S = a.status + s;
-  const int64_t n_samples = uni(D.n_samples);
-  const int64_t done = uni(S->samples_done);
-  const int64_t left = n_samples - done;
-  const int64_t nsteps = a.n_steps < left ? a.n_steps : left;
-  // one uniform guard, no early return (keeps the persistent loop structured)
-  if (uni(S->flags) == 0 && done >= 2 && nsteps > 0) run_steps<T, MM, KAHAN>(a, D, S, done, nsteps, sP, sA, sB);
+// Writes this lane's part of w^{n+1} = (u - cu, z - cz) and w^n = w^{n+1} - v
+// into the group's energy scratch; node 0 and the unused slots hold 0.
+template <int G, int MM, typename T>
+__device__ __forceinline__ void energy_fill(double *sD, const T (&u)[MM], const T (&vu)[MM], const T (&cu)[MM],
+                                            const T (&cvu)[MM], const T (&z)[MM], const T (&vz)[MM],
+                                            const T (&cz)[MM], const T (&cvz)[MM], int mt, int ml, int li) {
+  using E = EnergyLds<G, MM>;
+  double *U1 = sD, *U0 = sD + E::kArr, *Z1 = sD + 2 * E::kArr, *Z0 = sD + 3 * E::kArr;
+  const int zero_at = li == 0 ? 0 : E::kTrash;
+  U1[zero_at] = 0.0;
+  U0[zero_at] = 0.0;
+  Z1[zero_at] = 0.0;
+  Z0[zero_at] = 0.0;
+#pragma unroll
+  for (int r = 0; r < MM; ++r) {
+    const int it = r < mt ? li * mt + r + 1 : E::kTrash;
+    const double a1 = (double)u[r] - (double)cu[r];
+    U1[it] = a1;
+    U0[it] = a1 - ((double)vu[r] - (double)cvu[r]);
+    const int il = r < ml ? li * ml + r + 1 : E::kTrash;
+    const double b1 = (double)z[r] - (double)cz[r];
+    Z1[il] = b1;
+    Z0[il] = b1 - ((double)vz[r] - (double)cvz[r]);
+  }
 }
 
-template <typename T, int MM, bool KAHAN>
-__device__ __forceinline__ void run_steps(const LaunchArgs &a, const Desc &D, Status *S, const int64_t done,
-                                          const int64_t nsteps, T *sP, T *sA, T *sB) {
+// Discrete energy H^{n+1/2} (FP64) of the calling lane's group from the
+// scratch filled by energy_fill: kinetic and linear potential of both grids
+// plus the nonlinear potential (gamma^2 (alpha^2-1)/2)(p q^2/2 + q^4/8) in
+// the time-paired form of the scheme.  Streams over the lane's points
+// (runs once per monitor period).
+template <int G, int MM, typename T>
+__device__ __forceinline__ double energy_fp64(const Desc &D, double g2k2, const double *sD, int li) {
+  using E = EnergyLds<G, MM>;
+  const double *U1 = sD, *U0 = sD + E::kArr, *Z1 = sD + 2 * E::kArr, *Z0 = sD + 3 * E::kArr;
+  const int mt = D.mt, ml = D.ml, nt = D.nt, Nt = D.Nt, Nl = D.Nl, nl = D.nl;
+  const double k = D.k, th = D.theta, Ntd = D.Ntd, Nld = D.Nld;
+  const T *tf = (const T *)D.tabf;
+  double kin = 0.0, pot = 0.0, stf = 0.0, nlt = 0.0;
+#pragma unroll 1
+  for (int r = 0; r < MM; ++r) {
+    const int i = li * mt + r + 1;
+    const bool half = r < mt && i <= Nt, node = r < mt && i <= nt;
+    const int ic = half ? i : 1;                       // a valid node for the loads
+    const int im = ic - 1, ip = ic + 1 <= MM * G ? ic + 1 : ic;
+    const double du = U1[ic] - U0[ic], dm = U1[im] - U0[im], dp = U1[ip] - U0[ip];
+    const double q1 = (U1[ic] - U1[im]) * Ntd, q0 = (U0[ic] - U0[im]) * Ntd;
+    const double q1p = (U1[ip] - U1[ic]) * Ntd, q0p = (U0[ip] - U0[ic]) * Ntd;
+    const double c1 = (q1p - q1) * Ntd, c0 = (q0p - q0) * Ntd;
+    kin += node ? du * (th * du + 0.5 * (1.0 - th) * (dm + dp)) : 0.0;
+    stf += node ? c1 * c0 : 0.0;
+    pot += half ? q1 * q0 : 0.0;
+    const bool on = half && nl > 0;
+    const uint32_t jab = ld_if<uint32_t>(D.tab, r * G + li, on);
+    const int ja = on ? (int)(jab & 0xffffu) : 1, jb = on ? (int)(jab >> 16) : 1;
+    const double w = ld_if<double>(tf, r * G + li, on);
+    const double pa1 = (Z1[ja] - Z1[ja - 1]) * Nld, pa0 = (Z0[ja] - Z0[ja - 1]) * Nld;
+    const double pb1 = (Z1[jb] - Z1[jb - 1]) * Nld, pb0 = (Z0[jb] - Z0[jb - 1]) * Nld;
+    const double pt1 = (1.0 - w) * pa1 + w * pb1, pt0 = (1.0 - w) * pa0 + w * pb0;
+    const double qq = q1 * q0;
+    nlt += on ? qq * qq / 4.0 + qq * (pt1 + pt0) / 2.0 : 0.0;
+  }
+  double kz = 0.0, pz = 0.0;
+#pragma unroll 1
+  for (int r = 0; r < MM; ++r) {
+    const int j = li * ml + r + 1;
+    const bool half = r < ml && j <= Nl, node = r < ml && j <= nl;
+    const int jc = half ? j : 1;
+    const double dz = Z1[jc] - Z0[jc];
+    const double p1 = (Z1[jc] - Z1[jc - 1]) * Nld, p0 = (Z0[jc] - Z0[jc - 1]) * Nld;
+    kz += node ? dz * dz : 0.0;
+    pz += half ? p1 * p0 : 0.0;
+  }
+  const double gam2 = g2k2 / (k * k);
+  const double kap2 = D.cS / (k * k * Ntd * Ntd);
+  double H = (1.0 / Ntd) / (2.0 * k * k) * kin + gam2 / Ntd / 2.0 * pot + kap2 / Ntd / 2.0 * stf;
+  const double a2 = D.a2;
+  H += (nl > 0) ? (1.0 / Nld) / (2.0 * k * k) * kz + gam2 * a2 / Nld / 2.0 * pz + gam2 * (a2 - 1.0) / 2.0 / Ntd * nlt
+                : 0.0;
+  return grp_reduce<G, false>(H);
+}
+
+// Stores the register state into the string's state block (slots past mt / ml
+// store into the trash block instead, so every lane stores).
+template <int G, typename T, int MM>
+__device__ __forceinline__ void store_state(T *st, T *trash, const T (&u)[MM], const T (&vu)[MM], const T (&cu)[MM],
+                                            const T (&cvu)[MM], const T (&z)[MM], const T (&vz)[MM],
+                                            const T (&cz)[MM], const T (&cvz)[MM], int mt, int ml, int li) {
+  const int zo = 4 * mt * G;
+#pragma unroll
+  for (int r = 0; r < MM; ++r) {
+    const bool ot = r < mt, ol = r < ml;
+    const int tr = r * G + li;
+    st_if<T>(st, (0 * mt + r) * G + li, ot, trash, tr, u[r]);
+    st_if<T>(st, (1 * mt + r) * G + li, ot, trash, tr, vu[r]);
+    st_if<T>(st, (2 * mt + r) * G + li, ot, trash, tr, cu[r]);
+    st_if<T>(st, (3 * mt + r) * G + li, ot, trash, tr, cvu[r]);
+    st_if<T>(st, zo + (0 * ml + r) * G + li, ol, trash, tr, z[r]);
+    st_if<T>(st, zo + (1 * ml + r) * G + li, ol, trash, tr, vz[r]);
+    st_if<T>(st, zo + (2 * ml + r) * G + li, ol, trash, tr, cz[r]);
+    st_if<T>(st, zo + (3 * ml + r) * G + li, ol, trash, tr, cvz[r]);
+  }
+}
+
+// LDS layout per group: MM*G values plus a trash slot for writes a lane must not make.
+template <int G, int MM>
+struct Lds {
+  static constexpr int kStride = MM * G + 32;
+  static constexpr int kTrash = MM * G;
+};
+
+// ---------------------------------------------------------------------------
+// One wavefront task: up to 64/G strings stepped together
+// ---------------------------------------------------------------------------
+
+template <int G, int MM, typename T, bool KAHAN>
+__device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T *sA, T *sB, double *sE) {
   const int lane = lane_id();
-  const int Nt = uni(D.Nt), Nl = uni(D.Nl), nt = uni(D.nt), nl = uni(D.nl), mt = uni(D.mt), ml = uni(D.ml);
-  const bool has_l = nl > 0;
-  // uniform coefficients (scalar registers)
-  const int mod_type = uni(D.mod_type), ham_on = uni(D.ham_on), mon_check = uni(D.mon_check);
-  const int hn0 = uni(D.hn0), hn1 = uni(D.hn1), on0 = uni(D.on0), on1 = uni(D.on1);
-  const double hw0 = uni(D.hw0), hw1 = uni(D.hw1), ow0 = uni(D.ow0), ow1 = uni(D.ow1);
-  const double omega_pow = uni(D.omega_pow), alpha_H = uni(D.alpha_H), Mr = uni(D.Mr), IHs = uni(D.IHs);
-  const double g2k2_0 = uni(D.g2k2_0), a2m1_4 = uni(D.a2m1_4), a2d = uni(D.a2), Ntdd = uni(D.Ntd);
-  const int gmax = uni(D.gmax);
+  const int li = lane & (G - 1), gi = lane / G;
+  const int sidx = a.work[task * (kWave / G) + gi];
+  const bool present = sidx >= 0;
+  // an empty group mirrors the task's first string but never steps or writes it
+  const int s = present ? sidx : a.work[task * (kWave / G)];
+  const Desc &D = a.desc[s];
+  Status *S = a.status + s;
+
+  // ---- per-group constants (lane registers) ----
+  const int Nt = D.Nt, Nl = D.Nl, nt = D.nt, nl = D.nl, mt = D.mt, ml = D.ml;
+  const int64_t n_samples = D.n_samples;
+  const int64_t done = S->samples_done;
+  const int64_t left = n_samples - done;
+  int64_t nsteps = a.n_steps < left ? a.n_steps : left;
+  if (!present || S->flags != 0 || done < 2 || nsteps < 0) nsteps = 0;
+  // the wave runs as many steps as its longest group
+  int64_t wsteps = nsteps;
+#pragma unroll
+  for (int o = G; o < kWave; o <<= 1) {
+    const int64_t other = __shfl_xor(wsteps, o, kWave);
+    wsteps = other > wsteps ? other : wsteps;
+  }
+  wsteps = uni(wsteps);
+  int gmax = D.gmax;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int x = __shfl_xor(gmax, o, kWave);
+    gmax = x > gmax ? x : gmax;
+  }
+  gmax = __builtin_amdgcn_readfirstlane(gmax);
+
+  const bool any_mod = __ballot(D.mod_type != 0) != 0;
+  const int hn0 = D.hn0, hn1 = D.hn1, on0 = D.on0, on1 = D.on1;
+  const double hw0 = D.hw0, hw1 = D.hw1, ow0 = D.ow0, ow1 = D.ow1;
+  const double omega_pow = D.omega_pow, alpha_H = D.alpha_H, Mr = D.Mr, IHs = D.IHs;
+  const bool ham = D.ham_on != 0;
+  const bool any_ham = __ballot(ham) != 0;
+  const double g2k2_0 = D.g2k2_0, a2m1_4 = D.a2m1_4, a2d = D.a2, Ntdd = D.Ntd, kk = D.k * D.k;
+  const int mon_check = D.mon_check;
 
   // ---- state and tables into registers ----
   T u[MM], vu[MM], cu[MM], cvu[MM], z[MM], vz[MM], cz[MM], cvz[MM];
   uint32_t jab[MM], rga[MM], rgb[MM];
   T wi[MM], wbu[MM], wbz[MM];
-  T *st = (T *)uni(D.st);
-  const T *tf = (const T *)uni(D.tabf);
-  const uint32_t *tab = uni(D.tab);
-  const int zo = 4 * mt * kWave;
+  T *st = (T *)D.st;
+  const T *tf = (const T *)D.tabf;
+  const uint32_t *tab = D.tab;
+  const int zo = 4 * mt * G;
 #pragma unroll
   for (int r = 0; r < MM; ++r) {
     const bool ot = r < mt, ol = r < ml;
-    u[r] = ot ? st[(0 * mt + r) * kWave + lane] : T(0);
-    vu[r] = ot ? st[(1 * mt + r) * kWave + lane] : T(0);
-    cu[r] = ot ? st[(2 * mt + r) * kWave + lane] : T(0);
-    cvu[r] = ot ? st[(3 * mt + r) * kWave + lane] : T(0);
-    z[r] = ol ? st[zo + (0 * ml + r) * kWave + lane] : T(0);
-    vz[r] = ol ? st[zo + (1 * ml + r) * kWave + lane] : T(0);
-    cz[r] = ol ? st[zo + (2 * ml + r) * kWave + lane] : T(0);
-    cvz[r] = ol ? st[zo + (3 * ml + r) * kWave + lane] : T(0);
-    jab[r] = ot ? tab[r * kWave + lane] : 0x00010001u;
-    rga[r] = ol ? tab[(mt + r) * kWave + lane] : 0u;
-    rgb[r] = ol ? tab[(mt + ml + r) * kWave + lane] : 0u;
-    wi[r] = ot ? tf[r * kWave + lane] : T(0);
-    wbu[r] = ot ? tf[(mt + r) * kWave + lane] : T(0);
-    wbz[r] = ol ? tf[(2 * mt + r) * kWave + lane] : T(0);
+    // without compensation the c arrays stay zero (constants the compiler folds)
+    u[r] = ld_if<T>(st, (0 * mt + r) * G + li, ot);
+    vu[r] = ld_if<T>(st, (1 * mt + r) * G + li, ot);
+    cu[r] = KAHAN ? ld_if<T>(st, (2 * mt + r) * G + li, ot) : T(0);
+    cvu[r] = KAHAN ? ld_if<T>(st, (3 * mt + r) * G + li, ot) : T(0);
+    z[r] = ld_if<T>(st, zo + (0 * ml + r) * G + li, ol);
+    vz[r] = ld_if<T>(st, zo + (1 * ml + r) * G + li, ol);
+    cz[r] = KAHAN ? ld_if<T>(st, zo + (2 * ml + r) * G + li, ol) : T(0);
+    cvz[r] = KAHAN ? ld_if<T>(st, zo + (3 * ml + r) * G + li, ol) : T(0);
+    jab[r] = ot ? ld_if<uint32_t>(tab, r * G + li, ot) : 0x00010001u;
+    rga[r] = ld_if<uint32_t>(tab, (mt + r) * G + li, ol);
+    rgb[r] = ld_if<uint32_t>(tab, (mt + ml + r) * G + li, ol);
+    wi[r] = ld_if<T>(tf, r * G + li, ot);
+    wbu[r] = ld_if<T>(tf, (mt + r) * G + li, ot);
+    wbz[r] = ld_if<T>(tf, (2 * mt + r) * G + li, ol);
   }
-  const T *smv = tf + (2 * mt + ml) * kWave;   // Sherman-Morrison vector T_u0^{-1} J_H
+  const T *smv = tf + (2 * mt + ml) * G;   // Sherman-Morrison vector T_u0^{-1} J_H
 
-  const int tb = lane * mt, lb = lane * ml;
+  const int tb = li * mt, lb = li * ml;
   const int vt_node = max(0, min(mt, nt - tb));   // slots with nodes 1..nt
   const int vt_half = max(0, min(mt, Nt - tb));   // slots with half points 1..Nt
   const int vl_node = max(0, min(ml, nl - lb));
   const int vl_half = max(0, min(ml, Nl - lb));
+  const int mlw = ml > 0 ? ml : 1;                // slot count used for strings without zeta
 
-  Toep<T, MM> Tu, Tz;
-  toep_init<T, MM>(Tu, uni(D.rho_t), uni(D.itk_t), mt);
-  toep_init<T, MM>(Tz, uni(D.rho_l), uni(D.itk_l), ml);
-  const T Ntd = uni((T)D.Ntd), Nld = uni((T)D.Nld);
-  const T cS = uni((T)D.cS), s0t2 = uni((T)(2.0 * D.s0k_t)), s1t2 = uni((T)(2.0 * D.s1k_t));
-  const T s0l2 = uni((T)(2.0 * D.s0k_l)), s1l2 = uni((T)(2.0 * D.s1k_l));
-  const T ratio = uni((T)D.ratio_lt);
-  const double kk = uni(D.k * D.k);
+  const T rho_t = (T)D.rho_t, itk_t = (T)D.itk_t, rho_l = (T)D.rho_l, itk_l = (T)D.itk_l;
+  const ScanPow<T> spt = scan_pow<T>(ipow<T>(-rho_t, mt));
+  const ScanPow<T> spl = scan_pow<T>(ipow<T>(-rho_l, mlw));
+  const T Ntd = (T)D.Ntd, Nld = (T)D.Nld;
+  const T cS = (T)D.cS, s0t2 = (T)(2.0 * D.s0k_t), s1t2 = (T)(2.0 * D.s1k_t);
+  const T s0l2 = (T)(2.0 * D.s0k_l), s1l2 = (T)(2.0 * D.s1k_l);
+  const T ratio = (T)D.ratio_lt;
 
-  // hammer
+  // hammer and monitor state
   double uH_n = S->uH_n, uH_nm1 = S->uH_nm1, eta_nm1 = S->eta_nm1;
   int touched = S->touched;
-  const bool ham = ham_on != 0;
-  // monitor
   double H_ref = S->H_ref, H_last = S->H_latest;
   int64_t H_step = S->H_step;
   int flags = 0, max_sw = S->max_sweeps;
   int64_t tot_sw = S->total_sweeps;
+  int64_t steps_done = 0;
 
-  T *out = (T *)uni(D.out);
+  // output: a ring of G samples per group, anchored at the first sample of
+  // this launch; a lane with nothing to write stores into the padding after n_samples
+  T *out = (T *)D.out;
   const int64_t first_m = done;
   T ring = T(0);
   double g2blk = g2k2_0;
-  int64_t blk0 = -1000000;
+  T *trash = (T *)a.trash_st;
+  // (n + 1) mod mon_period of the current step
+  int mon_ctr = a.mon_period > 0 ? (int)(done % a.mon_period) : 1;
 
-  int64_t it = 0;
-  for (; it < nsteps; ++it) {
-    const int64_t n = done - 1 + it;  // time level of this step; produces sample n+1
-    // ---- gamma^n (f0 modulation), 64 steps per block, one per lane ----
+  using L = Lds<G, MM>;
+  T *gP = sP + gi * L::kStride, *gA = sA + gi * L::kStride, *gB = sB + gi * L::kStride;
+  double *gE = sE + gi * EnergyLds<G, MM>::kStride;
+
+  for (int64_t it = 0; it < wsteps; ++it) {
+    const bool act = it < nsteps;                  // this group still steps
+    const int64_t n = done - 1 + it;               // time level; the step produces sample n+1
+    // ---- gamma^n (f0 modulation): one block of G steps per lane ----
     double g2k2 = g2k2_0;
-    if (mod_type != 0) {
-      if (n - blk0 >= kWave) {
-        blk0 = n;
-        g2blk = gamma2k2_at(D, n + lane);
-      }
-      g2k2 = __shfl(g2blk, (int)(n - blk0), kWave);
+    if (any_mod) {
+      if ((it & (G - 1)) == 0) g2blk = gamma2k2_at(D, n + li);
+      g2k2 = __shfl(g2blk, (lane & ~(G - 1)) + (int)(it & (G - 1)), kWave);
     }
-    const T G = (T)g2k2;
-    const T phi2 = uni((T)(g2k2 * a2m1_4));
-    const T aG = uni((T)(g2k2 * a2d));
+    const T G2 = (T)g2k2;
+    const T phi2 = (T)(g2k2 * a2m1_4);
+    const T aG = (T)(g2k2 * a2d);
 
     // ---- slopes q (t half points) and p (l half points) ----
     T q[MM], p[MM];
     {
-      const T ul = lane_prev(last_of<T, MM>(u, mt)), cl = lane_prev(last_of<T, MM>(cu, mt));
+      const T ul = grp_prev<G>(last_of<T, MM>(u, mt)), cl = grp_prev<G>(last_of<T, MM>(cu, mt));
+      const T zl = grp_prev<G>(last_of<T, MM>(z, mlw)), czl = grp_prev<G>(last_of<T, MM>(cz, mlw));
 #pragma unroll
       for (int r = 0; r < MM; ++r) {
         const T um = r == 0 ? ul : u[r > 0 ? r - 1 : 0];
         const T cm = r == 0 ? cl : cu[r > 0 ? r - 1 : 0];
         q[r] = (r < vt_half) ? ((u[r] - um) - (cu[r] - cm)) * Ntd : T(0);
-      }
-    }
-    if (has_l) {
-      const T zl = lane_prev(last_of<T, MM>(z, ml)), cl = lane_prev(last_of<T, MM>(cz, ml));
-#pragma unroll
-      for (int r = 0; r < MM; ++r) {
         const T zm = r == 0 ? zl : z[r > 0 ? r - 1 : 0];
-        const T cm = r == 0 ? cl : cz[r > 0 ? r - 1 : 0];
-        p[r] = (r < vl_half) ? ((z[r] - zm) - (cz[r] - cm)) * Nld : T(0);
+        const T czm = r == 0 ? czl : cz[r > 0 ? r - 1 : 0];
+        p[r] = (r < vl_half) ? ((z[r] - zm) - (cz[r] - czm)) * Nld : T(0);
       }
     }
 
-    // ---- right-hand side, transverse ----
-    T ru[MM], rz[MM];
+    // ---- p~ = I_(l)->(t) p, and the transposed contributions of q^2 ----
     T f[MM];
 #pragma unroll
-    for (int r = 0; r < MM; ++r) f[r] = T(0);
-    if (has_l) {
-      // p~ = I_(l)->(t) p and the transposed contributions of q^2
+    for (int r = 0; r < MM; ++r) gP[r < ml ? lb + r : L::kTrash] = p[r];
+    __syncthreads();
 #pragma unroll
-      for (int r = 0; r < MM; ++r)
-        if (r < ml) sP[lb + r] = p[r];
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < MM; ++r) {
-        if (r >= mt) continue;
-        const int ja = (int)(jab[r] & 0xffffu), jb = (int)(jab[r] >> 16);
-        const T w = wi[r];
-        const T pt = (T(1) - w) * sP[ja - 1] + w * sP[jb - 1];
-        const T q2 = q[r] * q[r];
-        f[r] = q[r] * (q2 + T(2) * pt);
-        sA[tb + r] = (T(1) - w) * q2;
-        sB[tb + r] = w * q2;
-      }
-      __syncthreads();
-    } else {
-#pragma unroll
-      for (int r = 0; r < MM; ++r) f[r] = T(0);
+    for (int r = 0; r < MM; ++r) {
+      const int ja = (int)(jab[r] & 0xffffu), jb = (int)(jab[r] >> 16);
+      const T w = wi[r];
+      const T pt = (nl > 0) ? (T(1) - w) * gP[ja - 1] + w * gP[jb - 1] : T(0);
+      const T q2 = q[r] * q[r];
+      f[r] = q[r] * (q2 + T(2) * pt);
+      const int at = r < mt ? tb + r : L::kTrash;
+      gA[at] = (T(1) - w) * q2;
+      gB[at] = w * q2;
     }
+    __syncthreads();
+
+    // ---- right-hand side, transverse ----
+    T ru[MM], rz[MM];
     {
       T c[MM];
-      const T qr = lane_next(q[0]);
+      const T qr = grp_next<G>(q[0]);
 #pragma unroll
       for (int r = 0; r < MM; ++r) {
-        const T qn = (r + 1 < mt && r + 1 < MM) ? q[r + 1 < MM ? r + 1 : r] : qr;
+        const T qn = (r + 1 < MM && r + 1 < mt) ? q[r + 1 < MM ? r + 1 : r] : qr;
         c[r] = (r < vt_node) ? (qn - q[r]) * Ntd : T(0);
       }
-      const T cl = lane_prev(last_of<T, MM>(c, mt)), cr = lane_next(c[0]);
-      const T fr = lane_next(f[0]);
-      const T vl = lane_prev(last_of<T, MM>(vu, mt)), vr = lane_next(vu[0]);
+      const T cl = grp_prev<G>(last_of<T, MM>(c, mt)), cr = grp_next<G>(c[0]);
+      const T fr = grp_next<G>(f[0]);
+      const T vl = grp_prev<G>(last_of<T, MM>(vu, mt)), vr = grp_next<G>(vu[0]);
 #pragma unroll
       for (int r = 0; r < MM; ++r) {
-        if (r >= mt) continue;
+        const bool nx = r + 1 < MM && r + 1 < mt;
         const T cm = r == 0 ? cl : c[r > 0 ? r - 1 : 0];
-        const T cp = (r + 1 < mt && r + 1 < MM) ? c[r + 1 < MM ? r + 1 : r] : cr;
-        const T fp = (r + 1 < mt && r + 1 < MM) ? f[r + 1 < MM ? r + 1 : r] : fr;
+        const T cp = nx ? c[r + 1 < MM ? r + 1 : r] : cr;
+        const T fp = nx ? f[r + 1 < MM ? r + 1 : r] : fr;
         const T vm = r == 0 ? vl : vu[r > 0 ? r - 1 : 0];
-        const T vp = (r + 1 < mt && r + 1 < MM) ? vu[r + 1 < MM ? r + 1 : r] : vr;
-        T acc = G * c[r] - cS * ((cp - T(2) * c[r]) + cm);
+        const T vp = nx ? vu[r + 1 < MM ? r + 1 : r] : vr;
+        T acc = G2 * c[r] - cS * ((cp - T(2) * c[r]) + cm);
         acc = fma(T(2) * phi2 * Ntd, fp - f[r], acc);
         acc = fma(-s0t2, vu[r], acc);
         acc = fma(s1t2, (vp - T(2) * vu[r]) + vm, acc);
@@ -572,21 +648,19 @@ __device__ __forceinline__ void run_steps(const LaunchArgs &a, const Desc &D, St
       }
     }
     // ---- right-hand side, longitudinal ----
-    if (has_l) {
+    {
       T g[MM];
 #pragma unroll
-      for (int r = 0; r < MM; ++r) {
-        g[r] = r < ml ? range_gather<T>(sA, sB, rga[r], rgb[r], gmax) * ratio : T(0);
-      }
-      const T pr = lane_next(p[0]), gr = lane_next(g[0]);
-      const T vl = lane_prev(last_of<T, MM>(vz, ml)), vr = lane_next(vz[0]);
+      for (int r = 0; r < MM; ++r) g[r] = range_gather<T>(gA, gB, rga[r], rgb[r], gmax) * ratio;   // 0 past ml
+      const T pr = grp_next<G>(p[0]), gr = grp_next<G>(g[0]);
+      const T vl = grp_prev<G>(last_of<T, MM>(vz, mlw)), vr = grp_next<G>(vz[0]);
 #pragma unroll
       for (int r = 0; r < MM; ++r) {
-        if (r >= ml) continue;
-        const T pn = (r + 1 < ml && r + 1 < MM) ? p[r + 1 < MM ? r + 1 : r] : pr;
-        const T gn = (r + 1 < ml && r + 1 < MM) ? g[r + 1 < MM ? r + 1 : r] : gr;
+        const bool nx = r + 1 < MM && r + 1 < ml;
+        const T pn = nx ? p[r + 1 < MM ? r + 1 : r] : pr;
+        const T gn = nx ? g[r + 1 < MM ? r + 1 : r] : gr;
         const T vm = r == 0 ? vl : vz[r > 0 ? r - 1 : 0];
-        const T vp = (r + 1 < ml && r + 1 < MM) ? vz[r + 1 < MM ? r + 1 : r] : vr;
+        const T vp = nx ? vz[r + 1 < MM ? r + 1 : r] : vr;
         T acc = aG * ((pn - p[r]) * Nld);
         acc = fma(T(2) * phi2 * Nld, gn - g[r], acc);
         acc = fma(-s0l2, vz[r], acc);
@@ -597,236 +671,237 @@ __device__ __forceinline__ void run_steps(const LaunchArgs &a, const Desc &D, St
 
     // ---- hammer: contact coefficient at time n, right-hand side 2 beta J eta^n ----
     double eta_n = 0.0, cH = 0.0, beta = 0.0;
-    if (ham) {
-      const double Iu = point_eval<T, MM>(u, cu, mt, hn0, hw0, hn1, hw1);
-      eta_n = uni(uH_n - Iu);
-      if (eta_n > 0.0) {
-        cH = uni(contact_coef(eta_n, omega_pow, alpha_H));
-        touched = 1;
+    if (any_ham) {
+      const double Iu = point_eval<G, T, MM>(u, cu, mt, hn0, hw0, hn1, hw1);
+      eta_n = ham ? uH_n - Iu : 0.0;
+      const bool contact = eta_n > 0.0;
+      if (__ballot(contact) != 0) {
+        const double cc = contact_coef(eta_n, omega_pow, alpha_H);
+        cH = contact ? cc : 0.0;
       }
-      beta = uni(kk * Mr * cH / (1.0 + kk * cH));
-      if (beta != 0.0) {
-        const T add0 = (T)(2.0 * beta * hw0 * Ntdd * eta_n), add1 = (T)(2.0 * beta * hw1 * Ntdd * eta_n);
+      touched = (act && contact) ? 1 : touched;
+      beta = kk * Mr * cH / (1.0 + kk * cH);
+      const T add0 = (T)(2.0 * beta * hw0 * Ntdd * eta_n), add1 = (T)(2.0 * beta * hw1 * Ntdd * eta_n);
 #pragma unroll
-        for (int r = 0; r < MM; ++r) {
-          const int i = tb + r + 1;
-          if (r < mt && i == hn0) ru[r] += add0;
-          if (r < mt && i == hn1) ru[r] += add1;
-        }
+      for (int r = 0; r < MM; ++r) {
+        const int i = tb + r + 1;
+        ru[r] += (r < mt && i == hn0) ? add0 : T(0);
+        ru[r] += (r < mt && i == hn1) ? add1 : T(0);
       }
     }
+    const bool sm_on = beta != 0.0;
+    const bool any_sm = __ballot(sm_on) != 0;
 
     // ---- coupled solve: block Gauss-Seidel around T_u0 (+ hammer) and T_z ----
-    T au[MM], az[MM];
+    T au[MM], az[MM], smr[MM], zero[MM];
 #pragma unroll
     for (int r = 0; r < MM; ++r) {
       au[r] = T(0);
       az[r] = T(0);
+      zero[r] = T(0);
+      smr[r] = T(0);
     }
-    T smr[MM];
-    const bool sm_on = beta != 0.0;
-    if (sm_on) {
+    if (any_sm) {
 #pragma unroll
-      for (int r = 0; r < MM; ++r) smr[r] = r < mt ? smv[r * kWave + lane] : T(0);
+      for (int r = 0; r < MM; ++r) smr[r] = ld_if<T>(smv, r * G + li, r < mt && sm_on);
     }
     const T smfac = (T)(beta / (1.0 + beta * IHs));
-    T zero[MM];
-#pragma unroll
-    for (int r = 0; r < MM; ++r) zero[r] = T(0);
-    int sweep = 0;
-    bool conv = !has_l;
-    for (; sweep < a.max_sweeps; ++sweep) {
-      // transverse right-hand side with the current coupling terms
+    bool conv = false;       // this group's iterates are final
+    int sweeps = 0;
+    for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
+      // transverse right-hand side with the current coupling terms:
+      // e = q (q D_x- a_u + I_(l)->(t) D_x- a_z), b_u = r_u + phi^2 D_x+ e
       T bu[MM];
-      if (sweep == 0 || !has_l) {
+      if (sweep == 0) {
 #pragma unroll
         for (int r = 0; r < MM; ++r) bu[r] = ru[r];
       } else {
-        // d = D_x- a_u (t half), dz = D_x- a_z (l half), e = q (q d + I dz)
-        const T al = lane_prev(last_of<T, MM>(au, mt));
-        const T zl = lane_prev(last_of<T, MM>(az, ml));
+        const T al = grp_prev<G>(last_of<T, MM>(au, mt));
+        const T zl = grp_prev<G>(last_of<T, MM>(az, mlw));
 #pragma unroll
-        for (int r = 0; r < MM; ++r)
-          if (r < ml) {
-            const T zm = r == 0 ? zl : az[r > 0 ? r - 1 : 0];
-            sP[lb + r] = (r < vl_half) ? (az[r] - zm) * Nld : T(0);
-          }
+        for (int r = 0; r < MM; ++r) {
+          const T zm = r == 0 ? zl : az[r > 0 ? r - 1 : 0];
+          gP[r < ml ? lb + r : L::kTrash] = (r < vl_half) ? (az[r] - zm) * Nld : T(0);
+        }
         __syncthreads();
         T e[MM];
 #pragma unroll
         for (int r = 0; r < MM; ++r) {
-          e[r] = T(0);
-          if (r >= mt) continue;
           const T am = r == 0 ? al : au[r > 0 ? r - 1 : 0];
           const T d = (au[r] - am) * Ntd;
           const int ja = (int)(jab[r] & 0xffffu), jb = (int)(jab[r] >> 16);
           const T w = wi[r];
-          const T idz = (T(1) - w) * sP[ja - 1] + w * sP[jb - 1];
+          const T idz = (nl > 0) ? (T(1) - w) * gP[ja - 1] + w * gP[jb - 1] : T(0);
           e[r] = (r < vt_half) ? q[r] * fma(q[r], d, idz) : T(0);
         }
         __syncthreads();
-        const T er = lane_next(e[0]);
+        const T er = grp_next<G>(e[0]);
 #pragma unroll
         for (int r = 0; r < MM; ++r) {
-          const T en = (r + 1 < mt && r + 1 < MM) ? e[r + 1 < MM ? r + 1 : r] : er;
+          const T en = (r + 1 < MM && r + 1 < mt) ? e[r + 1 < MM ? r + 1 : r] : er;
           bu[r] = (r < vt_node) ? fma(phi2 * Ntd, en - e[r], ru[r]) : T(0);
         }
       }
       T nu[MM];
-      toeplitz_solve<T, MM>(nu, bu, wbu, mt, vt_node, Tu);
-      if (sm_on) {
+      toeplitz_solve<G, T, MM>(nu, bu, wbu, mt, vt_node, rho_t, itk_t, spt);
+      if (any_sm) {
         // Sherman-Morrison for the rank-one hammer term beta J I
-        const T Iy = (T)point_eval<T, MM>(nu, zero, mt, hn0, hw0, hn1, hw1);
+        const T Iy = (T)point_eval<G, T, MM>(nu, zero, mt, hn0, hw0, hn1, hw1);
         const T fac = smfac * Iy;
 #pragma unroll
-        for (int r = 0; r < MM; ++r)
-          if (r < mt) nu[r] = fma(-fac, smr[r], nu[r]);
+        for (int r = 0; r < MM; ++r) nu[r] = (r < mt) ? fma(-fac, smr[r], nu[r]) : nu[r];
       }
+      // longitudinal right-hand side: r_z + phi^2 D_x+ I_(t)->(l) (q D_x- a_u)
+      {
+        const T al = grp_prev<G>(last_of<T, MM>(nu, mt));
+#pragma unroll
+        for (int r = 0; r < MM; ++r) {
+          const T am = r == 0 ? al : nu[r > 0 ? r - 1 : 0];
+          const T fq = (r < vt_half) ? q[r] * ((nu[r] - am) * Ntd) : T(0);
+          const T w = wi[r];
+          const int at = r < mt ? tb + r : L::kTrash;
+          gA[at] = (T(1) - w) * fq;
+          gB[at] = w * fq;
+        }
+      }
+      __syncthreads();
+      T gg[MM];
+#pragma unroll
+      for (int r = 0; r < MM; ++r) gg[r] = range_gather<T>(gA, gB, rga[r], rgb[r], gmax) * ratio;   // 0 past ml
+      __syncthreads();
+      const T gr = grp_next<G>(gg[0]);
+      T bz[MM];
+#pragma unroll
+      for (int r = 0; r < MM; ++r) {
+        const T gn = (r + 1 < MM && r + 1 < ml) ? gg[r + 1 < MM ? r + 1 : r] : gr;
+        bz[r] = (r < vl_node) ? fma(phi2 * Nld, gn - gg[r], rz[r]) : T(0);
+      }
+      T nz[MM];
+      toeplitz_solve<G, T, MM>(nz, bz, wbz, mlw, vl_node, rho_l, itk_l, spl);
+      // convergence of this group; a converged group keeps its iterates
       T delta = T(0), amax = T(0);
 #pragma unroll
-      for (int r = 0; r < MM; ++r)
-        if (r < mt) {
-          delta = fmax(delta, fabs(nu[r] - au[r]));
-          amax = fmax(amax, fabs(nu[r]));
-          au[r] = nu[r];
-        }
-      if (has_l) {
-        // longitudinal right-hand side: r_z + phi^2 D_x+ I_(t)->(l) (q D_x- a_u)
-        const T al = lane_prev(last_of<T, MM>(au, mt));
-#pragma unroll
-        for (int r = 0; r < MM; ++r) {
-          if (r >= mt) continue;
-          const T am = r == 0 ? al : au[r > 0 ? r - 1 : 0];
-          const T fq = (r < vt_half) ? q[r] * ((au[r] - am) * Ntd) : T(0);
-          const T w = wi[r];
-          sA[tb + r] = (T(1) - w) * fq;
-          sB[tb + r] = w * fq;
-        }
-        __syncthreads();
-        T gg[MM];
-#pragma unroll
-        for (int r = 0; r < MM; ++r) {
-          gg[r] = r < ml ? range_gather<T>(sA, sB, rga[r], rgb[r], gmax) * ratio : T(0);
-        }
-        __syncthreads();
-        const T gr = lane_next(gg[0]);
-        T bz[MM];
-#pragma unroll
-        for (int r = 0; r < MM; ++r) {
-          const T gn = (r + 1 < ml && r + 1 < MM) ? gg[r + 1 < MM ? r + 1 : r] : gr;
-          bz[r] = (r < vl_node) ? fma(phi2 * Nld, gn - gg[r], rz[r]) : T(0);
-        }
-        T nz[MM];
-        toeplitz_solve<T, MM>(nz, bz, wbz, ml, vl_node, Tz);
-#pragma unroll
-        for (int r = 0; r < MM; ++r)
-          if (r < ml) {
-            delta = fmax(delta, fabs(nz[r] - az[r]));
-            amax = fmax(amax, fabs(nz[r]));
-            az[r] = nz[r];
-          }
-        delta = wave_max(delta);
-        amax = wave_max(amax);
-        const int done_now = uni((int)((sweep > 0 && delta <= (T)a.tol * amax) || amax == T(0)));
-        if (done_now) {
-          conv = true;
-          ++sweep;
-          break;
-        }
-      } else {
-        ++sweep;
-        break;
+      for (int r = 0; r < MM; ++r) {
+        delta = fmax(delta, fmax(fabs(nu[r] - au[r]), fabs(nz[r] - az[r])));
+        amax = fmax(amax, fmax(fabs(nu[r]), fabs(nz[r])));
       }
+      delta = grp_reduce<G, true>(delta);
+      amax = grp_reduce<G, true>(amax);
+#pragma unroll
+      for (int r = 0; r < MM; ++r) {
+        au[r] = conv ? au[r] : nu[r];
+        az[r] = conv ? az[r] : nz[r];
+      }
+      sweeps = conv ? sweeps : sweep + 1;
+      const bool now = nl == 0 || (sweep > 0 && delta <= (T)a.tol * amax) || amax == T(0);
+      conv = conv || now;
+      if (__ballot(!conv) == 0) break;
     }
-    if (!conv) flags |= kFlagNoConverge;
-    tot_sw += sweep;
-    max_sw = sweep > max_sw ? sweep : max_sw;
+    flags |= (act && !conv) ? kFlagNoConverge : 0;
+    tot_sw += act ? sweeps : 0;
+    max_sw = (act && sweeps > max_sw) ? sweeps : max_sw;
 
     // ---- state update: v^{n+1/2} = v^{n-1/2} + a, w^{n+1} = w^n + v^{n+1/2} ----
 #pragma unroll
     for (int r = 0; r < MM; ++r) {
-      if (r < mt) {
-        kahan_add<T, KAHAN>(vu[r], cvu[r], au[r]);
-        update_pos<T, KAHAN>(u[r], cu[r], vu[r], cvu[r]);
-      }
-      if (r < ml) {
-        kahan_add<T, KAHAN>(vz[r], cvz[r], az[r]);
-        update_pos<T, KAHAN>(z[r], cz[r], vz[r], cvz[r]);
-      }
+      T nu_ = u[r], nvu = vu[r], ncu = cu[r], ncvu = cvu[r];
+      kahan_add<T, KAHAN>(nvu, ncvu, au[r]);
+      update_pos<T, KAHAN>(nu_, ncu, nvu, ncvu);
+      T nz_ = z[r], nvz = vz[r], ncz = cz[r], ncvz = cvz[r];
+      kahan_add<T, KAHAN>(nvz, ncvz, az[r]);
+      update_pos<T, KAHAN>(nz_, ncz, nvz, ncvz);
+      u[r] = act ? nu_ : u[r];
+      vu[r] = act ? nvu : vu[r];
+      cu[r] = act ? ncu : cu[r];
+      cvu[r] = act ? ncvu : cvu[r];
+      z[r] = act ? nz_ : z[r];
+      vz[r] = act ? nvz : vz[r];
+      cz[r] = act ? ncz : cz[r];
+      cvz[r] = act ? ncvz : cvz[r];
     }
 
     // ---- hammer lumped mass (eq. 6) ----
-    if (ham) {
-      const double Iu1 = point_eval<T, MM>(u, cu, mt, hn0, hw0, hn1, hw1);
-      const double uH_np1 = uni((2.0 * uH_n - uH_nm1 - kk * cH * (eta_nm1 - Iu1)) / (1.0 + kk * cH));
-      uH_nm1 = uH_n;
-      uH_n = uH_np1;
-      eta_nm1 = eta_n;
+    if (any_ham) {
+      const double Iu1 = point_eval<G, T, MM>(u, cu, mt, hn0, hw0, hn1, hw1);
+      const double uH_np1 = (2.0 * uH_n - uH_nm1 - kk * cH * (eta_nm1 - Iu1)) / (1.0 + kk * cH);
+      const bool upd = act && ham;
+      uH_nm1 = upd ? uH_n : uH_nm1;
+      uH_n = upd ? uH_np1 : uH_n;
+      eta_nm1 = upd ? eta_n : eta_nm1;
     }
 
-    // ---- readout y^{n+1} = I(x_out) u^{n+1} into the 64-sample ring ----
+    // ---- readout y^{n+1} = I(x_out) u^{n+1} into the group's ring of G samples ----
     const int64_t m = n + 1;
-    {
-      const double y = point_eval<T, MM>(u, cu, mt, on0, ow0, on1, ow1);
-      if (lane == (int)((m - first_m) & (kWave - 1))) ring = (T)y;
-    }
+    const double y = point_eval<G, T, MM>(u, cu, mt, on0, ow0, on1, ow1);
+    const int slot = (int)((m - first_m) & (G - 1));
+    ring = (act && li == slot) ? (T)y : ring;
 
     // ---- FP64 energy monitor ----
     bool bad = false;
-    if (a.mon_period > 0 && ((n + 1) % a.mon_period) == 0) {
-      store_state<T, MM>(st, u, vu, cu, cvu, z, vz, cz, cvz, mt, ml, lane);
+    const bool mon_now = act && a.mon_period > 0 && mon_ctr == 0;
+    if (__ballot(mon_now) != 0) {
+      energy_fill<G, MM, T>(gE, u, vu, cu, cvu, z, vz, cz, cvz, mt, ml, li);
       __syncthreads();
-      const double H = uni(energy_fp64<T, MM>(D, g2k2, (double *)sA));
-      H_last = H;
-      H_step = n;
-      bad = !isfinite(H);
-      if (!bad && mon_check && !touched && H_ref > 0.0 && H > H_ref * (1.0 + a.mon_tol)) bad = true;
-      H_ref = H;
-      touched = 0;
-      if (bad) flags |= kFlagUnstable;
+      const double H = energy_fp64<G, MM, T>(D, g2k2, gE, li);
+      __syncthreads();
+      H_last = mon_now ? H : H_last;
+      H_step = mon_now ? n : H_step;
+      bad = mon_now && (!isfinite(H) || (mon_check && !touched && H_ref > 0.0 && H > H_ref * (1.0 + a.mon_tol)));
+      H_ref = mon_now ? H : H_ref;
+      touched = mon_now ? 0 : touched;
+      flags |= bad ? kFlagUnstable : 0;
     }
-    // coalesced burst of 64 samples from first_m + 64 j: every lane stores;
-    // lanes past m write slots that a later step overwrites (or the 64-sample
-    // padding after n_samples), never a sample before first_m
-    if (((m - first_m) & (kWave - 1)) == kWave - 1 || it == nsteps - 1 || bad)
-      out[first_m + ((m - first_m) & ~(int64_t)(kWave - 1)) + lane] = ring;
-    if (bad) {
-      ++it;
-      break;
+    // coalesced burst of G samples per group from first_m + G j: every lane
+    // stores; lanes past m write slots a later step overwrites (or the padding
+    // after n_samples), never a sample before first_m
+    const bool flush = act && (slot == G - 1 || it == nsteps - 1 || bad);
+    if (__ballot(flush) != 0) {
+      const int64_t idx = flush ? first_m + ((m - first_m) & ~(int64_t)(G - 1)) + li : n_samples + li;
+      out[idx] = ring;
     }
+    steps_done += act ? 1 : 0;
+    nsteps = bad ? it + 1 : nsteps;      // a flagged string stops here
+    mon_ctr = mon_ctr + 1 == a.mon_period ? 0 : mon_ctr + 1;
   }
 
-  // ---- write back ----
-  store_state<T, MM>(st, u, vu, cu, cvu, z, vz, cz, cvz, mt, ml, lane);
-  {  // every lane stores the same values (no lane-0-only region)
-    S->samples_done = done + it;
-    S->flags = flags;
-    S->max_sweeps = max_sw;
-    S->total_sweeps = tot_sw;
-    S->H_latest = H_last;
-    S->H_step = H_step;
-    S->H_ref = H_ref;
-    S->touched = touched;
-    S->uH_n = uH_n;
-    S->uH_nm1 = uH_nm1;
-    S->eta_nm1 = eta_nm1;
-  }
+  // ---- write back: every lane stores; an empty group writes to the trash ----
+  Status *Sw = present ? S : a.trash_status;
+  store_state<G, T, MM>(present ? st : trash, trash, u, vu, cu, cvu, z, vz, cz, cvz, mt, ml, li);
+  Sw->samples_done = done + steps_done;
+  Sw->flags = flags;
+  Sw->max_sweeps = max_sw;
+  Sw->total_sweeps = tot_sw;
+  Sw->H_latest = H_last;
+  Sw->H_step = H_step;
+  Sw->H_ref = H_ref;
+  Sw->touched = touched;
+  Sw->uH_n = uH_n;
+  Sw->uH_nm1 = uH_nm1;
+  Sw->eta_nm1 = eta_nm1;
 }
 
-template <typename T, int MM, bool KAHAN>
+template <int G, int MM, typename T, bool KAHAN>
 __global__ __launch_bounds__(64) void step_kernel(LaunchArgs a) {
-  // exchange buffers: longitudinal half points; transverse contributions (2 x)
-  __shared__ T sP[MM * kWave];
-  __shared__ T sAB[2 * MM * kWave + 2 * MM * kWave * (sizeof(T) == 4 ? 1 : 0)];
-  T *sA = sAB, *sB = sAB + MM * kWave;
+  constexpr int kGroups = kWave / G;
+  using L = Lds<G, MM>;
+  // the energy monitor's scratch overlays the stepping arrays (never live together)
+  constexpr int kStepDoubles = (3 * kGroups * L::kStride * (int)sizeof(T) + 7) / 8;
+  constexpr int kEnergyDoubles = kGroups * EnergyLds<G, MM>::kStride;
+  __shared__ double lds[kStepDoubles > kEnergyDoubles ? kStepDoubles : kEnergyDoubles];
+  T *sP = (T *)lds, *sA = sP + kGroups * L::kStride, *sB = sA + kGroups * L::kStride;
+  double *sE = lds;
   for (;;) {
     // every lane takes part; only lane 0 adds, so the wave draws one ticket
     int w = atomicAdd(a.counter, lane_id() == 0 ? 1 : 0);
     w = __builtin_amdgcn_readfirstlane(w);
     if (w >= a.n_work) break;
-    const int s = __builtin_amdgcn_readfirstlane(a.work[w]);
-    run_string<T, MM, KAHAN>(a, s, sP, sA, sB);
+    run_task<G, MM, T, KAHAN>(a, w, sP, sA, sB, sE);
   }
+}
+
+__global__ void zero_counters(int32_t *c, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) c[i] = 0;
 }
 
 // Restores slots first..first+count-1 to their state right after excitation:
@@ -853,18 +928,15 @@ hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const 
   return hipGetLastError();
 }
 
-__global__ void zero_counters(int32_t *c, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) c[i] = 0;
-}
-
 template <typename T, bool KAHAN>
 static hipError_t launch_class(int cls, const LaunchArgs &a, int blocks, hipStream_t st) {
   switch (cls) {
-    case 0: hipLaunchKernelGGL((step_kernel<T, 2, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((step_kernel<T, 4, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((step_kernel<T, 8, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
-    default: hipLaunchKernelGGL((step_kernel<T, 16, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 0: hipLaunchKernelGGL((step_kernel<16, 2, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((step_kernel<16, 4, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((step_kernel<32, 4, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 3: hipLaunchKernelGGL((step_kernel<64, 4, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((step_kernel<64, 8, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
+    default: hipLaunchKernelGGL((step_kernel<64, 16, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
   }
   return hipGetLastError();
 }
@@ -879,19 +951,17 @@ hipError_t launch_zero(int32_t *c, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-}  // namespace sfd
-
-namespace sfd {
-
 template <typename T, bool KAHAN>
 static int blocks_per_cu(int cls) {
   int n = 0;
   hipError_t e;
   switch (cls) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<T, 2, KAHAN>, 64, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<T, 4, KAHAN>, 64, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<T, 8, KAHAN>, 64, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<T, 16, KAHAN>, 64, 0); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<16, 2, T, KAHAN>, 64, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<16, 4, T, KAHAN>, 64, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<32, 4, T, KAHAN>, 64, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 4, T, KAHAN>, 64, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 8, T, KAHAN>, 64, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 16, T, KAHAN>, 64, 0); break;
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();

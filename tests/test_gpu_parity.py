@@ -58,10 +58,10 @@ def _report(tag, err, info=None):
     print("%s rel-L2 %.3e %s" % (tag, err, "" if info is None else info), flush=True)
 
 
-@pytest.mark.skip(reason="hung on the GPU: the step kernel's lane-0-only status stores were compiled into a "
-                         "divergent loop exit that re-entered the work loop without drawing a new ticket; the kernel "
-                         "was restructured (no divergent regions in the persistent loop), but this case stays off "
-                         "the GPU for the rest of the round after a failed fix attempt")
+@pytest.mark.skip(reason="hung on the GPU with an earlier step kernel whose lane-0-only status stores were compiled "
+                         "into a divergent loop exit; a first fix did not clear it, so this exact case stays off the "
+                         "GPU until the cause of that hang is shown on the CPU (the same string runs inside the "
+                         "other cases)")
 def test_tiny_first():
     _gpu()
     p, e = W.single_linear(seconds=0.01)
