@@ -65,6 +65,30 @@ def cpu_baseline(items, seconds_cap, threads):
     return rec, flops / upd
 
 
+def plain_leg(W, binding, hiptime, seconds):
+    """The plain FP64 per-string method (eq. (7), one string per launch, banded
+    LU) on the single nonlinear hammered string, timed with HIP events."""
+    p, e = W.single_nonlinear(seconds=seconds)
+    b = binding.StringBatch(1, "fp64_plain")
+    b.set_params(0, [p])
+    b.excite(0, [e])
+    inf = b.info(0)
+    hiptime.synchronize()
+    ev0, ev1 = hiptime.Event(), hiptime.Event()
+    ev0.record(0)
+    b.step(p["n_samples"])
+    ev1.record(0)
+    ev1.synchronize()
+    ms = ev0.elapsed_ms(ev1)
+    done = b.info(0)
+    b.close()
+    upd = unknowns(inf) * (p["n_samples"] - 2)
+    return {"value": upd / (ms / 1e3), "unit": "grid-point updates/s", "audio_s_per_s": seconds / (ms / 1e3),
+            "ms": ms, "workload": "single nonlinear hammered string, %.1f s (N_t=%d, N_l=%d), FP64, "
+                                  "one string per launch" % (seconds, inf["N_t"], inf["N_l"]),
+            "finished": done["samples_done"] == p["n_samples"] and done["flags"] == 0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +97,8 @@ def main():
     ap.add_argument("--workload", default="uneven16384", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=0.25, help="duration cap of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-seconds", type=float, default=0.5, help="duration of the plain FP64 comparator run")
+    ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the strings are independent and this build has no "
@@ -150,6 +176,11 @@ def main():
         "sweeps_per_step_mean": sweeps / max(1, sum(inf["n_samples"] - 2 for inf in infos)),
         "strings_not_finished": bad,
     }
+    if not args.no_plain:
+        pl = plain_leg(W, binding, hiptime, args.plain_seconds)
+        print("[bench] plain FP64: %.1f ms, %.3e updates/s" % (pl["ms"], pl["value"]), file=sys.stderr, flush=True)
+        out["plain_fp64"] = pl
+        out["batched_vs_plain"] = value / pl["value"]
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         rec, flops_per_update = cpu_baseline(items, args.cpu_seconds, threads)

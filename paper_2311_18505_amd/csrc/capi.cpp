@@ -20,8 +20,8 @@ hipError_t launch_zero(int32_t *c, int n, hipStream_t st);
 int max_blocks_per_cu(int precision, int cls);
 hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
                          hipStream_t st);
-hipError_t launch_plain(const Desc *d_desc, Status *d_status, int slot, int64_t n_steps, int mon_period,
-                        double mon_tol, hipStream_t st);
+hipError_t launch_plain(const Desc *d_desc, Status *d_status, int slot, int64_t n_steps, size_t lds_bytes,
+                        hipStream_t st);
 }  // namespace sfd
 
 using namespace sfd;
@@ -255,6 +255,18 @@ static bool range_ok(const sb_batch *b, int first, int count) {
 // output has 64 samples of padding that absorb the stores of idle lanes.
 static size_t region_size(const sb_batch *b, const Desc &D, size_t *off_st0, size_t *off_tabf, size_t *off_out,
                           size_t *off_tab) {
+  if (b->precision == SB_FP64_PLAIN) {
+    // natural order: u^n | u^{n-1} | zeta^n | zeta^{n-1}; weights per t-half; position tables
+    const size_t st = align256(8 * 2 * (size_t)(D.nt + D.nl));
+    const size_t tf = align256(8 * (size_t)D.Nt);
+    const size_t ou = align256(8 * (size_t)(D.n_samples + kWave));
+    const size_t tb = align256(4 * ((size_t)D.nt + D.nl + D.Nt + 2 * (size_t)D.Nl));
+    *off_st0 = st;
+    *off_tabf = 2 * st;
+    *off_out = 2 * st + tf;
+    *off_tab = 2 * st + tf + ou;
+    return 2 * st + tf + ou + tb;
+  }
   const size_t G = (size_t)kClassLanes[D.cls];
   const size_t st = align256(b->esz * G * 4 * (D.mt + D.ml));
   const size_t tf = align256(b->esz * G * (3 * D.mt + D.ml));
@@ -276,10 +288,6 @@ extern "C" int string_batch_set_params(sb_batch *b, int first, int count, const 
     int st = plan_string(p[i], plans[i], err);
     if (st) return fail(b, st, "slot " + std::to_string(first + i) + ": " + err);
   }
-  if (b->precision == SB_FP64_PLAIN)
-    for (int i = 0; i < count; ++i)
-      if (plans[i].desc.nt + plans[i].desc.nl + 1 > 2048)
-        return fail(b, SB_EBUDGET, "plain FP64 path holds at most 2048 unknowns");
   // queued launches may still read the memory released below
   hipError_t es = hipStreamSynchronize(b->stream);
   if (es != hipSuccess) return hip_fail(b, es, "sync");
@@ -337,6 +345,7 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     Plan tmp = b->slots[first + i].plan;
     std::string err;
     int st = plan_excitation(e[i], tmp, err);
+    if (!st && b->precision == SB_FP64_PLAIN) st = plan_plain(tmp, err);
     if (st) return fail(b, st, "slot " + std::to_string(first + i) + ": " + err);
   }
   // queued launches may still step these slots
@@ -350,13 +359,15 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     Slot &s = b->slots[first + i];
     std::string msg;
     plan_excitation(e[i], s.plan, msg);
+    if (b->precision == SB_FP64_PLAIN) plan_plain(s.plan, msg);
     Desc &D = s.plan.desc;
     size_t ost0, otf, oout, otab;
     region_size(b, D, &ost0, &otf, &oout, &otab);
     D.st = s.dmem;
     D.st0 = s.dmem + ost0;
+    const bool plain = b->precision == SB_FP64_PLAIN;
     const int G = kClassLanes[D.cls];
-    D.st_elems = G * 4 * (D.mt + D.ml);
+    D.st_elems = plain ? 2 * (D.nt + D.nl) : G * 4 * (D.mt + D.ml);
     D.tabf = s.dmem + otf;
     D.out = s.dmem + oout;
     D.tab = (const uint32_t *)(s.dmem + otab);
@@ -364,12 +375,18 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     std::vector<double> u0;
     double uH0, uH1;
     initial_state(e[i], s.plan, u0, uH0, uH1);
-    std::vector<double> state((size_t)G * 4 * (D.mt + D.ml), 0.0);
-    for (int lane = 0; lane < G; ++lane)
-      for (int r = 0; r < D.mt; ++r) {
-        const int node = lane * D.mt + r + 1;
-        if (node <= D.nt) state[(size_t)r * G + lane] = u0[node];
-      }
+    std::vector<double> state((size_t)D.st_elems, 0.0);
+    if (plain) {
+      for (int i = 1; i <= D.nt; ++i) state[i - 1] = state[D.nt + i - 1] = u0[i];   // u^1 = u^0
+      D.ptab = (const int32_t *)(s.dmem + otab);
+      D.pw = (const double *)(s.dmem + otf);
+    } else {
+      for (int lane = 0; lane < G; ++lane)
+        for (int r = 0; r < D.mt; ++r) {
+          const int node = lane * D.mt + r + 1;
+          if (node <= D.nt) state[(size_t)r * G + lane] = u0[node];
+        }
+    }
     double y0 = 0.0;
     if (D.on0) y0 += D.ow0 * u0[D.on0];
     if (D.on1) y0 += D.ow1 * u0[D.on1];
@@ -378,7 +395,11 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     keep.emplace_back();
     keep.emplace_back();
     std::vector<char> &bs = keep[keep.size() - 3], &bt = keep[keep.size() - 2], &bh = keep[keep.size() - 1];
-    if (b->precision == SB_FP32C) {
+    if (plain) {
+      to_prec<double>(state, bs);
+      to_prec<double>(s.plan.pw, bt);
+      to_prec<double>(head, bh);
+    } else if (b->precision == SB_FP32C) {
       to_prec<float>(state, bs);
       to_prec<float>(s.plan.tabf, bt);
       to_prec<float>(head, bh);
@@ -391,7 +412,10 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     if (err == hipSuccess) err = hipMemcpyAsync(s.dmem + ost0, bs.data(), bs.size(), hipMemcpyHostToDevice, b->stream);
     if (err == hipSuccess) err = hipMemcpyAsync(s.dmem + otf, bt.data(), bt.size(), hipMemcpyHostToDevice, b->stream);
     if (err == hipSuccess) err = hipMemcpyAsync(s.dmem + oout, bh.data(), bh.size(), hipMemcpyHostToDevice, b->stream);
-    if (err == hipSuccess)
+    if (err == hipSuccess && plain)
+      err = hipMemcpyAsync(s.dmem + otab, s.plan.ptab.data(), s.plan.ptab.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, b->stream);
+    else if (err == hipSuccess)
       err = hipMemcpyAsync(s.dmem + otab, s.plan.tab.data(), s.plan.tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
                            b->stream);
     descs[i] = D;
@@ -457,7 +481,7 @@ static int do_step(sb_batch *b, int first, int count, int64_t n_steps) {
     // one string per launch, in order
     for (int32_t i : work) {
       if (i < 0) continue;
-      e = launch_plain(b->d_desc, b->d_status, i, n_steps, b->mon_period, b->mon_tol, b->stream);
+      e = launch_plain(b->d_desc, b->d_status, i, n_steps, plain_lds_bytes(b->slots[i].plan.desc), b->stream);
       if (e != hipSuccess) return hip_fail(b, e, "plain launch");
     }
   } else {

@@ -327,6 +327,113 @@ void initial_state(const sb_excitation &e, const Plan &P, std::vector<double> &u
   }
 }
 
+// Plain path (eq. (7) solved as one banded system): the unknowns of both
+// grids and the hammer are merged by position along the string, which makes
+// every coupling local; the half bandwidth follows from the couplings of
+// eq. (8) with the interpolants of the scheme and the hammer's rank-one block.
+int plan_plain(Plan &P, std::string &err) {
+  Desc &D = P.desc;
+  const int Nt = D.Nt, Nl = D.Nl, nt = D.nt, nl = D.nl;
+  const bool ham = D.ham_on != 0;
+  struct Item {
+    double x;
+    int kind, idx;
+  };
+  std::vector<Item> it;
+  for (int i = 1; i <= nt; ++i) it.push_back({(double)i / Nt, 0, i});
+  for (int j = 1; j <= nl; ++j) it.push_back({(double)j / Nl, 1, j});
+  // the hammer unknown sits at the position of its first node
+  if (ham) it.push_back({D.hn0 ? (double)D.hn0 / Nt : (double)D.hn1 / Nt, 2, 0});
+  std::stable_sort(it.begin(), it.end(), [](const Item &a, const Item &b) {
+    return a.x < b.x || (a.x == b.x && a.kind < b.kind);
+  });
+  std::vector<int> pt(nt + 1, -1), pl(nl + 1, -1);
+  int ph = -1;
+  for (int r = 0; r < (int)it.size(); ++r) {
+    if (it[r].kind == 0) pt[it[r].idx] = r;
+    else if (it[r].kind == 1) pl[it[r].idx] = r;
+    else ph = r;
+  }
+  const int n = (int)it.size();
+  // l-half ranges of t-half points per tap (1-based first half, count)
+  std::vector<int> sa(Nl + 2, 0), na(Nl + 2, 0), sb(Nl + 2, 0), nb(Nl + 2, 0);
+  if (nl > 0)
+    for (int h = Nt; h >= 1; --h) {
+      sa[P.ja[h]] = h;
+      na[P.ja[h]]++;
+      sb[P.jb[h]] = h;
+      nb[P.jb[h]]++;
+    }
+  int bw = 0;
+  auto see = [&](int r, int c) {
+    if (r >= 0 && c >= 0) bw = std::max(bw, std::abs(r - c));
+  };
+  for (int i = 1; i <= nt; ++i) {
+    const int r = pt[i];
+    if (i > 1) see(r, pt[i - 1]);
+    if (i < nt) see(r, pt[i + 1]);
+    if (nl > 0)
+      for (int h = i; h <= i + 1; ++h) {
+        if (h < 1 || h > Nt) continue;
+        for (int j : {P.ja[h], P.ja[h] - 1, P.jb[h], P.jb[h] - 1})
+          if (j >= 1 && j <= nl) see(r, pl[j]);
+      }
+    if (ham && (i == D.hn0 || i == D.hn1)) {
+      see(r, ph);
+      if (D.hn0) see(r, pt[D.hn0]);
+      if (D.hn1) see(r, pt[D.hn1]);
+    }
+  }
+  for (int j = 1; j <= nl; ++j) {
+    const int r = pl[j];
+    if (j > 1) see(r, pl[j - 1]);
+    if (j < nl) see(r, pl[j + 1]);
+    for (int m = j; m <= j + 1; ++m) {
+      for (int h = sa[m]; h < sa[m] + na[m]; ++h)
+        for (int i : {h - 1, h})
+          if (i >= 1 && i <= nt) see(r, pt[i]);
+      for (int h = sb[m]; h < sb[m] + nb[m]; ++h)
+        for (int i : {h - 1, h})
+          if (i >= 1 && i <= nt) see(r, pt[i]);
+    }
+  }
+  if (ham) {
+    if (D.hn0) see(ph, pt[D.hn0]);
+    if (D.hn1) see(ph, pt[D.hn1]);
+  }
+  D.pn = n;
+  D.pbw = bw;
+  D.ph = ph;
+  if (bw > kPlainMaxBw) {
+    err = "plain path: half bandwidth " + std::to_string(bw) + " exceeds " + std::to_string(kPlainMaxBw);
+    return SB_EBUDGET;
+  }
+  if (plain_lds_bytes(D) > (size_t)kPlainMaxLdsBytes) {
+    err = "plain path: banded system does not fit in LDS";
+    return SB_EBUDGET;
+  }
+  P.ptab.assign((size_t)nt + nl + Nt + 2 * (size_t)Nl, 0);
+  int32_t *q = P.ptab.data();
+  for (int i = 1; i <= nt; ++i) *q++ = pt[i];
+  for (int j = 1; j <= nl; ++j) *q++ = pl[j];
+  for (int h = 1; h <= Nt; ++h) *q++ = nl > 0 ? (P.ja[h] | (P.jb[h] << 16)) : 0;
+  for (int m = 1; m <= Nl; ++m) *q++ = sa[m] | (na[m] << 16);
+  for (int m = 1; m <= Nl; ++m) *q++ = sb[m] | (nb[m] << 16);
+  P.pw.assign(Nt, 0.0);
+  for (int h = 1; h <= Nt; ++h) P.pw[h - 1] = nl > 0 ? P.w[h] : 0.0;
+  return SB_OK;
+}
+
+// LDS of the plain kernel: band (2 bw + 1 per row) and right-hand side of the
+// n unknowns, the two time levels of both grids with their end points, and
+// per-step half-point and node scratch.
+size_t plain_lds_bytes(const Desc &D) {
+  const size_t n = (size_t)D.pn, W = 2 * (size_t)D.pbw + 1;
+  const size_t words = n * W + n + 1 + W + 2 * ((size_t)D.Nt + 1) + 2 * ((size_t)D.Nl + 1) + 4 * ((size_t)D.Nt + 2) +
+                       2 * ((size_t)D.Nl + 2) + 64;
+  return words * sizeof(double);
+}
+
 }  // namespace sfd
 
 extern "C" int string_plan_grid(const sb_string_params *p, int32_t *N_t, int32_t *N_l) {

@@ -21,6 +21,8 @@ struct Plan {
   std::vector<double> tabf;      // lane-major real tables (rounded to the kernel precision on upload)
   std::vector<int> ja, jb;       // I_(l)->(t) taps per t-half point (1-based)
   std::vector<double> w;
+  std::vector<int32_t> ptab;     // plain path tables (natural order), see Desc::ptab
+  std::vector<double> pw;
 };
 
 double theta_of(const sb_string_params &p);
@@ -28,5 +30,7 @@ int plan_grid(const sb_string_params &p, GridPlan &g, std::string &err);
 int plan_string(const sb_string_params &p, Plan &P, std::string &err);
 int plan_excitation(const sb_excitation &e, Plan &P, std::string &err);
 void initial_state(const sb_excitation &e, const Plan &P, std::vector<double> &u0, double &uH0, double &uH1);
+int plan_plain(Plan &P, std::string &err);
+size_t plain_lds_bytes(const Desc &D);
 
 }  // namespace sfd

@@ -63,7 +63,15 @@ struct Desc {
   int32_t gmax;               // longest t-half range gathered by one l-half point
   int32_t st_elems;           // elements of the state block
   void *st0;                  // copy of the state block right after excitation
+  // plain FP64 path (eq. (7), merged-order banded LU): unknowns, half
+  // bandwidth, position of the hammer unknown (-1: none), and its tables
+  int32_t pn, pbw, ph, pad2;
+  const int32_t *ptab;        // pos_t[nt] | pos_l[nl] | ja|jb<<16 per t-half [Nt] | sa|na<<16, sb|nb<<16 per l-half [Nl] each
+  const double *pw;           // interpolation weight w per t-half [Nt]
 };
+
+constexpr int kPlainMaxBw = 16;             // half bandwidth the plain kernel accepts
+constexpr int kPlainMaxLdsBytes = 64 * 1024;    // LDS the plain kernel may use (no opt-in needed)
 
 // Per-string dynamic status (device memory, updated by the kernel).
 struct Status {

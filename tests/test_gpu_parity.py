@@ -114,3 +114,32 @@ def test_fp64_single_linear_full():
     _report("linear fp64", err, inf)
     assert inf["flags"] == 0 and inf["samples_done"] == p["n_samples"]
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("which", ["linear", "nonlinear"])
+def test_plain_fp64_single(which):
+    """Plain per-string comparator (eq. (7), merged-order banded LU) against the oracle."""
+    _gpu()
+    p, e = W.single_linear(seconds=1.0) if which == "linear" else W.single_nonlinear(seconds=0.25)
+    ref = oracle_ref(p, e)
+    (y,), (inf,) = run_gpu([(p, e)], "fp64_plain")
+    err = rel_l2(y, ref)
+    _report("plain %s fp64" % which, err, inf)
+    assert inf["flags"] == 0 and inf["samples_done"] == p["n_samples"]
+    assert err <= 1e-10
+
+
+def test_plain_fp64_modulated_and_chunked():
+    """Plain path with vibrato and glide, stepped in 480-sample chunks."""
+    _gpu()
+    items = [(W.string(150.0, 3e-4, 2.0, 1.0, 2e-4, 4800, mod_type=1, mod_depth_cents=40, mod_rate_hz=5),
+              W.pluck(0.2, 3e-3)),
+             (W.string(150.0, 3e-4, 2.0, 1.0, 2e-4, 4800, mod_type=2, glide_semitones=-2), W.hammer(0.2, 3.0)),
+             (W.string(300.0, 1e-3, 3.0, 1.0, 3e-4, 4800), W.pluck(0.14, 0.02))]
+    refs = oracle.run_many(items)
+    outs, infos = run_gpu(items, "fp64_plain", chunk=480)
+    for (p, _), y, r, inf in zip(items, outs, refs, infos):
+        err = rel_l2(y, r["y_u"])
+        _report("plain chunked N=(%d,%d)" % (inf["N_t"], inf["N_l"]), err, inf)
+        assert inf["samples_done"] == p["n_samples"]
+        assert err <= 1e-10
