@@ -89,6 +89,21 @@ def plain_leg(W, binding, hiptime, seconds):
             "finished": done["samples_done"] == p["n_samples"] and done["flags"] == 0}
 
 
+def serving_leg(W, serving, rate, seconds, capacity):
+    """Continuous-batching server under Poisson arrivals (one string per
+    request, durations U(0.25, 3) s), in real time."""
+    arrivals, items = W.serving_requests(rate_hz=rate, seconds=seconds)
+    reqs = serving.requests_from(arrivals, items)
+    srv = serving.Server(capacity=capacity)
+    stats, _ = srv.run(reqs)
+    srv.close()
+    rec = stats.summary()
+    rec.update({"rate_hz": rate, "seconds": seconds, "requests": len(reqs),
+                "offered_audio_s_per_s": sum(p["n_samples"] / p["fs"] for p, _ in items) / seconds,
+                "chunk_samples": serving.CHUNK, "capacity": capacity})
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +114,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-seconds", type=float, default=0.5, help="duration of the plain FP64 comparator run")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=60.0, help="arrival window of the serving run")
+    ap.add_argument("--serving-rate", type=float, default=2000.0)
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the strings are independent and this build has no "
@@ -181,6 +199,18 @@ def main():
         print("[bench] plain FP64: %.1f ms, %.3e updates/s" % (pl["ms"], pl["value"]), file=sys.stderr, flush=True)
         out["plain_fp64"] = pl
         out["batched_vs_plain"] = value / pl["value"]
+    if not args.no_serving:
+        from paper_2311_18505_amd import serving
+        print("[bench] serving: %.0f requests/s for %.0f s" % (args.serving_rate, args.serving_seconds),
+              file=sys.stderr, flush=True)
+        sv = serving_leg(W, serving, args.serving_rate, args.serving_seconds, 16384)
+        print("[bench] serving done: %s" % json.dumps(sv), file=sys.stderr, flush=True)
+        out["serving"] = sv
+        if "plain_fp64" in out:
+            # one stream, FIFO, one request at a time: the plain method sustains
+            # (its audio-s/s) / (mean request duration) requests per second
+            mean_T = 0.5 * (0.25 + 3.0)
+            out["serving"]["plain_fp64_max_rate_hz"] = out["plain_fp64"]["audio_s_per_s"] / mean_T
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         rec, flops_per_update = cpu_baseline(items, args.cpu_seconds, threads)

@@ -154,6 +154,18 @@ int string_batch_read_output(sb_batch *b, int idx, int64_t offset, int64_t count
  * batch precision); the batch owns the memory. */
 int string_batch_output_ptr(sb_batch *b, int idx, void **dev_ptr);
 
+/* Streaming readout of many slots at once (Sec. 3.4's output signal, one
+ * chunk per string): row i of dst (count elements of the batch precision)
+ * receives samples offsets[i] .. offsets[i]+count-1 of slot slots[i],
+ * clipped at that slot's n_samples (the rest of the row is left as is).
+ * One gather kernel and one copy, ordered on the batch stream and
+ * synchronous with it when dst_is_device == 0.  slots/offsets are host
+ * arrays of n entries, copied before the call returns.
+ * Errors: SB_EINVAL (bad slot, offset outside [0, n_samples)), SB_ESTATE
+ * (slot not excited), SB_ENOMEM, SB_EDEVICE. */
+int string_batch_gather_output(sb_batch *b, int n, const int32_t *slots, const int64_t *offsets, int64_t count,
+                               void *dst, int dst_is_device);
+
 /* Energy H^{n+1/2} of slot idx at its last monitor check (FP64, computed on
  * the GPU), and the step n of that check (-1 if none).  Synchronises the
  * stream.  Errors: SB_EINVAL, SB_EDEVICE. */

@@ -61,6 +61,8 @@ SIGNATURES = [
     ("string_batch_rewind", C.c_int, [_P, C.c_int, C.c_int]),
     ("string_batch_read_output", C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, _P, C.c_int]),
     ("string_batch_output_ptr", C.c_int, [_P, C.c_int, C.POINTER(_P)]),
+    ("string_batch_gather_output", C.c_int, [_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_int64,
+                                             _P, C.c_int]),
     ("string_batch_read_energy", C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("string_batch_info", C.c_int, [_P, C.c_int, C.POINTER(SbStringInfo)]),
     ("string_batch_set_monitor", C.c_int, [_P, C.c_int, C.c_double]),
@@ -195,6 +197,17 @@ class StringBatch:
         out = np.empty(count, dtype=self.dtype)
         self._check(self.lib.string_batch_read_output(self.h, idx, offset, count,
                                                       out.ctypes.data_as(C.c_void_p), 0), "read_output")
+        return out
+
+    def gather_output(self, slots, offsets, count: int) -> np.ndarray:
+        """Rows of `count` samples: row i holds samples offsets[i].. of slots[i]
+        (clipped at that slot's n_samples; the rest of the row is undefined)."""
+        sl = np.ascontiguousarray(slots, dtype=np.int32)
+        of = np.ascontiguousarray(offsets, dtype=np.int64)
+        out = np.empty((len(sl), count), dtype=self.dtype)
+        self._check(self.lib.string_batch_gather_output(
+            self.h, len(sl), sl.ctypes.data_as(C.POINTER(C.c_int32)), of.ctypes.data_as(C.POINTER(C.c_int64)),
+            count, out.ctypes.data_as(C.c_void_p), 0), "gather_output")
         return out
 
     def read_output_device(self, idx: int, dst_ptr: int, offset: int, count: int):

@@ -20,6 +20,8 @@ hipError_t launch_zero(int32_t *c, int n, hipStream_t st);
 int max_blocks_per_cu(int precision, int cls);
 hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
                          hipStream_t st);
+hipError_t launch_gather(int precision, const Desc *desc, const int32_t *slots, const int64_t *offs, int n,
+                         int64_t count, void *dst, hipStream_t st);
 hipError_t launch_plain(const Desc *d_desc, Status *d_status, int slot, int64_t n_steps, size_t lds_bytes,
                         hipStream_t st);
 }  // namespace sfd
@@ -126,6 +128,11 @@ struct sb_batch {
   int32_t *d_counters = nullptr;
   void *d_trash = nullptr;        // write target of empty groups and unused slots
   Status *d_trash_status = nullptr;
+  // streaming readout: slot list, offsets and the gathered rows (grown on demand)
+  int32_t *d_gslots = nullptr;
+  int64_t *d_goffs = nullptr;
+  void *d_gbuf = nullptr;
+  size_t gbuf_bytes = 0;
   std::vector<int32_t> h_work;
   bool work_dirty = true;
   int mon_period = 480;
@@ -235,6 +242,9 @@ extern "C" int string_batch_destroy(sb_batch *b) {
   hipFree(b->d_counters);
   hipFree(b->d_trash);
   hipFree(b->d_trash_status);
+  hipFree(b->d_gslots);
+  hipFree(b->d_goffs);
+  hipFree(b->d_gbuf);
   delete b;
   return SB_OK;
 }
@@ -556,6 +566,52 @@ extern "C" int string_batch_read_output(sb_batch *b, int idx, int64_t offset, in
                                 b->stream);
   if (e == hipSuccess && !dst_is_device) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(b, e, "read_output");
+  return SB_OK;
+}
+
+extern "C" int string_batch_gather_output(sb_batch *b, int n, const int32_t *slots, const int64_t *offsets,
+                                          int64_t count, void *dst, int dst_is_device) {
+  if (!b) return SB_EINVAL;
+  if (n < 0 || n > b->capacity || count < 0 || (n > 0 && (!slots || !offsets || !dst)))
+    return fail(b, SB_EINVAL, "bad arguments");
+  if (n == 0 || count == 0) return SB_OK;
+  for (int i = 0; i < n; ++i) {
+    if (slots[i] < 0 || slots[i] >= b->capacity) return fail(b, SB_EINVAL, "bad slot");
+    const Slot &s = b->slots[slots[i]];
+    if (!s.excited) return fail(b, SB_ESTATE, "slot " + std::to_string(slots[i]) + " not excited");
+    if (offsets[i] < 0 || offsets[i] >= s.plan.desc.n_samples) return fail(b, SB_EINVAL, "offset outside the output");
+  }
+  hipError_t e = hipSuccess;
+  if (!b->d_gslots) {
+    e = hipMalloc(&b->d_gslots, sizeof(int32_t) * b->capacity);
+    if (e == hipSuccess) e = hipMalloc(&b->d_goffs, sizeof(int64_t) * b->capacity);
+    if (e != hipSuccess) return hip_fail(b, e, "gather buffers");
+  }
+  const size_t bytes = (size_t)n * (size_t)count * b->esz;
+  void *rows = dst;
+  if (!dst_is_device) {
+    if (bytes > b->gbuf_bytes) {
+      // the previous buffer may still be read by queued copies
+      e = hipStreamSynchronize(b->stream);
+      if (e == hipSuccess) e = hipFree(b->d_gbuf);
+      b->d_gbuf = nullptr;
+      b->gbuf_bytes = 0;
+      if (e == hipSuccess) e = hipMalloc(&b->d_gbuf, bytes);
+      if (e != hipSuccess) return hip_fail(b, e, "gather buffer");
+      b->gbuf_bytes = bytes;
+    }
+    rows = b->d_gbuf;
+  }
+  // the index arrays of a previous call may still be read by its kernel
+  e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess) e = hipMemcpy(b->d_gslots, slots, sizeof(int32_t) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_goffs, offsets, sizeof(int64_t) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_gather(b->precision, b->d_desc, b->d_gslots, b->d_goffs, n, count, rows, b->stream);
+  if (e == hipSuccess && !dst_is_device) {
+    e = hipMemcpyAsync(dst, rows, bytes, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  }
+  if (e != hipSuccess) return hip_fail(b, e, "gather_output");
   return SB_OK;
 }
 

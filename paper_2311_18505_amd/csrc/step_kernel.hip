@@ -918,6 +918,30 @@ __global__ void rewind_kernel(const Desc *desc, Status *status, const Status *st
   if (threadIdx.x == 0) status[s] = status0[s];
 }
 
+// Row i of dst receives samples offs[i] .. offs[i]+count-1 of slot slots[i]'s
+// output, clipped at its n_samples: one block per row.
+template <typename T>
+__global__ void gather_kernel(const Desc *desc, const int32_t *slots, const int64_t *offs, int n, int64_t count,
+                              T *dst) {
+  const int i = (int)blockIdx.x;
+  if (i >= n) return;
+  const Desc &D = desc[slots[i]];
+  const int64_t left = D.n_samples - offs[i];
+  const int64_t c = count < left ? count : left;
+  const T *src = (const T *)D.out + offs[i];
+  for (int64_t s = threadIdx.x; s < c; s += blockDim.x) dst[(int64_t)i * count + s] = src[s];
+}
+
+hipError_t launch_gather(int precision, const Desc *desc, const int32_t *slots, const int64_t *offs, int n,
+                         int64_t count, void *dst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (precision == 1)
+    hipLaunchKernelGGL(gather_kernel<float>, dim3(n), dim3(256), 0, st, desc, slots, offs, n, count, (float *)dst);
+  else
+    hipLaunchKernelGGL(gather_kernel<double>, dim3(n), dim3(256), 0, st, desc, slots, offs, n, count, (double *)dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
                          hipStream_t st) {
   if (count <= 0) return hipSuccess;
