@@ -144,6 +144,27 @@ int string_batch_step_range(sb_batch *b, int first, int count, int64_t n_steps);
  * batch stream.  Errors: SB_EINVAL, SB_EDEVICE. */
 int string_batch_rewind(sb_batch *b, int first, int count);
 
+/* Launch capture (batched paths).  Records n_launches consecutive launches
+ * of steps_per_launch steps each, of every slot excited at the time of the
+ * call (the size classes forked onto their streams and joined back, counters
+ * cleared by a kernel), into a HIP graph owned by the batch; capture happens
+ * on an internal stream, so nothing runs.  string_batch_graph_launch replays
+ * it on the batch stream and advances every captured slot like the same
+ * sequence of string_batch_step calls would (slots that reach n_samples idle).
+ * set_params or excite on any slot invalidates the graph (launch then returns
+ * SB_ESTATE); rewind does not.  Errors: SB_EINVAL (plain path, bad shape),
+ * SB_ESTATE (nothing to step / stale graph), SB_EDEVICE. */
+int string_batch_graph_capture(sb_batch *b, int64_t steps_per_launch, int n_launches);
+int string_batch_graph_launch(sb_batch *b);
+
+/* Autotuner (batched paths): for every size class present, times a probe of
+ * probe_steps steps of that class alone at 1, 2, 4 and the occupancy limit of
+ * persistent blocks per CU, keeps the fastest for later launches and reports
+ * it in chosen[6] (0 for absent classes; chosen may be NULL).  Every slot is
+ * rewound to its excitation before and after, so call it right after excite.
+ * Errors: SB_EINVAL, SB_ESTATE (nothing excited), SB_EDEVICE. */
+int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *chosen);
+
 /* Copy samples offset .. offset+count-1 of slot idx to dst (count elements
  * of the batch precision: float for SB_FP32C, double otherwise), ordered on
  * the batch stream and synchronous with it when dst_is_device == 0.

@@ -63,6 +63,9 @@ SIGNATURES = [
     ("string_batch_output_ptr", C.c_int, [_P, C.c_int, C.POINTER(_P)]),
     ("string_batch_gather_output", C.c_int, [_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_int64,
                                              _P, C.c_int]),
+    ("string_batch_graph_capture", C.c_int, [_P, C.c_int64, C.c_int]),
+    ("string_batch_graph_launch", C.c_int, [_P]),
+    ("string_batch_autotune", C.c_int, [_P, C.c_int64, C.POINTER(C.c_int32)]),
     ("string_batch_read_energy", C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("string_batch_info", C.c_int, [_P, C.c_int, C.POINTER(SbStringInfo)]),
     ("string_batch_set_monitor", C.c_int, [_P, C.c_int, C.c_double]),
@@ -198,6 +201,17 @@ class StringBatch:
         self._check(self.lib.string_batch_read_output(self.h, idx, offset, count,
                                                       out.ctypes.data_as(C.c_void_p), 0), "read_output")
         return out
+
+    def graph_capture(self, steps_per_launch: int, n_launches: int):
+        self._check(self.lib.string_batch_graph_capture(self.h, steps_per_launch, n_launches), "graph_capture")
+
+    def graph_launch(self):
+        self._check(self.lib.string_batch_graph_launch(self.h), "graph_launch")
+
+    def autotune(self, probe_steps: int = 480) -> list:
+        chosen = (C.c_int32 * 6)()
+        self._check(self.lib.string_batch_autotune(self.h, probe_steps, chosen), "autotune")
+        return list(chosen)
 
     def gather_output(self, slots, offsets, count: int) -> np.ndarray:
         """Rows of `count` samples: row i holds samples offsets[i].. of slots[i]

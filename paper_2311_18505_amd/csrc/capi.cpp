@@ -134,7 +134,16 @@ struct sb_batch {
   void *d_gbuf = nullptr;
   size_t gbuf_bytes = 0;
   std::vector<int32_t> h_work;
+  std::vector<int32_t> h_plain;   // plain path: slots in launch order
   bool work_dirty = true;
+  int64_t epoch = 0;               // bumped whenever slots change (invalidates a captured graph)
+  int blocks_per_cu[kNumClasses] = {};   // persistent blocks per CU per class (0: occupancy limit)
+  // captured launches (string_batch_graph_capture)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int64_t graph_steps = 0, graph_epoch = -1;
+  std::vector<int> graph_members;
   int mon_period = 480;
   double mon_tol = 1e-9;
   double tol = 1e-13;
@@ -154,6 +163,7 @@ static int hip_fail(sb_batch *b, hipError_t e, const char *where) {
 }
 
 static size_t work_capacity(int capacity);
+static void graph_release(sb_batch *b);
 
 extern "C" int string_batch_create(int capacity, int precision, void *hip_stream, sb_batch **out) {
   g_create_error.clear();
@@ -213,6 +223,7 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming);
   }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     g_create_error = std::string("stream/event creation: ") + hipGetErrorString(e);
     (void)hipGetLastError();
@@ -234,6 +245,11 @@ extern "C" int string_batch_destroy(sb_batch *b) {
     if (b->ev_join[c]) (void)hipEventDestroy(b->ev_join[c]);
   }
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  graph_release(b);
+  if (b->cap_stream) {
+    (void)hipStreamSynchronize(b->cap_stream);
+    (void)hipStreamDestroy(b->cap_stream);
+  }
   b->arena.clear();
   hipFree(b->d_desc);
   hipFree(b->d_status);
@@ -321,6 +337,7 @@ extern "C" int string_batch_set_params(sb_batch *b, int first, int count, const 
     s.samples_host = 0;
   }
   b->work_dirty = true;
+  ++b->epoch;
   // mark the slots idle on the device until they are excited
   std::vector<Status> zs(count);
   for (auto &z : zs) {
@@ -449,14 +466,20 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
   if (err == hipSuccess) err = hipStreamSynchronize(b->stream);
   if (err != hipSuccess) return hip_fail(b, err, "excite upload");
   b->work_dirty = true;
+  ++b->epoch;
   return SB_OK;
 }
 
-static int do_step(sb_batch *b, int first, int count, int64_t n_steps) {
-  if (n_steps < 0) return fail(b, SB_EINVAL, "n_steps < 0");
-  if (!range_ok(b, first, count)) return fail(b, SB_EINVAL, "bad slot range");
-  if (n_steps == 0) return SB_OK;
-  // active slots per size class, longest remaining work first
+// Work lists of one launch: active slots per size class, packed into
+// wavefront tasks of 64/G strings with similar remaining work side by side (a
+// wavefront runs as long as its longest string), longest tasks first; the
+// device copy is refreshed when it changes.
+struct WorkPlan {
+  std::vector<int> off = std::vector<int>(kNumClasses + 1, 0);
+  std::vector<int> members;   // slots stepped
+};
+
+static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPlan &wp) {
   std::vector<std::vector<std::pair<double, int>>> cls(kNumClasses);
   bool any = false;
   for (int i = first; i < first + count; ++i) {
@@ -470,77 +493,204 @@ static int do_step(sb_batch *b, int first, int count, int64_t n_steps) {
     cls[c].push_back({cost, i});
   }
   if (!any) return fail(b, SB_ESTATE, "no excited slot");
-  // Tasks of 64/G strings per class, strings of similar remaining work side by
-  // side (a wavefront runs as long as its longest string); tasks are queued
-  // longest first.
   std::vector<int32_t> work;
-  std::vector<int> off(kNumClasses + 1, 0);
   for (int c = 0; c < kNumClasses; ++c) {
     std::stable_sort(cls[c].begin(), cls[c].end(), [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
       return x.first > y.first;
     });
-    off[c] = (int)work.size();
+    wp.off[c] = (int)work.size();
     const int groups = b->precision == SB_FP64_PLAIN ? 1 : kWave / kClassLanes[c];
     for (size_t i = 0; i < cls[c].size(); i += groups)
       for (int g = 0; g < groups; ++g) work.push_back(i + g < cls[c].size() ? cls[c][i + g].second : -1);
+    for (auto &w : cls[c]) wp.members.push_back(w.second);
   }
-  off[kNumClasses] = (int)work.size();
-  if (work.empty()) return SB_OK;
-  hipError_t e = hipSuccess;
+  wp.off[kNumClasses] = (int)work.size();
+  if (work.empty() || b->precision == SB_FP64_PLAIN) {
+    b->h_plain = std::move(work);
+    return SB_OK;
+  }
+  if (work != b->h_work || b->work_dirty) {
+    // the previous upload may still be read by queued launches: order the
+    // host buffer's reuse after them
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess && b->cap_stream) e = hipStreamSynchronize(b->cap_stream);
+    if (e != hipSuccess) return hip_fail(b, e, "sync");
+    b->h_work = work;
+    e = hipMemcpyAsync(b->d_work, b->h_work.data(), sizeof(int32_t) * work.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "work upload");
+    b->work_dirty = false;
+  }
+  return SB_OK;
+}
+
+// One launch of every size class on `st`: counters cleared by a kernel (no
+// memset nodes under capture), the classes forked onto their own streams and
+// joined back.  Issues no synchronisation and no copy, so it can be captured.
+static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t n_steps,
+                        unsigned class_mask = ~0u) {
+  hipError_t e = launch_zero(b->d_counters, kNumClasses, st);
+  if (e == hipSuccess) e = hipEventRecord(b->ev_fork, st);
+  if (e != hipSuccess) return hip_fail(b, e, "fork");
+  // largest strings first: their classes hold the longest per-step latency
+  for (int c = kNumClasses - 1; c >= 0; --c) {
+    const int nw = (wp.off[c + 1] - wp.off[c]) / (kWave / kClassLanes[c]);   // tasks of this class
+    if (nw == 0 || !(class_mask & (1u << c))) continue;
+    LaunchArgs a;
+    a.desc = b->d_desc;
+    a.status = b->d_status;
+    a.work = b->d_work + wp.off[c];
+    a.n_work = nw;
+    a.counter = b->d_counters + c;
+    a.n_steps = n_steps;
+    a.mon_period = b->mon_period;
+    a.max_sweeps = b->max_sweeps;
+    a.tol = b->tol;
+    a.mon_tol = b->mon_tol;
+    a.trash_st = b->d_trash;
+    a.trash_status = b->d_trash_status;
+    const int per_cu = b->blocks_per_cu[c] > 0 ? b->blocks_per_cu[c] : std::max(1, max_blocks_per_cu(b->precision, c));
+    const int blocks = std::min(nw, b->num_cu * per_cu);
+    hipStream_t cs = b->cls_stream[c];
+    e = hipStreamWaitEvent(cs, b->ev_fork, 0);
+    if (e == hipSuccess) e = launch_step(b->precision, c, a, blocks, cs);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_join[c], cs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[c], 0);
+    if (e != hipSuccess) return hip_fail(b, e, "step launch");
+  }
+  return SB_OK;
+}
+
+static void advance_host(sb_batch *b, const std::vector<int> &members, int64_t n_steps) {
+  for (int i : members) {
+    Slot &s = b->slots[i];
+    s.samples_host = std::min<int64_t>(s.samples_host + n_steps, s.plan.desc.n_samples);
+  }
+}
+
+static int do_step(sb_batch *b, int first, int count, int64_t n_steps) {
+  if (n_steps < 0) return fail(b, SB_EINVAL, "n_steps < 0");
+  if (!range_ok(b, first, count)) return fail(b, SB_EINVAL, "bad slot range");
+  if (n_steps == 0) return SB_OK;
+  WorkPlan wp;
+  int st = build_work(b, first, count, n_steps, wp);
+  if (st) return st;
+  if (wp.members.empty()) return SB_OK;
   if (b->precision == SB_FP64_PLAIN) {
     // one string per launch, in order
-    for (int32_t i : work) {
+    for (int32_t i : b->h_plain) {
       if (i < 0) continue;
-      e = launch_plain(b->d_desc, b->d_status, i, n_steps, plain_lds_bytes(b->slots[i].plan.desc), b->stream);
+      hipError_t e = launch_plain(b->d_desc, b->d_status, i, n_steps, plain_lds_bytes(b->slots[i].plan.desc), b->stream);
       if (e != hipSuccess) return hip_fail(b, e, "plain launch");
     }
   } else {
-    if (work != b->h_work || b->work_dirty) {
-      // the previous upload may still be read by queued launches: order the
-      // host buffer's reuse after them
-      e = hipStreamSynchronize(b->stream);
-      if (e != hipSuccess) return hip_fail(b, e, "sync");
-      b->h_work = work;
-      e = hipMemcpyAsync(b->d_work, b->h_work.data(), sizeof(int32_t) * work.size(), hipMemcpyHostToDevice, b->stream);
-      if (e != hipSuccess) return hip_fail(b, e, "work upload");
-      b->work_dirty = false;
-    }
-    e = launch_zero(b->d_counters, kNumClasses, b->stream);
-    if (e != hipSuccess) return hip_fail(b, e, "counter reset");
-    e = hipEventRecord(b->ev_fork, b->stream);
-    if (e != hipSuccess) return hip_fail(b, e, "fork event");
-    // largest strings first: their classes hold the longest per-step latency
-    for (int c = kNumClasses - 1; c >= 0; --c) {
-      const int nw = (off[c + 1] - off[c]) / (kWave / kClassLanes[c]);   // tasks of this class
-      if (nw == 0) continue;
-      LaunchArgs a;
-      a.desc = b->d_desc;
-      a.status = b->d_status;
-      a.work = b->d_work + off[c];
-      a.n_work = nw;
-      a.counter = b->d_counters + c;
-      a.n_steps = n_steps;
-      a.mon_period = b->mon_period;
-      a.max_sweeps = b->max_sweeps;
-      a.tol = b->tol;
-      a.mon_tol = b->mon_tol;
-      a.trash_st = b->d_trash;
-      a.trash_status = b->d_trash_status;
-      const int per_cu = std::max(1, max_blocks_per_cu(b->precision, c));
-      const int blocks = std::min(nw, b->num_cu * per_cu);
-      hipStream_t cs = b->cls_stream[c];
-      e = hipStreamWaitEvent(cs, b->ev_fork, 0);
-      if (e == hipSuccess) e = launch_step(b->precision, c, a, blocks, cs);
-      if (e == hipSuccess) e = hipEventRecord(b->ev_join[c], cs);
-      if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_join[c], 0);
-      if (e != hipSuccess) return hip_fail(b, e, "step launch");
-    }
+    st = enqueue_step(b, b->stream, wp, n_steps);
+    if (st) return st;
   }
-  for (int c = 0; c < kNumClasses; ++c)
-    for (auto &w : cls[c]) {
-      Slot &s = b->slots[w.second];
-      s.samples_host = std::min<int64_t>(s.samples_host + n_steps, s.plan.desc.n_samples);
+  advance_host(b, wp.members, n_steps);
+  return SB_OK;
+}
+
+static void graph_release(sb_batch *b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->graph_members.clear();
+}
+
+extern "C" int string_batch_graph_capture(sb_batch *b, int64_t steps_per_launch, int n_launches) {
+  if (!b) return SB_EINVAL;
+  if (b->precision == SB_FP64_PLAIN) return fail(b, SB_EINVAL, "the plain path launches one string at a time");
+  if (steps_per_launch < 1 || n_launches < 1 || n_launches > 100000) return fail(b, SB_EINVAL, "bad launch shape");
+  WorkPlan wp;
+  int st = build_work(b, 0, b->capacity, steps_per_launch * n_launches, wp);
+  if (st) return st;
+  if (wp.members.empty()) return fail(b, SB_ESTATE, "no slot left to step");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(b, e, "sync");
+  graph_release(b);
+  e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return hip_fail(b, e, "begin capture");
+  for (int l = 0; l < n_launches && st == SB_OK; ++l) st = enqueue_step(b, b->cap_stream, wp, steps_per_launch);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->cap_stream, &g);
+  if (st != SB_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != SB_OK ? st : hip_fail(b, e, "end capture");
+  }
+  e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    b->gexec = nullptr;
+    return hip_fail(b, e, "instantiate");
+  }
+  b->graph = g;
+  b->graph_steps = steps_per_launch * n_launches;
+  b->graph_members = wp.members;
+  b->graph_epoch = b->epoch;
+  return SB_OK;
+}
+
+// Autotuner: for every size class present, times a short probe of that class
+// alone at each candidate number of persistent blocks per CU (1, 2, 4 and the
+// occupancy limit) and keeps the fastest.  Probes step the excited state, so
+// every slot is rewound to its excitation before and after.
+extern "C" int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *chosen) {
+  if (!b) return SB_EINVAL;
+  if (b->precision == SB_FP64_PLAIN) return fail(b, SB_EINVAL, "the plain path has nothing to tune");
+  if (probe_steps < 1) return fail(b, SB_EINVAL, "probe_steps < 1");
+  int st = string_batch_rewind(b, 0, b->capacity);
+  if (st) return st;
+  WorkPlan wp;
+  st = build_work(b, 0, b->capacity, probe_steps, wp);
+  if (st) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int c = 0; c < kNumClasses && e == hipSuccess && st == SB_OK; ++c) {
+    const int nw = (wp.off[c + 1] - wp.off[c]) / (kWave / kClassLanes[c]);
+    if (chosen) chosen[c] = 0;
+    if (nw == 0) continue;
+    const int occ = std::max(1, max_blocks_per_cu(b->precision, c));
+    int best = occ;
+    float best_ms = 1e30f;
+    for (int cand : {1, 2, 4, occ}) {
+      if (cand > occ) continue;
+      b->blocks_per_cu[c] = cand;
+      st = string_batch_rewind(b, 0, b->capacity);
+      if (st) break;
+      e = hipEventRecord(e0, b->stream);
+      if (e != hipSuccess) break;
+      st = enqueue_step(b, b->stream, wp, probe_steps, 1u << c);
+      if (st) break;
+      e = hipEventRecord(e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = cand;
+      }
     }
+    b->blocks_per_cu[c] = best;
+    if (chosen) chosen[c] = best;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) return st;
+  if (e != hipSuccess) return hip_fail(b, e, "autotune");
+  return string_batch_rewind(b, 0, b->capacity);
+}
+
+extern "C" int string_batch_graph_launch(sb_batch *b) {
+  if (!b) return SB_EINVAL;
+  if (!b->gexec) return fail(b, SB_ESTATE, "no captured graph");
+  if (b->graph_epoch != b->epoch) return fail(b, SB_ESTATE, "slots changed since the capture");
+  hipError_t e = hipGraphLaunch(b->gexec, b->stream);
+  if (e != hipSuccess) return hip_fail(b, e, "graph launch");
+  advance_host(b, b->graph_members, b->graph_steps);
   return SB_OK;
 }
 

@@ -143,9 +143,13 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
     err = "string exceeds the largest size class";
     return SB_EBUDGET;
   }
+  // every string of a class is laid out with the class's MM slots per lane
+  // (the kernel's loops run over MM slots whatever the string's length, so
+  // spreading a shorter string over fewer slots would save nothing); nodes
+  // past the string's end hold zeros
   const int G = kClassLanes[D.cls];
-  D.mt = (Nt + G - 1) / G;
-  D.ml = Nl > 0 ? (Nl + G - 1) / G : 0;
+  D.mt = kClassSlots[D.cls];
+  D.ml = kClassSlots[D.cls];
   D.mon_check = p.mod_type == 0 ? 1 : 0;
   D.n_samples = p.n_samples;
   const double k = g.k, th = g.theta;

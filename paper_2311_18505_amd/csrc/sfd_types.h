@@ -27,7 +27,7 @@ enum : int32_t {
 struct Desc {
   int32_t Nt, Nl;             // intervals of the transverse / longitudinal grids (Nl = 0: no zeta)
   int32_t nt, nl;             // unknowns: Nt-1, Nl-1 (0)
-  int32_t mt, ml;             // points per lane: ceil(Nt/G), ceil(Nl/G)
+  int32_t mt, ml;             // slots per lane of each grid (the class's MM)
   int32_t cls;                // size class index
   int32_t mon_check;          // 1: energy must not grow (unforced, constant f0)
   int64_t n_samples;          // samples to produce

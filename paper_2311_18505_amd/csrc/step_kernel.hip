@@ -204,18 +204,19 @@ __device__ __forceinline__ T last_of(const T (&x)[MM], int m) {
 }
 
 // Point evaluation w0 x(n0) + w1 x(n1) (FP64) of a lane-blocked array of the
-// calling lane's group (m slots per lane, nodes 1-based, 0 = absent).
+// calling lane's group (MM slots per lane, nodes 1-based, 0 = absent).
 template <int G, typename T, int MM>
-__device__ __forceinline__ double point_eval(const T (&x)[MM], const T (&c)[MM], int m, int n0, double w0, int n1,
+__device__ __forceinline__ double point_eval(const T (&x)[MM], const T (&c)[MM], int n0, double w0, int n1,
                                              double w1) {
+  constexpr int m = MM;
   const int li = lane_id() & (G - 1), base = lane_id() & ~(G - 1);
   double part = 0.0;
 #pragma unroll
   for (int r = 0; r < MM; ++r) {
     const int i = li * m + r + 1;
     const double v = (double)x[r] - (double)c[r];
-    part += (r < m && i == n0) ? w0 * v : 0.0;
-    part += (r < m && i == n1) ? w1 * v : 0.0;
+    part += (i == n0) ? w0 * v : 0.0;
+    part += (i == n1) ? w1 * v : 0.0;
   }
   const int l0 = n0 ? (n0 - 1) / m : 0, l1 = n1 ? (n1 - 1) / m : 0;
   const double y0 = __shfl(part, base + l0, kWave);
@@ -228,22 +229,23 @@ __device__ __forceinline__ double point_eval(const T (&x)[MM], const T (&c)[MM],
 // ---------------------------------------------------------------------------
 
 // kT (1 + rho S-)(1 + rho S+) x = b on nodes 1..n of each group's string
-// (m slots per lane; this lane's first `valid` slots hold nodes <= n):
+// (MM slots per lane; mask[r] is 1 on this lane's nodes <= n, else 0):
 //   forward:  z_i = b_i / kT - rho z_{i-1},  z_0 = sum_i wb_i b_i  (odd extension)
 //   backward: x_i = z_i - rho x_{i+1},       x_N = 0
+// Lane-local recurrences, then group scans carry the lane boundary values.
 template <int G, typename T, int MM>
-__device__ __forceinline__ void toeplitz_solve(T (&x)[MM], const T (&b)[MM], const T (&wb)[MM], int m, int valid,
+__device__ __forceinline__ void toeplitz_solve(T (&x)[MM], const T (&b)[MM], const T (&wb)[MM], const T (&mask)[MM],
                                                T rho, T itk, const ScanPow<T> &sp) {
   T part = T(0);
 #pragma unroll
-  for (int r = 0; r < MM; ++r) part = (r < m) ? fma(wb[r], b[r], part) : part;
+  for (int r = 0; r < MM; ++r) part = fma(wb[r], b[r], part);
   const T z0 = grp_reduce<G, false>(part);
   T z[MM];
   T prev = T(0);
 #pragma unroll
   for (int r = 0; r < MM; ++r) {
     z[r] = fma(-rho, prev, b[r] * itk);
-    prev = (r < m) ? z[r] : prev;
+    prev = z[r];
   }
   const bool first = (lane_id() & (G - 1)) == 0;
   const T e = first ? fma(sp.g1, z0, prev) : prev;
@@ -253,22 +255,22 @@ __device__ __forceinline__ void toeplitz_solve(T (&x)[MM], const T (&b)[MM], con
   T pw = -rho;
 #pragma unroll
   for (int r = 0; r < MM; ++r) {
-    z[r] = (r < valid) ? fma(pw, C, z[r]) : T(0);
+    z[r] = fma(pw, C, z[r]) * mask[r];
     pw = pw * (-rho);
   }
   prev = T(0);
 #pragma unroll
   for (int r = MM - 1; r >= 0; --r) {
     x[r] = fma(-rho, prev, z[r]);
-    prev = (r < m) ? x[r] : prev;
+    prev = x[r];
   }
   const T X = grp_scan_bwd<G>(prev, sp);
   const T Dn = grp_next<G>(X);
   pw = T(1);
 #pragma unroll
   for (int r = MM - 1; r >= 0; --r) {
-    pw = (r < m) ? pw * (-rho) : pw;
-    x[r] = (r < valid) ? fma(pw, Dn, x[r]) : T(0);
+    pw = pw * (-rho);
+    x[r] = fma(pw, Dn, x[r]) * mask[r];
   }
 }
 
@@ -322,20 +324,73 @@ __device__ __forceinline__ double to_d(T hi, T c) {
   return (double)hi - (double)c;
 }
 
-// I_(t)->(l) gather for one longitudinal half point: the sums of the two
-// contribution arrays over its ranges [sa, sa+na) and [sb, sb+nb) (packed as
-// start | count << 16).  Uniform trip count gmax, predicated per lane.
+// LDS layout per group: the l-half slopes p (for I_(l)->(t)) and the two
+// t-half contribution arrays of I_(t)->(l), each MM*G values plus one trash
+// entry per lane (writes a lane must not make go there, without bank
+// conflicts).
+template <int G, int MM>
+struct Lds {
+  static constexpr int kArr = MM * G + G;
+  static constexpr int kTrash = MM * G;   // + lane in group
+  static constexpr int kStride = 3 * kArr;
+};
+
+// I_(t)->(l) up to the factor h_t/h_l at one l-half point: the sums of the
+// two contribution arrays over its t-half ranges [sa, sa+na) and [sb, sb+nb)
+// (packed as start | count << 16), with KG >= na, nb: every load is issued
+// before the first is used.
+template <int KG, typename T>
+__device__ __forceinline__ T range_gather(const T *sA, const T *sB, uint32_t ra, uint32_t rb) {
+  const int sa = (int)(ra & 0xffffu), na = (int)(ra >> 16);
+  const int sb = (int)(rb & 0xffffu), nb = (int)(rb >> 16);
+  T va[KG], vb[KG];
+#pragma unroll
+  for (int c = 0; c < KG; ++c) {
+    va[c] = sA[c < na ? sa + c : 0];
+    vb[c] = sB[c < nb ? sb + c : 0];
+  }
+  T acc = T(0);
+#pragma unroll
+  for (int c = 0; c < KG; ++c) acc += (c < na ? va[c] : T(0)) + (c < nb ? vb[c] : T(0));
+  return acc;
+}
+
+// The same with a run-time bound (ranges longer than the unrolled cases).
 template <typename T>
-__device__ __forceinline__ T range_gather(const T *sA, const T *sB, uint32_t ra, uint32_t rb, int gmax) {
+__device__ __forceinline__ T range_gather_n(const T *sA, const T *sB, uint32_t ra, uint32_t rb, int kg) {
   const int sa = (int)(ra & 0xffffu), na = (int)(ra >> 16);
   const int sb = (int)(rb & 0xffffu), nb = (int)(rb >> 16);
   T acc = T(0);
-  for (int c = 0; c < gmax; ++c) {
+  for (int c = 0; c < kg; ++c) {
     const T va = sA[c < na ? sa + c : 0];
     const T vb = sB[c < nb ? sb + c : 0];
     acc += (c < na ? va : T(0)) + (c < nb ? vb : T(0));
   }
   return acc;
+}
+
+// g[r] = I_(t)->(l) contributions at this lane's l-half points (0 past ml:
+// their ranges are empty); kg is the wave's longest range.
+template <int MM, typename T>
+__device__ __forceinline__ void gather_lt(T (&g)[MM], const T *sA, const T *sB, const uint32_t (&rga)[MM],
+                                          const uint32_t (&rgb)[MM], int kg) {
+  if (MM > 8) {
+    // the unrolled forms would hold 2 KG MM loads in flight: too many registers
+#pragma unroll
+    for (int r = 0; r < MM; ++r) g[r] = range_gather_n<T>(sA, sB, rga[r], rgb[r], kg);
+  } else if (kg <= 2) {
+#pragma unroll
+    for (int r = 0; r < MM; ++r) g[r] = range_gather<2, T>(sA, sB, rga[r], rgb[r]);
+  } else if (kg <= 4) {
+#pragma unroll
+    for (int r = 0; r < MM; ++r) g[r] = range_gather<4, T>(sA, sB, rga[r], rgb[r]);
+  } else if (kg <= 6) {
+#pragma unroll
+    for (int r = 0; r < MM; ++r) g[r] = range_gather<6, T>(sA, sB, rga[r], rgb[r]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < MM; ++r) g[r] = range_gather_n<T>(sA, sB, rga[r], rgb[r], kg);
+  }
 }
 
 // LDS scratch of the energy monitor per group: u^{n+1}, u^n, zeta^{n+1},
@@ -451,19 +506,12 @@ __device__ __forceinline__ void store_state(T *st, T *trash, const T (&u)[MM], c
   }
 }
 
-// LDS layout per group: MM*G values plus a trash slot for writes a lane must not make.
-template <int G, int MM>
-struct Lds {
-  static constexpr int kStride = MM * G + 32;
-  static constexpr int kTrash = MM * G;
-};
-
 // ---------------------------------------------------------------------------
 // One wavefront task: up to 64/G strings stepped together
 // ---------------------------------------------------------------------------
 
 template <int G, int MM, typename T, bool KAHAN>
-__device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T *sA, T *sB, double *sE) {
+__device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, double *sE) {
   const int lane = lane_id();
   const int li = lane & (G - 1), gi = lane / G;
   const int sidx = a.work[task * (kWave / G) + gi];
@@ -474,7 +522,8 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
   Status *S = a.status + s;
 
   // ---- per-group constants (lane registers) ----
-  const int Nt = D.Nt, Nl = D.Nl, nt = D.nt, nl = D.nl, mt = D.mt, ml = D.ml;
+  const int nt = D.nt, nl = D.nl;
+  constexpr int mt = MM, ml = MM;   // every string is laid out with MM slots per lane
   const int64_t n_samples = D.n_samples;
   const int64_t done = S->samples_done;
   const int64_t left = n_samples - done;
@@ -488,13 +537,6 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
     wsteps = other > wsteps ? other : wsteps;
   }
   wsteps = uni(wsteps);
-  int gmax = D.gmax;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int x = __shfl_xor(gmax, o, kWave);
-    gmax = x > gmax ? x : gmax;
-  }
-  gmax = __builtin_amdgcn_readfirstlane(gmax);
 
   const bool any_mod = __ballot(D.mod_type != 0) != 0;
   const int hn0 = D.hn0, hn1 = D.hn1, on0 = D.on0, on1 = D.on1;
@@ -502,6 +544,14 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
   const double omega_pow = D.omega_pow, alpha_H = D.alpha_H, Mr = D.Mr, IHs = D.IHs;
   const bool ham = D.ham_on != 0;
   const bool any_ham = __ballot(ham) != 0;
+  const bool any_l = __ballot(D.nl > 0) != 0;
+  int gmax = D.gmax;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int x = __shfl_xor(gmax, o, kWave);
+    gmax = x > gmax ? x : gmax;
+  }
+  gmax = __builtin_amdgcn_readfirstlane(gmax);
   const double g2k2_0 = D.g2k2_0, a2m1_4 = D.a2m1_4, a2d = D.a2, Ntdd = D.Ntd, kk = D.k * D.k;
   const int mon_check = D.mon_check;
 
@@ -534,16 +584,20 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
   }
   const T *smv = tf + (2 * mt + ml) * G;   // Sherman-Morrison vector T_u0^{-1} J_H
 
+  // Nodes past the string's end hold zero state, which the solves keep
+  // (node masks); slopes, couplings and LDS contributions there vanish by
+  // themselves, so no other predicate is needed.
   const int tb = li * mt, lb = li * ml;
-  const int vt_node = max(0, min(mt, nt - tb));   // slots with nodes 1..nt
-  const int vt_half = max(0, min(mt, Nt - tb));   // slots with half points 1..Nt
-  const int vl_node = max(0, min(ml, nl - lb));
-  const int vl_half = max(0, min(ml, Nl - lb));
-  const int mlw = ml > 0 ? ml : 1;                // slot count used for strings without zeta
+  T mask_t[MM], mask_l[MM];
+#pragma unroll
+  for (int r = 0; r < MM; ++r) {
+    mask_t[r] = (tb + r + 1 <= nt) ? T(1) : T(0);
+    mask_l[r] = (lb + r + 1 <= nl) ? T(1) : T(0);
+  }
 
   const T rho_t = (T)D.rho_t, itk_t = (T)D.itk_t, rho_l = (T)D.rho_l, itk_l = (T)D.itk_l;
   const ScanPow<T> spt = scan_pow<T>(ipow<T>(-rho_t, mt));
-  const ScanPow<T> spl = scan_pow<T>(ipow<T>(-rho_l, mlw));
+  const ScanPow<T> spl = scan_pow<T>(ipow<T>(-rho_l, ml));
   const T Ntd = (T)D.Ntd, Nld = (T)D.Nld;
   const T cS = (T)D.cS, s0t2 = (T)(2.0 * D.s0k_t), s1t2 = (T)(2.0 * D.s1k_t);
   const T s0l2 = (T)(2.0 * D.s0k_l), s1l2 = (T)(2.0 * D.s1k_l);
@@ -569,7 +623,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
   int mon_ctr = a.mon_period > 0 ? (int)(done % a.mon_period) : 1;
 
   using L = Lds<G, MM>;
-  T *gP = sP + gi * L::kStride, *gA = sA + gi * L::kStride, *gB = sB + gi * L::kStride;
+  T *gP = sS + gi * L::kStride, *gA = gP + L::kArr, *gB = gA + L::kArr;
   double *gE = sE + gi * EnergyLds<G, MM>::kStride;
 
   for (int64_t it = 0; it < wsteps; ++it) {
@@ -589,33 +643,32 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
     T q[MM], p[MM];
     {
       const T ul = grp_prev<G>(last_of<T, MM>(u, mt)), cl = grp_prev<G>(last_of<T, MM>(cu, mt));
-      const T zl = grp_prev<G>(last_of<T, MM>(z, mlw)), czl = grp_prev<G>(last_of<T, MM>(cz, mlw));
+      const T zl = grp_prev<G>(last_of<T, MM>(z, ml)), czl = grp_prev<G>(last_of<T, MM>(cz, ml));
 #pragma unroll
       for (int r = 0; r < MM; ++r) {
         const T um = r == 0 ? ul : u[r > 0 ? r - 1 : 0];
         const T cm = r == 0 ? cl : cu[r > 0 ? r - 1 : 0];
-        q[r] = (r < vt_half) ? ((u[r] - um) - (cu[r] - cm)) * Ntd : T(0);
+        q[r] = ((u[r] - um) - (cu[r] - cm)) * Ntd;
         const T zm = r == 0 ? zl : z[r > 0 ? r - 1 : 0];
         const T czm = r == 0 ? czl : cz[r > 0 ? r - 1 : 0];
-        p[r] = (r < vl_half) ? ((z[r] - zm) - (cz[r] - czm)) * Nld : T(0);
+        p[r] = ((z[r] - zm) - (cz[r] - czm)) * Nld;
       }
     }
 
     // ---- p~ = I_(l)->(t) p, and the transposed contributions of q^2 ----
-    T f[MM];
+    T f[MM], q2[MM];
 #pragma unroll
-    for (int r = 0; r < MM; ++r) gP[r < ml ? lb + r : L::kTrash] = p[r];
+    for (int r = 0; r < MM; ++r) gP[lb + r] = p[r];
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < MM; ++r) {
       const int ja = (int)(jab[r] & 0xffffu), jb = (int)(jab[r] >> 16);
       const T w = wi[r];
-      const T pt = (nl > 0) ? (T(1) - w) * gP[ja - 1] + w * gP[jb - 1] : T(0);
-      const T q2 = q[r] * q[r];
-      f[r] = q[r] * (q2 + T(2) * pt);
-      const int at = r < mt ? tb + r : L::kTrash;
-      gA[at] = (T(1) - w) * q2;
-      gB[at] = w * q2;
+      const T pt = (T(1) - w) * gP[ja - 1] + w * gP[jb - 1];
+      q2[r] = q[r] * q[r];
+      f[r] = q[r] * (q2[r] + T(2) * pt);
+      gA[tb + r] = (T(1) - w) * q2[r];
+      gB[tb + r] = w * q2[r];
     }
     __syncthreads();
 
@@ -627,7 +680,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
 #pragma unroll
       for (int r = 0; r < MM; ++r) {
         const T qn = (r + 1 < MM && r + 1 < mt) ? q[r + 1 < MM ? r + 1 : r] : qr;
-        c[r] = (r < vt_node) ? (qn - q[r]) * Ntd : T(0);
+        c[r] = (qn - q[r]) * Ntd * mask_t[r];
       }
       const T cl = grp_prev<G>(last_of<T, MM>(c, mt)), cr = grp_next<G>(c[0]);
       const T fr = grp_next<G>(f[0]);
@@ -644,16 +697,17 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
         acc = fma(T(2) * phi2 * Ntd, fp - f[r], acc);
         acc = fma(-s0t2, vu[r], acc);
         acc = fma(s1t2, (vp - T(2) * vu[r]) + vm, acc);
-        ru[r] = (r < vt_node) ? acc : T(0);
+        ru[r] = acc;
       }
     }
     // ---- right-hand side, longitudinal ----
     {
       T g[MM];
+      gather_lt<MM, T>(g, gA, gB, rga, rgb, gmax);
 #pragma unroll
-      for (int r = 0; r < MM; ++r) g[r] = range_gather<T>(gA, gB, rga[r], rgb[r], gmax) * ratio;   // 0 past ml
+      for (int r = 0; r < MM; ++r) g[r] *= ratio;
       const T pr = grp_next<G>(p[0]), gr = grp_next<G>(g[0]);
-      const T vl = grp_prev<G>(last_of<T, MM>(vz, mlw)), vr = grp_next<G>(vz[0]);
+      const T vl = grp_prev<G>(last_of<T, MM>(vz, ml)), vr = grp_next<G>(vz[0]);
 #pragma unroll
       for (int r = 0; r < MM; ++r) {
         const bool nx = r + 1 < MM && r + 1 < ml;
@@ -665,14 +719,14 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
         acc = fma(T(2) * phi2 * Nld, gn - g[r], acc);
         acc = fma(-s0l2, vz[r], acc);
         acc = fma(s1l2, (vp - T(2) * vz[r]) + vm, acc);
-        rz[r] = (r < vl_node) ? acc : T(0);
+        rz[r] = acc;
       }
     }
 
     // ---- hammer: contact coefficient at time n, right-hand side 2 beta J eta^n ----
     double eta_n = 0.0, cH = 0.0, beta = 0.0;
     if (any_ham) {
-      const double Iu = point_eval<G, T, MM>(u, cu, mt, hn0, hw0, hn1, hw1);
+      const double Iu = point_eval<G, T, MM>(u, cu, hn0, hw0, hn1, hw1);
       eta_n = ham ? uH_n - Iu : 0.0;
       const bool contact = eta_n > 0.0;
       if (__ballot(contact) != 0) {
@@ -685,8 +739,8 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
 #pragma unroll
       for (int r = 0; r < MM; ++r) {
         const int i = tb + r + 1;
-        ru[r] += (r < mt && i == hn0) ? add0 : T(0);
-        ru[r] += (r < mt && i == hn1) ? add1 : T(0);
+        ru[r] += (i == hn0) ? add0 : T(0);
+        ru[r] += (i == hn1) ? add1 : T(0);
       }
     }
     const bool sm_on = beta != 0.0;
@@ -703,7 +757,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
     }
     if (any_sm) {
 #pragma unroll
-      for (int r = 0; r < MM; ++r) smr[r] = ld_if<T>(smv, r * G + li, r < mt && sm_on);
+      for (int r = 0; r < MM; ++r) smr[r] = ld_if<T>(smv, r * G + li, sm_on);
     }
     const T smfac = (T)(beta / (1.0 + beta * IHs));
     bool conv = false;       // this group's iterates are final
@@ -717,11 +771,11 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
         for (int r = 0; r < MM; ++r) bu[r] = ru[r];
       } else {
         const T al = grp_prev<G>(last_of<T, MM>(au, mt));
-        const T zl = grp_prev<G>(last_of<T, MM>(az, mlw));
+        const T zl = grp_prev<G>(last_of<T, MM>(az, ml));
 #pragma unroll
         for (int r = 0; r < MM; ++r) {
           const T zm = r == 0 ? zl : az[r > 0 ? r - 1 : 0];
-          gP[r < ml ? lb + r : L::kTrash] = (r < vl_half) ? (az[r] - zm) * Nld : T(0);
+          gP[lb + r] = (az[r] - zm) * Nld;
         }
         __syncthreads();
         T e[MM];
@@ -731,69 +785,82 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
           const T d = (au[r] - am) * Ntd;
           const int ja = (int)(jab[r] & 0xffffu), jb = (int)(jab[r] >> 16);
           const T w = wi[r];
-          const T idz = (nl > 0) ? (T(1) - w) * gP[ja - 1] + w * gP[jb - 1] : T(0);
-          e[r] = (r < vt_half) ? q[r] * fma(q[r], d, idz) : T(0);
+          const T idz = (T(1) - w) * gP[ja - 1] + w * gP[jb - 1];
+          e[r] = q[r] * fma(q[r], d, idz);
         }
         __syncthreads();
         const T er = grp_next<G>(e[0]);
 #pragma unroll
         for (int r = 0; r < MM; ++r) {
           const T en = (r + 1 < MM && r + 1 < mt) ? e[r + 1 < MM ? r + 1 : r] : er;
-          bu[r] = (r < vt_node) ? fma(phi2 * Ntd, en - e[r], ru[r]) : T(0);
+          bu[r] = fma(phi2 * Ntd, en - e[r], ru[r]);
         }
       }
       T nu[MM];
-      toeplitz_solve<G, T, MM>(nu, bu, wbu, mt, vt_node, rho_t, itk_t, spt);
+      toeplitz_solve<G, T, MM>(nu, bu, wbu, mask_t, rho_t, itk_t, spt);
       if (any_sm) {
         // Sherman-Morrison for the rank-one hammer term beta J I
-        const T Iy = (T)point_eval<G, T, MM>(nu, zero, mt, hn0, hw0, hn1, hw1);
+        const T Iy = (T)point_eval<G, T, MM>(nu, zero, hn0, hw0, hn1, hw1);
         const T fac = smfac * Iy;
 #pragma unroll
-        for (int r = 0; r < MM; ++r) nu[r] = (r < mt) ? fma(-fac, smr[r], nu[r]) : nu[r];
+        for (int r = 0; r < MM; ++r) nu[r] = fma(-fac, smr[r], nu[r]);
       }
       // longitudinal right-hand side: r_z + phi^2 D_x+ I_(t)->(l) (q D_x- a_u)
+      T gg[MM];
       {
         const T al = grp_prev<G>(last_of<T, MM>(nu, mt));
 #pragma unroll
         for (int r = 0; r < MM; ++r) {
           const T am = r == 0 ? al : nu[r > 0 ? r - 1 : 0];
-          const T fq = (r < vt_half) ? q[r] * ((nu[r] - am) * Ntd) : T(0);
+          const T fq = q[r] * ((nu[r] - am) * Ntd);
           const T w = wi[r];
-          const int at = r < mt ? tb + r : L::kTrash;
-          gA[at] = (T(1) - w) * fq;
-          gB[at] = w * fq;
+          gA[tb + r] = (T(1) - w) * fq;
+          gB[tb + r] = w * fq;
         }
-      }
-      __syncthreads();
-      T gg[MM];
+        __syncthreads();
+        gather_lt<MM, T>(gg, gA, gB, rga, rgb, gmax);
+        __syncthreads();
 #pragma unroll
-      for (int r = 0; r < MM; ++r) gg[r] = range_gather<T>(gA, gB, rga[r], rgb[r], gmax) * ratio;   // 0 past ml
-      __syncthreads();
+        for (int r = 0; r < MM; ++r) gg[r] *= ratio;
+      }
       const T gr = grp_next<G>(gg[0]);
       T bz[MM];
 #pragma unroll
       for (int r = 0; r < MM; ++r) {
         const T gn = (r + 1 < MM && r + 1 < ml) ? gg[r + 1 < MM ? r + 1 : r] : gr;
-        bz[r] = (r < vl_node) ? fma(phi2 * Nld, gn - gg[r], rz[r]) : T(0);
+        bz[r] = fma(phi2 * Nld, gn - gg[r], rz[r]);
       }
       T nz[MM];
-      toeplitz_solve<G, T, MM>(nz, bz, wbz, mlw, vl_node, rho_l, itk_l, spl);
-      // convergence of this group; a converged group keeps its iterates
-      T delta = T(0), amax = T(0);
+      toeplitz_solve<G, T, MM>(nz, bz, wbz, mask_l, rho_l, itk_l, spl);
+      // convergence of this group (from the second sweep on; a string without
+      // a longitudinal grid is solved exactly by the first); a converged group
+      // keeps its iterates
+      bool now = nl == 0;
+      if (sweep > 0 && any_l) {
+        T delta = T(0), amax = T(0);
 #pragma unroll
-      for (int r = 0; r < MM; ++r) {
-        delta = fmax(delta, fmax(fabs(nu[r] - au[r]), fabs(nz[r] - az[r])));
-        amax = fmax(amax, fmax(fabs(nu[r]), fabs(nz[r])));
+        for (int r = 0; r < MM; ++r) {
+          delta = fmax(delta, fmax(fabs(nu[r] - au[r]), fabs(nz[r] - az[r])));
+          amax = fmax(amax, fmax(fabs(nu[r]), fabs(nz[r])));
+        }
+        delta = grp_reduce<G, true>(delta);
+        amax = grp_reduce<G, true>(amax);
+        now = now || delta <= (T)a.tol * amax;
       }
-      delta = grp_reduce<G, true>(delta);
-      amax = grp_reduce<G, true>(amax);
+      if (__ballot(conv) != 0) {
 #pragma unroll
-      for (int r = 0; r < MM; ++r) {
-        au[r] = conv ? au[r] : nu[r];
-        az[r] = conv ? az[r] : nz[r];
+        for (int r = 0; r < MM; ++r) {
+          au[r] = conv ? au[r] : nu[r];
+          az[r] = conv ? az[r] : nz[r];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < MM; ++r) {
+          au[r] = nu[r];
+          az[r] = nz[r];
+        }
       }
       sweeps = conv ? sweeps : sweep + 1;
-      const bool now = nl == 0 || (sweep > 0 && delta <= (T)a.tol * amax) || amax == T(0);
       conv = conv || now;
       if (__ballot(!conv) == 0) break;
     }
@@ -802,27 +869,37 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
     max_sw = (act && sweeps > max_sw) ? sweeps : max_sw;
 
     // ---- state update: v^{n+1/2} = v^{n-1/2} + a, w^{n+1} = w^n + v^{n+1/2} ----
+    if (__ballot(!act) == 0) {
 #pragma unroll
-    for (int r = 0; r < MM; ++r) {
-      T nu_ = u[r], nvu = vu[r], ncu = cu[r], ncvu = cvu[r];
-      kahan_add<T, KAHAN>(nvu, ncvu, au[r]);
-      update_pos<T, KAHAN>(nu_, ncu, nvu, ncvu);
-      T nz_ = z[r], nvz = vz[r], ncz = cz[r], ncvz = cvz[r];
-      kahan_add<T, KAHAN>(nvz, ncvz, az[r]);
-      update_pos<T, KAHAN>(nz_, ncz, nvz, ncvz);
-      u[r] = act ? nu_ : u[r];
-      vu[r] = act ? nvu : vu[r];
-      cu[r] = act ? ncu : cu[r];
-      cvu[r] = act ? ncvu : cvu[r];
-      z[r] = act ? nz_ : z[r];
-      vz[r] = act ? nvz : vz[r];
-      cz[r] = act ? ncz : cz[r];
-      cvz[r] = act ? ncvz : cvz[r];
+      for (int r = 0; r < MM; ++r) {
+        kahan_add<T, KAHAN>(vu[r], cvu[r], au[r]);
+        update_pos<T, KAHAN>(u[r], cu[r], vu[r], cvu[r]);
+        kahan_add<T, KAHAN>(vz[r], cvz[r], az[r]);
+        update_pos<T, KAHAN>(z[r], cz[r], vz[r], cvz[r]);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < MM; ++r) {
+        T nu_ = u[r], nvu = vu[r], ncu = cu[r], ncvu = cvu[r];
+        kahan_add<T, KAHAN>(nvu, ncvu, au[r]);
+        update_pos<T, KAHAN>(nu_, ncu, nvu, ncvu);
+        T nz_ = z[r], nvz = vz[r], ncz = cz[r], ncvz = cvz[r];
+        kahan_add<T, KAHAN>(nvz, ncvz, az[r]);
+        update_pos<T, KAHAN>(nz_, ncz, nvz, ncvz);
+        u[r] = act ? nu_ : u[r];
+        vu[r] = act ? nvu : vu[r];
+        cu[r] = act ? ncu : cu[r];
+        cvu[r] = act ? ncvu : cvu[r];
+        z[r] = act ? nz_ : z[r];
+        vz[r] = act ? nvz : vz[r];
+        cz[r] = act ? ncz : cz[r];
+        cvz[r] = act ? ncvz : cvz[r];
+      }
     }
 
     // ---- hammer lumped mass (eq. 6) ----
     if (any_ham) {
-      const double Iu1 = point_eval<G, T, MM>(u, cu, mt, hn0, hw0, hn1, hw1);
+      const double Iu1 = point_eval<G, T, MM>(u, cu, hn0, hw0, hn1, hw1);
       const double uH_np1 = (2.0 * uH_n - uH_nm1 - kk * cH * (eta_nm1 - Iu1)) / (1.0 + kk * cH);
       const bool upd = act && ham;
       uH_nm1 = upd ? uH_n : uH_nm1;
@@ -832,7 +909,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sP, T
 
     // ---- readout y^{n+1} = I(x_out) u^{n+1} into the group's ring of G samples ----
     const int64_t m = n + 1;
-    const double y = point_eval<G, T, MM>(u, cu, mt, on0, ow0, on1, ow1);
+    const double y = point_eval<G, T, MM>(u, cu, on0, ow0, on1, ow1);
     const int slot = (int)((m - first_m) & (G - 1));
     ring = (act && li == slot) ? (T)y : ring;
 
@@ -885,17 +962,17 @@ __global__ __launch_bounds__(64) void step_kernel(LaunchArgs a) {
   constexpr int kGroups = kWave / G;
   using L = Lds<G, MM>;
   // the energy monitor's scratch overlays the stepping arrays (never live together)
-  constexpr int kStepDoubles = (3 * kGroups * L::kStride * (int)sizeof(T) + 7) / 8;
+  constexpr int kStepDoubles = (kGroups * L::kStride * (int)sizeof(T) + 7) / 8;
   constexpr int kEnergyDoubles = kGroups * EnergyLds<G, MM>::kStride;
   __shared__ double lds[kStepDoubles > kEnergyDoubles ? kStepDoubles : kEnergyDoubles];
-  T *sP = (T *)lds, *sA = sP + kGroups * L::kStride, *sB = sA + kGroups * L::kStride;
+  T *sS = (T *)lds;
   double *sE = lds;
   for (;;) {
     // every lane takes part; only lane 0 adds, so the wave draws one ticket
     int w = atomicAdd(a.counter, lane_id() == 0 ? 1 : 0);
     w = __builtin_amdgcn_readfirstlane(w);
     if (w >= a.n_work) break;
-    run_task<G, MM, T, KAHAN>(a, w, sP, sA, sB, sE);
+    run_task<G, MM, T, KAHAN>(a, w, sS, sE);
   }
 }
 
