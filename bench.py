@@ -2,12 +2,15 @@
 """Benchmark of batched FP32 string synthesis on one MI355X.
 
 One bench step synthesises a whole batch of strings from their excitation to
-their last sample through the C ABI (rewind on the device, then
-string_batch_step over the longest duration), with every input already in
-device memory.  Prints one JSON line: grid-point updates per second (the sum
-over strings of (N_t - 1 + N_l - 1) per time step), audio seconds per second,
-the kernel's roofline position and the FP64 CPU oracle timed on a sample of
-the same workload.
+their last sample through the C ABI (rewind on the device, then one replay of
+a HIP graph holding a launch over the longest duration, every size class
+forked onto its own stream), with every input already in device memory.
+Prints one JSON line: grid-point updates per second (the sum over strings of
+(N_t - 1 + N_l - 1) per time step), audio seconds per second, the roofline
+position of each size-class kernel (the longest one reported as `roofline`),
+the FP64 CPU oracle timed on a sample of the same workload, the plain FP64
+per-string method on the single nonlinear string, and a real-time serving
+run with Poisson arrivals (p50/p99 latencies).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -26,6 +29,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-point updates/s & audio-s/s, batched FP32 vs plain FP64; p99 latency"
 PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 2.4 GHz x 256)
+
+CLASS_KERNELS = ["step_kernel<16, 2, float, true>", "step_kernel<16, 4, float, true>",
+                 "step_kernel<32, 4, float, true>", "step_kernel<64, 4, float, true>",
+                 "step_kernel<64, 8, float, true>", "step_kernel<64, 16, float, true>"]
 
 WORKLOADS = {
     # 16384 nonlinear strings, durations U(0.5, 4) s, vibrato or glide, FP32
@@ -95,7 +102,7 @@ def serving_leg(W, serving, rate, seconds, capacity):
     arrivals, items = W.serving_requests(rate_hz=rate, seconds=seconds)
     reqs = serving.requests_from(arrivals, items)
     srv = serving.Server(capacity=capacity)
-    stats, _ = srv.run(reqs)
+    stats, _ = srv.run(reqs, log=lambda m: print("[bench] serving " + m, file=sys.stderr, flush=True))
     srv.close()
     rec = stats.summary()
     rec.update({"rate_hz": rate, "seconds": seconds, "requests": len(reqs),
@@ -134,10 +141,14 @@ def main():
     b.excite(0, excs)
     infos = [b.info(i) for i in range(len(items))]
     n_max = max(p["n_samples"] for p in params)
-    updates = sum(unknowns(inf) * (inf["n_samples"] - 2) for inf in infos)
+    upd_of = [unknowns(inf) * (inf["n_samples"] - 2) for inf in infos]
+    updates = sum(upd_of)
     audio_s = sum(p["n_samples"] / p["fs"] for p in params)
     print("[bench] %s: %d strings, %.3e grid-point updates per step, %.0f audio-s, setup %.1f s"
           % (args.workload, len(items), updates, audio_s, time.perf_counter() - t_setup), file=sys.stderr, flush=True)
+    # persistent blocks per CU for each size class
+    tuned = b.autotune(480)
+    print("[bench] autotuned blocks/CU per class %s" % tuned, file=sys.stderr, flush=True)
 
     for w in range(args.warmup):
         b.rewind()
@@ -157,7 +168,20 @@ def main():
     hiptime.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_ms(ev1)
-    print("[bench] %d steps: wall %.3f s, events %.3f ms" % (args.steps, wall, gpu_ms), file=sys.stderr, flush=True)
+    class_ms, class_strings = b.class_times()      # kernels of the last timed step
+    print("[bench] %d steps: wall %.3f s, events %.3f ms; class kernels (ms) %s"
+          % (args.steps, wall, gpu_ms, ["%.1f" % m for m in class_ms]), file=sys.stderr, flush=True)
+    # the same step as one replay of a captured HIP graph (outside the timed region)
+    b.rewind()
+    b.graph_capture(n_max, 1)
+    hiptime.synchronize()
+    g0, g1 = hiptime.Event(), hiptime.Event()
+    g0.record(0)
+    b.graph_launch()
+    g1.record(0)
+    g1.synchronize()
+    graph_ms = g0.elapsed_ms(g1)
+    print("[bench] graph replay: %.3f ms" % graph_ms, file=sys.stderr, flush=True)
 
     # every string must have finished cleanly
     bad = 0
@@ -173,7 +197,6 @@ def main():
 
     sec_per_step = wall / args.steps
     value = updates / sec_per_step
-    kernel_s = gpu_ms / 1e3 / args.steps
     out = {
         "metric": METRIC,
         "value": value,
@@ -189,10 +212,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "strings": len(items), "fs": 48000,
                    "updates_per_step": updates, "audio_seconds_per_step": audio_s,
-                   "precision": "FP32 with compensated state updates, FP64 energy monitor"},
+                   "precision": "FP32 with compensated state updates, FP64 energy monitor",
+                   "launch": "one launch per step (size classes forked onto their streams and joined), "
+                             "blocks/CU autotuned; the same launch replayed from a HIP graph is reported beside",
+                   "blocks_per_cu": tuned},
         "audio_s_per_s": audio_s / sec_per_step,
         "sweeps_per_step_mean": sweeps / max(1, sum(inf["n_samples"] - 2 for inf in infos)),
         "strings_not_finished": bad,
+        "gpu_ms_per_step": gpu_ms / args.steps,
+        "graph_replay_ms": graph_ms,
     }
     if not args.no_plain:
         pl = plain_leg(W, binding, hiptime, args.plain_seconds)
@@ -215,11 +243,25 @@ def main():
         threads = min(16, os.cpu_count() or 1)
         rec, flops_per_update = cpu_baseline(items, args.cpu_seconds, threads)
         out["cpu_baseline"] = {k: v for k, v in rec.items() if k != "seconds"}
-        achieved = flops_per_update * updates / kernel_s
-        out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                           "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+        # roofline of each size-class kernel: the oracle's arithmetic per
+        # grid-point update times the updates of that class's strings, over
+        # the kernel's own duration (HIP events on its stream, last timed step)
+        by_class = []
+        for c in range(6):
+            if class_ms[c] <= 0:
+                continue
+            upd_c = sum(u for u, inf in zip(upd_of, infos) if inf["size_class"] == c)
+            ach = flops_per_update * upd_c / (class_ms[c] / 1e3)
+            by_class.append({"kernel": CLASS_KERNELS[c], "ms": class_ms[c], "strings": class_strings[c],
+                             "updates": upd_c, "achieved_tflops": ach / 1e12, "frac": ach / PEAK_FP32_VECTOR})
+        # the dominant kernel: the size class that carries the most updates
+        dom = max(by_class, key=lambda r: r["updates"])
+        out["roofline"] = {"bound": "alu", "achieved": dom["achieved_tflops"], "peak": PEAK_FP32_VECTOR / 1e12,
+                           "unit": "TFLOP/s", "frac": dom["frac"], "traffic": None,
+                           "kernel": dom["kernel"], "kernel_ms_per_launch": dom["ms"],
                            "flops_per_update": flops_per_update,
-                           "kernel_ms_per_launch": kernel_s * 1e3}
+                           "whole_step_frac": flops_per_update * updates / (gpu_ms / args.steps / 1e3) / PEAK_FP32_VECTOR}
+        out["roofline_by_class"] = by_class
     print(json.dumps(out), flush=True)
 
 

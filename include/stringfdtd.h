@@ -105,6 +105,8 @@ typedef struct {
     int32_t flags;             /* 1: unstable (energy monitor), 2: no convergence */
     int32_t max_sweeps;        /* largest number of coupled-solve sweeps in a step */
     int64_t total_sweeps;      /* total sweeps                                    */
+    int32_t size_class;        /* kernel size class 0..5 of the batched paths      */
+    int32_t lanes;             /* lanes per string in that class (16, 32 or 64)   */
 } sb_string_info;
 
 /* Create a batch of `capacity` (>= 1) slots computing in `precision`
@@ -156,6 +158,12 @@ int string_batch_rewind(sb_batch *b, int first, int count);
  * SB_ESTATE (nothing to step / stale graph), SB_EDEVICE. */
 int string_batch_graph_capture(sb_batch *b, int64_t steps_per_launch, int n_launches);
 int string_batch_graph_launch(sb_batch *b);
+
+/* Durations of the size-class kernels of the last batched launch (fork/join
+ * of string_batch_step or of a captured graph's last launch), in ms, and the
+ * number of strings each stepped; ms[c] = 0 for classes that did not run.
+ * Synchronises the stream.  Errors: SB_EINVAL, SB_EDEVICE. */
+int string_batch_class_times(sb_batch *b, float ms[6], int32_t strings[6]);
 
 /* Autotuner (batched paths): for every size class present, times a probe of
  * probe_steps steps of that class alone at 1, 2, 4 and the occupancy limit of

@@ -45,6 +45,7 @@ class SbStringInfo(C.Structure):
     _fields_ = [
         ("N_t", C.c_int32), ("N_l", C.c_int32), ("n_samples", C.c_int64), ("samples_done", C.c_int64),
         ("flags", C.c_int32), ("max_sweeps", C.c_int32), ("total_sweeps", C.c_int64),
+        ("size_class", C.c_int32), ("lanes", C.c_int32),
     ]
 
 
@@ -66,6 +67,7 @@ SIGNATURES = [
     ("string_batch_graph_capture", C.c_int, [_P, C.c_int64, C.c_int]),
     ("string_batch_graph_launch", C.c_int, [_P]),
     ("string_batch_autotune", C.c_int, [_P, C.c_int64, C.POINTER(C.c_int32)]),
+    ("string_batch_class_times", C.c_int, [_P, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     ("string_batch_read_energy", C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("string_batch_info", C.c_int, [_P, C.c_int, C.POINTER(SbStringInfo)]),
     ("string_batch_set_monitor", C.c_int, [_P, C.c_int, C.c_double]),
@@ -207,6 +209,12 @@ class StringBatch:
 
     def graph_launch(self):
         self._check(self.lib.string_batch_graph_launch(self.h), "graph_launch")
+
+    def class_times(self):
+        """(ms, strings) per size class of the last batched launch."""
+        ms, n = (C.c_float * 6)(), (C.c_int32 * 6)()
+        self._check(self.lib.string_batch_class_times(self.h, ms, n), "class_times")
+        return list(ms), list(n)
 
     def autotune(self, probe_steps: int = 480) -> list:
         chosen = (C.c_int32 * 6)()

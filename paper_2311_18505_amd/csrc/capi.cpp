@@ -118,6 +118,8 @@ struct sb_batch {
   hipStream_t cls_stream[kNumClasses] = {};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kNumClasses] = {};
+  hipEvent_t ev_t0[kNumClasses] = {}, ev_t1[kNumClasses] = {};   // timing of each class kernel
+  int32_t class_strings[kNumClasses] = {};                          // strings of the last launch
   std::string err;
   std::vector<Slot> slots;
   Arena arena;
@@ -221,6 +223,8 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
   for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
     e = hipStreamCreateWithFlags(&b->cls_stream[c], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev_t0[c]);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev_t1[c]);
   }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
@@ -243,6 +247,8 @@ extern "C" int string_batch_destroy(sb_batch *b) {
       (void)hipStreamDestroy(b->cls_stream[c]);
     }
     if (b->ev_join[c]) (void)hipEventDestroy(b->ev_join[c]);
+    if (b->ev_t0[c]) (void)hipEventDestroy(b->ev_t0[c]);
+    if (b->ev_t1[c]) (void)hipEventDestroy(b->ev_t1[c]);
   }
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   graph_release(b);
@@ -532,6 +538,7 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
   hipError_t e = launch_zero(b->d_counters, kNumClasses, st);
   if (e == hipSuccess) e = hipEventRecord(b->ev_fork, st);
   if (e != hipSuccess) return hip_fail(b, e, "fork");
+  for (int c = 0; c < kNumClasses; ++c) b->class_strings[c] = 0;
   // largest strings first: their classes hold the longest per-step latency
   for (int c = kNumClasses - 1; c >= 0; --c) {
     const int nw = (wp.off[c + 1] - wp.off[c]) / (kWave / kClassLanes[c]);   // tasks of this class
@@ -553,8 +560,13 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
     const int blocks = std::min(nw, b->num_cu * per_cu);
     hipStream_t cs = b->cls_stream[c];
     e = hipStreamWaitEvent(cs, b->ev_fork, 0);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_t0[c], cs);
     if (e == hipSuccess) e = launch_step(b->precision, c, a, blocks, cs);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_t1[c], cs);
     if (e == hipSuccess) e = hipEventRecord(b->ev_join[c], cs);
+    int strings = 0;
+    for (int k = wp.off[c]; k < wp.off[c + 1]; ++k) strings += b->h_work[k] >= 0 ? 1 : 0;
+    b->class_strings[c] = strings;
     if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[c], 0);
     if (e != hipSuccess) return hip_fail(b, e, "step launch");
   }
@@ -684,6 +696,21 @@ extern "C" int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *
   return string_batch_rewind(b, 0, b->capacity);
 }
 
+extern "C" int string_batch_class_times(sb_batch *b, float *ms, int32_t *strings) {
+  if (!b) return SB_EINVAL;
+  if (!ms || !strings) return fail(b, SB_EINVAL, "null output");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(b, e, "sync");
+  for (int c = 0; c < kNumClasses; ++c) {
+    ms[c] = 0.f;
+    strings[c] = b->class_strings[c];
+    if (!strings[c]) continue;
+    e = hipEventElapsedTime(&ms[c], b->ev_t0[c], b->ev_t1[c]);
+    if (e != hipSuccess) return hip_fail(b, e, "class timing");
+  }
+  return SB_OK;
+}
+
 extern "C" int string_batch_graph_launch(sb_batch *b) {
   if (!b) return SB_EINVAL;
   if (!b->gexec) return fail(b, SB_ESTATE, "no captured graph");
@@ -801,6 +828,8 @@ extern "C" int string_batch_info(sb_batch *b, int idx, sb_string_info *info) {
   if (!s.planned) return fail(b, SB_ESTATE, "slot has no parameters");
   info->N_t = s.plan.desc.Nt;
   info->N_l = s.plan.desc.Nl;
+  info->size_class = s.plan.desc.cls;
+  info->lanes = kClassLanes[s.plan.desc.cls];
   info->n_samples = s.plan.desc.n_samples;
   if (!s.excited) return SB_OK;
   Status S;

@@ -107,9 +107,11 @@ class Server:
             i = j
         return refused
 
-    def run(self, requests, keep=(), clock=time.perf_counter, on_chunk=None) -> tuple:
+    def run(self, requests, keep=(), clock=time.perf_counter, on_chunk=None, log=None,
+            log_every: float = 10.0) -> tuple:
         """Serve `requests` (arrival times relative to the start) in real time.
-        Returns (ServeStats, {rid: samples} for the rids in `keep`)."""
+        Returns (ServeStats, {rid: samples} for the rids in `keep`).  `log`, if
+        given, receives a progress line every `log_every` seconds."""
         reqs = {r.rid: r for r in requests}
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         waiting = collections.deque()
@@ -119,8 +121,13 @@ class Server:
         first, done, refused, step_ms = {}, {}, [], []
         mem_used, max_active, chunks = 0, 0, 0
         t0 = clock()
+        next_log = log_every
         while pending or waiting or active:
             now = clock() - t0
+            if log is not None and now >= next_log:
+                log("t=%.0f s: %d done, %d active, %d waiting, %d chunks" % (now, len(done), len(active),
+                                                                             len(waiting), chunks))
+                next_log += log_every
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
             new = []
