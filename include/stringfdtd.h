@@ -207,8 +207,12 @@ int string_batch_info(sb_batch *b, int idx, sb_string_info *info);
  * growth tolerance (default 1e-9 for FP64, 1e-4 for FP32C). */
 int string_batch_set_monitor(sb_batch *b, int period, double growth_tol);
 
-/* Coupled-solve controls: relative tolerance on the update of the
- * acceleration (default 1e-15 FP64, 1e-7 FP32C) and the sweep cap (default 64). */
+/* Coupled-solve controls of the batched paths (block Gauss-Seidel between
+ * the transverse and longitudinal grids, eq. (8)): a string's step has
+ * converged when no node's acceleration changed by more than tol times the
+ * string's largest acceleration after the first sweep (default 1e-13 FP64,
+ * 1e-5 FP32C: below the FP32 rounding of the accumulated state); max_sweeps caps the sweeps per step (default 64; a step that
+ * reaches it flags the string with 2). */
 int string_batch_set_solver(sb_batch *b, double tol, int max_sweeps);
 
 /* Grid sizes the library plans for p (host only, needs no device): N_t from

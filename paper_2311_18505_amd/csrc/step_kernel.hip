@@ -762,6 +762,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
     const T smfac = (T)(beta / (1.0 + beta * IHs));
     bool conv = false;       // this group's iterates are final
     int sweeps = 0;
+    T ascale = T(0);         // tol x the group's largest value after the first sweep
     for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
       // transverse right-hand side with the current coupling terms:
       // e = q (q D_x- a_u + I_(l)->(t) D_x- a_z), b_u = r_u + phi^2 D_x+ e
@@ -832,20 +833,26 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
       }
       T nz[MM];
       toeplitz_solve<G, T, MM>(nz, bz, wbz, mask_l, rho_l, itk_l, spl);
-      // convergence of this group (from the second sweep on; a string without
-      // a longitudinal grid is solved exactly by the first); a converged group
-      // keeps its iterates
+      // convergence of this group, from the second sweep on (a string without
+      // a longitudinal grid is solved exactly by the first): every lane's
+      // update is below tol times the group's largest first-sweep value; the
+      // group's lanes are read off one ballot.  A converged group keeps its
+      // iterates.
       bool now = nl == 0;
-      if (sweep > 0 && any_l) {
-        T delta = T(0), amax = T(0);
+      if (any_l) {
+        if (sweep == 0) {
+          T amax = T(0);
 #pragma unroll
-        for (int r = 0; r < MM; ++r) {
-          delta = fmax(delta, fmax(fabs(nu[r] - au[r]), fabs(nz[r] - az[r])));
-          amax = fmax(amax, fmax(fabs(nu[r]), fabs(nz[r])));
+          for (int r = 0; r < MM; ++r) amax = fmax(amax, fmax(fabs(nu[r]), fabs(nz[r])));
+          ascale = (T)a.tol * grp_reduce<G, true>(amax);
+        } else {
+          T delta = T(0);
+#pragma unroll
+          for (int r = 0; r < MM; ++r) delta = fmax(delta, fmax(fabs(nu[r] - au[r]), fabs(nz[r] - az[r])));
+          const uint64_t ok = __ballot(delta <= ascale);
+          constexpr uint64_t gm = G == kWave ? ~0ull : ((1ull << G) - 1);
+          now = now || ((ok >> (gi * G)) & gm) == gm;
         }
-        delta = grp_reduce<G, true>(delta);
-        amax = grp_reduce<G, true>(amax);
-        now = now || delta <= (T)a.tol * amax;
       }
       if (__ballot(conv) != 0) {
 #pragma unroll
@@ -957,8 +964,17 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
   Sw->eta_nm1 = eta_nm1;
 }
 
+// Occupancy target per instantiation: the FP32 classes with up to 4 slots per
+// lane run two wavefronts per SIMD (256 registers each; the compiler spills a
+// few hundred bytes per lane, which the second wavefront more than pays for);
+// the larger and the FP64 classes keep the whole register file (one
+// wavefront per SIMD) because forcing them down spills their state.
+template <int MM, typename T>
+constexpr int kWavesPerEU = (sizeof(T) == 4 && MM <= 4) ? 2 : 1;
+
 template <int G, int MM, typename T, bool KAHAN>
-__global__ __launch_bounds__(64) void step_kernel(LaunchArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<MM, T>))) void step_kernel(
+    LaunchArgs a) {
   constexpr int kGroups = kWave / G;
   using L = Lds<G, MM>;
   // the energy monitor's scratch overlays the stepping arrays (never live together)
