@@ -335,6 +335,23 @@ struct Lds {
   static constexpr int kStride = 3 * kArr;
 };
 
+// The compensation arrays of the largest class live in LDS between their
+// uses (4 MM G values per group) instead of in registers: with 16 slots per
+// lane they would otherwise crowd the register file and spill the state.
+template <int MM, typename T, bool KAHAN>
+constexpr bool kSideComp = KAHAN && MM >= 16;
+
+template <int G, int MM, typename T>
+__device__ __forceinline__ void side_load(T (&x)[MM], const T *side, int k, int li) {
+#pragma unroll
+  for (int r = 0; r < MM; ++r) x[r] = side[(k * MM + r) * G + li];
+}
+template <int G, int MM, typename T>
+__device__ __forceinline__ void side_save(const T (&x)[MM], T *side, int k, int li) {
+#pragma unroll
+  for (int r = 0; r < MM; ++r) side[(k * MM + r) * G + li] = x[r];
+}
+
 // I_(t)->(l) up to the factor h_t/h_l at one l-half point: the sums of the
 // two contribution arrays over its t-half ranges [sa, sa+na) and [sb, sb+nb)
 // (packed as start | count << 16), with KG >= na, nb: every load is issued
@@ -511,7 +528,7 @@ __device__ __forceinline__ void store_state(T *st, T *trash, const T (&u)[MM], c
 // ---------------------------------------------------------------------------
 
 template <int G, int MM, typename T, bool KAHAN>
-__device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, double *sE) {
+__device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, double *sE, T *sC) {
   const int lane = lane_id();
   const int li = lane & (G - 1), gi = lane / G;
   const int sidx = a.work[task * (kWave / G) + gi];
@@ -583,6 +600,14 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
     wbz[r] = ld_if<T>(tf, (2 * mt + r) * G + li, ol);
   }
   const T *smv = tf + (2 * mt + ml) * G;   // Sherman-Morrison vector T_u0^{-1} J_H
+  constexpr bool kSide = kSideComp<MM, T, KAHAN>;
+  T *side = sC + gi * 4 * MM * G;
+  if constexpr (kSide) {
+    side_save<G, MM, T>(cu, side, 0, li);
+    side_save<G, MM, T>(cvu, side, 1, li);
+    side_save<G, MM, T>(cz, side, 2, li);
+    side_save<G, MM, T>(cvz, side, 3, li);
+  }
 
   // Nodes past the string's end hold zero state, which the solves keep
   // (node masks); slopes, couplings and LDS contributions there vanish by
@@ -641,6 +666,10 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
 
     // ---- slopes q (t half points) and p (l half points) ----
     T q[MM], p[MM];
+    if constexpr (kSide) {
+      side_load<G, MM, T>(cu, side, 0, li);
+      side_load<G, MM, T>(cz, side, 2, li);
+    }
     {
       const T ul = grp_prev<G>(last_of<T, MM>(u, mt)), cl = grp_prev<G>(last_of<T, MM>(cu, mt));
       const T zl = grp_prev<G>(last_of<T, MM>(z, ml)), czl = grp_prev<G>(last_of<T, MM>(cz, ml));
@@ -726,6 +755,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
     // ---- hammer: contact coefficient at time n, right-hand side 2 beta J eta^n ----
     double eta_n = 0.0, cH = 0.0, beta = 0.0;
     if (any_ham) {
+      if constexpr (kSide) side_load<G, MM, T>(cu, side, 0, li);
       const double Iu = point_eval<G, T, MM>(u, cu, hn0, hw0, hn1, hw1);
       eta_n = ham ? uH_n - Iu : 0.0;
       const bool contact = eta_n > 0.0;
@@ -876,6 +906,12 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
     max_sw = (act && sweeps > max_sw) ? sweeps : max_sw;
 
     // ---- state update: v^{n+1/2} = v^{n-1/2} + a, w^{n+1} = w^n + v^{n+1/2} ----
+    if constexpr (kSide) {
+      side_load<G, MM, T>(cu, side, 0, li);
+      side_load<G, MM, T>(cvu, side, 1, li);
+      side_load<G, MM, T>(cz, side, 2, li);
+      side_load<G, MM, T>(cvz, side, 3, li);
+    }
     if (__ballot(!act) == 0) {
 #pragma unroll
       for (int r = 0; r < MM; ++r) {
@@ -904,6 +940,13 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
       }
     }
 
+    if constexpr (kSide) {
+      side_save<G, MM, T>(cu, side, 0, li);
+      side_save<G, MM, T>(cvu, side, 1, li);
+      side_save<G, MM, T>(cz, side, 2, li);
+      side_save<G, MM, T>(cvz, side, 3, li);
+    }
+
     // ---- hammer lumped mass (eq. 6) ----
     if (any_ham) {
       const double Iu1 = point_eval<G, T, MM>(u, cu, hn0, hw0, hn1, hw1);
@@ -924,6 +967,12 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
     bool bad = false;
     const bool mon_now = act && a.mon_period > 0 && mon_ctr == 0;
     if (__ballot(mon_now) != 0) {
+      if constexpr (kSide) {
+        side_load<G, MM, T>(cu, side, 0, li);
+        side_load<G, MM, T>(cvu, side, 1, li);
+        side_load<G, MM, T>(cz, side, 2, li);
+        side_load<G, MM, T>(cvz, side, 3, li);
+      }
       energy_fill<G, MM, T>(gE, u, vu, cu, cvu, z, vz, cz, cvz, mt, ml, li);
       __syncthreads();
       const double H = energy_fp64<G, MM, T>(D, g2k2, gE, li);
@@ -950,6 +999,12 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
 
   // ---- write back: every lane stores; an empty group writes to the trash ----
   Status *Sw = present ? S : a.trash_status;
+  if constexpr (kSide) {
+    side_load<G, MM, T>(cu, side, 0, li);
+    side_load<G, MM, T>(cvu, side, 1, li);
+    side_load<G, MM, T>(cz, side, 2, li);
+    side_load<G, MM, T>(cvz, side, 3, li);
+  }
   store_state<G, T, MM>(present ? st : trash, trash, u, vu, cu, cvu, z, vz, cz, cvz, mt, ml, li);
   Sw->samples_done = done + steps_done;
   Sw->flags = flags;
@@ -981,14 +1036,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
   constexpr int kStepDoubles = (kGroups * L::kStride * (int)sizeof(T) + 7) / 8;
   constexpr int kEnergyDoubles = kGroups * EnergyLds<G, MM>::kStride;
   __shared__ double lds[kStepDoubles > kEnergyDoubles ? kStepDoubles : kEnergyDoubles];
+  // compensation arrays of the largest class (a separate region: they are
+  // read while the energy scratch is written)
+  constexpr int kSideDoubles = kSideComp<MM, T, KAHAN> ? (kGroups * 4 * MM * G * (int)sizeof(T) + 7) / 8 : 1;
+  __shared__ double lds_side[kSideDoubles];
   T *sS = (T *)lds;
   double *sE = lds;
+  T *sC = (T *)lds_side;
   for (;;) {
     // every lane takes part; only lane 0 adds, so the wave draws one ticket
     int w = atomicAdd(a.counter, lane_id() == 0 ? 1 : 0);
     w = __builtin_amdgcn_readfirstlane(w);
     if (w >= a.n_work) break;
-    run_task<G, MM, T, KAHAN>(a, w, sS, sE);
+    run_task<G, MM, T, KAHAN>(a, w, sS, sE, sC);
   }
 }
 
