@@ -126,7 +126,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the strings are independent and this build has no "
+        print("bench.py runs on one GPU only: the strings are independent and the library has no "
               "multi-GPU path (got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

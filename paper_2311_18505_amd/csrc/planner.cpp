@@ -173,7 +173,6 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
   double kTt;
   toeplitz_factor(dt, ct, D.rho_t, kTt);
   D.itk_t = 1.0 / kTt;
-  D.gt_t = std::pow(-D.rho_t, (double)D.mt);
   std::vector<double> wbt, wbl;
   boundary_weights(D.rho_t, kTt, Nt, wbt);
   double kTl = 1.0;
@@ -181,7 +180,6 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
     const double dl = 1.0 + D.s0k_l + 2.0 * D.s1k_l, cl = -D.s1k_l;
     toeplitz_factor(dl, cl, D.rho_l, kTl);
     D.itk_l = 1.0 / kTl;
-    D.gt_l = std::pow(-D.rho_l, (double)D.ml);
     boundary_weights(D.rho_l, kTl, Nl, wbl);
   }
 

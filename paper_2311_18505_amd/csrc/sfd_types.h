@@ -47,7 +47,6 @@ struct Desc {
   double ratio_lt;            // h_t / h_l = Nl / Nt
   double rho_t, itk_t;        // Toeplitz factor of T_u0: rho, 1/kappa_T
   double rho_l, itk_l;        // same for T_z
-  double gt_t, gt_l;          // (-rho)^mt, (-rho)^ml: lane-to-lane carry factors
   // f0 modulation
   int32_t mod_type, pad0;     // 0 none, 1 vibrato, 2 glide
   double f0, fs, mod_a, mod_b;   // vibrato: a = depth/1200, b = rate; glide: a = semis/12, b = 1/T

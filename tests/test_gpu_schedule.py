@@ -48,7 +48,7 @@ def test_graph_replays_match_eager():
             _ = g.info(0)                    # eager work between replays
         outs = [g.read_output(i) for i in range(len(items))]
         bad = [i for i in range(len(items)) if not np.array_equal(outs[i], ref[i])]
-        print("[gpu] replay round %d: %d mismatching strings" % (rep, len(bad)), flush=True)
+        print("[gpu] replay pass %d: %d mismatching strings" % (rep, len(bad)), flush=True)
         assert not bad
     # a changed slot invalidates the graph
     g.excite(0, [items[0][1]])
