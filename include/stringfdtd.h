@@ -165,13 +165,21 @@ int string_batch_graph_launch(sb_batch *b);
  * Synchronises the stream.  Errors: SB_EINVAL, SB_EDEVICE. */
 int string_batch_class_times(sb_batch *b, float ms[6], int32_t strings[6]);
 
-/* Autotuner (batched paths): for every size class present, times a probe of
- * probe_steps steps of that class alone at 1, 2, 4 and the occupancy limit of
- * persistent blocks per CU, keeps the fastest for later launches and reports
- * it in chosen[6] (0 for absent classes; chosen may be NULL).  Every slot is
- * rewound to its excitation before and after, so call it right after excite.
+/* Autotuner (batched paths): chooses the persistent blocks per CU of every
+ * size class jointly.  Each probe is a whole launch of probe_steps steps (all
+ * classes concurrently, as string_batch_step runs them); coordinate descent
+ * over the classes, largest first, tries 1, 2, 4, 6 and 8 blocks per CU (up
+ * to the class's occupancy limit) and keeps the shortest probe.  The choice
+ * applies to later launches and is reported in chosen[6] (0 for absent
+ * classes; chosen may be NULL).  Every slot is rewound to its excitation
+ * before and after, so call it right after excite.
  * Errors: SB_EINVAL, SB_ESTATE (nothing excited), SB_EDEVICE. */
 int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *chosen);
+
+/* Persistent blocks per CU of each size class for later launches (blocks[6];
+ * 0 = the class's occupancy limit), e.g. a schedule found by the autotuner on
+ * a previous run.  Errors: SB_EINVAL. */
+int string_batch_set_blocks_per_cu(sb_batch *b, const int32_t *blocks);
 
 /* Copy samples offset .. offset+count-1 of slot idx to dst (count elements
  * of the batch precision: float for SB_FP32C, double otherwise), ordered on

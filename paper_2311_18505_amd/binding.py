@@ -68,6 +68,7 @@ SIGNATURES = [
     ("string_batch_graph_launch", C.c_int, [_P]),
     ("string_batch_autotune", C.c_int, [_P, C.c_int64, C.POINTER(C.c_int32)]),
     ("string_batch_class_times", C.c_int, [_P, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
+    ("string_batch_set_blocks_per_cu", C.c_int, [_P, C.POINTER(C.c_int32)]),
     ("string_batch_read_energy", C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("string_batch_info", C.c_int, [_P, C.c_int, C.POINTER(SbStringInfo)]),
     ("string_batch_set_monitor", C.c_int, [_P, C.c_int, C.c_double]),
@@ -215,6 +216,10 @@ class StringBatch:
         ms, n = (C.c_float * 6)(), (C.c_int32 * 6)()
         self._check(self.lib.string_batch_class_times(self.h, ms, n), "class_times")
         return list(ms), list(n)
+
+    def set_blocks_per_cu(self, blocks):
+        arr = (C.c_int32 * 6)(*blocks)
+        self._check(self.lib.string_batch_set_blocks_per_cu(self.h, arr), "set_blocks_per_cu")
 
     def autotune(self, probe_steps: int = 480) -> list:
         chosen = (C.c_int32 * 6)()

@@ -20,6 +20,7 @@ hipError_t launch_zero(int32_t *c, int n, hipStream_t st);
 int max_blocks_per_cu(int precision, int cls);
 hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
                          hipStream_t st);
+hipError_t launch_scatter(const void *src, const UploadSeg *segs, int n, hipStream_t st);
 hipError_t launch_gather(int precision, const Desc *desc, const int32_t *slots, const int64_t *offs, int n,
                          int64_t count, void *dst, hipStream_t st);
 hipError_t launch_plain(const Desc *d_desc, Status *d_status, int slot, int64_t n_steps, size_t lds_bytes,
@@ -131,6 +132,11 @@ struct sb_batch {
   void *d_trash = nullptr;        // write target of empty groups and unused slots
   Status *d_trash_status = nullptr;
   // streaming readout: slot list, offsets and the gathered rows (grown on demand)
+  // bulk uploads of excite: staging buffer and segment list (grown on demand)
+  char *d_stage = nullptr;
+  size_t stage_bytes = 0;
+  UploadSeg *d_segs = nullptr;
+  size_t segs_cap = 0;
   int32_t *d_gslots = nullptr;
   int64_t *d_goffs = nullptr;
   void *d_gbuf = nullptr;
@@ -267,6 +273,8 @@ extern "C" int string_batch_destroy(sb_batch *b) {
   hipFree(b->d_gslots);
   hipFree(b->d_goffs);
   hipFree(b->d_gbuf);
+  hipFree(b->d_stage);
+  hipFree(b->d_segs);
   delete b;
   return SB_OK;
 }
@@ -384,7 +392,18 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
   // queued launches may still step these slots
   hipError_t es = hipStreamSynchronize(b->stream);
   if (es != hipSuccess) return hip_fail(b, es, "sync");
-  std::vector<std::vector<char>> keep;   // host buffers alive until the stream sync below
+  // every string's state, tables and first samples go into one staging
+  // buffer: one copy and one scatter kernel instead of five copies a string
+  std::vector<char> stage;
+  std::vector<UploadSeg> segs;
+  auto put = [&](const void *src, size_t bytes, void *dst) {
+    const size_t off = (stage.size() + 15) & ~size_t(15);
+    stage.resize(off + bytes);
+    std::memcpy(stage.data() + off, src, bytes);
+    segs.push_back(UploadSeg{off, dst, bytes});
+    return off;
+  };
+  std::vector<char> bs, bt, bh;
   std::vector<Desc> descs(count);
   std::vector<Status> stats(count);
   hipError_t err = hipSuccess;
@@ -424,10 +443,6 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     if (D.on0) y0 += D.ow0 * u0[D.on0];
     if (D.on1) y0 += D.ow1 * u0[D.on1];
     std::vector<double> head = {y0, y0};   // y^0 = y^1 (w^1 = w^0)
-    keep.emplace_back();
-    keep.emplace_back();
-    keep.emplace_back();
-    std::vector<char> &bs = keep[keep.size() - 3], &bt = keep[keep.size() - 2], &bh = keep[keep.size() - 1];
     if (plain) {
       to_prec<double>(state, bs);
       to_prec<double>(s.plan.pw, bt);
@@ -441,16 +456,14 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
       to_prec<double>(s.plan.tabf, bt);
       to_prec<double>(head, bh);
     }
-    err = hipMemcpyAsync(s.dmem, bs.data(), bs.size(), hipMemcpyHostToDevice, b->stream);
-    if (err == hipSuccess) err = hipMemcpyAsync(s.dmem + ost0, bs.data(), bs.size(), hipMemcpyHostToDevice, b->stream);
-    if (err == hipSuccess) err = hipMemcpyAsync(s.dmem + otf, bt.data(), bt.size(), hipMemcpyHostToDevice, b->stream);
-    if (err == hipSuccess) err = hipMemcpyAsync(s.dmem + oout, bh.data(), bh.size(), hipMemcpyHostToDevice, b->stream);
-    if (err == hipSuccess && plain)
-      err = hipMemcpyAsync(s.dmem + otab, s.plan.ptab.data(), s.plan.ptab.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, b->stream);
-    else if (err == hipSuccess)
-      err = hipMemcpyAsync(s.dmem + otab, s.plan.tab.data(), s.plan.tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
-                           b->stream);
+    put(bs.data(), bs.size(), s.dmem);
+    put(bs.data(), bs.size(), s.dmem + ost0);
+    put(bt.data(), bt.size(), s.dmem + otf);
+    put(bh.data(), bh.size(), s.dmem + oout);
+    if (plain)
+      put(s.plan.ptab.data(), s.plan.ptab.size() * sizeof(int32_t), s.dmem + otab);
+    else
+      put(s.plan.tab.data(), s.plan.tab.size() * sizeof(uint32_t), s.dmem + otab);
     descs[i] = D;
     Status &S = stats[i];
     std::memset(&S, 0, sizeof(S));
@@ -463,6 +476,27 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     s.flagged = false;
     s.samples_host = S.samples_done;
   }
+  // staging buffers of the batch (the previous upload has completed: the
+  // stream was synchronised above)
+  if (err == hipSuccess && stage.size() > b->stage_bytes) {
+    err = hipFree(b->d_stage);
+    b->d_stage = nullptr;
+    b->stage_bytes = 0;
+    if (err == hipSuccess) err = hipMalloc(&b->d_stage, stage.size());
+    if (err == hipSuccess) b->stage_bytes = stage.size();
+  }
+  if (err == hipSuccess && segs.size() > b->segs_cap) {
+    err = hipFree(b->d_segs);
+    b->d_segs = nullptr;
+    b->segs_cap = 0;
+    if (err == hipSuccess) err = hipMalloc(&b->d_segs, sizeof(UploadSeg) * segs.size());
+    if (err == hipSuccess) b->segs_cap = segs.size();
+  }
+  if (err == hipSuccess && !stage.empty())
+    err = hipMemcpyAsync(b->d_stage, stage.data(), stage.size(), hipMemcpyHostToDevice, b->stream);
+  if (err == hipSuccess && !segs.empty())
+    err = hipMemcpyAsync(b->d_segs, segs.data(), sizeof(UploadSeg) * segs.size(), hipMemcpyHostToDevice, b->stream);
+  if (err == hipSuccess) err = launch_scatter(b->d_stage, b->d_segs, (int)segs.size(), b->stream);
   if (err == hipSuccess)
     err = hipMemcpyAsync(b->d_desc + first, descs.data(), sizeof(Desc) * count, hipMemcpyHostToDevice, b->stream);
   if (err == hipSuccess)
@@ -648,6 +682,14 @@ extern "C" int string_batch_graph_capture(sb_batch *b, int64_t steps_per_launch,
 // alone at each candidate number of persistent blocks per CU (1, 2, 4 and the
 // occupancy limit) and keeps the fastest.  Probes step the excited state, so
 // every slot is rewound to its excitation before and after.
+// Autotuner: the persistent blocks per CU of every size class, chosen
+// jointly.  A probe is one whole launch (all classes forked and joined) of
+// probe_steps steps from the excited state: every task runs probe_steps steps,
+// so the probe is the run in miniature, with the contention between the
+// classes' kernels.  Coordinate descent over the classes, largest first,
+// keeps for each the candidate (1, 2, 4, 6 or 8 blocks per CU, up to its
+// occupancy limit) with the shortest probe.  Every slot is rewound to its
+// excitation before and after.
 extern "C" int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *chosen) {
   if (!b) return SB_EINVAL;
   if (b->precision == SB_FP64_PLAIN) return fail(b, SB_EINVAL, "the plain path has nothing to tune");
@@ -660,40 +702,62 @@ extern "C" int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  for (int c = 0; c < kNumClasses && e == hipSuccess && st == SB_OK; ++c) {
-    const int nw = (wp.off[c + 1] - wp.off[c]) / (kWave / kClassLanes[c]);
+  auto probe = [&](float &ms) -> int {
+    int r = string_batch_rewind(b, 0, b->capacity);
+    if (r) return r;
+    hipError_t x = hipEventRecord(e0, b->stream);
+    if (x != hipSuccess) return hip_fail(b, x, "autotune");
+    r = enqueue_step(b, b->stream, wp, probe_steps);
+    if (r) return r;
+    x = hipEventRecord(e1, b->stream);
+    if (x == hipSuccess) x = hipEventSynchronize(e1);
+    if (x == hipSuccess) x = hipEventElapsedTime(&ms, e0, e1);
+    return x == hipSuccess ? SB_OK : hip_fail(b, x, "autotune");
+  };
+  int occ[kNumClasses], nw[kNumClasses];
+  for (int c = 0; c < kNumClasses; ++c) {
+    nw[c] = (wp.off[c + 1] - wp.off[c]) / (kWave / kClassLanes[c]);
+    occ[c] = std::max(1, max_blocks_per_cu(b->precision, c));
+    b->blocks_per_cu[c] = occ[c];
     if (chosen) chosen[c] = 0;
-    if (nw == 0) continue;
-    const int occ = std::max(1, max_blocks_per_cu(b->precision, c));
-    int best = occ;
-    float best_ms = 1e30f;
-    for (int cand : {1, 2, 4, occ}) {
-      if (cand > occ) continue;
+  }
+  float best_ms = 1e30f;
+  if (e == hipSuccess) {
+    float ms = 0.f;
+    (void)probe(ms);        // first launch of every kernel: not timed
+    st = probe(best_ms);
+  }
+  for (int c = kNumClasses - 1; c >= 0 && e == hipSuccess && st == SB_OK; --c) {
+    if (nw[c] == 0) continue;
+    int best = b->blocks_per_cu[c];
+    for (int cand : {1, 2, 4, 6, 8}) {
+      if (cand > occ[c] || cand == best) continue;
       b->blocks_per_cu[c] = cand;
-      st = string_batch_rewind(b, 0, b->capacity);
-      if (st) break;
-      e = hipEventRecord(e0, b->stream);
-      if (e != hipSuccess) break;
-      st = enqueue_step(b, b->stream, wp, probe_steps, 1u << c);
-      if (st) break;
-      e = hipEventRecord(e1, b->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) break;
+      st = probe(ms);
+      if (st) break;
       if (ms < best_ms) {
         best_ms = ms;
         best = cand;
       }
     }
     b->blocks_per_cu[c] = best;
-    if (chosen) chosen[c] = best;
   }
+  for (int c = 0; c < kNumClasses && chosen; ++c) chosen[c] = nw[c] ? b->blocks_per_cu[c] : 0;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (st) return st;
   if (e != hipSuccess) return hip_fail(b, e, "autotune");
   return string_batch_rewind(b, 0, b->capacity);
+}
+
+extern "C" int string_batch_set_blocks_per_cu(sb_batch *b, const int32_t *blocks) {
+  if (!b) return SB_EINVAL;
+  if (!blocks) return fail(b, SB_EINVAL, "null blocks");
+  for (int c = 0; c < kNumClasses; ++c)
+    if (blocks[c] < 0 || blocks[c] > 64) return fail(b, SB_EINVAL, "blocks per CU outside 0..64");
+  for (int c = 0; c < kNumClasses; ++c) b->blocks_per_cu[c] = blocks[c];
+  return SB_OK;
 }
 
 extern "C" int string_batch_class_times(sb_batch *b, float *ms, int32_t *strings) {

@@ -104,4 +104,12 @@ struct LaunchArgs {
 
 constexpr int kMaxTrash = 4 * 2 * kMaxSlots * kWave * 8;   // largest state block in FP64
 
+// One segment of a bulk upload (excitation): bytes (a multiple of 4) from
+// offset src_off of the staging buffer to dst.
+struct UploadSeg {
+  uint64_t src_off;
+  void *dst;
+  uint64_t bytes;
+};
+
 }  // namespace sfd

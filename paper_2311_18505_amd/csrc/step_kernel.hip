@@ -1095,6 +1095,23 @@ hipError_t launch_gather(int precision, const Desc *desc, const int32_t *slots, 
   return hipGetLastError();
 }
 
+// Bulk upload: segment i copies bytes[i] bytes (a multiple of 4) from
+// src + src_off[i] to dst[i], one block per segment.
+__global__ void scatter_kernel(const uint32_t *src, const UploadSeg *segs, int n) {
+  const int i = (int)blockIdx.x;
+  if (i >= n) return;
+  const UploadSeg g = segs[i];
+  const uint32_t *from = src + g.src_off / 4;
+  uint32_t *to = (uint32_t *)g.dst;
+  for (uint64_t w = threadIdx.x; w < g.bytes / 4; w += blockDim.x) to[w] = from[w];
+}
+
+hipError_t launch_scatter(const void *src, const UploadSeg *segs, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_kernel, dim3(n), dim3(256), 0, st, (const uint32_t *)src, segs, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
                          hipStream_t st) {
   if (count <= 0) return hipSuccess;
