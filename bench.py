@@ -30,9 +30,9 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-point updates/s & audio-s/s, batched FP32 vs plain FP64; p99 latency"
 PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 2.4 GHz x 256)
 
-CLASS_KERNELS = ["step_kernel<16, 2, float, true>", "step_kernel<16, 4, float, true>",
-                 "step_kernel<32, 4, float, true>", "step_kernel<64, 4, float, true>",
-                 "step_kernel<64, 8, float, true>", "step_kernel<64, 16, float, true>"]
+# the kernels of the three launches of a step (size classes 0..3 merged, 4, 5)
+LAUNCH_KERNELS = ["step_kernel_small<float, true>", "step_kernel<64, 8, float, true>",
+                  "step_kernel<64, 16, float, true>"]
 
 WORKLOADS = {
     # 16384 nonlinear strings, durations U(0.5, 4) s, vibrato or glide, FP32
@@ -146,9 +146,9 @@ def main():
     audio_s = sum(p["n_samples"] / p["fs"] for p in params)
     print("[bench] %s: %d strings, %.3e grid-point updates per step, %.0f audio-s, setup %.1f s"
           % (args.workload, len(items), updates, audio_s, time.perf_counter() - t_setup), file=sys.stderr, flush=True)
-    # persistent blocks per CU for each size class
+    # persistent blocks per CU for each launch
     tuned = b.autotune(480)
-    print("[bench] autotuned blocks/CU per class %s" % tuned, file=sys.stderr, flush=True)
+    print("[bench] autotuned blocks/CU per launch %s" % tuned, file=sys.stderr, flush=True)
 
     for w in range(args.warmup):
         b.rewind()
@@ -168,9 +168,9 @@ def main():
     hiptime.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_ms(ev1)
-    class_ms, class_strings = b.class_times()      # kernels of the last timed step
-    print("[bench] %d steps: wall %.3f s, events %.3f ms; class kernels (ms) %s"
-          % (args.steps, wall, gpu_ms, ["%.1f" % m for m in class_ms]), file=sys.stderr, flush=True)
+    launch_ms, launch_strings = b.launch_times()      # kernels of the last timed step
+    print("[bench] %d steps: wall %.3f s, events %.3f ms; launch kernels (ms) %s"
+          % (args.steps, wall, gpu_ms, ["%.1f" % m for m in launch_ms]), file=sys.stderr, flush=True)
     # the same step as one replay of a captured HIP graph (outside the timed region)
     b.rewind()
     b.graph_capture(n_max, 1)
@@ -213,8 +213,9 @@ def main():
         "config": {"workload": args.workload, "strings": len(items), "fs": 48000,
                    "updates_per_step": updates, "audio_seconds_per_step": audio_s,
                    "precision": "FP32 with compensated state updates, FP64 energy monitor",
-                   "launch": "one launch per step (size classes forked onto their streams and joined), "
-                             "blocks/CU autotuned; the same launch replayed from a HIP graph is reported beside",
+                   "launch": "three concurrent persistent launches per step (size classes 0-3 merged, 4, 5; "
+                             "forked onto their streams and joined), blocks/CU autotuned; the same step "
+                             "replayed from a HIP graph is reported beside",
                    "blocks_per_cu": tuned},
         "audio_s_per_s": audio_s / sec_per_step,
         "sweeps_per_step_mean": sweeps / max(1, sum(inf["n_samples"] - 2 for inf in infos)),
@@ -243,25 +244,26 @@ def main():
         threads = min(16, os.cpu_count() or 1)
         rec, flops_per_update = cpu_baseline(items, args.cpu_seconds, threads)
         out["cpu_baseline"] = {k: v for k, v in rec.items() if k != "seconds"}
-        # roofline of each size-class kernel: the oracle's arithmetic per
-        # grid-point update times the updates of that class's strings, over
+        # roofline of each launch's kernel: the oracle's arithmetic per
+        # grid-point update times the updates of that launch's strings, over
         # the kernel's own duration (HIP events on its stream, last timed step)
-        by_class = []
-        for c in range(6):
-            if class_ms[c] <= 0:
+        by_launch = []
+        for u in range(binding.NUM_LAUNCHES):
+            if launch_ms[u] <= 0:
                 continue
-            upd_c = sum(u for u, inf in zip(upd_of, infos) if inf["size_class"] == c)
-            ach = flops_per_update * upd_c / (class_ms[c] / 1e3)
-            by_class.append({"kernel": CLASS_KERNELS[c], "ms": class_ms[c], "strings": class_strings[c],
-                             "updates": upd_c, "achieved_tflops": ach / 1e12, "frac": ach / PEAK_FP32_VECTOR})
-        # the dominant kernel: the size class that carries the most updates
-        dom = max(by_class, key=lambda r: r["updates"])
+            upd_u = sum(x for x, inf in zip(upd_of, infos) if inf["size_class"] in binding.LAUNCH_CLASSES[u])
+            ach = flops_per_update * upd_u / (launch_ms[u] / 1e3)
+            by_launch.append({"kernel": LAUNCH_KERNELS[u], "classes": list(binding.LAUNCH_CLASSES[u]),
+                              "ms": launch_ms[u], "strings": launch_strings[u], "updates": upd_u,
+                              "achieved_tflops": ach / 1e12, "frac": ach / PEAK_FP32_VECTOR})
+        # the dominant kernel: the launch that carries the most updates
+        dom = max(by_launch, key=lambda r: r["updates"])
         out["roofline"] = {"bound": "alu", "achieved": dom["achieved_tflops"], "peak": PEAK_FP32_VECTOR / 1e12,
                            "unit": "TFLOP/s", "frac": dom["frac"], "traffic": None,
                            "kernel": dom["kernel"], "kernel_ms_per_launch": dom["ms"],
                            "flops_per_update": flops_per_update,
                            "whole_step_frac": flops_per_update * updates / (gpu_ms / args.steps / 1e3) / PEAK_FP32_VECTOR}
-        out["roofline_by_class"] = by_class
+        out["roofline_by_launch"] = by_launch
     print(json.dumps(out), flush=True)
 
 

@@ -148,7 +148,7 @@ int string_batch_rewind(sb_batch *b, int first, int count);
 
 /* Launch capture (batched paths).  Records n_launches consecutive launches
  * of steps_per_launch steps each, of every slot excited at the time of the
- * call (the size classes forked onto their streams and joined back, counters
+ * call (the launches forked onto their streams and joined back, counters
  * cleared by a kernel), into a HIP graph owned by the batch; capture happens
  * on an internal stream, so nothing runs.  string_batch_graph_launch replays
  * it on the batch stream and advances every captured slot like the same
@@ -159,26 +159,34 @@ int string_batch_rewind(sb_batch *b, int first, int count);
 int string_batch_graph_capture(sb_batch *b, int64_t steps_per_launch, int n_launches);
 int string_batch_graph_launch(sb_batch *b);
 
-/* Durations of the size-class kernels of the last batched launch (fork/join
- * of string_batch_step or of a captured graph's last launch), in ms, and the
- * number of strings each stepped; ms[c] = 0 for classes that did not run.
- * Synchronises the stream.  Errors: SB_EINVAL, SB_EDEVICE. */
-int string_batch_class_times(sb_batch *b, float ms[6], int32_t strings[6]);
+/* A batched step runs as SB_NUM_LAUNCHES concurrent kernel launches, each on
+ * its own stream, forked from and joined back to the batch stream:
+ *   0: size classes 0..3 (up to 256 points), one persistent launch with one
+ *      work queue, tasks of class 3 first and class 0 last;
+ *   1: size class 4 (up to 512 points);
+ *   2: size class 5 (up to 1024 points). */
+#define SB_NUM_LAUNCHES 3
 
-/* Autotuner (batched paths): chooses the persistent blocks per CU of every
- * size class jointly.  Each probe is a whole launch of probe_steps steps (all
- * classes concurrently, as string_batch_step runs them); coordinate descent
- * over the classes, largest first, tries 1, 2, 4, 6 and 8 blocks per CU (up
- * to the class's occupancy limit) and keeps the shortest probe.  The choice
- * applies to later launches and is reported in chosen[6] (0 for absent
- * classes; chosen may be NULL).  Every slot is rewound to its excitation
- * before and after, so call it right after excite.
+/* Durations of the launches of the last batched step (string_batch_step or a
+ * captured graph's last launch), in ms, and the number of strings each
+ * stepped; ms[u] = 0 for launches that did not run.  Synchronises the stream.
+ * Errors: SB_EINVAL, SB_EDEVICE. */
+int string_batch_launch_times(sb_batch *b, float ms[SB_NUM_LAUNCHES], int32_t strings[SB_NUM_LAUNCHES]);
+
+/* Autotuner (batched paths): chooses the persistent blocks per CU of the
+ * launches jointly.  Each probe is a whole step of probe_steps steps (all
+ * launches concurrently, as string_batch_step runs them); coordinate descent
+ * over the launches, largest strings first, tries 1, 2, 4, 6 and 8 blocks per
+ * CU (up to the launch's occupancy limit) and keeps the shortest probe.  The
+ * choice applies to later steps and is reported in chosen[SB_NUM_LAUNCHES]
+ * (0 for launches with nothing to step; chosen may be NULL).  Every slot is
+ * rewound to its excitation before and after, so call it right after excite.
  * Errors: SB_EINVAL, SB_ESTATE (nothing excited), SB_EDEVICE. */
 int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *chosen);
 
-/* Persistent blocks per CU of each size class for later launches (blocks[6];
- * 0 = the class's occupancy limit), e.g. a schedule found by the autotuner on
- * a previous run.  Errors: SB_EINVAL. */
+/* Persistent blocks per CU of each launch for later steps
+ * (blocks[SB_NUM_LAUNCHES]; 0 = the launch's occupancy limit), e.g. a
+ * schedule found by the autotuner on a previous run.  Errors: SB_EINVAL. */
 int string_batch_set_blocks_per_cu(sb_batch *b, const int32_t *blocks);
 
 /* Copy samples offset .. offset+count-1 of slot idx to dst (count elements

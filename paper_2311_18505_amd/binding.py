@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(HERE, "libstringfdtd.so")
 SB_OK, SB_EINVAL, SB_ENOMEM, SB_EBUDGET, SB_EUNSTABLE, SB_ESTATE, SB_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 SB_FP64, SB_FP32C, SB_FP64_PLAIN = 0, 1, 2
 PRECISIONS = {"fp64": SB_FP64, "fp32c": SB_FP32C, "fp64_plain": SB_FP64_PLAIN}
+# concurrent launches of a batched step: classes 0..3 merged, class 4, class 5
+NUM_LAUNCHES = 3
+LAUNCH_CLASSES = ((0, 1, 2, 3), (4,), (5,))
 STATUS_NAMES = {0: "SB_OK", -1: "SB_EINVAL", -2: "SB_ENOMEM", -3: "SB_EBUDGET", -4: "SB_EUNSTABLE",
                 -5: "SB_ESTATE", -6: "SB_EDEVICE"}
 
@@ -67,7 +70,7 @@ SIGNATURES = [
     ("string_batch_graph_capture", C.c_int, [_P, C.c_int64, C.c_int]),
     ("string_batch_graph_launch", C.c_int, [_P]),
     ("string_batch_autotune", C.c_int, [_P, C.c_int64, C.POINTER(C.c_int32)]),
-    ("string_batch_class_times", C.c_int, [_P, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
+    ("string_batch_launch_times", C.c_int, [_P, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     ("string_batch_set_blocks_per_cu", C.c_int, [_P, C.POINTER(C.c_int32)]),
     ("string_batch_read_energy", C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("string_batch_info", C.c_int, [_P, C.c_int, C.POINTER(SbStringInfo)]),
@@ -211,18 +214,18 @@ class StringBatch:
     def graph_launch(self):
         self._check(self.lib.string_batch_graph_launch(self.h), "graph_launch")
 
-    def class_times(self):
-        """(ms, strings) per size class of the last batched launch."""
-        ms, n = (C.c_float * 6)(), (C.c_int32 * 6)()
-        self._check(self.lib.string_batch_class_times(self.h, ms, n), "class_times")
+    def launch_times(self):
+        """(ms, strings) per launch of the last batched step (NUM_LAUNCHES each)."""
+        ms, n = (C.c_float * NUM_LAUNCHES)(), (C.c_int32 * NUM_LAUNCHES)()
+        self._check(self.lib.string_batch_launch_times(self.h, ms, n), "launch_times")
         return list(ms), list(n)
 
     def set_blocks_per_cu(self, blocks):
-        arr = (C.c_int32 * 6)(*blocks)
+        arr = (C.c_int32 * NUM_LAUNCHES)(*blocks)
         self._check(self.lib.string_batch_set_blocks_per_cu(self.h, arr), "set_blocks_per_cu")
 
     def autotune(self, probe_steps: int = 480) -> list:
-        chosen = (C.c_int32 * 6)()
+        chosen = (C.c_int32 * NUM_LAUNCHES)()
         self._check(self.lib.string_batch_autotune(self.h, probe_steps, chosen), "autotune")
         return list(chosen)
 

@@ -15,9 +15,9 @@
 #include "sfd_types.h"
 
 namespace sfd {
-hipError_t launch_step(int precision, int cls, const LaunchArgs &a, int blocks, hipStream_t st);
+hipError_t launch_unit(int precision, int unit, const LaunchArgs &a, int blocks, hipStream_t st);
 hipError_t launch_zero(int32_t *c, int n, hipStream_t st);
-int max_blocks_per_cu(int precision, int cls);
+int max_blocks_per_cu(int precision, int unit);
 hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
                          hipStream_t st);
 hipError_t launch_scatter(const void *src, const UploadSeg *segs, int n, hipStream_t st);
@@ -116,11 +116,11 @@ struct sb_batch {
   hipStream_t stream = nullptr;
   // size classes run concurrently on streams of their own, forked from and
   // joined back into `stream` through events (default priority)
-  hipStream_t cls_stream[kNumClasses] = {};
+  hipStream_t unit_stream[kNumUnits] = {};
   hipEvent_t ev_fork = nullptr;
-  hipEvent_t ev_join[kNumClasses] = {};
-  hipEvent_t ev_t0[kNumClasses] = {}, ev_t1[kNumClasses] = {};   // timing of each class kernel
-  int32_t class_strings[kNumClasses] = {};                          // strings of the last launch
+  hipEvent_t ev_join[kNumUnits] = {};
+  hipEvent_t ev_t0[kNumUnits] = {}, ev_t1[kNumUnits] = {};   // timing of each launch
+  int32_t unit_strings[kNumUnits] = {};                       // strings of the last launch
   std::string err;
   std::vector<Slot> slots;
   Arena arena;
@@ -145,7 +145,7 @@ struct sb_batch {
   std::vector<int32_t> h_plain;   // plain path: slots in launch order
   bool work_dirty = true;
   int64_t epoch = 0;               // bumped whenever slots change (invalidates a captured graph)
-  int blocks_per_cu[kNumClasses] = {};   // persistent blocks per CU per class (0: occupancy limit)
+  int blocks_per_cu[kNumUnits] = {};   // persistent blocks per CU per launch (0: occupancy limit)
   // captured launches (string_batch_graph_capture)
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -169,6 +169,8 @@ static int hip_fail(sb_batch *b, hipError_t e, const char *where) {
   (void)hipGetLastError();
   return fail(b, SB_EDEVICE, m);
 }
+
+static_assert(kNumUnits == SB_NUM_LAUNCHES, "launch units of the C ABI");
 
 static size_t work_capacity(int capacity);
 static void graph_release(sb_batch *b);
@@ -226,8 +228,8 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
     delete b;
     return SB_EDEVICE;
   }
-  for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
-    e = hipStreamCreateWithFlags(&b->cls_stream[c], hipStreamNonBlocking);
+  for (int c = 0; c < kNumUnits && e == hipSuccess; ++c) {
+    e = hipStreamCreateWithFlags(&b->unit_stream[c], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreate(&b->ev_t0[c]);
     if (e == hipSuccess) e = hipEventCreate(&b->ev_t1[c]);
@@ -247,10 +249,10 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
 extern "C" int string_batch_destroy(sb_batch *b) {
   if (!b) return SB_EINVAL;
   (void)hipStreamSynchronize(b->stream);
-  for (int c = 0; c < kNumClasses; ++c) {
-    if (b->cls_stream[c]) {
-      (void)hipStreamSynchronize(b->cls_stream[c]);
-      (void)hipStreamDestroy(b->cls_stream[c]);
+  for (int c = 0; c < kNumUnits; ++c) {
+    if (b->unit_stream[c]) {
+      (void)hipStreamSynchronize(b->unit_stream[c]);
+      (void)hipStreamDestroy(b->unit_stream[c]);
     }
     if (b->ev_join[c]) (void)hipEventDestroy(b->ev_join[c]);
     if (b->ev_t0[c]) (void)hipEventDestroy(b->ev_t0[c]);
@@ -284,7 +286,11 @@ extern "C" const char *string_batch_last_error(const sb_batch *b) {
 }
 
 // Entries of the task array: every class pads its last task with at most 64/G - 1 empty groups.
-static size_t work_capacity(int capacity) { return (size_t)capacity + (size_t)kNumClasses * kWave; }
+static_assert(kNumUnits == SB_NUM_LAUNCHES, "launch units of the C ABI");
+
+// task lists (strings, padded per class to whole tasks) and the ticket map of
+// the merged launch (at most one ticket per string)
+static size_t work_capacity(int capacity) { return 2 * (size_t)capacity + (size_t)kNumClasses * kWave; }
 
 static bool range_ok(const sb_batch *b, int first, int count) {
   return first >= 0 && count >= 0 && (int64_t)first + count <= b->capacity;
@@ -516,8 +522,10 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
 // device copy is refreshed when it changes.
 struct WorkPlan {
   std::vector<int> off = std::vector<int>(kNumClasses + 1, 0);
+  int tickets_off = 0, n_tickets = 0;   // ticket map of the merged launch
   std::vector<int> members;   // slots stepped
 };
+
 
 static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPlan &wp) {
   std::vector<std::vector<std::pair<double, int>>> cls(kNumClasses);
@@ -545,6 +553,26 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
     for (auto &w : cls[c]) wp.members.push_back(w.second);
   }
   wp.off[kNumClasses] = (int)work.size();
+  if (b->precision != SB_FP64_PLAIN) {
+    // tickets of the merged launch: the tasks of classes 0..3 dealt out in
+    // proportion to their counts (task t of a class of n tasks at t / n), each
+    // class longest first.  The mix of classes on the CUs then stays the same
+    // over the whole launch, which runs faster than one class after another
+    // (their bottlenecks differ), and the shortest tasks of every class fill
+    // the tail.
+    std::vector<std::pair<double, int32_t>> tk;
+    for (int c = 0; c < kNumSmall; ++c) {
+      const int groups = kWave / kClassLanes[c];
+      const int nt = (int)((cls[c].size() + groups - 1) / groups);
+      for (int t = 0; t < nt; ++t) tk.push_back({-(double)t / (double)nt, (int32_t)((c << 24) | t)});
+    }
+    std::stable_sort(tk.begin(), tk.end(), [](const std::pair<double, int32_t> &x, const std::pair<double, int32_t> &y) {
+      return x.first > y.first;
+    });
+    wp.tickets_off = (int)work.size();
+    wp.n_tickets = (int)tk.size();
+    for (auto &t : tk) work.push_back(t.second);
+  }
   if (work.empty() || b->precision == SB_FP64_PLAIN) {
     b->h_plain = std::move(work);
     return SB_OK;
@@ -564,25 +592,39 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
   return SB_OK;
 }
 
-// One launch of every size class on `st`: counters cleared by a kernel (no
-// memset nodes under capture), the classes forked onto their own streams and
-// joined back.  Issues no synchronisation and no copy, so it can be captured.
-static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t n_steps,
-                        unsigned class_mask = ~0u) {
-  hipError_t e = launch_zero(b->d_counters, kNumClasses, st);
+// One step launch on `st`: counters cleared by a kernel (no memset nodes
+// under capture), the three launches (classes 0..3 merged, class 4, class 5)
+// forked onto their own streams and joined back.  Issues no synchronisation
+// and no copy, so it can be captured.
+static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t n_steps) {
+  hipError_t e = launch_zero(b->d_counters, kNumUnits, st);
   if (e == hipSuccess) e = hipEventRecord(b->ev_fork, st);
   if (e != hipSuccess) return hip_fail(b, e, "fork");
-  for (int c = 0; c < kNumClasses; ++c) b->class_strings[c] = 0;
-  // largest strings first: their classes hold the longest per-step latency
-  for (int c = kNumClasses - 1; c >= 0; --c) {
-    const int nw = (wp.off[c + 1] - wp.off[c]) / (kWave / kClassLanes[c]);   // tasks of this class
-    if (nw == 0 || !(class_mask & (1u << c))) continue;
+  int tasks[kNumClasses];
+  for (int c = 0; c < kNumClasses; ++c) tasks[c] = (wp.off[c + 1] - wp.off[c]) / (kWave / kClassLanes[c]);
+  // largest strings first: their launches hold the longest per-step latency
+  for (int u = kNumUnits - 1; u >= 0; --u) {
     LaunchArgs a;
     a.desc = b->d_desc;
     a.status = b->d_status;
-    a.work = b->d_work + wp.off[c];
-    a.n_work = nw;
-    a.counter = b->d_counters + c;
+    int strings = 0;
+    if (u == 0) {
+      for (int c = 0; c < kNumSmall; ++c) a.part_work[c] = b->d_work + wp.off[c];
+      a.tickets = b->d_work + wp.tickets_off;
+      a.work = b->d_work;
+      a.n_work = wp.n_tickets;
+      for (int k = wp.off[0]; k < wp.off[kNumSmall]; ++k) strings += b->h_work[k] >= 0 ? 1 : 0;
+    } else {
+      const int c = kNumSmall + u - 1;
+      a.work = b->d_work + wp.off[c];
+      a.n_work = tasks[c];
+      for (int p = 0; p < kNumSmall; ++p) a.part_work[p] = nullptr;
+      a.tickets = nullptr;
+      for (int k = wp.off[c]; k < wp.off[c + 1]; ++k) strings += b->h_work[k] >= 0 ? 1 : 0;
+    }
+    b->unit_strings[u] = strings;
+    if (a.n_work == 0) continue;
+    a.counter = b->d_counters + u;
     a.n_steps = n_steps;
     a.mon_period = b->mon_period;
     a.max_sweeps = b->max_sweeps;
@@ -590,18 +632,15 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
     a.mon_tol = b->mon_tol;
     a.trash_st = b->d_trash;
     a.trash_status = b->d_trash_status;
-    const int per_cu = b->blocks_per_cu[c] > 0 ? b->blocks_per_cu[c] : std::max(1, max_blocks_per_cu(b->precision, c));
-    const int blocks = std::min(nw, b->num_cu * per_cu);
-    hipStream_t cs = b->cls_stream[c];
+    const int per_cu = b->blocks_per_cu[u] > 0 ? b->blocks_per_cu[u] : std::max(1, max_blocks_per_cu(b->precision, u));
+    const int blocks = std::min(a.n_work, b->num_cu * per_cu);
+    hipStream_t cs = b->unit_stream[u];
     e = hipStreamWaitEvent(cs, b->ev_fork, 0);
-    if (e == hipSuccess) e = hipEventRecord(b->ev_t0[c], cs);
-    if (e == hipSuccess) e = launch_step(b->precision, c, a, blocks, cs);
-    if (e == hipSuccess) e = hipEventRecord(b->ev_t1[c], cs);
-    if (e == hipSuccess) e = hipEventRecord(b->ev_join[c], cs);
-    int strings = 0;
-    for (int k = wp.off[c]; k < wp.off[c + 1]; ++k) strings += b->h_work[k] >= 0 ? 1 : 0;
-    b->class_strings[c] = strings;
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[c], 0);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_t0[u], cs);
+    if (e == hipSuccess) e = launch_unit(b->precision, u, a, blocks, cs);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_t1[u], cs);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_join[u], cs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[u], 0);
     if (e != hipSuccess) return hip_fail(b, e, "step launch");
   }
   return SB_OK;
@@ -678,15 +717,11 @@ extern "C" int string_batch_graph_capture(sb_batch *b, int64_t steps_per_launch,
   return SB_OK;
 }
 
-// Autotuner: for every size class present, times a short probe of that class
-// alone at each candidate number of persistent blocks per CU (1, 2, 4 and the
-// occupancy limit) and keeps the fastest.  Probes step the excited state, so
-// every slot is rewound to its excitation before and after.
-// Autotuner: the persistent blocks per CU of every size class, chosen
-// jointly.  A probe is one whole launch (all classes forked and joined) of
-// probe_steps steps from the excited state: every task runs probe_steps steps,
-// so the probe is the run in miniature, with the contention between the
-// classes' kernels.  Coordinate descent over the classes, largest first,
+// Autotuner: the persistent blocks per CU of the three launches, chosen
+// jointly.  A probe is one whole step launch (all three forked and joined)
+// of probe_steps steps from the excited state: every task runs probe_steps
+// steps, so the probe is the run in miniature, with the contention between
+// the launches.  Coordinate descent over the launches, largest strings first,
 // keeps for each the candidate (1, 2, 4, 6 or 8 blocks per CU, up to its
 // occupancy limit) with the shortest probe.  Every slot is rewound to its
 // excitation before and after.
@@ -714,12 +749,12 @@ extern "C" int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *
     if (x == hipSuccess) x = hipEventElapsedTime(&ms, e0, e1);
     return x == hipSuccess ? SB_OK : hip_fail(b, x, "autotune");
   };
-  int occ[kNumClasses], nw[kNumClasses];
-  for (int c = 0; c < kNumClasses; ++c) {
-    nw[c] = (wp.off[c + 1] - wp.off[c]) / (kWave / kClassLanes[c]);
-    occ[c] = std::max(1, max_blocks_per_cu(b->precision, c));
-    b->blocks_per_cu[c] = occ[c];
-    if (chosen) chosen[c] = 0;
+  int occ[kNumUnits], nw[kNumUnits] = {};
+  for (int c = 0; c < kNumClasses; ++c) nw[unit_of_class(c)] += (wp.off[c + 1] - wp.off[c]) / (kWave / kClassLanes[c]);
+  for (int u = 0; u < kNumUnits; ++u) {
+    occ[u] = std::max(1, max_blocks_per_cu(b->precision, u));
+    b->blocks_per_cu[u] = occ[u];
+    if (chosen) chosen[u] = 0;
   }
   float best_ms = 1e30f;
   if (e == hipSuccess) {
@@ -727,7 +762,7 @@ extern "C" int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *
     (void)probe(ms);        // first launch of every kernel: not timed
     st = probe(best_ms);
   }
-  for (int c = kNumClasses - 1; c >= 0 && e == hipSuccess && st == SB_OK; --c) {
+  for (int c = kNumUnits - 1; c >= 0 && e == hipSuccess && st == SB_OK; --c) {
     if (nw[c] == 0) continue;
     int best = b->blocks_per_cu[c];
     for (int cand : {1, 2, 4, 6, 8}) {
@@ -743,7 +778,7 @@ extern "C" int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *
     }
     b->blocks_per_cu[c] = best;
   }
-  for (int c = 0; c < kNumClasses && chosen; ++c) chosen[c] = nw[c] ? b->blocks_per_cu[c] : 0;
+  for (int c = 0; c < kNumUnits && chosen; ++c) chosen[c] = nw[c] ? b->blocks_per_cu[c] : 0;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (st) return st;
@@ -754,23 +789,23 @@ extern "C" int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *
 extern "C" int string_batch_set_blocks_per_cu(sb_batch *b, const int32_t *blocks) {
   if (!b) return SB_EINVAL;
   if (!blocks) return fail(b, SB_EINVAL, "null blocks");
-  for (int c = 0; c < kNumClasses; ++c)
+  for (int c = 0; c < kNumUnits; ++c)
     if (blocks[c] < 0 || blocks[c] > 64) return fail(b, SB_EINVAL, "blocks per CU outside 0..64");
-  for (int c = 0; c < kNumClasses; ++c) b->blocks_per_cu[c] = blocks[c];
+  for (int c = 0; c < kNumUnits; ++c) b->blocks_per_cu[c] = blocks[c];
   return SB_OK;
 }
 
-extern "C" int string_batch_class_times(sb_batch *b, float *ms, int32_t *strings) {
+extern "C" int string_batch_launch_times(sb_batch *b, float *ms, int32_t *strings) {
   if (!b) return SB_EINVAL;
   if (!ms || !strings) return fail(b, SB_EINVAL, "null output");
   hipError_t e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(b, e, "sync");
-  for (int c = 0; c < kNumClasses; ++c) {
+  for (int c = 0; c < kNumUnits; ++c) {
     ms[c] = 0.f;
-    strings[c] = b->class_strings[c];
+    strings[c] = b->unit_strings[c];
     if (!strings[c]) continue;
     e = hipEventElapsedTime(&ms[c], b->ev_t0[c], b->ev_t1[c]);
-    if (e != hipSuccess) return hip_fail(b, e, "class timing");
+    if (e != hipSuccess) return hip_fail(b, e, "launch timing");
   }
   return SB_OK;
 }

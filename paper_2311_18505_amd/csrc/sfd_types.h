@@ -17,6 +17,14 @@ constexpr int kNumClasses = 6;
 constexpr int kClassLanes[kNumClasses] = {16, 16, 32, 64, 64, 64};
 constexpr int kClassSlots[kNumClasses] = {2, 4, 4, 4, 8, 16};
 
+// Launches of one step.  The classes up to 256 points share one occupancy
+// profile and run as one persistent launch with one work queue (unit 0);
+// the two largest classes run as launches of their own (units 1, 2), each on
+// its own stream, so the three run concurrently.
+constexpr int kNumSmall = 4;        // classes 0..3
+constexpr int kNumUnits = 3;
+constexpr int unit_of_class(int c) { return c < kNumSmall ? 0 : c - kNumSmall + 1; }
+
 enum : int32_t {
   kFlagUnstable = 1,      // energy monitor: non-finite or growing energy
   kFlagNoConverge = 2,    // coupled solve did not converge within the sweep cap
@@ -91,7 +99,11 @@ struct LaunchArgs {
   const Desc *desc;
   Status *status;
   const int32_t *work;        // 64/G string indices per wavefront task (-1: empty group)
-  int32_t n_work;             // number of wavefront tasks
+  int32_t n_work;             // number of wavefront tasks (tickets)
+  // unit 0: ticket w runs task tickets[w] & 0xffffff of class
+  // tickets[w] >> 24, whose tasks are listed at part_work[class]
+  const int32_t *part_work[kNumSmall];
+  const int32_t *tickets;
   int32_t *counter;           // work-queue head (zeroed before the launch)
   int64_t n_steps;            // steps to advance each string (clamped at n_samples)
   int32_t mon_period;         // steps between energy checks (0: off)

@@ -229,13 +229,14 @@ __device__ __forceinline__ double point_eval(const T (&x)[MM], const T (&c)[MM],
 // ---------------------------------------------------------------------------
 
 // kT (1 + rho S-)(1 + rho S+) x = b on nodes 1..n of each group's string
-// (MM slots per lane; mask[r] is 1 on this lane's nodes <= n, else 0):
+// (MM slots per lane; mask[r] is 1 on this lane's nodes <= n, else 0; wb[r]
+// are the lane's weights of z_0):
 //   forward:  z_i = b_i / kT - rho z_{i-1},  z_0 = sum_i wb_i b_i  (odd extension)
 //   backward: x_i = z_i - rho x_{i+1},       x_N = 0
 // Lane-local recurrences, then group scans carry the lane boundary values.
-template <int G, typename T, int MM>
-__device__ __forceinline__ void toeplitz_solve(T (&x)[MM], const T (&b)[MM], const T (&wb)[MM], const T (&mask)[MM],
-                                               T rho, T itk, const ScanPow<T> &sp) {
+template <int G, typename T, int MM, typename WB, typename MK>
+__device__ __forceinline__ void toeplitz_solve(T (&x)[MM], const T (&b)[MM], const WB &wb, const MK &mask, T rho,
+                                               T itk, const ScanPow<T> &sp) {
   T part = T(0);
 #pragma unroll
   for (int r = 0; r < MM; ++r) part = fma(wb[r], b[r], part);
@@ -335,6 +336,56 @@ struct Lds {
   static constexpr int kStride = 3 * kArr;
 };
 
+// MM per-lane values of a group: in registers, or (largest class) in LDS at
+// [r G] from the lane's entry, read where they are used.  With 16 slots per
+// lane the tables would otherwise take a third of the register file.
+template <int MM>
+constexpr bool kTabLds = MM >= 16;
+
+template <int G, int MM, typename V, bool IN_LDS>
+struct LaneTab {
+  V v[MM];
+  __device__ V operator[](int r) const { return v[r]; }
+  __device__ void put(int r, V x) { v[r] = x; }
+};
+template <int G, int MM, typename V>
+struct LaneTab<G, MM, V, true> {
+  V *p;
+  __device__ V operator[](int r) const { return p[r * G]; }
+  __device__ void put(int r, V x) { p[r * G] = x; }
+};
+
+// Node mask of a lane (1 on its nodes <= n, else 0), as an array or computed.
+template <int MM, typename T, bool COMPUTED>
+struct NodeMask {
+  T v[MM];
+  __device__ void init(int nb, int n) {
+#pragma unroll
+    for (int r = 0; r < MM; ++r) v[r] = (nb + r + 1 <= n) ? T(1) : T(0);
+  }
+  __device__ T operator[](int r) const { return v[r]; }
+};
+template <int MM, typename T>
+struct NodeMask<MM, T, true> {
+  int nb, n;
+  __device__ void init(int nb_, int n_) {
+    nb = nb_;
+    n = n_;
+  }
+  __device__ T operator[](int r) const { return (nb + r + 1 <= n) ? T(1) : T(0); }
+};
+
+// LDS of the tables per group (where kTabLds): the index pair of
+// I_(l)->(t) and the two ranges of I_(t)->(l) (32-bit words), then the
+// interpolation weight, the z_0 weights of both grids and the
+// Sherman-Morrison vector (T), each MM*G values.
+template <int G, int MM, typename T>
+struct TabLds {
+  static constexpr int kWordsU = kTabLds<MM> ? 3 * MM * G : 0;
+  static constexpr int kWordsT = kTabLds<MM> ? 4 * MM * G : 0;
+  static constexpr int kBytes = kWordsU * 4 + kWordsT * (int)sizeof(T);
+};
+
 // The compensation arrays of the largest class live in LDS between their
 // uses (4 MM G values per group) instead of in registers: with 16 slots per
 // lane they would otherwise crowd the register file and spill the state.
@@ -388,9 +439,9 @@ __device__ __forceinline__ T range_gather_n(const T *sA, const T *sB, uint32_t r
 
 // g[r] = I_(t)->(l) contributions at this lane's l-half points (0 past ml:
 // their ranges are empty); kg is the wave's longest range.
-template <int MM, typename T>
-__device__ __forceinline__ void gather_lt(T (&g)[MM], const T *sA, const T *sB, const uint32_t (&rga)[MM],
-                                          const uint32_t (&rgb)[MM], int kg) {
+template <int MM, typename T, typename RG>
+__device__ __forceinline__ void gather_lt(T (&g)[MM], const T *sA, const T *sB, const RG &rga, const RG &rgb,
+                                          int kg) {
   if (MM > 8) {
     // the unrolled forms would hold 2 KG MM loads in flight: too many registers
 #pragma unroll
@@ -528,13 +579,14 @@ __device__ __forceinline__ void store_state(T *st, T *trash, const T (&u)[MM], c
 // ---------------------------------------------------------------------------
 
 template <int G, int MM, typename T, bool KAHAN>
-__device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, double *sE, T *sC) {
+__device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *work, int task, T *sS, double *sE, T *sC,
+                                         uint32_t *sTu, T *sTf) {
   const int lane = lane_id();
   const int li = lane & (G - 1), gi = lane / G;
-  const int sidx = a.work[task * (kWave / G) + gi];
+  const int sidx = work[task * (kWave / G) + gi];
   const bool present = sidx >= 0;
   // an empty group mirrors the task's first string but never steps or writes it
-  const int s = present ? sidx : a.work[task * (kWave / G)];
+  const int s = present ? sidx : work[task * (kWave / G)];
   const Desc &D = a.desc[s];
   Status *S = a.status + s;
 
@@ -574,8 +626,20 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
 
   // ---- state and tables into registers ----
   T u[MM], vu[MM], cu[MM], cvu[MM], z[MM], vz[MM], cz[MM], cvz[MM];
-  uint32_t jab[MM], rga[MM], rgb[MM];
-  T wi[MM], wbu[MM], wbz[MM];
+  constexpr bool kTL = kTabLds<MM>;
+  using TU = LaneTab<G, MM, uint32_t, kTL>;
+  using TF = LaneTab<G, MM, T, kTL>;
+  TU jab, rga, rgb;
+  TF wi, wbu, wbz, smt;
+  if constexpr (kTL) {
+    jab.p = sTu + gi * TabLds<G, MM, T>::kWordsU + li;
+    rga.p = jab.p + MM * G;
+    rgb.p = rga.p + MM * G;
+    wi.p = sTf + gi * TabLds<G, MM, T>::kWordsT + li;
+    wbu.p = wi.p + MM * G;
+    wbz.p = wbu.p + MM * G;
+    smt.p = wbz.p + MM * G;
+  }
   T *st = (T *)D.st;
   const T *tf = (const T *)D.tabf;
   const uint32_t *tab = D.tab;
@@ -592,12 +656,14 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
     vz[r] = ld_if<T>(st, zo + (1 * ml + r) * G + li, ol);
     cz[r] = KAHAN ? ld_if<T>(st, zo + (2 * ml + r) * G + li, ol) : T(0);
     cvz[r] = KAHAN ? ld_if<T>(st, zo + (3 * ml + r) * G + li, ol) : T(0);
-    jab[r] = ot ? ld_if<uint32_t>(tab, r * G + li, ot) : 0x00010001u;
-    rga[r] = ld_if<uint32_t>(tab, (mt + r) * G + li, ol);
-    rgb[r] = ld_if<uint32_t>(tab, (mt + ml + r) * G + li, ol);
-    wi[r] = ld_if<T>(tf, r * G + li, ot);
-    wbu[r] = ld_if<T>(tf, (mt + r) * G + li, ot);
-    wbz[r] = ld_if<T>(tf, (2 * mt + r) * G + li, ol);
+    jab.put(r, ot ? ld_if<uint32_t>(tab, r * G + li, ot) : 0x00010001u);
+    rga.put(r, ld_if<uint32_t>(tab, (mt + r) * G + li, ol));
+    rgb.put(r, ld_if<uint32_t>(tab, (mt + ml + r) * G + li, ol));
+    wi.put(r, ld_if<T>(tf, r * G + li, ot));
+    wbu.put(r, ld_if<T>(tf, (mt + r) * G + li, ot));
+    wbz.put(r, ld_if<T>(tf, (2 * mt + r) * G + li, ol));
+    // Sherman-Morrison vector (zero without a hammer), kept in LDS
+    if constexpr (kTL) smt.put(r, ld_if<T>(tf, (2 * mt + ml + r) * G + li, ot));
   }
   const T *smv = tf + (2 * mt + ml) * G;   // Sherman-Morrison vector T_u0^{-1} J_H
   constexpr bool kSide = kSideComp<MM, T, KAHAN>;
@@ -613,12 +679,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
   // (node masks); slopes, couplings and LDS contributions there vanish by
   // themselves, so no other predicate is needed.
   const int tb = li * mt, lb = li * ml;
-  T mask_t[MM], mask_l[MM];
-#pragma unroll
-  for (int r = 0; r < MM; ++r) {
-    mask_t[r] = (tb + r + 1 <= nt) ? T(1) : T(0);
-    mask_l[r] = (lb + r + 1 <= nl) ? T(1) : T(0);
-  }
+  NodeMask<MM, T, kTL> mask_t, mask_l;
+  mask_t.init(tb, nt);
+  mask_l.init(lb, nl);
 
   const T rho_t = (T)D.rho_t, itk_t = (T)D.itk_t, rho_l = (T)D.rho_l, itk_l = (T)D.itk_l;
   const ScanPow<T> spt = scan_pow<T>(ipow<T>(-rho_t, mt));
@@ -785,7 +848,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
       zero[r] = T(0);
       smr[r] = T(0);
     }
-    if (any_sm) {
+    if (!kTL && any_sm) {
 #pragma unroll
       for (int r = 0; r < MM; ++r) smr[r] = ld_if<T>(smv, r * G + li, sm_on);
     }
@@ -834,7 +897,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, int task, T *sS, d
         const T Iy = (T)point_eval<G, T, MM>(nu, zero, hn0, hw0, hn1, hw1);
         const T fac = smfac * Iy;
 #pragma unroll
-        for (int r = 0; r < MM; ++r) nu[r] = fma(-fac, smr[r], nu[r]);
+        for (int r = 0; r < MM; ++r) nu[r] = fma(-fac, kTL ? (sm_on ? smt[r] : T(0)) : smr[r], nu[r]);
       }
       // longitudinal right-hand side: r_z + phi^2 D_x+ I_(t)->(l) (q D_x- a_u)
       T gg[MM];
@@ -1040,15 +1103,57 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
   // read while the energy scratch is written)
   constexpr int kSideDoubles = kSideComp<MM, T, KAHAN> ? (kGroups * 4 * MM * G * (int)sizeof(T) + 7) / 8 : 1;
   __shared__ double lds_side[kSideDoubles];
+  // per-lane tables (largest class)
+  constexpr int kTabDoubles = (kGroups * TabLds<G, MM, T>::kBytes + 7) / 8;
+  __shared__ double lds_tab[kTabDoubles > 0 ? kTabDoubles : 1];
   T *sS = (T *)lds;
   double *sE = lds;
   T *sC = (T *)lds_side;
+  T *sTf = (T *)lds_tab;
+  uint32_t *sTu = (uint32_t *)(sTf + kGroups * TabLds<G, MM, T>::kWordsT);
   for (;;) {
     // every lane takes part; only lane 0 adds, so the wave draws one ticket
     int w = atomicAdd(a.counter, lane_id() == 0 ? 1 : 0);
     w = __builtin_amdgcn_readfirstlane(w);
     if (w >= a.n_work) break;
-    run_task<G, MM, T, KAHAN>(a, w, sS, sE, sC);
+    run_task<G, MM, T, KAHAN>(a, a.work, w, sS, sE, sC, sTu, sTf);
+  }
+}
+
+// The classes up to 256 points in one persistent launch: one ticket counter
+// over their tasks in the order the host chose (estimated work, longest
+// first), so that the short tasks fill the tail.  They share the occupancy
+// target and need neither LDS tables nor LDS compensation.
+template <typename T>
+constexpr int small_lds_doubles() {
+  constexpr int a = (Lds<64, 4>::kStride * (int)sizeof(T) + 7) / 8, ae = EnergyLds<64, 4>::kStride;
+  constexpr int b = (2 * Lds<32, 4>::kStride * (int)sizeof(T) + 7) / 8, be = 2 * EnergyLds<32, 4>::kStride;
+  constexpr int c = (4 * Lds<16, 4>::kStride * (int)sizeof(T) + 7) / 8, ce = 4 * EnergyLds<16, 4>::kStride;
+  constexpr int d = (4 * Lds<16, 2>::kStride * (int)sizeof(T) + 7) / 8, de = 4 * EnergyLds<16, 2>::kStride;
+  constexpr int m1 = a > ae ? a : ae, m2 = b > be ? b : be, m3 = c > ce ? c : ce, m4 = d > de ? d : de;
+  constexpr int m12 = m1 > m2 ? m1 : m2, m34 = m3 > m4 ? m3 : m4;
+  return m12 > m34 ? m12 : m34;
+}
+
+template <typename T, bool KAHAN>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<4, T>))) void step_kernel_small(
+    LaunchArgs a) {
+  static_assert(kWavesPerEU<2, T> == kWavesPerEU<4, T>, "one occupancy target for the merged classes");
+  static_assert(!kSideComp<4, T, KAHAN> && !kTabLds<4>, "no LDS tables in the merged classes");
+  __shared__ double lds[small_lds_doubles<T>()];
+  T *sS = (T *)lds;
+  double *sE = lds;
+  for (;;) {
+    int w = atomicAdd(a.counter, lane_id() == 0 ? 1 : 0);
+    w = __builtin_amdgcn_readfirstlane(w);
+    if (w >= a.n_work) break;
+    const int m = __builtin_amdgcn_readfirstlane(a.tickets[w]), t = m & 0xffffff;
+    switch (m >> 24) {
+      case 3: run_task<64, 4, T, KAHAN>(a, a.part_work[3], t, sS, sE, sS, nullptr, nullptr); break;
+      case 2: run_task<32, 4, T, KAHAN>(a, a.part_work[2], t, sS, sE, sS, nullptr, nullptr); break;
+      case 1: run_task<16, 4, T, KAHAN>(a, a.part_work[1], t, sS, sE, sS, nullptr, nullptr); break;
+      default: run_task<16, 2, T, KAHAN>(a, a.part_work[0], t, sS, sE, sS, nullptr, nullptr); break;
+    }
   }
 }
 
@@ -1123,21 +1228,18 @@ hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const 
 }
 
 template <typename T, bool KAHAN>
-static hipError_t launch_class(int cls, const LaunchArgs &a, int blocks, hipStream_t st) {
-  switch (cls) {
-    case 0: hipLaunchKernelGGL((step_kernel<16, 2, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((step_kernel<16, 4, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((step_kernel<32, 4, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
-    case 3: hipLaunchKernelGGL((step_kernel<64, 4, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((step_kernel<64, 8, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
+static hipError_t launch_unit_t(int unit, const LaunchArgs &a, int blocks, hipStream_t st) {
+  switch (unit) {
+    case 0: hipLaunchKernelGGL((step_kernel_small<T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((step_kernel<64, 8, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
     default: hipLaunchKernelGGL((step_kernel<64, 16, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_step(int precision, int cls, const LaunchArgs &a, int blocks, hipStream_t st) {
-  if (precision == 1) return launch_class<float, true>(cls, a, blocks, st);
-  return launch_class<double, false>(cls, a, blocks, st);
+hipError_t launch_unit(int precision, int unit, const LaunchArgs &a, int blocks, hipStream_t st) {
+  if (precision == 1) return launch_unit_t<float, true>(unit, a, blocks, st);
+  return launch_unit_t<double, false>(unit, a, blocks, st);
 }
 
 hipError_t launch_zero(int32_t *c, int n, hipStream_t st) {
@@ -1146,15 +1248,12 @@ hipError_t launch_zero(int32_t *c, int n, hipStream_t st) {
 }
 
 template <typename T, bool KAHAN>
-static int blocks_per_cu(int cls) {
+static int blocks_per_cu(int unit) {
   int n = 0;
   hipError_t e;
-  switch (cls) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<16, 2, T, KAHAN>, 64, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<16, 4, T, KAHAN>, 64, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<32, 4, T, KAHAN>, 64, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 4, T, KAHAN>, 64, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 8, T, KAHAN>, 64, 0); break;
+  switch (unit) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_small<T, KAHAN>, 64, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 8, T, KAHAN>, 64, 0); break;
     default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 16, T, KAHAN>, 64, 0); break;
   }
   if (e != hipSuccess) {
@@ -1164,8 +1263,8 @@ static int blocks_per_cu(int cls) {
   return n;
 }
 
-int max_blocks_per_cu(int precision, int cls) {
-  return precision == 1 ? blocks_per_cu<float, true>(cls) : blocks_per_cu<double, false>(cls);
+int max_blocks_per_cu(int precision, int unit) {
+  return precision == 1 ? blocks_per_cu<float, true>(unit) : blocks_per_cu<double, false>(unit);
 }
 
 }  // namespace sfd
