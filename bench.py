@@ -30,6 +30,14 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-point updates/s & audio-s/s, batched FP32 vs plain FP64; p99 latency"
 PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 2.4 GHz x 256)
 
+# HBM traffic of one launch of the dominant kernel (step_kernel_small, the
+# uneven 16384-string batch, one full step), from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a
+# 512 MiB device copy (x2.000 and x1.000); profiles/hbm_traffic_uneven16384.md.
+# Valid only for the kernel source it was measured on (sha256 prefix).
+TRAFFIC = {"kernel": "step_kernel_small<float, true>", "source_sha256": "6bdcb5d9a19f1163",
+           "fetch_bytes": 257.75e9, "write_bytes": 825.58e9}
+
 # the kernels of the three launches of a step (size classes 0..3 merged, 4, 5)
 LAUNCH_KERNELS = ["step_kernel_small<float, true>", "step_kernel<64, 8, float, true>",
                   "step_kernel<64, 16, float, true>"]
@@ -44,6 +52,16 @@ WORKLOADS = {
 
 def unknowns(info):
     return (info["N_t"] - 1) + max(info["N_l"] - 1, 0)
+
+
+def measured_traffic():
+    """TRAFFIC when the kernel source is the one it was measured on, else None."""
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2311_18505_amd", "csrc", "step_kernel.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != TRAFFIC["source_sha256"]:
+            return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 
 
 def cpu_baseline(items, seconds_cap, threads):
@@ -124,6 +142,8 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=60.0, help="arrival window of the serving run")
     ap.add_argument("--serving-rate", type=float, default=2000.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, one device copy of this size (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the strings are independent and the library has no "
@@ -259,12 +279,16 @@ def main():
         # the dominant kernel: the launch that carries the most updates
         dom = max(by_launch, key=lambda r: r["updates"])
         out["roofline"] = {"bound": "alu", "achieved": dom["achieved_tflops"], "peak": PEAK_FP32_VECTOR / 1e12,
-                           "unit": "TFLOP/s", "frac": dom["frac"], "traffic": None,
+                           "unit": "TFLOP/s", "frac": dom["frac"],
+                           "traffic": measured_traffic() if dom["kernel"] == TRAFFIC["kernel"] else None,
                            "kernel": dom["kernel"], "kernel_ms_per_launch": dom["ms"],
                            "flops_per_update": flops_per_update,
                            "whole_step_frac": flops_per_update * updates / (gpu_ms / args.steps / 1e3) / PEAK_FP32_VECTOR}
         out["roofline_by_launch"] = by_launch
     print(json.dumps(out), flush=True)
+    if args.copy_probe_mib > 0:
+        hiptime.copy_probe(args.copy_probe_mib << 20)
+        print("[bench] copy probe: %d MiB device to device" % args.copy_probe_mib, file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

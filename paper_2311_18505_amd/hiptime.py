@@ -1,5 +1,6 @@
-"""HIP events and device synchronisation through the HIP runtime that
-libstringfdtd itself is linked against (ctypes; used for timing only)."""
+"""HIP events, device synchronisation and a plain device copy through the
+HIP runtime that libstringfdtd itself is linked against (ctypes; used for
+timing, and the copy to calibrate HBM byte counters)."""
 from __future__ import annotations
 
 import ctypes as C
@@ -20,6 +21,9 @@ def hip():
         lib.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
         lib.hipEventDestroy.argtypes = [C.c_void_p]
         lib.hipDeviceSynchronize.argtypes = []
+        lib.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+        lib.hipFree.argtypes = [C.c_void_p]
+        lib.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
         _hip = lib
     return _hip
 
@@ -54,3 +58,19 @@ class Event:
 
 def synchronize():
     _ok(hip().hipDeviceSynchronize(), "hipDeviceSynchronize")
+
+
+def copy_probe(nbytes: int) -> None:
+    """One device-to-device copy of nbytes (a reference for byte counters)."""
+    h = hip()
+    src, dst = C.c_void_p(), C.c_void_p()
+    _ok(h.hipMalloc(C.byref(src), nbytes), "hipMalloc")
+    try:
+        _ok(h.hipMalloc(C.byref(dst), nbytes), "hipMalloc")
+        try:
+            _ok(h.hipMemcpy(dst, src, nbytes, 3), "hipMemcpy")   # hipMemcpyDeviceToDevice
+            synchronize()
+        finally:
+            h.hipFree(dst)
+    finally:
+        h.hipFree(src)
