@@ -42,6 +42,8 @@ class OrcExcitation(C.Structure):
         ("type", C.c_int32), ("pad0", C.c_int32), ("x", C.c_double), ("c0", C.c_double),
         ("v_H", C.c_double), ("M_H", C.c_double), ("K_H", C.c_double),
         ("alpha_H", C.c_double), ("rhoA", C.c_double),
+        ("x_end", C.c_double), ("v_B", C.c_double), ("F_B", C.c_double), ("attack", C.c_double),
+        ("fric_a", C.c_double), ("fric_eps", C.c_double),
     ]
 
 
@@ -60,6 +62,7 @@ class OrcOutputs(C.Structure):
     _fields_ = [
         ("y_u", _DP), ("y_z", _DP), ("energy", _DP), ("traj_u", _DP), ("traj_z", _DP),
         ("u_H", _DP), ("flops", C.c_double), ("steps_done", C.c_int64),
+        ("bow_phi", _DP), ("bow_vrel", _DP),
     ]
 
 
@@ -90,6 +93,8 @@ def _load():
         lib.orc_dump_system.restype = C.c_int
         lib.orc_gamma_at.argtypes = [C.POINTER(OrcString), C.c_int64]
         lib.orc_gamma_at.restype = C.c_double
+        lib.orc_bow_solve.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _DP]
+        lib.orc_bow_solve.restype = C.c_double
         _lib = lib
     return _lib
 
@@ -97,7 +102,8 @@ def _load():
 STRING_KEYS = ("fs", "f0", "B", "alpha", "theta", "sigma0_t", "sigma1_t", "sigma0_l", "sigma1_l",
                "x_out", "n_samples", "mod_type", "mod_depth_cents", "mod_rate_hz",
                "glide_semitones", "grid_t", "grid_l")
-EXC_KEYS = ("type", "x", "c0", "v_H", "M_H", "K_H", "alpha_H", "rhoA")
+EXC_KEYS = ("type", "x", "c0", "v_H", "M_H", "K_H", "alpha_H", "rhoA", "x_end", "v_B", "F_B", "attack",
+            "fric_a", "fric_eps")
 
 
 def _string(p: dict) -> OrcString:
@@ -133,6 +139,13 @@ def gamma_at(p: dict, n: int) -> float:
     return _load().orc_gamma_at(C.byref(_string(p)), n)
 
 
+def bow_solve(b: float, c: float, a: float, eps: float) -> tuple:
+    """(phi, v_rel) of the bow's scalar problem of one step (eq. 5)."""
+    v = C.c_double()
+    phi = _load().orc_bow_solve(b, c, a, eps, C.byref(v))
+    return phi, v.value
+
+
 def _ptr(a):
     return a.ctypes.data_as(_DP) if a is not None else None
 
@@ -140,7 +153,7 @@ def _ptr(a):
 def run(p: dict, e: dict | None, want=("y_u",), allow_fail: bool = False) -> dict:
     """Run one string for p['n_samples'] samples; return the requested arrays.
 
-    want: any of "y_u", "y_z", "energy", "traj_u", "traj_z", "u_H".
+    want: any of "y_u", "y_z", "energy", "traj_u", "traj_z", "u_H", "bow_phi", "bow_vrel".
     """
     lib = _load()
     g = grid(p)
@@ -148,12 +161,12 @@ def run(p: dict, e: dict | None, want=("y_u",), allow_fail: bool = False) -> dic
     nt, nl = g["N_t"] - 1, max(g["N_l"] - 1, 0)
     res: dict = {"grid": g}
     arrs = {}
-    for key in ("y_u", "y_z", "energy", "u_H"):
+    for key in ("y_u", "y_z", "energy", "u_H", "bow_phi", "bow_vrel"):
         arrs[key] = np.zeros(ns) if key in want else None
     arrs["traj_u"] = np.zeros((ns, nt)) if "traj_u" in want else None
     arrs["traj_z"] = np.zeros((ns, max(nl, 0))) if "traj_z" in want else None
     out = OrcOutputs()
-    for key in ("y_u", "y_z", "energy", "traj_u", "traj_z", "u_H"):
+    for key in ("y_u", "y_z", "energy", "traj_u", "traj_z", "u_H", "bow_phi", "bow_vrel"):
         setattr(out, key, _ptr(arrs[key]))
     st = lib.orc_run(C.byref(_string(p)), C.byref(_exc(e)), C.byref(out))
     if st != 0 and not allow_fail:

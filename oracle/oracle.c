@@ -16,7 +16,9 @@
  *   interpolants  I_(l)->(t), I_(t)->(l) of Sec. 3.1
  *   blocks        Q+-, K^(tl), K^(lt), V, Lambda, G, S, Theta of eq. (9)
  *   recursion     eq. (7)-(8), excitation Gamma of eq. (6) solved jointly
- *                 with the string (Sec. 3.3 / 3.4)
+ *                 with the string (Sec. 3.3 / 3.4); the bow of eq. (5) by
+ *                 one extra solve A g = [J; 0] and the step's scalar
+ *                 stick/slip problem
  * Readings of passages that are silent or inconsistent are marked READING.
  */
 #include "oracle.h"
@@ -583,7 +585,7 @@ typedef struct {
 
 static int exc_validate(const orc_excitation *e) {
     if (!e) return ORC_OK;
-    if (e->type < 0 || e->type > 2) return ORC_EINVAL;
+    if (e->type < 0 || e->type > 3) return ORC_EINVAL;
     if (e->type == 0) return ORC_OK;
     if (!(e->x > 0.0 && e->x < 1.0)) return ORC_EINVAL;
     if (e->type == 1 && !isfinite(e->c0)) return ORC_EINVAL;
@@ -591,7 +593,86 @@ static int exc_validate(const orc_excitation *e) {
         if (!(e->M_H > 0.0) || !(e->K_H > 0.0) || !(e->alpha_H >= 1.0) || !(e->rhoA > 0.0)) return ORC_EINVAL;
         if (!isfinite(e->v_H) || !isfinite(e->M_H) || !isfinite(e->K_H) || !isfinite(e->alpha_H)) return ORC_EINVAL;
     }
+    if (e->type == 3) {
+        if (!(e->x_end > 0.0 && e->x_end < 1.0) || !isfinite(e->v_B) || !(e->F_B >= 0.0) || !isfinite(e->F_B))
+            return ORC_EINVAL;
+        if (!(e->attack >= 0.0) || !(e->fric_a >= 0.0) || !isfinite(e->fric_a)) return ORC_EINVAL;
+        if (!(e->fric_eps >= 0.0 && e->fric_eps <= 1.0)) return ORC_EINVAL;
+    }
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bow (eq. 5)                                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int on;
+    double x0, x1, T;              /* position x0 -> x1 over the note of length T */
+    double vB, FB, ta;             /* bow velocity and force, attack time */
+    double a, eps;                 /* friction curve */
+} bow_t;
+
+/* Control values at time t.  READING: the paper gives the controls as
+ * time-varying without their form; here force and velocity rise linearly
+ * over the attack and then hold, and the position moves linearly. */
+static void bow_controls(const bow_t *bw, double t, double *x, double *vB, double *FB) {
+    double r = bw->ta > 0.0 ? (t < bw->ta ? t / bw->ta : 1.0) : 1.0;
+    double q = bw->T > 0.0 ? (t < bw->T ? t / bw->T : 1.0) : 0.0;
+    *x = bw->x0 + (bw->x1 - bw->x0) * q;
+    *vB = bw->vB * r;
+    *FB = bw->FB * r;
+}
+
+/* The step's scalar problem.  With w* the solution of eq. (7) without the
+ * bow and g = A^{-1} [J_p(x_B); 0], the bow adds -k^2 F_B phi g, so
+ *     v_rel = I_p(x_B)(u^{n+1} - u^{n-1}) / 2k - v_B = b - c phi,
+ *     b = I_p(x_B)(u* - u^{n-1}) / 2k - v_B,   c = k F_B I_p(x_B) g / 2 >= 0.
+ * READING (the paper names Newton-Raphson without the treatment of the
+ * curve's jump at v_rel = 0, and writes eta for v_rel in phi): phi(0) is any
+ * value in [-1, 1] (static friction).  If |b| <= c the string sticks to the
+ * bow: v_rel = 0, phi = b/c.  Otherwise it slips with v_rel = sign(b) x, where
+ * x in (0, |b|) is the one root of x + c (eps + (1-eps) e^{-a x}) = |b| (the
+ * left side is convex in x and below |b| at 0), found by Newton's method
+ * kept inside a shrinking bracket. */
+double orc_bow_solve(double b, double c, double a, double eps, double *v) {
+    if (!(c > 0.0)) {            /* no bow force */
+        *v = b;
+        return 0.0;
+    }
+    if (fabs(b) <= c) {
+        *v = 0.0;
+        return b / c;
+    }
+    double sg = b > 0.0 ? 1.0 : -1.0, ab = fabs(b);
+    double lo = 0.0, hi = ab, x = ab;
+    for (int it = 0; it < 200; ++it) {
+        double ex = exp(-a * x);
+        double h = x + c * (eps + (1.0 - eps) * ex) - ab;
+        if (h == 0.0) break;
+        if (h > 0.0) hi = x; else lo = x;
+        double dh = 1.0 - c * (1.0 - eps) * a * ex;
+        double xn = dh > 0.0 ? x - h / dh : 0.5 * (lo + hi);
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        if (fabs(xn - x) <= 4e-16 * ab || hi - lo <= 4e-16 * ab) { x = xn; break; }
+        x = xn;
+    }
+    *v = sg * x;
+    return sg * (eps + (1.0 - eps) * exp(-a * x));
+}
+
+static void bow_setup(const orc_excitation *e, const orc_string *s, bow_t *bw) {
+    memset(bw, 0, sizeof(*bw));
+    if (!e || e->type != 3) return;
+    bw->on = 1;
+    bw->x0 = e->x;
+    bw->x1 = e->x_end;
+    bw->T = (double)s->n_samples / s->fs;
+    bw->vB = e->v_B;
+    bw->FB = e->F_B;
+    bw->ta = e->attack;
+    bw->a = e->fric_a;
+    bw->eps = e->fric_eps;
 }
 
 /* Contact coefficient at time n of eq. (6): F_H = c_n (eta^{n+1} + eta^{n-1})
@@ -772,12 +853,16 @@ int orc_run(const orc_string *s, const orc_excitation *e, orc_outputs *out) {
     ops_build(s, &g, &o);
     hammer_t hm;
     hammer_setup(e, &g, &hm);
+    bow_t bw;
+    bow_setup(e, s, &bw);
     int n = o.n, nt = o.nt, nl = o.nl, Ns = (int)s->n_samples;
     /* three rotating time levels; each has room for the hammer unknown */
     double *w0 = (double *)calloc((size_t)n + 1, sizeof(double));   /* w^{n-1} */
     double *w1 = (double *)calloc((size_t)n + 1, sizeof(double));   /* w^n     */
     double *w2 = (double *)calloc((size_t)n + 1, sizeof(double));   /* w^{n+1} (+ u_H^{n+1}) */
     double *rhs = (double *)calloc((size_t)n + 1, sizeof(double));
+    double *gb = bw.on ? (double *)calloc((size_t)n + 1, sizeof(double)) : NULL;   /* A^{-1} [J_B; 0] */
+    double *rb = bw.on ? (double *)calloc((size_t)n + 1, sizeof(double)) : NULL;
     double uH0 = 0.0, uH1 = 0.0;
     int io[2]; double wo[2];
     interp_row(s->x_out, g.N_t, io, wo);
@@ -798,6 +883,7 @@ int orc_run(const orc_string *s, const orc_excitation *e, orc_outputs *out) {
          * velocity v_H: u_H^0 = 0, u_H^1 = k v_H */
         uH0 = 0.0; uH1 = g.k * e->v_H;
     }
+    /* the bow starts on the string at rest (w^0 = w^1 = 0) */
     int *perm = position_order(&o, hm.on, e && e->type == 2 ? e->x : 0.0);
 
     double flops = 0.0;
@@ -814,6 +900,8 @@ int orc_run(const orc_string *s, const orc_excitation *e, orc_outputs *out) {
         out->energy[0] = energy_half(s, &o, orc_gamma_at(s, 0), w1, w0, w1 + nt, w0 + nt);
         out->energy[Ns - 1] = 0.0;
     }
+    if (out->bow_phi) memset(out->bow_phi, 0, sizeof(double) * (size_t)Ns);
+    if (out->bow_vrel) memset(out->bow_vrel, 0, sizeof(double) * (size_t)Ns);
     int status = ORC_OK;
     int64_t steps = 0;
     for (int step = 1; step <= Ns - 2; ++step) {
@@ -824,6 +912,26 @@ int orc_run(const orc_string *s, const orc_excitation *e, orc_outputs *out) {
         if (hm.on) c_n = hammer_c(&hm, uH1 - interp_apply(hm.iH, hm.wH, w1));
         csr M = joint_build(&o, &sy, &hm, c_n, w1, w0, uH1, uH0, rhs, &flops);
         status = band_solve(&M, perm, rhs, w2, &flops);
+        if (!status && bw.on) {
+            /* eq. (5): Gamma^n = k^2 [J_B F_B phi; 0] (friction against v_rel) */
+            double xB, vB, FB;
+            bow_controls(&bw, step * g.k, &xB, &vB, &FB);
+            int iB[2]; double wB[2];
+            interp_row(xB, g.N_t, iB, wB);
+            memset(rb, 0, sizeof(double) * (size_t)(n + 1));
+            for (int a = 0; a < 2; ++a)
+                if (iB[a] >= 0) rb[iB[a]] += wB[a] / g.h_t;
+            status = band_solve(&M, perm, rb, gb, &flops);
+            if (!status) {
+                double c = g.k * FB * interp_apply(iB, wB, gb) / 2.0;
+                double b = (interp_apply(iB, wB, w2) - interp_apply(iB, wB, w0)) / (2.0 * g.k) - vB;
+                double vrel;
+                double phi = orc_bow_solve(b, c, bw.a, bw.eps, &vrel);
+                for (int i = 0; i < n; ++i) w2[i] -= g.k * g.k * FB * phi * gb[i];
+                if (out->bow_phi) out->bow_phi[step] = phi;
+                if (out->bow_vrel) out->bow_vrel[step] = vrel;
+            }
+        }
         csr_free(&M);
         system_free(&sy);
         if (status) break;
@@ -842,7 +950,7 @@ int orc_run(const orc_string *s, const orc_excitation *e, orc_outputs *out) {
     }
     out->flops = flops;
     out->steps_done = steps;
-    free(perm); free(w0); free(w1); free(w2); free(rhs);
+    free(perm); free(w0); free(w1); free(w2); free(rhs); free(gb); free(rb);
     ops_free(&o);
     return status;
 }

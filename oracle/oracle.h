@@ -43,15 +43,20 @@ typedef struct {
 } orc_string;
 
 typedef struct {
-    int32_t type;         /* 0 none, 1 pluck (initial condition), 2 hammer (eq. 6) */
+    int32_t type;         /* 0 none, 1 pluck (initial condition), 2 hammer (eq. 6), 3 bow (eq. 5) */
     int32_t pad0;
-    double x;             /* excitation position in (0,1) */
+    double x;             /* excitation position in (0,1); the bow's position at t = 0 */
     double c0;            /* pluck peak displacement [m] */
     double v_H;           /* hammer initial velocity [m/s] */
     double M_H;           /* hammer mass [kg] */
     double K_H;           /* hammer felt stiffness [N/m^alpha_H] */
     double alpha_H;       /* hammer nonlinear exponent */
     double rhoA;          /* string linear mass density [kg/m] */
+    /* bow (eq. 5): position x -> x_end linearly over the note (T = n_samples/fs),
+     * bow velocity v_B [m/s] and force F_B (per unit linear density, m/s^2 on
+     * the normalised string) rising linearly over `attack` seconds; friction
+     * curve phi(v) = sign(v) (eps + (1 - eps) exp(-a |v|)) */
+    double x_end, v_B, F_B, attack, fric_a, fric_eps;
 } orc_excitation;
 
 typedef struct {
@@ -71,6 +76,8 @@ typedef struct {
     double flops;         /* out: floating point operations of the RHS matvecs and the
                              banded factor/solve (the direct method's arithmetic)     */
     int64_t steps_done;   /* out: number of recursion steps taken                      */
+    double *bow_phi;      /* [n_samples]  bow: friction value phi used at step n        */
+    double *bow_vrel;     /* [n_samples]  bow: relative velocity v_rel at step n        */
 } orc_outputs;
 
 /* status codes */
@@ -91,6 +98,11 @@ int orc_dump_system(const orc_string *s, const orc_excitation *e, int64_t n,
 
 /* gamma^n = 2 f0(n k) under the modulation of the string (Sec. 1 abstract). */
 double orc_gamma_at(const orc_string *s, int64_t n);
+
+/* The bow's scalar problem of one step (eq. 5): v = b - c phi with phi the
+ * friction curve at v (slip, v != 0) or any value in [-1, 1] at v = 0
+ * (stick).  Returns phi and stores v. */
+double orc_bow_solve(double b, double c, double a, double eps, double *v);
 
 #ifdef __cplusplus
 }

@@ -48,6 +48,20 @@ def hammer(x, v_H, M_H=HAMMER["M_H"], K_H=HAMMER["K_H"], alpha_H=HAMMER["alpha_H
                 alpha_H=float(alpha_H), rhoA=float(rhoA))
 
 
+def bow(x, v_B, F_B, x_end=None, attack=0.02, fric_a=100.0, fric_eps=0.2) -> dict:
+    """Bow (eq. 5) at x (moving linearly to x_end over the note), bow speed v_B
+    [m/s] and force F_B, both rising over `attack` seconds; friction curve
+    parameters a and eps."""
+    return dict(type=3, x=float(x), c0=0.0, x_end=float(x if x_end is None else x_end), v_B=float(v_B),
+                F_B=float(F_B), attack=float(attack), fric_a=float(fric_a), fric_eps=float(fric_eps))
+
+
+def single_bowed(seconds: float = 0.5):
+    """A linear string of 110 Hz bowed at 0.12 (stick-slip locked to f0)."""
+    p = string(110.0, 1e-4, 1.0, 0.5, 1e-4, int(round(seconds * FS)))
+    return p, bow(0.12, 0.1, 100.0)
+
+
 def single_linear(seconds: float = 1.0, theta: float = 0.0):
     """Single linear stiff string: fs 48 kHz, f0 110 Hz, B 1e-4, sigma0 1, sigma1 5e-4,
     pluck at 0.2 with peak 1e-3, readout at 0.8, fixed ends, alpha = 1."""

@@ -325,3 +325,125 @@ def test_golden_paper_constants():
     # gamma = 2 f0 and kappa from K = (pi kappa / gamma)^2
     assert abs(g["gamma0"] - 2 * p["f0"]) == 0
     assert abs(g["kappa"] - gold["kappa_config1"]["value"]) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Bow (eq. 5)
+# ---------------------------------------------------------------------------
+
+def _bow_controls(e, p, t):
+    """x_B, v_B, F_B at time t (linear attack, linear position sweep)."""
+    r = min(1.0, t / e["attack"]) if e["attack"] > 0 else 1.0
+    T = p["n_samples"] / p["fs"]
+    return e["x"] + (e["x_end"] - e["x"]) * min(1.0, t / T), e["v_B"] * r, e["F_B"] * r
+
+
+def _interp(x, N, u):
+    """Linear interpolation of interior-node values u (nodes 1..N-1) at x; ends are 0."""
+    l = int(math.floor(x * N))
+    w = x * N - l
+    full = np.concatenate([[0.0], u, [0.0]])
+    return (1 - w) * full[l] + w * full[min(l + 1, N)]
+
+
+def _friction(v, a, eps):
+    return math.copysign(eps + (1 - eps) * math.exp(-a * abs(v)), v)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 2.0])
+def test_pb1_bow_energy_balance(alpha):
+    """Lossless string: H^{n+1/2} - H^{n-1/2} = -k F_B phi I_p(x_B) delta_t. u^n,
+    the work of the friction force, with the bow position moving."""
+    p = W.string(110.0, 1e-4, alpha, 0.0, 0.0, 4800)
+    p = dict(p, sigma0_t=0.0, sigma1_t=0.0, sigma0_l=0.0, sigma1_l=0.0)
+    e = W.bow(0.12, 0.1, 100.0, x_end=0.2)
+    r = oracle.run(p, e, want=("traj_u", "energy", "bow_phi"))
+    g = r["grid"]
+    k, N = g["k"], g["N_t"]
+    U, H, phi = r["traj_u"], r["energy"], r["bow_phi"]
+    worst = 0.0
+    for n in range(1, len(H) - 1):
+        xB, _, FB = _bow_controls(e, p, n * k)
+        work = k * FB * phi[n] * (_interp(xB, N, U[n + 1]) - _interp(xB, N, U[n - 1])) / (2 * k)
+        worst = max(worst, abs((H[n] - H[n - 1]) + work))
+    assert np.max(np.abs(H)) > 1e-3
+    assert worst <= 1e-12 * np.max(np.abs(H))
+
+
+def test_pb2_bow_friction_law_stick_or_slip():
+    """Every step either sticks (v_rel = 0 from the trajectory, |phi| <= 1) or
+    slips with phi on the friction curve at the trajectory's v_rel."""
+    p, e = W.single_bowed(seconds=0.1)
+    e = dict(e, x_end=0.16)
+    r = oracle.run(p, e, want=("traj_u", "bow_phi", "bow_vrel"))
+    g = r["grid"]
+    k, N = g["k"], g["N_t"]
+    U, phi, vrel = r["traj_u"], r["bow_phi"], r["bow_vrel"]
+    n_stick = n_slip = 0
+    for n in range(1, len(phi) - 1):
+        xB, vB, FB = _bow_controls(e, p, n * k)
+        v = (_interp(xB, N, U[n + 1]) - _interp(xB, N, U[n - 1])) / (2 * k) - vB
+        assert abs(v - vrel[n]) <= 1e-9 * e["v_B"]
+        if vrel[n] == 0.0:
+            n_stick += 1
+            assert abs(v) <= 1e-9 * e["v_B"]
+            assert abs(phi[n]) <= 1.0
+        else:
+            n_slip += 1
+            assert abs(phi[n] - _friction(v, e["fric_a"], e["fric_eps"])) <= 1e-9
+    assert n_stick > 100 and n_slip > 100
+
+
+def _brute_bow(b, c, a, eps):
+    """Stick if |b| <= c; else the root of x + c f(x) = |b| on (0, |b|) by a
+    dense scan for the sign change and bisection."""
+    if c <= 0:
+        return 0.0, b
+    if abs(b) <= c:
+        return b / c, 0.0
+    s, ab = math.copysign(1.0, b), abs(b)
+    h = lambda x: x + c * (eps + (1 - eps) * math.exp(-a * x)) - ab
+    xs = np.linspace(0.0, ab, 2001)
+    hs = np.array([h(x) for x in xs])
+    i = int(np.nonzero(hs > 0)[0][0])
+    lo, hi = xs[i - 1], xs[i]
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if h(mid) > 0:
+            hi = mid
+        else:
+            lo = mid
+    x = 0.5 * (lo + hi)
+    return s * (eps + (1 - eps) * math.exp(-a * x)), s * x
+
+
+def test_pb3_bow_scalar_solve_against_brute_force():
+    rng = np.random.default_rng(7)
+    for _ in range(400):
+        b = rng.uniform(-0.5, 0.5)
+        c = rng.choice([0.0, rng.uniform(0.0, 0.3)])
+        a = rng.uniform(0.0, 300.0)
+        eps = rng.uniform(0.0, 1.0)
+        phi, v = oracle.bow_solve(b, c, a, eps)
+        phi_r, v_r = _brute_bow(b, c, a, eps)
+        assert abs(v - v_r) <= 1e-12 * max(1.0, abs(b))
+        if c > 0:
+            assert abs(phi - phi_r) <= 1e-9
+            assert abs(v + c * phi - b) <= 1e-14 * max(1.0, abs(b))
+
+
+def test_pb4_bowed_string_locks_to_the_fundamental():
+    """Stick-slip motion: the steady output repeats at the string's period
+    (Helmholtz motion), with both stick and slip in every period."""
+    p, e = W.single_bowed(seconds=0.3)
+    r = oracle.run(p, e, want=("y_u", "bow_vrel"))
+    y, vrel = r["y_u"], r["bow_vrel"]
+    n = len(y)
+    z = y[n // 2:] - y[n // 2:].mean()
+    ac = np.correlate(z, z, "full")[len(z) - 1:]
+    T0 = p["fs"] / p["f0"]
+    lag = int(np.argmax(ac[int(0.5 * T0):int(1.5 * T0)])) + int(0.5 * T0)
+    assert abs(lag - T0) <= 0.01 * T0
+    late = vrel[n // 2:n - 1]
+    stick = np.mean(late == 0.0)
+    assert 0.1 < stick < 0.9
