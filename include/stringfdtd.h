@@ -50,6 +50,7 @@ extern "C" {
 #define SB_EXC_NONE    0
 #define SB_EXC_PLUCK   1
 #define SB_EXC_HAMMER  2
+#define SB_EXC_BOW     3   /* batched paths only */
 
 /* f0 modulation types */
 #define SB_MOD_NONE    0
@@ -88,13 +89,24 @@ typedef struct {
 /* Excitation (Sec. 3.3).  Pluck: initial triangle of peak c0 at x, released
  * from rest.  Hammer (eq. 6): lumped mass M_H [kg] at x with initial velocity
  * v_H [m/s], felt force K_H max(0, compression)^alpha_H, mass ratio
- * M_H / (rhoA * 1 m); starts touching the string at rest. */
+ * M_H / (rhoA * 1 m); starts touching the string at rest.  Bow (eq. 5): the
+ * string starts at rest; the term -J_p(x_B) F_B phi(v_rel) acts on u with
+ * v_rel = I_p(x_B) delta_t. u - v_B and the friction curve
+ * phi(v) = sign(v) (fric_eps + (1 - fric_eps) exp(-fric_a |v|)); at
+ * v_rel = 0 the string sticks (|phi| <= 1).  F_B (force per unit linear
+ * density, m/s^2 on the string of length 1) and v_B [m/s] rise linearly over
+ * `attack` seconds; the position moves linearly from x to x_end over the note
+ * (n_samples / fs).  Each step solves the stick/slip problem exactly inside
+ * the coupled solve.  SB_FP64_PLAIN does not take a bow (SB_EINVAL). */
 typedef struct {
     int32_t type;              /* SB_EXC_*                                        */
     int32_t reserved;
-    double x;                  /* position in (0,1)                               */
+    double x;                  /* position in (0,1); the bow's at t = 0           */
     double c0;                 /* pluck peak [m]                                  */
     double v_H, M_H, K_H, alpha_H, rhoA;
+    double x_end;              /* bow position at the end of the note, in (0,1)   */
+    double v_B, F_B, attack;   /* bow speed [m/s], force (>= 0), attack [s]       */
+    double fric_a, fric_eps;   /* friction curve: a >= 0 [s/m], 0 <= eps <= 1     */
 } sb_excitation;
 
 /* Per-slot information (grid sizes and progress). */

@@ -40,7 +40,8 @@ class SbExcitation(C.Structure):
     _fields_ = [
         ("type", C.c_int32), ("reserved", C.c_int32), ("x", C.c_double), ("c0", C.c_double),
         ("v_H", C.c_double), ("M_H", C.c_double), ("K_H", C.c_double), ("alpha_H", C.c_double),
-        ("rhoA", C.c_double),
+        ("rhoA", C.c_double), ("x_end", C.c_double), ("v_B", C.c_double), ("F_B", C.c_double),
+        ("attack", C.c_double), ("fric_a", C.c_double), ("fric_eps", C.c_double),
     ]
 
 
@@ -138,6 +139,8 @@ def excitation_struct(e: dict) -> SbExcitation:
     for f, _ in SbExcitation._fields_:
         if f in e:
             setattr(s, f, e[f])
+    if e.get("type") == 3 and "x_end" not in e:
+        s.x_end = s.x          # a bow that stays in place
     return s
 
 

@@ -15,9 +15,9 @@
 #include "sfd_types.h"
 
 namespace sfd {
-hipError_t launch_unit(int precision, int unit, const LaunchArgs &a, int blocks, hipStream_t st);
+hipError_t launch_unit(int precision, int unit, bool bow, const LaunchArgs &a, int blocks, hipStream_t st);
 hipError_t launch_zero(int32_t *c, int n, hipStream_t st);
-int max_blocks_per_cu(int precision, int unit);
+int max_blocks_per_cu(int precision, int unit, bool bow);
 hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
                          hipStream_t st);
 hipError_t launch_scatter(const void *src, const UploadSeg *segs, int n, hipStream_t st);
@@ -290,7 +290,7 @@ static_assert(kNumUnits == SB_NUM_LAUNCHES, "launch units of the C ABI");
 
 // task lists (strings, padded per class to whole tasks) and the ticket map of
 // the merged launch (at most one ticket per string)
-static size_t work_capacity(int capacity) { return 2 * (size_t)capacity + (size_t)kNumClasses * kWave; }
+static size_t work_capacity(int capacity) { return 2 * (size_t)capacity + 2 * (size_t)kNumClasses * kWave; }
 
 static bool range_ok(const sb_batch *b, int first, int count) {
   return first >= 0 && count >= 0 && (int64_t)first + count <= b->capacity;
@@ -392,6 +392,10 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     Plan tmp = b->slots[first + i].plan;
     std::string err;
     int st = plan_excitation(e[i], tmp, err);
+    if (!st && b->precision == SB_FP64_PLAIN && e[i].type == SB_EXC_BOW) {
+      err = "the plain path takes no bow";
+      st = SB_EINVAL;
+    }
     if (!st && b->precision == SB_FP64_PLAIN) st = plan_plain(tmp, err);
     if (st) return fail(b, st, "slot " + std::to_string(first + i) + ": " + err);
   }
@@ -520,15 +524,17 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
 // wavefront tasks of 64/G strings with similar remaining work side by side (a
 // wavefront runs as long as its longest string), longest tasks first; the
 // device copy is refreshed when it changes.
+// Variant 1 holds the tasks with bowed strings: they run in kernels of their
+// own, which keeps the bow's code and registers out of every other task.
 struct WorkPlan {
-  std::vector<int> off = std::vector<int>(kNumClasses + 1, 0);
-  int tickets_off = 0, n_tickets = 0;   // ticket map of the merged launch
+  int off[2][kNumClasses + 1] = {};      // per variant, start of each class's tasks
+  int tickets_off[2] = {}, n_tickets[2] = {};   // ticket maps of the merged launches
   std::vector<int> members;   // slots stepped
 };
 
 
 static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPlan &wp) {
-  std::vector<std::vector<std::pair<double, int>>> cls(kNumClasses);
+  std::vector<std::pair<double, int>> cls[2][kNumClasses];
   bool any = false;
   for (int i = first; i < first + count; ++i) {
     Slot &s = b->slots[i];
@@ -538,40 +544,43 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
     const int64_t st = std::min<int64_t>(n_steps, s.plan.desc.n_samples - s.samples_host);
     const double cost = (double)st * (double)(s.plan.desc.nt + s.plan.desc.nl + 8);
     const int c = b->precision == SB_FP64_PLAIN ? 0 : s.plan.desc.cls;
-    cls[c].push_back({cost, i});
+    cls[s.plan.desc.bow_on ? 1 : 0][c].push_back({cost, i});
   }
   if (!any) return fail(b, SB_ESTATE, "no excited slot");
   std::vector<int32_t> work;
-  for (int c = 0; c < kNumClasses; ++c) {
-    std::stable_sort(cls[c].begin(), cls[c].end(), [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
-      return x.first > y.first;
-    });
-    wp.off[c] = (int)work.size();
-    const int groups = b->precision == SB_FP64_PLAIN ? 1 : kWave / kClassLanes[c];
-    for (size_t i = 0; i < cls[c].size(); i += groups)
-      for (int g = 0; g < groups; ++g) work.push_back(i + g < cls[c].size() ? cls[c][i + g].second : -1);
-    for (auto &w : cls[c]) wp.members.push_back(w.second);
-  }
-  wp.off[kNumClasses] = (int)work.size();
-  if (b->precision != SB_FP64_PLAIN) {
-    // tickets of the merged launch: the tasks of classes 0..3 dealt out in
-    // proportion to their counts (task t of a class of n tasks at t / n), each
-    // class longest first.  The mix of classes on the CUs then stays the same
-    // over the whole launch, which runs faster than one class after another
-    // (their bottlenecks differ), and the shortest tasks of every class fill
-    // the tail.
-    std::vector<std::pair<double, int32_t>> tk;
-    for (int c = 0; c < kNumSmall; ++c) {
-      const int groups = kWave / kClassLanes[c];
-      const int nt = (int)((cls[c].size() + groups - 1) / groups);
-      for (int t = 0; t < nt; ++t) tk.push_back({-(double)t / (double)nt, (int32_t)((c << 24) | t)});
+  for (int v = 0; v < 2; ++v) {
+    for (int c = 0; c < kNumClasses; ++c) {
+      auto &L = cls[v][c];
+      std::stable_sort(L.begin(), L.end(), [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
+        return x.first > y.first;
+      });
+      wp.off[v][c] = (int)work.size();
+      const int groups = b->precision == SB_FP64_PLAIN ? 1 : kWave / kClassLanes[c];
+      for (size_t i = 0; i < L.size(); i += groups)
+        for (int g = 0; g < groups; ++g) work.push_back(i + g < L.size() ? L[i + g].second : -1);
+      for (auto &w : L) wp.members.push_back(w.second);
     }
-    std::stable_sort(tk.begin(), tk.end(), [](const std::pair<double, int32_t> &x, const std::pair<double, int32_t> &y) {
-      return x.first > y.first;
-    });
-    wp.tickets_off = (int)work.size();
-    wp.n_tickets = (int)tk.size();
-    for (auto &t : tk) work.push_back(t.second);
+    wp.off[v][kNumClasses] = (int)work.size();
+    if (b->precision != SB_FP64_PLAIN) {
+      // tickets of the merged launch: the tasks of classes 0..3 dealt out in
+      // proportion to their counts (task t of a class of n tasks at t / n),
+      // each class longest first.  The mix of classes on the CUs then stays
+      // the same over the whole launch, which runs faster than one class
+      // after another (their bottlenecks differ), and the shortest tasks of
+      // every class fill the tail.
+      std::vector<std::pair<double, int32_t>> tk;
+      for (int c = 0; c < kNumSmall; ++c) {
+        const int groups = kWave / kClassLanes[c];
+        const int nt = (int)((cls[v][c].size() + groups - 1) / groups);
+        for (int t = 0; t < nt; ++t) tk.push_back({-(double)t / (double)nt, (int32_t)((c << 24) | t)});
+      }
+      std::stable_sort(tk.begin(), tk.end(), [](const std::pair<double, int32_t> &x, const std::pair<double, int32_t> &y) {
+        return x.first > y.first;
+      });
+      wp.tickets_off[v] = (int)work.size();
+      wp.n_tickets[v] = (int)tk.size();
+      for (auto &t : tk) work.push_back(t.second);
+    }
   }
   if (work.empty() || b->precision == SB_FP64_PLAIN) {
     b->h_plain = std::move(work);
@@ -597,48 +606,62 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
 // forked onto their own streams and joined back.  Issues no synchronisation
 // and no copy, so it can be captured.
 static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t n_steps) {
-  hipError_t e = launch_zero(b->d_counters, kNumUnits, st);
+  hipError_t e = launch_zero(b->d_counters, 2 * kNumUnits, st);
   if (e == hipSuccess) e = hipEventRecord(b->ev_fork, st);
   if (e != hipSuccess) return hip_fail(b, e, "fork");
-  int tasks[kNumClasses];
-  for (int c = 0; c < kNumClasses; ++c) tasks[c] = (wp.off[c + 1] - wp.off[c]) / (kWave / kClassLanes[c]);
   // largest strings first: their launches hold the longest per-step latency
   for (int u = kNumUnits - 1; u >= 0; --u) {
-    LaunchArgs a;
-    a.desc = b->d_desc;
-    a.status = b->d_status;
-    int strings = 0;
-    if (u == 0) {
-      for (int c = 0; c < kNumSmall; ++c) a.part_work[c] = b->d_work + wp.off[c];
-      a.tickets = b->d_work + wp.tickets_off;
-      a.work = b->d_work;
-      a.n_work = wp.n_tickets;
-      for (int k = wp.off[0]; k < wp.off[kNumSmall]; ++k) strings += b->h_work[k] >= 0 ? 1 : 0;
-    } else {
-      const int c = kNumSmall + u - 1;
-      a.work = b->d_work + wp.off[c];
-      a.n_work = tasks[c];
-      for (int p = 0; p < kNumSmall; ++p) a.part_work[p] = nullptr;
-      a.tickets = nullptr;
-      for (int k = wp.off[c]; k < wp.off[c + 1]; ++k) strings += b->h_work[k] >= 0 ? 1 : 0;
-    }
-    b->unit_strings[u] = strings;
-    if (a.n_work == 0) continue;
-    a.counter = b->d_counters + u;
-    a.n_steps = n_steps;
-    a.mon_period = b->mon_period;
-    a.max_sweeps = b->max_sweeps;
-    a.tol = b->tol;
-    a.mon_tol = b->mon_tol;
-    a.trash_st = b->d_trash;
-    a.trash_status = b->d_trash_status;
-    const int per_cu = b->blocks_per_cu[u] > 0 ? b->blocks_per_cu[u] : std::max(1, max_blocks_per_cu(b->precision, u));
-    const int blocks = std::min(a.n_work, b->num_cu * per_cu);
     hipStream_t cs = b->unit_stream[u];
-    e = hipStreamWaitEvent(cs, b->ev_fork, 0);
-    if (e == hipSuccess) e = hipEventRecord(b->ev_t0[u], cs);
-    if (e == hipSuccess) e = launch_unit(b->precision, u, a, blocks, cs);
-    if (e == hipSuccess) e = hipEventRecord(b->ev_t1[u], cs);
+    b->unit_strings[u] = 0;
+    bool forked = false;
+    // the bowed variant follows the other on the same stream
+    for (int v = 0; v < 2; ++v) {
+      LaunchArgs a;
+      a.desc = b->d_desc;
+      a.status = b->d_status;
+      int lo, hi;
+      if (u == 0) {
+        for (int c = 0; c < kNumSmall; ++c) a.part_work[c] = b->d_work + wp.off[v][c];
+        a.tickets = b->d_work + wp.tickets_off[v];
+        a.work = b->d_work + wp.off[v][0];
+        a.n_work = wp.n_tickets[v];
+        lo = wp.off[v][0];
+        hi = wp.off[v][kNumSmall];
+      } else {
+        const int c = kNumSmall + u - 1;
+        a.work = b->d_work + wp.off[v][c];
+        a.n_work = (wp.off[v][c + 1] - wp.off[v][c]) / (kWave / kClassLanes[c]);
+        for (int p = 0; p < kNumSmall; ++p) a.part_work[p] = nullptr;
+        a.tickets = nullptr;
+        lo = wp.off[v][c];
+        hi = wp.off[v][c + 1];
+      }
+      for (int k = lo; k < hi; ++k) b->unit_strings[u] += b->h_work[k] >= 0 ? 1 : 0;
+      if (a.n_work == 0) continue;
+      a.counter = b->d_counters + 2 * u + v;
+      a.n_steps = n_steps;
+      a.mon_period = b->mon_period;
+      a.max_sweeps = b->max_sweeps;
+      a.tol = b->tol;
+      a.mon_tol = b->mon_tol;
+      a.trash_st = b->d_trash;
+      a.trash_status = b->d_trash_status;
+      int per_cu = b->blocks_per_cu[u];
+      if (per_cu <= 0 || v == 1) {
+        const int occ = std::max(1, max_blocks_per_cu(b->precision, u, v == 1));
+        per_cu = per_cu > 0 ? std::min(per_cu, occ) : occ;
+      }
+      const int blocks = std::min(a.n_work, b->num_cu * per_cu);
+      if (!forked) {
+        e = hipStreamWaitEvent(cs, b->ev_fork, 0);
+        if (e == hipSuccess) e = hipEventRecord(b->ev_t0[u], cs);
+        forked = true;
+      }
+      if (e == hipSuccess) e = launch_unit(b->precision, u, v == 1, a, blocks, cs);
+      if (e != hipSuccess) return hip_fail(b, e, "step launch");
+    }
+    if (!forked) continue;
+    e = hipEventRecord(b->ev_t1[u], cs);
     if (e == hipSuccess) e = hipEventRecord(b->ev_join[u], cs);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[u], 0);
     if (e != hipSuccess) return hip_fail(b, e, "step launch");
@@ -750,9 +773,11 @@ extern "C" int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *
     return x == hipSuccess ? SB_OK : hip_fail(b, x, "autotune");
   };
   int occ[kNumUnits], nw[kNumUnits] = {};
-  for (int c = 0; c < kNumClasses; ++c) nw[unit_of_class(c)] += (wp.off[c + 1] - wp.off[c]) / (kWave / kClassLanes[c]);
+  for (int v = 0; v < 2; ++v)
+    for (int c = 0; c < kNumClasses; ++c)
+      nw[unit_of_class(c)] += (wp.off[v][c + 1] - wp.off[v][c]) / (kWave / kClassLanes[c]);
   for (int u = 0; u < kNumUnits; ++u) {
-    occ[u] = std::max(1, max_blocks_per_cu(b->precision, u));
+    occ[u] = std::max(1, max_blocks_per_cu(b->precision, u, false));
     b->blocks_per_cu[u] = occ[u];
     if (chosen) chosen[u] = 0;
   }

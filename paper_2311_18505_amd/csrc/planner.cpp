@@ -257,11 +257,12 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
 
 int plan_excitation(const sb_excitation &e, Plan &P, std::string &err) {
   Desc &D = P.desc;
-  if (e.type < 0 || e.type > 2) {
+  if (e.type < 0 || e.type > 3) {
     err = "bad excitation type";
     return SB_EINVAL;
   }
-  if (!finite_all({e.x, e.c0, e.v_H, e.M_H, e.K_H, e.alpha_H})) {
+  if (!finite_all({e.x, e.c0, e.v_H, e.M_H, e.K_H, e.alpha_H}) ||
+      (e.type == 3 && !finite_all({e.x_end, e.v_B, e.F_B, e.attack, e.fric_a, e.fric_eps}))) {
     err = "non-finite excitation parameter";
     return SB_EINVAL;
   }
@@ -273,8 +274,28 @@ int plan_excitation(const sb_excitation &e, Plan &P, std::string &err) {
     err = "hammer needs M_H, K_H, rhoA > 0 and alpha_H >= 1";
     return SB_EINVAL;
   }
+  if (e.type == 3 && (!(e.x_end > 0 && e.x_end < 1) || !(e.F_B >= 0) || !(e.attack >= 0) || !(e.fric_a >= 0) ||
+                      !(e.fric_eps >= 0 && e.fric_eps <= 1))) {
+    err = "bow needs x_end in (0,1), F_B >= 0, attack >= 0, fric_a >= 0 and fric_eps in [0,1]";
+    return SB_EINVAL;
+  }
   const int Nt = D.Nt, mt = D.mt, ml = D.ml, nt = D.nt;
   const int G = kClassLanes[D.cls];
+  D.bow_on = e.type == 3;
+  D.bow_moves = e.type == 3 && e.x_end != e.x;
+  D.bx0 = D.bx1 = D.bT = D.bvB = D.bFB = D.bta = D.ba = D.beps = 0.0;
+  if (e.type == 3) {
+    D.bx0 = e.x;
+    D.bx1 = e.x_end;
+    D.bT = (double)D.n_samples / D.fs;
+    D.bvB = e.v_B;
+    D.bFB = e.F_B;
+    D.bta = e.attack;
+    D.ba = e.fric_a;
+    D.beps = e.fric_eps;
+  }
+  // the energy may grow under modulation or a bow (forced)
+  D.mon_check = (D.mod_type == 0 && e.type != 3) ? 1 : 0;
   D.ham_on = e.type == 2;
   D.hn0 = D.hn1 = 0;
   D.hw0 = D.hw1 = 0.0;

@@ -320,6 +320,69 @@ __device__ __forceinline__ double contact_coef(double eta, double omega_pow, dou
   return eta > 0.0 ? 0.5 * omega_pow * pow(eta > 0.0 ? eta : 1.0, alpha_H - 1.0) : 0.0;
 }
 
+// Per-group bow record in LDS (doubles): the controls (set at the start of a
+// task), then the step's values that the sweeps read.  The bow's vector
+// g = T_u0^{-1} J_p(x_B) follows it, MM G values in the kernel precision
+// (slot r of a lane at [r G + lane]).  Kept out of registers: only
+// wavefronts with a bowed string read them, and only inside the solve.
+constexpr int kBowX0 = 0, kBowX1 = 1, kBowT = 2, kBowVB = 3, kBowFB = 4, kBowTa = 5, kBowA = 6, kBowEps = 7;
+constexpr int kBowStepVB = 8, kBowStepK2F = 9, kBowStepIv = 10, kBowStepC = 11, kBowStepW0 = 12, kBowStepW1 = 13,
+              kBowStepN0 = 14, kBowStepN1 = 15, kBowIg = 16;
+constexpr int kBowRec = 18;
+
+template <int G, int MM, typename T>
+struct BowLds {
+  static constexpr int kDoubles = kBowRec + (MM * G * (int)sizeof(T) + 7) / 8;   // per group
+};
+
+// Bow of eq. (5).  Controls at time t: force and bow speed rise linearly
+// over the attack, the position moves linearly over the note.
+__device__ __forceinline__ void bow_controls(const double *R, double t, double &x, double &vB, double &FB) {
+  const double r = R[kBowTa] > 0.0 ? (t < R[kBowTa] ? t / R[kBowTa] : 1.0) : 1.0;
+  const double q = R[kBowT] > 0.0 ? (t < R[kBowT] ? t / R[kBowT] : 1.0) : 0.0;
+  x = R[kBowX0] + (R[kBowX1] - R[kBowX0]) * q;
+  vB = R[kBowVB] * r;
+  FB = R[kBowFB] * r;
+}
+
+// Nodes (1-based, 0 = absent) and weights of the linear interpolant at x.
+__device__ __forceinline__ void bow_interp(double x, int N, int &n0, int &n1, double &w0, double &w1) {
+  const int l = (int)floor(x * N);
+  const double w = x * N - l;
+  n0 = (l >= 1 && l <= N - 1) ? l : 0;
+  n1 = (l + 1 >= 1 && l + 1 <= N - 1) ? l + 1 : 0;
+  w0 = n0 ? 1.0 - w : 0.0;
+  w1 = n1 ? w : 0.0;
+}
+
+// The step's scalar problem v_rel = b - c phi (c >= 0): stick (v_rel = 0,
+// phi = b/c) when |b| <= c, else slip at the root x in (0, |b|) of
+// x + c (eps + (1-eps) e^{-a x}) = |b| (convex left side, below |b| at 0):
+// Newton's method inside a shrinking bracket.  Every lane of the wavefront
+// takes part; the loop ends when all have converged.  Returns phi.
+__device__ __forceinline__ double bow_phi(double b, double c, double a, double eps) {
+  const bool slip = c > 0.0 && fabs(b) > c;
+  const double ab = fabs(b), sg = b > 0.0 ? 1.0 : -1.0;
+  double lo = 0.0, hi = ab, x = ab;
+  bool done = !slip;
+  for (int it = 0; it < 100; ++it) {
+    if (__ballot(!done) == 0) break;
+    const double ex = exp(-a * x);
+    const double h = x + c * (eps + (1.0 - eps) * ex) - ab;
+    hi = (!done && h > 0.0) ? x : hi;
+    lo = (!done && h < 0.0) ? x : lo;
+    const double dh = 1.0 - c * (1.0 - eps) * a * ex;
+    double xn = dh > 0.0 ? x - h / dh : 0.5 * (lo + hi);
+    xn = (xn > lo && xn < hi) ? xn : 0.5 * (lo + hi);
+    const bool fin = h == 0.0 || fabs(xn - x) <= 4e-16 * ab || hi - lo <= 4e-16 * ab;
+    x = (done || h == 0.0) ? x : xn;
+    done = done || fin;
+  }
+  if (!(c > 0.0)) return 0.0;
+  if (!slip) return b / c;
+  return sg * (eps + (1.0 - eps) * exp(-a * x));
+}
+
 template <typename T>
 __device__ __forceinline__ double to_d(T hi, T c) {
   return (double)hi - (double)c;
@@ -578,9 +641,9 @@ __device__ __forceinline__ void store_state(T *st, T *trash, const T (&u)[MM], c
 // One wavefront task: up to 64/G strings stepped together
 // ---------------------------------------------------------------------------
 
-template <int G, int MM, typename T, bool KAHAN>
+template <int G, int MM, typename T, bool KAHAN, bool BOW>
 __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *work, int task, T *sS, double *sE, T *sC,
-                                         uint32_t *sTu, T *sTf) {
+                                         uint32_t *sTu, T *sTf, double *sB) {
   const int lane = lane_id();
   const int li = lane & (G - 1), gi = lane / G;
   const int sidx = work[task * (kWave / G) + gi];
@@ -613,6 +676,23 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   const double omega_pow = D.omega_pow, alpha_H = D.alpha_H, Mr = D.Mr, IHs = D.IHs;
   const bool ham = D.ham_on != 0;
   const bool any_ham = __ballot(ham) != 0;
+  const bool bowed = BOW && D.bow_on != 0;
+  // the bow's code exists only in the BOW instantiation (its registers would
+  // crowd every other task's)
+  const bool any_bow = BOW && __ballot(bowed) != 0;
+  const bool any_bow_moves = __ballot(bowed && D.bow_moves != 0) != 0;
+  double *bR = sB + gi * BowLds<G, MM, T>::kDoubles;   // this group's bow record
+  T *bG = (T *)(bR + kBowRec) + li;                     // g, slot r at [r G]
+  if (any_bow) {
+    bR[kBowX0] = D.bx0;
+    bR[kBowX1] = D.bx1;
+    bR[kBowT] = D.bT;
+    bR[kBowVB] = bowed ? D.bvB : 0.0;
+    bR[kBowFB] = bowed ? D.bFB : 0.0;
+    bR[kBowTa] = D.bta;
+    bR[kBowA] = D.ba;
+    bR[kBowEps] = D.beps;
+  }
   const bool any_l = __ballot(D.nl > 0) != 0;
   int gmax = D.gmax;
 #pragma unroll
@@ -839,6 +919,44 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     const bool sm_on = beta != 0.0;
     const bool any_sm = __ballot(sm_on) != 0;
 
+    // ---- bow: controls at time n, the vector g = T_u0^{-1} J_p(x_B), and
+    // the parts of v_rel that the sweeps do not change ----
+    if (any_bow) {
+      double xB, vB, FB;
+      bow_controls(bR, (double)n * D.k, xB, vB, FB);
+      int bn0, bn1;
+      double bw0, bw1;
+      bow_interp(xB, nt + 1, bn0, bn1, bw0, bw1);
+      if (it == 0 || any_bow_moves) {
+        T jb[MM], gv[MM], zr[MM];
+#pragma unroll
+        for (int r = 0; r < MM; ++r) {
+          const int i = tb + r + 1;
+          jb[r] = (i == bn0 ? (T)(bw0 * (nt + 1)) : T(0)) + (i == bn1 ? (T)(bw1 * (nt + 1)) : T(0));
+          zr[r] = T(0);
+        }
+        toeplitz_solve<G, T, MM>(gv, jb, wbu, mask_t, rho_t, itk_t, spt);
+#pragma unroll
+        for (int r = 0; r < MM; ++r) bG[r * G] = gv[r];
+        bR[kBowIg] = point_eval<G, T, MM>(gv, zr, bn0, bw0, bn1, bw1);
+      }
+      const double kk = D.k * D.k;
+      bR[kBowStepVB] = vB;
+      bR[kBowStepK2F] = kk * FB;
+      if constexpr (kSide) {
+        T cv[MM];
+        side_load<G, MM, T>(cv, side, 1, li);
+        bR[kBowStepIv] = point_eval<G, T, MM>(vu, cv, bn0, bw0, bn1, bw1);
+      } else {
+        bR[kBowStepIv] = point_eval<G, T, MM>(vu, cvu, bn0, bw0, bn1, bw1);
+      }
+      bR[kBowStepC] = D.k * FB * bR[kBowIg] * 0.5;
+      bR[kBowStepW0] = bw0;
+      bR[kBowStepW1] = bw1;
+      bR[kBowStepN0] = (double)bn0;
+      bR[kBowStepN1] = (double)bn1;
+    }
+
     // ---- coupled solve: block Gauss-Seidel around T_u0 (+ hammer) and T_z ----
     T au[MM], az[MM], smr[MM], zero[MM];
 #pragma unroll
@@ -898,6 +1016,16 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
         const T fac = smfac * Iy;
 #pragma unroll
         for (int r = 0; r < MM; ++r) nu[r] = fma(-fac, kTL ? (sm_on ? smt[r] : T(0)) : smr[r], nu[r]);
+      }
+      if (any_bow) {
+        // bow: v_rel = I_p(x_B)(a + 2 v^{n-1/2}) / 2k - v_B with a = nu - k^2 F_B phi g
+        const int bn0 = (int)bR[kBowStepN0], bn1 = (int)bR[kBowStepN1];
+        const double Ia = point_eval<G, T, MM>(nu, zero, bn0, bR[kBowStepW0], bn1, bR[kBowStepW1]);
+        const double bb = (Ia + 2.0 * bR[kBowStepIv]) / (2.0 * D.k) - bR[kBowStepVB];
+        const double phi = bow_phi(bb, bR[kBowStepC], bR[kBowA], bR[kBowEps]);
+        const T f = (T)(bR[kBowStepK2F] * phi);
+#pragma unroll
+        for (int r = 0; r < MM; ++r) nu[r] = fma(-f, bG[r * G], nu[r]);
       }
       // longitudinal right-hand side: r_z + phi^2 D_x+ I_(t)->(l) (q D_x- a_u)
       T gg[MM];
@@ -1090,7 +1218,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
 template <int MM, typename T>
 constexpr int kWavesPerEU = (sizeof(T) == 4 && MM <= 4) ? 2 : 1;
 
-template <int G, int MM, typename T, bool KAHAN>
+// BOW: the instantiation for tasks with bowed strings (the host keeps them
+// in work lists of their own); the other instantiation has no bow code.
+template <int G, int MM, typename T, bool KAHAN, bool BOW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<MM, T>))) void step_kernel(
     LaunchArgs a) {
   constexpr int kGroups = kWave / G;
@@ -1111,12 +1241,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
   T *sC = (T *)lds_side;
   T *sTf = (T *)lds_tab;
   uint32_t *sTu = (uint32_t *)(sTf + kGroups * TabLds<G, MM, T>::kWordsT);
+  __shared__ double lds_bow[BOW ? kGroups * BowLds<G, MM, T>::kDoubles : 1];
   for (;;) {
     // every lane takes part; only lane 0 adds, so the wave draws one ticket
     int w = atomicAdd(a.counter, lane_id() == 0 ? 1 : 0);
     w = __builtin_amdgcn_readfirstlane(w);
     if (w >= a.n_work) break;
-    run_task<G, MM, T, KAHAN>(a, a.work, w, sS, sE, sC, sTu, sTf);
+    run_task<G, MM, T, KAHAN, BOW>(a, a.work, w, sS, sE, sC, sTu, sTf, lds_bow);
   }
 }
 
@@ -1135,12 +1266,16 @@ constexpr int small_lds_doubles() {
   return m12 > m34 ? m12 : m34;
 }
 
-template <typename T, bool KAHAN>
+template <typename T, bool KAHAN, bool BOW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<4, T>))) void step_kernel_small(
     LaunchArgs a) {
   static_assert(kWavesPerEU<2, T> == kWavesPerEU<4, T>, "one occupancy target for the merged classes");
   static_assert(!kSideComp<4, T, KAHAN> && !kTabLds<4>, "no LDS tables in the merged classes");
   __shared__ double lds[small_lds_doubles<T>()];
+  constexpr int kB4 = BowLds<64, 4, T>::kDoubles, kB3 = 2 * BowLds<32, 4, T>::kDoubles;
+  constexpr int kB2 = 4 * BowLds<16, 4, T>::kDoubles, kB1 = 4 * BowLds<16, 2, T>::kDoubles;
+  constexpr int kB43 = kB4 > kB3 ? kB4 : kB3, kB21 = kB2 > kB1 ? kB2 : kB1;
+  __shared__ double lds_bow[BOW ? (kB43 > kB21 ? kB43 : kB21) : 1];
   T *sS = (T *)lds;
   double *sE = lds;
   for (;;) {
@@ -1149,10 +1284,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
     if (w >= a.n_work) break;
     const int m = __builtin_amdgcn_readfirstlane(a.tickets[w]), t = m & 0xffffff;
     switch (m >> 24) {
-      case 3: run_task<64, 4, T, KAHAN>(a, a.part_work[3], t, sS, sE, sS, nullptr, nullptr); break;
-      case 2: run_task<32, 4, T, KAHAN>(a, a.part_work[2], t, sS, sE, sS, nullptr, nullptr); break;
-      case 1: run_task<16, 4, T, KAHAN>(a, a.part_work[1], t, sS, sE, sS, nullptr, nullptr); break;
-      default: run_task<16, 2, T, KAHAN>(a, a.part_work[0], t, sS, sE, sS, nullptr, nullptr); break;
+      case 3: run_task<64, 4, T, KAHAN, BOW>(a, a.part_work[3], t, sS, sE, sS, nullptr, nullptr, lds_bow); break;
+      case 2: run_task<32, 4, T, KAHAN, BOW>(a, a.part_work[2], t, sS, sE, sS, nullptr, nullptr, lds_bow); break;
+      case 1: run_task<16, 4, T, KAHAN, BOW>(a, a.part_work[1], t, sS, sE, sS, nullptr, nullptr, lds_bow); break;
+      default: run_task<16, 2, T, KAHAN, BOW>(a, a.part_work[0], t, sS, sE, sS, nullptr, nullptr, lds_bow); break;
     }
   }
 }
@@ -1227,19 +1362,21 @@ hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const 
   return hipGetLastError();
 }
 
-template <typename T, bool KAHAN>
+template <typename T, bool KAHAN, bool BOW>
 static hipError_t launch_unit_t(int unit, const LaunchArgs &a, int blocks, hipStream_t st) {
   switch (unit) {
-    case 0: hipLaunchKernelGGL((step_kernel_small<T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((step_kernel<64, 8, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
-    default: hipLaunchKernelGGL((step_kernel<64, 16, T, KAHAN>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 0: hipLaunchKernelGGL((step_kernel_small<T, KAHAN, BOW>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((step_kernel<64, 8, T, KAHAN, BOW>), dim3(blocks), dim3(64), 0, st, a); break;
+    default: hipLaunchKernelGGL((step_kernel<64, 16, T, KAHAN, BOW>), dim3(blocks), dim3(64), 0, st, a); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_unit(int precision, int unit, const LaunchArgs &a, int blocks, hipStream_t st) {
-  if (precision == 1) return launch_unit_t<float, true>(unit, a, blocks, st);
-  return launch_unit_t<double, false>(unit, a, blocks, st);
+hipError_t launch_unit(int precision, int unit, bool bow, const LaunchArgs &a, int blocks, hipStream_t st) {
+  if (precision == 1)
+    return bow ? launch_unit_t<float, true, true>(unit, a, blocks, st) : launch_unit_t<float, true, false>(unit, a, blocks, st);
+  return bow ? launch_unit_t<double, false, true>(unit, a, blocks, st)
+             : launch_unit_t<double, false, false>(unit, a, blocks, st);
 }
 
 hipError_t launch_zero(int32_t *c, int n, hipStream_t st) {
@@ -1247,14 +1384,14 @@ hipError_t launch_zero(int32_t *c, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T, bool KAHAN>
+template <typename T, bool KAHAN, bool BOW>
 static int blocks_per_cu(int unit) {
   int n = 0;
   hipError_t e;
   switch (unit) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_small<T, KAHAN>, 64, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 8, T, KAHAN>, 64, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 16, T, KAHAN>, 64, 0); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_small<T, KAHAN, BOW>, 64, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 8, T, KAHAN, BOW>, 64, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 16, T, KAHAN, BOW>, 64, 0); break;
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -1263,8 +1400,9 @@ static int blocks_per_cu(int unit) {
   return n;
 }
 
-int max_blocks_per_cu(int precision, int unit) {
-  return precision == 1 ? blocks_per_cu<float, true>(unit) : blocks_per_cu<double, false>(unit);
+int max_blocks_per_cu(int precision, int unit, bool bow) {
+  if (precision == 1) return bow ? blocks_per_cu<float, true, true>(unit) : blocks_per_cu<float, true, false>(unit);
+  return bow ? blocks_per_cu<double, false, true>(unit) : blocks_per_cu<double, false, false>(unit);
 }
 
 }  // namespace sfd

@@ -62,6 +62,31 @@ def single_bowed(seconds: float = 0.5):
     return p, bow(0.12, 0.1, 100.0)
 
 
+def bowed_batch(n: int, seed: int = SEED + 11, seconds: float = 0.25):
+    """Bowed strings with seed-drawn parameters: string draws as in
+    random_batch (f0 log-U(40, 1000), alpha U(1, 4), ...), bow at U(0.05, 0.3)
+    moving by U(-0.05, 0.05) over the note (a third stay in place), v_B
+    U(0.05, 0.2) m/s, F_B log-U(20, 300), attack U(0.005, 0.05) s, friction
+    a U(20, 200) s/m and eps U(0.1, 0.5)."""
+    rng = np.random.default_rng(seed)
+    f0 = _loguniform(rng, 40.0, 1000.0, n)
+    B = _loguniform(rng, 1e-5, 1e-2, n)
+    sigma0 = rng.uniform(0.5, 3.0, n)
+    sigma1 = _loguniform(rng, 1e-5, 1e-3, n)
+    alpha = rng.uniform(1.0, 4.0, n)
+    pos = rng.uniform(0.05, 0.3, n)
+    move = np.where(rng.uniform(0.0, 1.0, n) < 1.0 / 3.0, 0.0, rng.uniform(-0.05, 0.05, n))
+    vB = rng.uniform(0.05, 0.2, n)
+    FB = _loguniform(rng, 20.0, 300.0, n)
+    att = rng.uniform(0.005, 0.05, n)
+    fa = rng.uniform(20.0, 200.0, n)
+    fe = rng.uniform(0.1, 0.5, n)
+    ns = int(round(seconds * FS))
+    return [(string(f0[i], B[i], alpha[i], sigma0[i], sigma1[i], ns),
+             bow(pos[i], vB[i], FB[i], x_end=pos[i] + move[i], attack=att[i], fric_a=fa[i], fric_eps=fe[i]))
+            for i in range(n)]
+
+
 def single_linear(seconds: float = 1.0, theta: float = 0.0):
     """Single linear stiff string: fs 48 kHz, f0 110 Hz, B 1e-4, sigma0 1, sigma1 5e-4,
     pluck at 0.2 with peak 1e-3, readout at 0.8, fixed ends, alpha = 1."""
