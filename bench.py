@@ -114,6 +114,43 @@ def plain_leg(W, binding, hiptime, seconds):
             "finished": done["samples_done"] == p["n_samples"] and done["flags"] == 0}
 
 
+def bow_leg(W, binding, hiptime, n, seconds):
+    """Bowed strings (eq. 5) in FP32 compensated: a seeded batch of n bowed
+    nonlinear strings, and the same strings plucked, one launch each (HIP
+    events); the ratio is the cost of the stick/slip solve inside the sweeps."""
+    items = W.bowed_batch(n, seconds=seconds)
+    pluck = W.pluck(0.2, 1e-3)
+    res = {}
+    for name, excs in (("bowed", [e for _, e in items]), ("plucked", [pluck] * n)):
+        b = binding.StringBatch(n, "fp32c")
+        b.set_params(0, [p for p, _ in items])
+        b.excite(0, excs)
+        infos = [b.info(i) for i in range(n)]
+        steps = max(p["n_samples"] for p, _ in items)
+        b.step(480)                     # first launch of the kernels, not timed
+        b.rewind()
+        hiptime.synchronize()
+        ev0, ev1 = hiptime.Event(), hiptime.Event()
+        ev0.record(0)
+        b.step(steps)
+        ev1.record(0)
+        ev1.synchronize()
+        ms = ev0.elapsed_ms(ev1)
+        bad = sum(1 for i in range(n) if b.info(i)["flags"] != 0 or b.info(i)["samples_done"] != infos[i]["n_samples"])
+        sweeps = sum(b.info(i)["total_sweeps"] for i in range(n))
+        b.close()
+        upd = sum(unknowns(inf) * (inf["n_samples"] - 2) for inf in infos)
+        res[name] = {"value": upd / (ms / 1e3), "ms": ms, "audio_s_per_s": n * seconds / (ms / 1e3),
+                     "sweeps_per_step_mean": sweeps / max(1, sum(inf["n_samples"] - 2 for inf in infos)),
+                     "strings_not_finished": bad}
+    return {"value": res["bowed"]["value"], "unit": "grid-point updates/s",
+            "audio_s_per_s": res["bowed"]["audio_s_per_s"], "ms": res["bowed"]["ms"],
+            "sweeps_per_step_mean": res["bowed"]["sweeps_per_step_mean"],
+            "strings_not_finished": res["bowed"]["strings_not_finished"],
+            "plucked_same_strings": res["plucked"], "bowed_vs_plucked": res["bowed"]["value"] / res["plucked"]["value"],
+            "workload": "%d bowed nonlinear strings of %.1f s (seeded draws), FP32 compensated" % (n, seconds)}
+
+
 def serving_leg(W, serving, rate, seconds, capacity):
     """Continuous-batching server under Poisson arrivals (one string per
     request, durations U(0.25, 3) s), in real time."""
@@ -139,6 +176,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-seconds", type=float, default=0.5, help="duration of the plain FP64 comparator run")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--bow-strings", type=int, default=4096, help="strings of the bowed-batch leg")
+    ap.add_argument("--no-bow", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=60.0, help="arrival window of the serving run")
     ap.add_argument("--serving-rate", type=float, default=2000.0)
     ap.add_argument("--no-serving", action="store_true")
@@ -248,6 +287,11 @@ def main():
         print("[bench] plain FP64: %.1f ms, %.3e updates/s" % (pl["ms"], pl["value"]), file=sys.stderr, flush=True)
         out["plain_fp64"] = pl
         out["batched_vs_plain"] = value / pl["value"]
+    if not args.no_bow:
+        bw = bow_leg(W, binding, hiptime, args.bow_strings, 1.0)
+        print("[bench] bow: %.1f ms, %.3e updates/s (%.2f x the same strings plucked)"
+              % (bw["ms"], bw["value"], bw["bowed_vs_plucked"]), file=sys.stderr, flush=True)
+        out["bow_fp32c"] = bw
     if not args.no_serving:
         from paper_2311_18505_amd import serving
         print("[bench] serving: %.0f requests/s for %.0f s" % (args.serving_rate, args.serving_seconds),

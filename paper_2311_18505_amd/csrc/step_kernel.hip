@@ -321,19 +321,12 @@ __device__ __forceinline__ double contact_coef(double eta, double omega_pow, dou
 }
 
 // Per-group bow record in LDS (doubles): the controls (set at the start of a
-// task), then the step's values that the sweeps read.  The bow's vector
-// g = T_u0^{-1} J_p(x_B) follows it, MM G values in the kernel precision
-// (slot r of a lane at [r G + lane]).  Kept out of registers: only
-// wavefronts with a bowed string read them, and only inside the solve.
+// task), then the step's values that the bow's correction after the solve
+// reads.  Kept out of registers through the sweeps.
 constexpr int kBowX0 = 0, kBowX1 = 1, kBowT = 2, kBowVB = 3, kBowFB = 4, kBowTa = 5, kBowA = 6, kBowEps = 7;
-constexpr int kBowStepVB = 8, kBowStepK2F = 9, kBowStepIv = 10, kBowStepC = 11, kBowStepW0 = 12, kBowStepW1 = 13,
-              kBowStepN0 = 14, kBowStepN1 = 15, kBowIg = 16;
-constexpr int kBowRec = 18;
-
-template <int G, int MM, typename T>
-struct BowLds {
-  static constexpr int kDoubles = kBowRec + (MM * G * (int)sizeof(T) + 7) / 8;   // per group
-};
+constexpr int kBowStepVB = 8, kBowStepK2F = 9, kBowStepIv = 10, kBowStepW0 = 11, kBowStepW1 = 12, kBowStepN0 = 13,
+              kBowStepN1 = 14;
+constexpr int kBowRec = 16;
 
 // Bow of eq. (5).  Controls at time t: force and bow speed rise linearly
 // over the attack, the position moves linearly over the note.
@@ -680,9 +673,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   // the bow's code exists only in the BOW instantiation (its registers would
   // crowd every other task's)
   const bool any_bow = BOW && __ballot(bowed) != 0;
-  const bool any_bow_moves = __ballot(bowed && D.bow_moves != 0) != 0;
-  double *bR = sB + gi * BowLds<G, MM, T>::kDoubles;   // this group's bow record
-  T *bG = (T *)(bR + kBowRec) + li;                     // g, slot r at [r G]
+  double *bR = sB + gi * kBowRec;   // this group's bow record
   if (any_bow) {
     bR[kBowX0] = D.bx0;
     bR[kBowX1] = D.bx1;
@@ -919,27 +910,14 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     const bool sm_on = beta != 0.0;
     const bool any_sm = __ballot(sm_on) != 0;
 
-    // ---- bow: controls at time n, the vector g = T_u0^{-1} J_p(x_B), and
-    // the parts of v_rel that the sweeps do not change ----
+    // ---- bow: controls at time n and the part of v_rel that the solve
+    // does not change ----
     if (any_bow) {
       double xB, vB, FB;
       bow_controls(bR, (double)n * D.k, xB, vB, FB);
       int bn0, bn1;
       double bw0, bw1;
       bow_interp(xB, nt + 1, bn0, bn1, bw0, bw1);
-      if (it == 0 || any_bow_moves) {
-        T jb[MM], gv[MM], zr[MM];
-#pragma unroll
-        for (int r = 0; r < MM; ++r) {
-          const int i = tb + r + 1;
-          jb[r] = (i == bn0 ? (T)(bw0 * (nt + 1)) : T(0)) + (i == bn1 ? (T)(bw1 * (nt + 1)) : T(0));
-          zr[r] = T(0);
-        }
-        toeplitz_solve<G, T, MM>(gv, jb, wbu, mask_t, rho_t, itk_t, spt);
-#pragma unroll
-        for (int r = 0; r < MM; ++r) bG[r * G] = gv[r];
-        bR[kBowIg] = point_eval<G, T, MM>(gv, zr, bn0, bw0, bn1, bw1);
-      }
       const double kk = D.k * D.k;
       bR[kBowStepVB] = vB;
       bR[kBowStepK2F] = kk * FB;
@@ -950,7 +928,6 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
       } else {
         bR[kBowStepIv] = point_eval<G, T, MM>(vu, cvu, bn0, bw0, bn1, bw1);
       }
-      bR[kBowStepC] = D.k * FB * bR[kBowIg] * 0.5;
       bR[kBowStepW0] = bw0;
       bR[kBowStepW1] = bw1;
       bR[kBowStepN0] = (double)bn0;
@@ -958,11 +935,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     }
 
     // ---- coupled solve: block Gauss-Seidel around T_u0 (+ hammer) and T_z ----
-    T au[MM], az[MM], smr[MM], zero[MM];
+    T smr[MM], zero[MM];
 #pragma unroll
     for (int r = 0; r < MM; ++r) {
-      au[r] = T(0);
-      az[r] = T(0);
       zero[r] = T(0);
       smr[r] = T(0);
     }
@@ -971,126 +946,161 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
       for (int r = 0; r < MM; ++r) smr[r] = ld_if<T>(smv, r * G + li, sm_on);
     }
     const T smfac = (T)(beta / (1.0 + beta * IHs));
-    bool conv = false;       // this group's iterates are final
-    int sweeps = 0;
-    T ascale = T(0);         // tol x the group's largest value after the first sweep
-    for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
-      // transverse right-hand side with the current coupling terms:
-      // e = q (q D_x- a_u + I_(l)->(t) D_x- a_z), b_u = r_u + phi^2 D_x+ e
-      T bu[MM];
-      if (sweep == 0) {
-#pragma unroll
-        for (int r = 0; r < MM; ++r) bu[r] = ru[r];
-      } else {
-        const T al = grp_prev<G>(last_of<T, MM>(au, mt));
-        const T zl = grp_prev<G>(last_of<T, MM>(az, ml));
-#pragma unroll
-        for (int r = 0; r < MM; ++r) {
-          const T zm = r == 0 ? zl : az[r > 0 ? r - 1 : 0];
-          gP[lb + r] = (az[r] - zm) * Nld;
-        }
-        __syncthreads();
-        T e[MM];
-#pragma unroll
-        for (int r = 0; r < MM; ++r) {
-          const T am = r == 0 ? al : au[r > 0 ? r - 1 : 0];
-          const T d = (au[r] - am) * Ntd;
-          const int ja = (int)(jab[r] & 0xffffu), jb = (int)(jab[r] >> 16);
-          const T w = wi[r];
-          const T idz = (T(1) - w) * gP[ja - 1] + w * gP[jb - 1];
-          e[r] = q[r] * fma(q[r], d, idz);
-        }
-        __syncthreads();
-        const T er = grp_next<G>(e[0]);
-#pragma unroll
-        for (int r = 0; r < MM; ++r) {
-          const T en = (r + 1 < MM && r + 1 < mt) ? e[r + 1 < MM ? r + 1 : r] : er;
-          bu[r] = fma(phi2 * Ntd, en - e[r], ru[r]);
-        }
-      }
-      T nu[MM];
-      toeplitz_solve<G, T, MM>(nu, bu, wbu, mask_t, rho_t, itk_t, spt);
-      if (any_sm) {
-        // Sherman-Morrison for the rank-one hammer term beta J I
-        const T Iy = (T)point_eval<G, T, MM>(nu, zero, hn0, hw0, hn1, hw1);
-        const T fac = smfac * Iy;
-#pragma unroll
-        for (int r = 0; r < MM; ++r) nu[r] = fma(-fac, kTL ? (sm_on ? smt[r] : T(0)) : smr[r], nu[r]);
-      }
-      if (any_bow) {
-        // bow: v_rel = I_p(x_B)(a + 2 v^{n-1/2}) / 2k - v_B with a = nu - k^2 F_B phi g
-        const int bn0 = (int)bR[kBowStepN0], bn1 = (int)bR[kBowStepN1];
-        const double Ia = point_eval<G, T, MM>(nu, zero, bn0, bR[kBowStepW0], bn1, bR[kBowStepW1]);
-        const double bb = (Ia + 2.0 * bR[kBowStepIv]) / (2.0 * D.k) - bR[kBowStepVB];
-        const double phi = bow_phi(bb, bR[kBowStepC], bR[kBowA], bR[kBowEps]);
-        const T f = (T)(bR[kBowStepK2F] * phi);
-#pragma unroll
-        for (int r = 0; r < MM; ++r) nu[r] = fma(-f, bG[r * G], nu[r]);
-      }
-      // longitudinal right-hand side: r_z + phi^2 D_x+ I_(t)->(l) (q D_x- a_u)
-      T gg[MM];
-      {
-        const T al = grp_prev<G>(last_of<T, MM>(nu, mt));
-#pragma unroll
-        for (int r = 0; r < MM; ++r) {
-          const T am = r == 0 ? al : nu[r > 0 ? r - 1 : 0];
-          const T fq = q[r] * ((nu[r] - am) * Ntd);
-          const T w = wi[r];
-          gA[tb + r] = (T(1) - w) * fq;
-          gB[tb + r] = w * fq;
-        }
-        __syncthreads();
-        gather_lt<MM, T>(gg, gA, gB, rga, rgb, gmax);
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < MM; ++r) gg[r] *= ratio;
-      }
-      const T gr = grp_next<G>(gg[0]);
-      T bz[MM];
+    // One solve of the step's coupled system A [a_u; a_z] = [f_u; f_z] (the
+    // hammer's rank-one term included when `hammer`); returns this group's
+    // sweeps and whether it converged.
+    auto gs_solve = [&](const T (&fu)[MM], const T (&fz)[MM], bool hammer, T (&au)[MM], T (&az)[MM],
+                        bool &conv) -> int {
 #pragma unroll
       for (int r = 0; r < MM; ++r) {
-        const T gn = (r + 1 < MM && r + 1 < ml) ? gg[r + 1 < MM ? r + 1 : r] : gr;
-        bz[r] = fma(phi2 * Nld, gn - gg[r], rz[r]);
+        au[r] = T(0);
+        az[r] = T(0);
       }
-      T nz[MM];
-      toeplitz_solve<G, T, MM>(nz, bz, wbz, mask_l, rho_l, itk_l, spl);
-      // convergence of this group, from the second sweep on (a string without
-      // a longitudinal grid is solved exactly by the first): every lane's
-      // update is below tol times the group's largest first-sweep value; the
-      // group's lanes are read off one ballot.  A converged group keeps its
-      // iterates.
-      bool now = nl == 0;
-      if (any_l) {
+      conv = false;            // this group's iterates are final
+      int sweeps = 0;
+      T ascale = T(0);         // tol x the group's largest value after the first sweep
+      for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
+        // transverse right-hand side with the current coupling terms:
+        // e = q (q D_x- a_u + I_(l)->(t) D_x- a_z), b_u = r_u + phi^2 D_x+ e
+        T bu[MM];
         if (sweep == 0) {
-          T amax = T(0);
-#pragma unroll
-          for (int r = 0; r < MM; ++r) amax = fmax(amax, fmax(fabs(nu[r]), fabs(nz[r])));
-          ascale = (T)a.tol * grp_reduce<G, true>(amax);
+  #pragma unroll
+          for (int r = 0; r < MM; ++r) bu[r] = fu[r];
         } else {
-          T delta = T(0);
-#pragma unroll
-          for (int r = 0; r < MM; ++r) delta = fmax(delta, fmax(fabs(nu[r] - au[r]), fabs(nz[r] - az[r])));
-          const uint64_t ok = __ballot(delta <= ascale);
-          constexpr uint64_t gm = G == kWave ? ~0ull : ((1ull << G) - 1);
-          now = now || ((ok >> (gi * G)) & gm) == gm;
+          const T al = grp_prev<G>(last_of<T, MM>(au, mt));
+          const T zl = grp_prev<G>(last_of<T, MM>(az, ml));
+  #pragma unroll
+          for (int r = 0; r < MM; ++r) {
+            const T zm = r == 0 ? zl : az[r > 0 ? r - 1 : 0];
+            gP[lb + r] = (az[r] - zm) * Nld;
+          }
+          __syncthreads();
+          T e[MM];
+  #pragma unroll
+          for (int r = 0; r < MM; ++r) {
+            const T am = r == 0 ? al : au[r > 0 ? r - 1 : 0];
+            const T d = (au[r] - am) * Ntd;
+            const int ja = (int)(jab[r] & 0xffffu), jb = (int)(jab[r] >> 16);
+            const T w = wi[r];
+            const T idz = (T(1) - w) * gP[ja - 1] + w * gP[jb - 1];
+            e[r] = q[r] * fma(q[r], d, idz);
+          }
+          __syncthreads();
+          const T er = grp_next<G>(e[0]);
+  #pragma unroll
+          for (int r = 0; r < MM; ++r) {
+            const T en = (r + 1 < MM && r + 1 < mt) ? e[r + 1 < MM ? r + 1 : r] : er;
+            bu[r] = fma(phi2 * Ntd, en - e[r], fu[r]);
+          }
         }
+        T nu[MM];
+        toeplitz_solve<G, T, MM>(nu, bu, wbu, mask_t, rho_t, itk_t, spt);
+        if (hammer && any_sm) {
+          // Sherman-Morrison for the rank-one hammer term beta J I
+          const T Iy = (T)point_eval<G, T, MM>(nu, zero, hn0, hw0, hn1, hw1);
+          const T fac = smfac * Iy;
+  #pragma unroll
+          for (int r = 0; r < MM; ++r) nu[r] = fma(-fac, kTL ? (sm_on ? smt[r] : T(0)) : smr[r], nu[r]);
+        }
+        // longitudinal right-hand side: r_z + phi^2 D_x+ I_(t)->(l) (q D_x- a_u)
+        T gg[MM];
+        {
+          const T al = grp_prev<G>(last_of<T, MM>(nu, mt));
+  #pragma unroll
+          for (int r = 0; r < MM; ++r) {
+            const T am = r == 0 ? al : nu[r > 0 ? r - 1 : 0];
+            const T fq = q[r] * ((nu[r] - am) * Ntd);
+            const T w = wi[r];
+            gA[tb + r] = (T(1) - w) * fq;
+            gB[tb + r] = w * fq;
+          }
+          __syncthreads();
+          gather_lt<MM, T>(gg, gA, gB, rga, rgb, gmax);
+          __syncthreads();
+  #pragma unroll
+          for (int r = 0; r < MM; ++r) gg[r] *= ratio;
+        }
+        const T gr = grp_next<G>(gg[0]);
+        T bz[MM];
+  #pragma unroll
+        for (int r = 0; r < MM; ++r) {
+          const T gn = (r + 1 < MM && r + 1 < ml) ? gg[r + 1 < MM ? r + 1 : r] : gr;
+          bz[r] = fma(phi2 * Nld, gn - gg[r], fz[r]);
+        }
+        T nz[MM];
+        toeplitz_solve<G, T, MM>(nz, bz, wbz, mask_l, rho_l, itk_l, spl);
+        // convergence of this group, from the second sweep on (a string without
+        // a longitudinal grid is solved exactly by the first): every lane's
+        // update is below tol times the group's largest first-sweep value; the
+        // group's lanes are read off one ballot.  A converged group keeps its
+        // iterates.
+        bool now = nl == 0;
+        if (any_l) {
+          if (sweep == 0) {
+            T amax = T(0);
+  #pragma unroll
+            for (int r = 0; r < MM; ++r) amax = fmax(amax, fmax(fabs(nu[r]), fabs(nz[r])));
+            ascale = (T)a.tol * grp_reduce<G, true>(amax);
+          } else {
+            T delta = T(0);
+  #pragma unroll
+            for (int r = 0; r < MM; ++r) delta = fmax(delta, fmax(fabs(nu[r] - au[r]), fabs(nz[r] - az[r])));
+            const uint64_t ok = __ballot(delta <= ascale);
+            constexpr uint64_t gm = G == kWave ? ~0ull : ((1ull << G) - 1);
+            now = now || ((ok >> (gi * G)) & gm) == gm;
+          }
+        }
+        if (__ballot(conv) != 0) {
+  #pragma unroll
+          for (int r = 0; r < MM; ++r) {
+            au[r] = conv ? au[r] : nu[r];
+            az[r] = conv ? az[r] : nz[r];
+          }
+        } else {
+  #pragma unroll
+          for (int r = 0; r < MM; ++r) {
+            au[r] = nu[r];
+            az[r] = nz[r];
+          }
+        }
+        sweeps = conv ? sweeps : sweep + 1;
+        conv = conv || now;
+        if (__ballot(!conv) == 0) break;
       }
-      if (__ballot(conv) != 0) {
+      return sweeps;
+    };
+    T au[MM], az[MM];
+    bool conv;
+    int sweeps = gs_solve(ru, rz, true, au, az, conv);
+    if constexpr (BOW) {
+      if (any_bow) {
+        // bow (eq. 5): the system's response to the unit force J_p(x_B),
+        // A [d_u; d_z] = [J_p(x_B); 0], then the step's stick/slip problem
+        // v_rel = b - c phi with b = I_p(a_u + 2 v^{n-1/2}) / 2k - v_B and
+        // c = k F_B I_p d_u / 2, and a -= k^2 F_B phi d
+        const int bn0 = (int)bR[kBowStepN0], bn1 = (int)bR[kBowStepN1];
+        const double bw0 = bR[kBowStepW0], bw1 = bR[kBowStepW1];
+        T fb[MM], du[MM], dz[MM];
 #pragma unroll
         for (int r = 0; r < MM; ++r) {
-          au[r] = conv ? au[r] : nu[r];
-          az[r] = conv ? az[r] : nz[r];
+          const int i = tb + r + 1;
+          fb[r] = (i == bn0 ? (T)(bw0 * (nt + 1)) : T(0)) + (i == bn1 ? (T)(bw1 * (nt + 1)) : T(0));
         }
-      } else {
+        bool convd;
+        sweeps += gs_solve(fb, zero, false, du, dz, convd);
+        conv = conv && convd;
+        const double Ia = point_eval<G, T, MM>(au, zero, bn0, bw0, bn1, bw1);
+        const double Id = point_eval<G, T, MM>(du, zero, bn0, bw0, bn1, bw1);
+        const double bb = (Ia + 2.0 * bR[kBowStepIv]) / (2.0 * D.k) - bR[kBowStepVB];
+        const double c = 0.5 * bR[kBowStepK2F] / D.k * Id;
+        const double phi = bow_phi(bb, c, bR[kBowA], bR[kBowEps]);
+        const T f = (T)(bR[kBowStepK2F] * phi);
 #pragma unroll
         for (int r = 0; r < MM; ++r) {
-          au[r] = nu[r];
-          az[r] = nz[r];
+          au[r] = fma(-f, du[r], au[r]);
+          az[r] = fma(-f, dz[r], az[r]);
         }
       }
-      sweeps = conv ? sweeps : sweep + 1;
-      conv = conv || now;
-      if (__ballot(!conv) == 0) break;
     }
     flags |= (act && !conv) ? kFlagNoConverge : 0;
     tot_sw += act ? sweeps : 0;
@@ -1241,7 +1251,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
   T *sC = (T *)lds_side;
   T *sTf = (T *)lds_tab;
   uint32_t *sTu = (uint32_t *)(sTf + kGroups * TabLds<G, MM, T>::kWordsT);
-  __shared__ double lds_bow[BOW ? kGroups * BowLds<G, MM, T>::kDoubles : 1];
+  __shared__ double lds_bow[BOW ? kGroups * kBowRec : 1];
   for (;;) {
     // every lane takes part; only lane 0 adds, so the wave draws one ticket
     int w = atomicAdd(a.counter, lane_id() == 0 ? 1 : 0);
@@ -1272,10 +1282,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
   static_assert(kWavesPerEU<2, T> == kWavesPerEU<4, T>, "one occupancy target for the merged classes");
   static_assert(!kSideComp<4, T, KAHAN> && !kTabLds<4>, "no LDS tables in the merged classes");
   __shared__ double lds[small_lds_doubles<T>()];
-  constexpr int kB4 = BowLds<64, 4, T>::kDoubles, kB3 = 2 * BowLds<32, 4, T>::kDoubles;
-  constexpr int kB2 = 4 * BowLds<16, 4, T>::kDoubles, kB1 = 4 * BowLds<16, 2, T>::kDoubles;
-  constexpr int kB43 = kB4 > kB3 ? kB4 : kB3, kB21 = kB2 > kB1 ? kB2 : kB1;
-  __shared__ double lds_bow[BOW ? (kB43 > kB21 ? kB43 : kB21) : 1];
+  __shared__ double lds_bow[BOW ? 4 * kBowRec : 1];   // up to four groups per wavefront
   T *sS = (T *)lds;
   double *sE = lds;
   for (;;) {
