@@ -18,6 +18,7 @@ namespace sfd {
 hipError_t launch_unit(int precision, int unit, bool bow, const LaunchArgs &a, int blocks, hipStream_t st);
 hipError_t launch_zero(int32_t *c, int n, hipStream_t st);
 int max_blocks_per_cu(int precision, int unit, bool bow);
+hipError_t launch_delay(uint64_t ticks, hipStream_t st);
 hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
                          hipStream_t st);
 hipError_t launch_scatter(const void *src, const UploadSeg *segs, int n, hipStream_t st);
@@ -118,6 +119,7 @@ struct sb_batch {
   // joined back into `stream` through events (default priority)
   hipStream_t unit_stream[kNumUnits] = {};
   hipEvent_t ev_fork = nullptr;
+  uint64_t delay_ticks = 0;      // head start of the large-class launches (wall-clock ticks, ~20 us)
   hipEvent_t ev_join[kNumUnits] = {};
   hipEvent_t ev_t0[kNumUnits] = {}, ev_t1[kNumUnits] = {};   // timing of each launch
   int32_t unit_strings[kNumUnits] = {};                       // strings of the last launch
@@ -235,6 +237,11 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
     if (e == hipSuccess) e = hipEventCreate(&b->ev_t1[c]);
   }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+    b->delay_ticks = (uint64_t)khz / 50;   // 20 us
+  }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     g_create_error = std::string("stream/event creation: ") + hipGetErrorString(e);
@@ -610,6 +617,7 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
   if (e == hipSuccess) e = hipEventRecord(b->ev_fork, st);
   if (e != hipSuccess) return hip_fail(b, e, "fork");
   // largest strings first: their launches hold the longest per-step latency
+  bool big_launched = false;
   for (int u = kNumUnits - 1; u >= 0; --u) {
     hipStream_t cs = b->unit_stream[u];
     b->unit_strings[u] = 0;
@@ -654,6 +662,9 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
       const int blocks = std::min(a.n_work, b->num_cu * per_cu);
       if (!forked) {
         e = hipStreamWaitEvent(cs, b->ev_fork, 0);
+        // the merged launch starts a little after the large classes (their
+        // wavefronts need whole SIMDs; the merged one's would fill them first)
+        if (e == hipSuccess && u == 0 && big_launched) e = launch_delay(b->delay_ticks, cs);
         if (e == hipSuccess) e = hipEventRecord(b->ev_t0[u], cs);
         forked = true;
       }
@@ -661,6 +672,7 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
       if (e != hipSuccess) return hip_fail(b, e, "step launch");
     }
     if (!forked) continue;
+    big_launched = big_launched || u > 0;
     e = hipEventRecord(b->ev_t1[u], cs);
     if (e == hipSuccess) e = hipEventRecord(b->ev_join[u], cs);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[u], 0);

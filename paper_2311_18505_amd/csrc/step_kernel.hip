@@ -1386,6 +1386,22 @@ hipError_t launch_unit(int precision, int unit, bool bow, const LaunchArgs &a, i
              : launch_unit_t<double, false, false>(unit, a, blocks, st);
 }
 
+// Holds its stream for `ticks` of the constant-rate wall clock and exits
+// (bounded by time, independent of any other kernel).  Placed before the
+// merged launch so that the two large-class launches, which need whole SIMDs
+// (512 registers per wavefront), are dispatched before the merged launch's
+// persistent wavefronts fill every CU.
+__global__ void delay_kernel(uint64_t ticks) {
+  const uint64_t t0 = wall_clock64();
+  // the iteration cap bounds the wait (~20 ms) even if the clock stood still
+  for (int i = 0; i < 100000 && wall_clock64() - t0 < ticks; ++i) __builtin_amdgcn_s_sleep(8);
+}
+
+hipError_t launch_delay(uint64_t ticks, hipStream_t st) {
+  hipLaunchKernelGGL(delay_kernel, dim3(1), dim3(64), 0, st, ticks);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(int32_t *c, int n, hipStream_t st) {
   hipLaunchKernelGGL(zero_counters, dim3((n + 255) / 256), dim3(256), 0, st, c, n);
   return hipGetLastError();
