@@ -96,8 +96,10 @@ typedef struct {
  * v_rel = 0 the string sticks (|phi| <= 1).  F_B (force per unit linear
  * density, m/s^2 on the string of length 1) and v_B [m/s] rise linearly over
  * `attack` seconds; the position moves linearly from x to x_end over the note
- * (n_samples / fs).  Each step solves the stick/slip problem exactly inside
- * the coupled solve.  SB_FP64_PLAIN does not take a bow (SB_EINVAL). */
+ * (n_samples / fs).  Each step solves the coupled system for its right-hand
+ * side and for the bow's unit force, then the step's stick/slip problem
+ * exactly (as a direct solve of eq. (7) would).  SB_FP64_PLAIN does not take
+ * a bow (SB_EINVAL). */
 typedef struct {
     int32_t type;              /* SB_EXC_*                                        */
     int32_t reserved;
