@@ -50,7 +50,7 @@ extern "C" {
 #define SB_EXC_NONE    0
 #define SB_EXC_PLUCK   1
 #define SB_EXC_HAMMER  2
-#define SB_EXC_BOW     3   /* batched paths only */
+#define SB_EXC_BOW     3
 
 /* f0 modulation types */
 #define SB_MOD_NONE    0
@@ -98,8 +98,8 @@ typedef struct {
  * `attack` seconds; the position moves linearly from x to x_end over the note
  * (n_samples / fs).  Each step solves the coupled system for its right-hand
  * side and for the bow's unit force, then the step's stick/slip problem
- * exactly (as a direct solve of eq. (7) would).  SB_FP64_PLAIN does not take
- * a bow (SB_EINVAL). */
+ * exactly (as a direct solve of eq. (7) would); SB_FP64_PLAIN carries the
+ * unit force through its band elimination as a second right-hand side. */
 typedef struct {
     int32_t type;              /* SB_EXC_*                                        */
     int32_t reserved;

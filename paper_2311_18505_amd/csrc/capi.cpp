@@ -399,10 +399,6 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     Plan tmp = b->slots[first + i].plan;
     std::string err;
     int st = plan_excitation(e[i], tmp, err);
-    if (!st && b->precision == SB_FP64_PLAIN && e[i].type == SB_EXC_BOW) {
-      err = "the plain path takes no bow";
-      st = SB_EINVAL;
-    }
     if (!st && b->precision == SB_FP64_PLAIN) st = plan_plain(tmp, err);
     if (st) return fail(b, st, "slot " + std::to_string(first + i) + ": " + err);
   }

@@ -3,7 +3,9 @@
 //     A^n w^{n+1} = -B^n w^n - C^n w^{n-1} - Gamma^n,
 // with the blocks of eq. (8)-(9) (loss as in eq. (4), nonlinear couplings
 // K^(tl) = -phi^2 D+ Lambda I_(l)->(t) D-^(l), K^(lt) = -phi^2 D+^(l) I_(t)->(l) Lambda D-),
-// and the hammer of eq. (6) as one more unknown u_H^{n+1}.  Every step
+// and the hammer of eq. (6) as one more unknown u_H^{n+1}; a bow (eq. (5))
+// by a second right-hand side [J_p(x_B); 0] carried through the same
+// elimination and the step's stick/slip problem.  Every step
 // assembles the system in an order that merges both grids and the hammer by
 // position along the string (a band matrix), eliminates it row by row
 // without pivoting (W A is symmetric positive definite for a positive
@@ -12,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "sfd_types.h"
+#include "bow.h"
 
 namespace sfd {
 
@@ -63,6 +66,9 @@ __global__ __launch_bounds__(64) void plain_kernel(PlainArgs a) {
   double *ptm = pt + (Nt + 2);        // I_(l)->(t) D- zeta^{n-1}
   double *cxx = ptm + (Nt + 2);       // D_xx u^n at nodes 0..Nt (0 at the ends)
   double *gz = cxx + (Nt + 2);        // I_(t)->(l) (q D- u^{n-1}) at l-halves 1..Nl
+  double *rhs2 = gz + (Nl + 2);       // bow: n (+1 trash), becomes A^{-1} [J_p(x_B); 0]
+  const bool bow = D.bow_on != 0;
+  const double bR[8] = {D.bx0, D.bx1, D.bT, D.bvB, D.bFB, D.bta, D.ba, D.beps};
 
   const int32_t *pos_t = D.ptab, *pos_l = pos_t + nt, *jab = pos_l + nl;
   const int32_t *rga = jab + Nt, *rgb = rga + Nl;
@@ -120,7 +126,19 @@ __global__ __launch_bounds__(64) void plain_kernel(PlainArgs a) {
     }
     for (int b = 0; b < n * W; b += 64) put_or_trash(band + b + lane(), b + lane() < n * W, trash, 0.0);
     for (int b = 0; b <= n; b += 64) put_or_trash(rhs + b + lane(), b + lane() <= n, trash, 0.0);
+    for (int b = 0; b <= n; b += 64) put_or_trash(rhs2 + b + lane(), bow && b + lane() <= n, trash, 0.0);
+    // bow: controls at time tn and the interpolant at x_B
+    double xB = 0.0, vB = 0.0, FB = 0.0, bw0 = 0.0, bw1 = 0.0;
+    int bn0 = 0, bn1 = 0;
+    if (bow) {
+      bow_controls(bR, (double)tn * k, xB, vB, FB);
+      bow_interp(xB, Nt, bn0, bn1, bw0, bw1);
+    }
     __syncthreads();
+    if (bow && lane() == 0) {
+      if (bn0) rhs2[pos_t[bn0 - 1]] += bw0 * Ntd;
+      if (bn1) rhs2[pos_t[bn1 - 1]] += bw1 * Ntd;
+    }
 
     // I_(t)->(l)(q D- u^{n-1}) at the l-halves (ranges of t-halves per tap)
     for (int b = 0; b < Nl + 2; b += 64) {
@@ -250,31 +268,55 @@ __global__ __launch_bounds__(64) void plain_kernel(PlainArgs a) {
     }
     __syncthreads();
 
-    // ---- elimination without pivoting, right-hand side carried along ----
-    const int tasks = bw * (bw + 1);
+    // ---- elimination without pivoting, right-hand side(s) carried along ----
+    const int cols = bw + (bow ? 2 : 1);     // band columns right of the pivot, then rhs (, rhs2)
+    const int tasks = bw * cols;
     for (int kk = 0; kk < n - 1; ++kk) {
       const double piv = band[kk * W + bw];
       for (int t0 = 0; t0 < tasks; t0 += 64) {
         const int t = t0 + lane();
-        const int ao = t / (bw + 1) + 1, bo = t % (bw + 1) + 1;
+        const int ao = t / cols + 1, bo = t % cols + 1;
         const int i = kk + ao;
         const bool ok = t < tasks && i < n;
         const double L = ok ? band[i * W + bw - ao] / piv : 0.0;
-        const bool col = bo <= bw;
+        const bool col = bo <= bw, second = bo == bw + 2;
         const bool okc = ok && (col ? kk + bo < n : true);
-        const double src = col ? band[kk * W + bw + (col ? bo : 0)] : rhs[kk];
-        double *dst = !okc ? trash : col ? band + i * W + bw + bo - ao : rhs + i;
+        const double src = col ? band[kk * W + bw + (col ? bo : 0)] : second ? rhs2[kk] : rhs[kk];
+        double *dst = !okc ? trash : col ? band + i * W + bw + bo - ao : second ? rhs2 + i : rhs + i;
         *dst -= L * src;
       }
       __syncthreads();
     }
-    // ---- back substitution (every lane computes the same value) ----
+    // ---- back substitution (every lane computes the same values) ----
     for (int kk = n - 1; kk >= 0; --kk) {
-      double s = rhs[kk];
-      for (int bo = 1; bo <= bw; ++bo) s -= (kk + bo < n) ? band[kk * W + bw + bo] * rhs[kk + bo < n ? kk + bo : kk] : 0.0;
-      const double x = s / band[kk * W + bw];
+      double s = rhs[kk], s2 = bow ? rhs2[kk] : 0.0;
+      for (int bo = 1; bo <= bw; ++bo) {
+        const bool in = kk + bo < n;
+        const double a_ = in ? band[kk * W + bw + bo] : 0.0;
+        s -= a_ * rhs[in ? kk + bo : kk];
+        s2 -= bow ? a_ * rhs2[in ? kk + bo : kk] : 0.0;
+      }
+      const double x = s / band[kk * W + bw], x2 = s2 / band[kk * W + bw];
       __syncthreads();
       rhs[kk] = x;
+      put_or_trash(rhs2 + kk, bow, trash, x2);
+      __syncthreads();
+    }
+    // ---- bow: the step's stick/slip problem, then w -= k^2 F_B phi A^{-1} [J; 0] ----
+    if (bow) {
+      const double Iw = (bn0 ? bw0 * rhs[pos_t[bn0 - 1]] : 0.0) + (bn1 ? bw1 * rhs[pos_t[bn1 - 1]] : 0.0);
+      const double Ig = (bn0 ? bw0 * rhs2[pos_t[bn0 - 1]] : 0.0) + (bn1 ? bw1 * rhs2[pos_t[bn1 - 1]] : 0.0);
+      const double Ium = bw0 * Um[bn0] + bw1 * Um[bn1];
+      const double bb = (Iw - Ium) / (2.0 * k) - vB;
+      const double c = 0.5 * k * FB * Ig;
+      const double f = k * k * FB * bow_phi(bb, c, D.ba, D.beps);
+      __syncthreads();
+      for (int b = 0; b < n; b += 64) {
+        const int i = b + lane();
+        const bool ok = i < n;
+        const double v = rhs[ok ? i : 0] - f * rhs2[ok ? i : 0];
+        put_or_trash(rhs + i, ok, trash, v);
+      }
       __syncthreads();
     }
 

@@ -452,7 +452,7 @@ int plan_plain(Plan &P, std::string &err) {
 size_t plain_lds_bytes(const Desc &D) {
   const size_t n = (size_t)D.pn, W = 2 * (size_t)D.pbw + 1;
   const size_t words = n * W + n + 1 + W + 2 * ((size_t)D.Nt + 1) + 2 * ((size_t)D.Nl + 1) + 4 * ((size_t)D.Nt + 2) +
-                       2 * ((size_t)D.Nl + 2) + 64;
+                       2 * ((size_t)D.Nl + 2) + (D.bow_on ? n + 1 : 0) + 64;
   return words * sizeof(double);
 }
 

@@ -121,11 +121,21 @@ def test_bowed_fp32c_long_run_within_conditioning():
     assert worst <= 1.0
 
 
-def test_plain_path_refuses_a_bow():
+def test_plain_fp64_bow_matches_oracle():
+    """The plain FP64 comparator carries the bow's unit force through its
+    band elimination as a second right-hand side."""
     _gpu()
-    p, e = W.single_bowed(seconds=0.01)
-    b = binding.StringBatch(1, "fp64_plain")
-    b.set_params(0, [p])
-    with pytest.raises(binding.SbError):
-        b.excite(0, [e])
-    b.close()
+    p, e = W.single_bowed(seconds=0.05)
+    items = [(p, e), (p, dict(e, x_end=0.2))] + W.bowed_batch(3, seconds=0.05)
+    refs = oracle.run_many(items)
+    for (pp, ee), r in zip(items, refs):
+        b = binding.StringBatch(1, "fp64_plain")
+        b.set_params(0, [pp])
+        b.excite(0, [ee])
+        b.step(pp["n_samples"])
+        y, inf = b.read_output(0), b.info(0)
+        b.close()
+        err = rel_l2(y, r["y_u"])
+        print("[gpu] plain bow: N=(%d,%d) rel-L2 %.3e" % (inf["N_t"], inf["N_l"], err), flush=True)
+        assert inf["flags"] == 0 and inf["samples_done"] == pp["n_samples"]
+        assert err <= 1e-10
