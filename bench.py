@@ -34,9 +34,9 @@ PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 2.4 GHz x 25
 # uneven 16384-string batch, one full step), from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a
 # 512 MiB device copy (x2.000 and x1.000); profiles/hbm_traffic_uneven16384.md.
-# Valid only for the kernel source it was measured on (sha256 prefix).
-TRAFFIC = {"kernel": "step_kernel_small<float, true>", "source_sha256": "1d7f45be3ba7a271",
-           "fetch_bytes": 236.11e9, "write_bytes": 748.37e9}
+# Valid only for the kernel sources it was measured on (kernel_source_hash).
+TRAFFIC = {"kernel": "step_kernel_small<float, true>", "source_sha256": "847ab18123328c04",
+           "fetch_bytes": 237.60e9, "write_bytes": 744.43e9}
 
 # the kernels of the three launches of a step (size classes 0..3 merged, 4, 5)
 LAUNCH_KERNELS = ["step_kernel_small<float, true>", "step_kernel<64, 8, float, true>",
@@ -54,13 +54,24 @@ def unknowns(info):
     return (info["N_t"] - 1) + max(info["N_l"] - 1, 0)
 
 
-def measured_traffic():
-    """TRAFFIC when the kernel source is the one it was measured on, else None."""
+KERNEL_SOURCES = ("step_kernel.hip", "bow.h", "sfd_types.h")
+
+
+def kernel_source_hash() -> str:
+    """sha256 prefix over the sources the stepping kernels are built from."""
     import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2311_18505_amd", "csrc", "step_kernel.hip")
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest()[:16] != TRAFFIC["source_sha256"]:
-            return None
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2311_18505_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """TRAFFIC when the kernels are built from the sources it was measured on, else None."""
+    if kernel_source_hash() != TRAFFIC["source_sha256"]:
+        return None
     return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 
 
