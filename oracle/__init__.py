@@ -88,6 +88,9 @@ def _load():
         lib.orc_grid_plan.restype = C.c_int
         lib.orc_run.argtypes = [C.POINTER(OrcString), C.POINTER(OrcExcitation), C.POINTER(OrcOutputs)]
         lib.orc_run.restype = C.c_int
+        lib.orc_run_schedule.argtypes = [C.POINTER(OrcString), C.POINTER(OrcExcitation), C.c_int,
+                                         C.POINTER(C.c_int64), C.POINTER(OrcExcitation), C.POINTER(OrcOutputs)]
+        lib.orc_run_schedule.restype = C.c_int
         lib.orc_dump_system.argtypes = [C.POINTER(OrcString), C.POINTER(OrcExcitation), C.c_int64,
                                         _DP, _DP, C.c_double, C.c_double, _DP, _DP, _DP, _DP]
         lib.orc_dump_system.restype = C.c_int
@@ -150,10 +153,12 @@ def _ptr(a):
     return a.ctypes.data_as(_DP) if a is not None else None
 
 
-def run(p: dict, e: dict | None, want=("y_u",), allow_fail: bool = False) -> dict:
+def run(p: dict, e: dict | None, want=("y_u",), allow_fail: bool = False, schedule=None) -> dict:
     """Run one string for p['n_samples'] samples; return the requested arrays.
 
     want: any of "y_u", "y_z", "energy", "traj_u", "traj_z", "u_H", "bow_phi", "bow_vrel".
+    schedule: optional [(step, excitation)] of hammers or bows applied to the
+    sounding string before the step that computes w^{step+1}.
     """
     lib = _load()
     g = grid(p)
@@ -168,7 +173,12 @@ def run(p: dict, e: dict | None, want=("y_u",), allow_fail: bool = False) -> dic
     out = OrcOutputs()
     for key in ("y_u", "y_z", "energy", "traj_u", "traj_z", "u_H", "bow_phi", "bow_vrel"):
         setattr(out, key, _ptr(arrs[key]))
-    st = lib.orc_run(C.byref(_string(p)), C.byref(_exc(e)), C.byref(out))
+    if schedule:
+        steps = (C.c_int64 * len(schedule))(*[int(n) for n, _ in schedule])
+        excs = (OrcExcitation * len(schedule))(*[_exc(x) for _, x in schedule])
+        st = lib.orc_run_schedule(C.byref(_string(p)), C.byref(_exc(e)), len(schedule), steps, excs, C.byref(out))
+    else:
+        st = lib.orc_run(C.byref(_string(p)), C.byref(_exc(e)), C.byref(out))
     if st != 0 and not allow_fail:
         raise OracleError("orc_run failed with status %d" % st)
     for key in want:

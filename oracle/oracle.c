@@ -608,7 +608,8 @@ static int exc_validate(const orc_excitation *e) {
 
 typedef struct {
     int on;
-    double x0, x1, T;              /* position x0 -> x1 over the note of length T */
+    double t0;                     /* time the bow was set on the string */
+    double x0, x1, T;              /* position x0 -> x1 over T seconds from t0 */
     double vB, FB, ta;             /* bow velocity and force, attack time */
     double a, eps;                 /* friction curve */
 } bow_t;
@@ -617,6 +618,7 @@ typedef struct {
  * time-varying without their form; here force and velocity rise linearly
  * over the attack and then hold, and the position moves linearly. */
 static void bow_controls(const bow_t *bw, double t, double *x, double *vB, double *FB) {
+    t -= bw->t0;
     double r = bw->ta > 0.0 ? (t < bw->ta ? t / bw->ta : 1.0) : 1.0;
     double q = bw->T > 0.0 ? (t < bw->T ? t / bw->T : 1.0) : 0.0;
     *x = bw->x0 + (bw->x1 - bw->x0) * q;
@@ -661,13 +663,17 @@ double orc_bow_solve(double b, double c, double a, double eps, double *v) {
     return sg * (eps + (1.0 - eps) * exp(-a * x));
 }
 
-static void bow_setup(const orc_excitation *e, const orc_string *s, bow_t *bw) {
+/* A bow set on the string at level n0 (0 for the initial excitation): its
+ * controls run from t0 = n0 k and its position sweep over the rest of the
+ * note, (n_samples - n0) / fs. */
+static void bow_setup(const orc_excitation *e, const orc_string *s, int64_t n0, bow_t *bw) {
     memset(bw, 0, sizeof(*bw));
     if (!e || e->type != 3) return;
     bw->on = 1;
+    bw->t0 = (double)n0 / s->fs;
     bw->x0 = e->x;
     bw->x1 = e->x_end;
-    bw->T = (double)s->n_samples / s->fs;
+    bw->T = (double)(s->n_samples - n0) / s->fs;
     bw->vB = e->v_B;
     bw->FB = e->F_B;
     bw->ta = e->attack;
@@ -840,6 +846,11 @@ static int hammer_setup(const orc_excitation *e, const orc_grid *g, hammer_t *hm
 }
 
 int orc_run(const orc_string *s, const orc_excitation *e, orc_outputs *out) {
+    return orc_run_schedule(s, e, 0, NULL, NULL, out);
+}
+
+int orc_run_schedule(const orc_string *s, const orc_excitation *e, int n_re, const int64_t *re_step,
+                     const orc_excitation *re_exc, orc_outputs *out) {
     if (!s || !out) return ORC_EINVAL;
     orc_grid g;
     int st = orc_grid_plan(s, &g);
@@ -848,21 +859,27 @@ int orc_run(const orc_string *s, const orc_excitation *e, orc_outputs *out) {
     if (s->mod_type < 0 || s->mod_type > 2) return ORC_EINVAL;
     if (!(s->sigma0_t >= 0.0) || !(s->sigma1_t >= 0.0) || !(s->sigma0_l >= 0.0) || !(s->sigma1_l >= 0.0)) return ORC_EINVAL;
     if ((st = exc_validate(e))) return st;
+    for (int r = 0; r < n_re; ++r) {
+        if (!re_exc || !re_step || re_step[r] < 1 || (r > 0 && re_step[r] <= re_step[r - 1])) return ORC_EINVAL;
+        if (re_exc[r].type != 2 && re_exc[r].type != 3) return ORC_EINVAL;
+        if ((st = exc_validate(&re_exc[r]))) return st;
+    }
 
     ops_t o;
     ops_build(s, &g, &o);
     hammer_t hm;
     hammer_setup(e, &g, &hm);
     bow_t bw;
-    bow_setup(e, s, &bw);
+    bow_setup(e, s, 0, &bw);
     int n = o.n, nt = o.nt, nl = o.nl, Ns = (int)s->n_samples;
+    int next_re = 0;
     /* three rotating time levels; each has room for the hammer unknown */
     double *w0 = (double *)calloc((size_t)n + 1, sizeof(double));   /* w^{n-1} */
     double *w1 = (double *)calloc((size_t)n + 1, sizeof(double));   /* w^n     */
     double *w2 = (double *)calloc((size_t)n + 1, sizeof(double));   /* w^{n+1} (+ u_H^{n+1}) */
     double *rhs = (double *)calloc((size_t)n + 1, sizeof(double));
-    double *gb = bw.on ? (double *)calloc((size_t)n + 1, sizeof(double)) : NULL;   /* A^{-1} [J_B; 0] */
-    double *rb = bw.on ? (double *)calloc((size_t)n + 1, sizeof(double)) : NULL;
+    double *gb = (double *)calloc((size_t)n + 1, sizeof(double));   /* bow: A^{-1} [J_B; 0] */
+    double *rb = (double *)calloc((size_t)n + 1, sizeof(double));
     double uH0 = 0.0, uH1 = 0.0;
     int io[2]; double wo[2];
     interp_row(s->x_out, g.N_t, io, wo);
@@ -905,6 +922,23 @@ int orc_run(const orc_string *s, const orc_excitation *e, orc_outputs *out) {
     int status = ORC_OK;
     int64_t steps = 0;
     for (int step = 1; step <= Ns - 2; ++step) {
+        if (next_re < n_re && re_step[next_re] == step) {
+            /* a new excitation on the sounding string (Sec. 3.3, several
+             * excitations per note).  READING: a hammer arrives touching the
+             * string at level n-1 and moves with v_H: u_H^{n-1} = I_H u^{n-1},
+             * u_H^n = u_H^{n-1} + k v_H (the initial hammer when the string
+             * rests); a bow's controls restart from level n-1, so that its
+             * first step is n, as step 1 is for the initial bow. */
+            const orc_excitation *x = &re_exc[next_re++];
+            hammer_setup(x, &g, &hm);
+            bow_setup(x, s, step - 1, &bw);
+            if (hm.on) {
+                uH0 = interp_apply(hm.iH, hm.wH, w0);
+                uH1 = uH0 + g.k * x->v_H;
+            }
+            free(perm);
+            perm = position_order(&o, hm.on, x->type == 2 ? x->x : 0.0);
+        }
         double gamma = orc_gamma_at(s, step);
         system_t sy;
         system_build(s, &o, gamma, w1, &sy);

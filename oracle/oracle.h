@@ -89,6 +89,14 @@ typedef struct {
 int orc_grid_plan(const orc_string *s, orc_grid *g);
 int orc_run(const orc_string *s, const orc_excitation *e, orc_outputs *out);
 
+/* The same with n_re more excitations (hammer or bow) applied to the sounding
+ * string: re_exc[r] before the step that computes w^{re_step[r]+1}
+ * (re_step increasing, >= 1).  A hammer arrives touching the string at level
+ * n-1 with velocity v_H; a bow's controls restart from level n-1 (its first
+ * step is n, as step 1 is for the initial bow). */
+int orc_run_schedule(const orc_string *s, const orc_excitation *e, int n_re, const int64_t *re_step,
+                     const orc_excitation *re_exc, orc_outputs *out);
+
 /* Assemble A^n, B^n, C^n (eq. 8-9, hammer block included) for a given state and
  * return them densely (row-major, size n x n with n = N_t-1 + N_l-1) together
  * with the right-hand side -B w^n - C w^{n-1} - Gamma^n.  For tests only. */

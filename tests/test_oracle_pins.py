@@ -447,3 +447,34 @@ def test_pb4_bowed_string_locks_to_the_fundamental():
     late = vrel[n // 2:n - 1]
     stick = np.mean(late == 0.0)
     assert 0.1 < stick < 0.9
+
+
+# ---------------------------------------------------------------------------
+# Several excitations per note (a hammer or bow set on the sounding string)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["hammer", "bow"])
+def test_pr1_restrike_at_rest_is_a_fresh_excitation(kind):
+    """On a string at rest, an excitation applied before step 1 is the initial
+    excitation itself (bit for bit)."""
+    p, _ = W.single_linear(seconds=0.05)
+    x = W.hammer(0.12, 2.0) if kind == "hammer" else W.bow(0.12, 0.1, 100.0, x_end=0.15)
+    a = oracle.run(p, x)["y_u"]
+    b = oracle.run(p, None, schedule=[(1, x)])["y_u"]
+    assert np.max(np.abs(a)) > 0
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("kind", ["hammer", "bow"])
+def test_pr2_restrike_is_time_invariant(kind):
+    """The scheme without modulation is autonomous: the same excitation set on
+    the resting string m-1 steps later gives the same output m-1 samples later
+    (the bow's sweep covers the same remaining duration)."""
+    m = 97
+    p, _ = W.single_linear(seconds=0.04)
+    x = W.hammer(0.12, 2.0) if kind == "hammer" else W.bow(0.12, 0.1, 100.0, x_end=0.15)
+    a = oracle.run(p, x)["y_u"]
+    q = dict(p, n_samples=p["n_samples"] + m - 1)
+    b = oracle.run(q, None, schedule=[(m, x)])["y_u"]
+    assert np.all(b[:m] == 0.0)
+    np.testing.assert_allclose(b[m - 1:], a, rtol=0, atol=1e-12 * np.max(np.abs(a)))
