@@ -154,6 +154,19 @@ int string_batch_step(sb_batch *b, int64_t n_steps);
 /* Same as string_batch_step but only for slots first .. first+count-1. */
 int string_batch_step_range(sb_batch *b, int first, int count, int64_t n_steps);
 
+/* Several excitations per note: a new hammer or bow (e[i].type
+ * SB_EXC_HAMMER or SB_EXC_BOW) on each of slots first .. first+count-1 while
+ * they sound, applied before their next step n (the one computing sample
+ * samples_done).  The string keeps its state and the new excitation replaces
+ * the slot's hammer or bow: a hammer arrives touching the string at level
+ * n-1 with velocity v_H toward it (the initial hammer when the string
+ * rests); a bow's controls (attack, position sweep over the rest of the
+ * note) restart from level n-1.  Synchronises the batch stream; a rewind of
+ * a re-excited slot is refused until it is excited again.  Errors: SB_EINVAL
+ * (plain path, other types, bad parameters), SB_ESTATE (slot not excited or
+ * finished), SB_EDEVICE. */
+int string_batch_restrike(sb_batch *b, int first, int count, const sb_excitation *e);
+
 /* Return slots first .. first+count-1 to their state right after
  * string_batch_excite (samples_done = 2, flags cleared) without host work:
  * a device copy of the excited state is kept for this.  Asynchronous on the

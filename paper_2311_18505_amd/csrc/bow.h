@@ -12,12 +12,14 @@ namespace sfd {
 // reads.  Kept out of registers through the sweeps.
 constexpr int kBowX0 = 0, kBowX1 = 1, kBowT = 2, kBowVB = 3, kBowFB = 4, kBowTa = 5, kBowA = 6, kBowEps = 7;
 constexpr int kBowStepVB = 8, kBowStepK2F = 9, kBowStepIv = 10, kBowStepW0 = 11, kBowStepW1 = 12, kBowStepN0 = 13,
-              kBowStepN1 = 14;
+              kBowStepN1 = 14, kBowT0 = 15;
 constexpr int kBowRec = 16;
 
 // Bow of eq. (5).  Controls at time t: force and bow speed rise linearly
-// over the attack, the position moves linearly over the note.
+// over the attack, the position moves linearly over the note, both counted
+// from the time the bow was set on the string.
 __device__ __forceinline__ void bow_controls(const double *R, double t, double &x, double &vB, double &FB) {
+  t -= R[kBowT0];
   const double r = R[kBowTa] > 0.0 ? (t < R[kBowTa] ? t / R[kBowTa] : 1.0) : 1.0;
   const double q = R[kBowT] > 0.0 ? (t < R[kBowT] ? t / R[kBowT] : 1.0) : 0.0;
   x = R[kBowX0] + (R[kBowX1] - R[kBowX0]) * q;

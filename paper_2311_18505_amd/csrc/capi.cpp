@@ -105,6 +105,7 @@ struct Slot {
   size_t dsize = 0;
   int64_t samples_host = 0;   // samples expected after the launches issued so far
   bool flagged = false;       // a flag was observed on the device
+  bool restruck = false;      // re-excited since string_batch_excite (no rewind)
 };
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
@@ -486,6 +487,7 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     S.uH_nm1 = uH0;
     S.eta_nm1 = uH0;   // eta^0 = u_H^0 - I u^0, the string starts at rest under the hammer
     s.excited = true;
+    s.restruck = false;
     s.flagged = false;
     s.samples_host = S.samples_done;
   }
@@ -992,9 +994,90 @@ extern "C" int string_batch_set_solver(sb_batch *b, double tol, int max_sweeps) 
   return SB_OK;
 }
 
+// A new hammer or bow on sounding strings (several excitations per note).
+// The state stays; the slot's plan takes the new excitation; a hammer
+// arrives touching the string at level n-1 (the level before the next step
+// n) with velocity v_H, a bow's controls restart from level n-1.
+extern "C" int string_batch_restrike(sb_batch *b, int first, int count, const sb_excitation *e) {
+  if (!b) return SB_EINVAL;
+  if (!e || !range_ok(b, first, count)) return fail(b, SB_EINVAL, "bad slot range or null excitation");
+  if (b->precision == SB_FP64_PLAIN) return fail(b, SB_EINVAL, "the plain path takes excitations only at the start");
+  std::vector<Plan> plans(count);
+  for (int i = 0; i < count; ++i) {
+    Slot &s = b->slots[first + i];
+    if (!s.excited) return fail(b, SB_ESTATE, "slot " + std::to_string(first + i) + " is not excited");
+    if (e[i].type != SB_EXC_HAMMER && e[i].type != SB_EXC_BOW)
+      return fail(b, SB_EINVAL, "slot " + std::to_string(first + i) + ": a new excitation is a hammer or a bow");
+    if (s.samples_host >= s.plan.desc.n_samples)
+      return fail(b, SB_ESTATE, "slot " + std::to_string(first + i) + " has finished");
+    plans[i] = s.plan;
+    std::string err;
+    const int st = plan_excitation(e[i], plans[i], err);
+    if (st) return fail(b, st, "slot " + std::to_string(first + i) + ": " + err);
+  }
+  // the state must be current: queued launches finish first
+  hipError_t he = hipStreamSynchronize(b->stream);
+  if (he == hipSuccess && b->cap_stream) he = hipStreamSynchronize(b->cap_stream);
+  if (he != hipSuccess) return hip_fail(b, he, "sync");
+  for (int i = 0; i < count && he == hipSuccess; ++i) {
+    Slot &s = b->slots[first + i];
+    Plan &P = plans[i];
+    Desc &D = P.desc;
+    Status S;
+    he = hipMemcpy(&S, b->d_status + first + i, sizeof(Status), hipMemcpyDeviceToHost);
+    if (he != hipSuccess) break;
+    const int64_t n = S.samples_done - 1;   // the next step computes w^{n+1}
+    if (e[i].type == SB_EXC_BOW) {
+      D.bt0 = (double)(n - 1) / D.fs;
+      D.bT = (double)(D.n_samples - (n - 1)) / D.fs;
+    } else {
+      // u_H^{n-1} = I_H u^{n-1}, u_H^n = u_H^{n-1} + k v_H, from the state
+      // (u^n and v^{n-1/2} = u^n - u^{n-1}, each as value minus compensation)
+      const int G = kClassLanes[D.cls], mt = D.mt;
+      std::vector<double> st((size_t)4 * mt * G, 0.0);
+      if (b->precision == SB_FP32C) {
+        std::vector<float> f(st.size());
+        he = hipMemcpy(f.data(), D.st, sizeof(float) * f.size(), hipMemcpyDeviceToHost);
+        for (size_t k = 0; k < f.size(); ++k) st[k] = f[k];
+      } else {
+        he = hipMemcpy(st.data(), D.st, sizeof(double) * st.size(), hipMemcpyDeviceToHost);
+      }
+      if (he != hipSuccess) break;
+      auto prev = [&](int node) {   // u^{n-1} at a node (1-based)
+        if (node <= 0) return 0.0;
+        const int lane = (node - 1) / mt, r = (node - 1) % mt;
+        auto at = [&](int a) { return st[((size_t)a * mt + r) * G + lane]; };
+        return (at(0) - at(2)) - (at(1) - at(3));
+      };
+      const double uHm = D.hw0 * prev(D.hn0) + D.hw1 * prev(D.hn1);
+      S.uH_nm1 = uHm;
+      S.uH_n = uHm + D.k * e[i].v_H;
+      S.eta_nm1 = 0.0;
+      S.touched = 0;
+    }
+    std::vector<char> bt;
+    if (b->precision == SB_FP32C)
+      to_prec<float>(P.tabf, bt);
+    else
+      to_prec<double>(P.tabf, bt);
+    he = hipMemcpy(const_cast<void *>(D.tabf), bt.data(), bt.size(), hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(b->d_desc + first + i, &D, sizeof(Desc), hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(b->d_status + first + i, &S, sizeof(Status), hipMemcpyHostToDevice);
+    if (he != hipSuccess) break;
+    s.plan = P;
+    s.restruck = true;
+  }
+  if (he != hipSuccess) return hip_fail(b, he, "restrike upload");
+  ++b->epoch;
+  b->work_dirty = true;
+  return SB_OK;
+}
+
 extern "C" int string_batch_rewind(sb_batch *b, int first, int count) {
   if (!b) return SB_EINVAL;
   if (!range_ok(b, first, count)) return fail(b, SB_EINVAL, "bad slot range");
+  for (int i = first; i < first + count; ++i)
+    if (b->slots[i].restruck) return fail(b, SB_ESTATE, "slot " + std::to_string(i) + " was re-excited; excite it again");
   for (int i = first; i < first + count; ++i) {
     Slot &s = b->slots[i];
     if (!s.excited) continue;

@@ -282,7 +282,7 @@ int plan_excitation(const sb_excitation &e, Plan &P, std::string &err) {
   const int Nt = D.Nt, mt = D.mt, ml = D.ml, nt = D.nt;
   const int G = kClassLanes[D.cls];
   D.bow_on = e.type == 3;
-  D.bx0 = D.bx1 = D.bT = D.bvB = D.bFB = D.bta = D.ba = D.beps = 0.0;
+  D.bx0 = D.bx1 = D.bT = D.bvB = D.bFB = D.bta = D.ba = D.beps = D.bt0 = 0.0;
   if (e.type == 3) {
     D.bx0 = e.x;
     D.bx1 = e.x_end;

@@ -64,10 +64,11 @@ struct Desc {
   int32_t pad1;
   double hw0, hw1;            // weights of I_H
   double omega_pow, alpha_H, Mr, IHs;   // K_H/M_H, exponent, M_H/(rho A), I_H T_u0^{-1} J_H
-  // bow (eq. 5): position bx0 -> bx1 over bT seconds, bow speed and force
-  // rising over bta seconds, friction curve sign(v) (beps + (1-beps) e^{-ba|v|})
+  // bow (eq. 5), set on the string at time bt0: position bx0 -> bx1 over bT
+  // seconds, bow speed and force rising over bta seconds, friction curve
+  // sign(v) (beps + (1-beps) e^{-ba|v|})
   int32_t bow_on, pad3;       // 1 if the excitation is a bow
-  double bx0, bx1, bT, bvB, bFB, bta, ba, beps;
+  double bx0, bx1, bT, bvB, bFB, bta, ba, beps, bt0;
   // readout
   int32_t on0, on1;           // nodes of I(x_out)
   double ow0, ow1;

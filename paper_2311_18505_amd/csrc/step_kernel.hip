@@ -628,6 +628,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     bR[kBowTa] = D.bta;
     bR[kBowA] = D.ba;
     bR[kBowEps] = D.beps;
+    bR[kBowT0] = D.bt0;
   }
   const bool any_l = __ballot(D.nl > 0) != 0;
   int gmax = D.gmax;
