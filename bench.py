@@ -162,6 +162,27 @@ def bow_leg(W, binding, hiptime, n, seconds):
             "workload": "%d bowed nonlinear strings of %.1f s (seeded draws), FP32 compensated" % (n, seconds)}
 
 
+def dataset_leg(hiptime, n, seconds):
+    """The dataset generator: n labelled notes of U(seconds) s, a third each
+    plucked, hammered and bowed, half of them given one or two more hammers
+    or bows mid-note (FP32 compensated, one batch); wall time of the
+    synthesis with the host work of its re-excitations."""
+    from paper_2311_18505_amd import dataset
+    notes = dataset.draw_notes(n, seconds=seconds, restrike_prob=0.5)
+    dataset.synthesize(notes[:64], "fp32c", capacity=64)      # first launches of the kernels
+    hiptime.synchronize()
+    t0 = time.perf_counter()
+    audio = dataset.synthesize(notes, "fp32c", capacity=n)
+    hiptime.synchronize()
+    wall = time.perf_counter() - t0
+    secs = sum(x["params"]["n_samples"] for x in notes) / 48000.0
+    return {"value": secs / wall, "unit": "audio-s/s", "notes_per_s": n / wall, "wall_s": wall,
+            "notes": n, "events": sum(len(x["events"]) for x in notes),
+            "finite": bool(all(np.isfinite(a).all() for a in audio)),
+            "workload": "%d notes of U(%.1f, %.1f) s, pluck/hammer/bow, half re-excited mid-note once or twice, "
+                        "FP32 compensated" % (n, seconds[0], seconds[1])}
+
+
 def serving_leg(W, serving, rate, seconds, capacity):
     """Continuous-batching server under Poisson arrivals (one string per
     request, durations U(0.25, 3) s), in real time."""
@@ -189,6 +210,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--bow-strings", type=int, default=4096, help="strings of the bowed-batch leg")
     ap.add_argument("--no-bow", action="store_true")
+    ap.add_argument("--dataset-notes", type=int, default=16384, help="notes of the dataset-generator leg")
+    ap.add_argument("--no-dataset", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=60.0, help="arrival window of the serving run")
     ap.add_argument("--serving-rate", type=float, default=2000.0)
     ap.add_argument("--no-serving", action="store_true")
@@ -303,6 +326,11 @@ def main():
         print("[bench] bow: %.1f ms, %.3e updates/s (%.2f x the same strings plucked)"
               % (bw["ms"], bw["value"], bw["bowed_vs_plucked"]), file=sys.stderr, flush=True)
         out["bow_fp32c"] = bw
+    if not args.no_dataset:
+        ds = dataset_leg(hiptime, args.dataset_notes, (0.5, 2.0))
+        print("[bench] dataset: %d notes (%d re-excitations) in %.2f s, %.0f audio-s/s"
+              % (ds["notes"], ds["events"], ds["wall_s"], ds["value"]), file=sys.stderr, flush=True)
+        out["dataset_fp32c"] = ds
     if not args.no_serving:
         from paper_2311_18505_amd import serving
         print("[bench] serving: %.0f requests/s for %.0f s" % (args.serving_rate, args.serving_seconds),

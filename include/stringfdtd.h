@@ -167,6 +167,10 @@ int string_batch_step_range(sb_batch *b, int first, int count, int64_t n_steps);
  * finished), SB_EDEVICE. */
 int string_batch_restrike(sb_batch *b, int first, int count, const sb_excitation *e);
 
+/* The same for count arbitrary slots slots[i] (each listed once), e[i]
+ * applied to slots[i]; the slots of one call share two synchronisations. */
+int string_batch_restrike_list(sb_batch *b, int count, const int32_t *slots, const sb_excitation *e);
+
 /* Return slots first .. first+count-1 to their state right after
  * string_batch_excite (samples_done = 2, flags cleared) without host work:
  * a device copy of the excited state is kept for this.  Asynchronous on the

@@ -73,6 +73,7 @@ SIGNATURES = [
     ("string_batch_autotune", C.c_int, [_P, C.c_int64, C.POINTER(C.c_int32)]),
     ("string_batch_launch_times", C.c_int, [_P, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     ("string_batch_restrike", C.c_int, [_P, C.c_int, C.c_int, C.c_void_p]),
+    ("string_batch_restrike_list", C.c_int, [_P, C.c_int, C.POINTER(C.c_int32), C.c_void_p]),
     ("string_batch_set_blocks_per_cu", C.c_int, [_P, C.POINTER(C.c_int32)]),
     ("string_batch_read_energy", C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("string_batch_info", C.c_int, [_P, C.c_int, C.POINTER(SbStringInfo)]),
@@ -216,6 +217,13 @@ class StringBatch:
         """A new hammer or bow on sounding slots first.. (before their next step)."""
         arr = (SbExcitation * len(excs))(*[excitation_struct(e) for e in excs])
         self._check(self.lib.string_batch_restrike(self.h, first, len(excs), C.cast(arr, C.c_void_p)), "restrike")
+
+    def restrike_list(self, slots, excs):
+        """A new hammer or bow on each of the listed sounding slots."""
+        sl = np.ascontiguousarray(slots, dtype=np.int32)
+        arr = (SbExcitation * len(excs))(*[excitation_struct(e) for e in excs])
+        self._check(self.lib.string_batch_restrike_list(self.h, len(sl), sl.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                        C.cast(arr, C.c_void_p)), "restrike_list")
 
     def graph_capture(self, steps_per_launch: int, n_launches: int):
         self._check(self.lib.string_batch_graph_capture(self.h, steps_per_launch, n_launches), "graph_capture")

@@ -997,36 +997,51 @@ extern "C" int string_batch_set_solver(sb_batch *b, double tol, int max_sweeps) 
 // A new hammer or bow on sounding strings (several excitations per note).
 // The state stays; the slot's plan takes the new excitation; a hammer
 // arrives touching the string at level n-1 (the level before the next step
-// n) with velocity v_H, a bow's controls restart from level n-1.
-extern "C" int string_batch_restrike(sb_batch *b, int first, int count, const sb_excitation *e) {
+// n) with velocity v_H, a bow's controls restart from level n-1.  All slots
+// of one call share two synchronisations: one after reading their status
+// (and, for hammers, their state), one after writing plans and status.
+extern "C" int string_batch_restrike_list(sb_batch *b, int count, const int32_t *slots, const sb_excitation *e) {
   if (!b) return SB_EINVAL;
-  if (!e || !range_ok(b, first, count)) return fail(b, SB_EINVAL, "bad slot range or null excitation");
+  if (count < 0 || (count > 0 && (!e || !slots))) return fail(b, SB_EINVAL, "null slots or excitations");
   if (b->precision == SB_FP64_PLAIN) return fail(b, SB_EINVAL, "the plain path takes excitations only at the start");
   std::vector<Plan> plans(count);
   for (int i = 0; i < count; ++i) {
-    Slot &s = b->slots[first + i];
-    if (!s.excited) return fail(b, SB_ESTATE, "slot " + std::to_string(first + i) + " is not excited");
+    const int k = slots[i];
+    if (k < 0 || k >= b->capacity) return fail(b, SB_EINVAL, "slot index out of range");
+    for (int j = 0; j < i; ++j)
+      if (slots[j] == k) return fail(b, SB_EINVAL, "slot " + std::to_string(k) + " listed twice");
+    Slot &s = b->slots[k];
+    if (!s.excited) return fail(b, SB_ESTATE, "slot " + std::to_string(k) + " is not excited");
     if (e[i].type != SB_EXC_HAMMER && e[i].type != SB_EXC_BOW)
-      return fail(b, SB_EINVAL, "slot " + std::to_string(first + i) + ": a new excitation is a hammer or a bow");
-    if (s.samples_host >= s.plan.desc.n_samples)
-      return fail(b, SB_ESTATE, "slot " + std::to_string(first + i) + " has finished");
+      return fail(b, SB_EINVAL, "slot " + std::to_string(k) + ": a new excitation is a hammer or a bow");
+    if (s.samples_host >= s.plan.desc.n_samples) return fail(b, SB_ESTATE, "slot " + std::to_string(k) + " has finished");
     plans[i] = s.plan;
     std::string err;
     const int st = plan_excitation(e[i], plans[i], err);
-    if (st) return fail(b, st, "slot " + std::to_string(first + i) + ": " + err);
+    if (st) return fail(b, st, "slot " + std::to_string(k) + ": " + err);
   }
+  if (count == 0) return SB_OK;
   // the state must be current: queued launches finish first
   hipError_t he = hipStreamSynchronize(b->stream);
   if (he == hipSuccess && b->cap_stream) he = hipStreamSynchronize(b->cap_stream);
   if (he != hipSuccess) return hip_fail(b, he, "sync");
+  // read status (and the state of hammered slots)
+  std::vector<Status> S(count);
+  std::vector<std::vector<char>> raw(count);
   for (int i = 0; i < count && he == hipSuccess; ++i) {
-    Slot &s = b->slots[first + i];
-    Plan &P = plans[i];
-    Desc &D = P.desc;
-    Status S;
-    he = hipMemcpy(&S, b->d_status + first + i, sizeof(Status), hipMemcpyDeviceToHost);
-    if (he != hipSuccess) break;
-    const int64_t n = S.samples_done - 1;   // the next step computes w^{n+1}
+    he = hipMemcpyAsync(&S[i], b->d_status + slots[i], sizeof(Status), hipMemcpyDeviceToHost, b->stream);
+    if (he == hipSuccess && e[i].type == SB_EXC_HAMMER) {
+      const Desc &D = plans[i].desc;
+      raw[i].resize((size_t)4 * D.mt * kClassLanes[D.cls] * b->esz);
+      he = hipMemcpyAsync(raw[i].data(), D.st, raw[i].size(), hipMemcpyDeviceToHost, b->stream);
+    }
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(b->stream);
+  if (he != hipSuccess) return hip_fail(b, he, "restrike read");
+  std::vector<std::vector<char>> tabs(count);
+  for (int i = 0; i < count; ++i) {
+    Desc &D = plans[i].desc;
+    const int64_t n = S[i].samples_done - 1;   // the next step computes w^{n+1}
     if (e[i].type == SB_EXC_BOW) {
       D.bt0 = (double)(n - 1) / D.fs;
       D.bT = (double)(D.n_samples - (n - 1)) / D.fs;
@@ -1034,43 +1049,52 @@ extern "C" int string_batch_restrike(sb_batch *b, int first, int count, const sb
       // u_H^{n-1} = I_H u^{n-1}, u_H^n = u_H^{n-1} + k v_H, from the state
       // (u^n and v^{n-1/2} = u^n - u^{n-1}, each as value minus compensation)
       const int G = kClassLanes[D.cls], mt = D.mt;
-      std::vector<double> st((size_t)4 * mt * G, 0.0);
-      if (b->precision == SB_FP32C) {
-        std::vector<float> f(st.size());
-        he = hipMemcpy(f.data(), D.st, sizeof(float) * f.size(), hipMemcpyDeviceToHost);
-        for (size_t k = 0; k < f.size(); ++k) st[k] = f[k];
-      } else {
-        he = hipMemcpy(st.data(), D.st, sizeof(double) * st.size(), hipMemcpyDeviceToHost);
-      }
-      if (he != hipSuccess) break;
+      auto at = [&](int a, int r, int lane) {
+        const size_t idx = ((size_t)a * mt + r) * G + lane;
+        return b->precision == SB_FP32C ? (double)((const float *)raw[i].data())[idx]
+                                        : ((const double *)raw[i].data())[idx];
+      };
       auto prev = [&](int node) {   // u^{n-1} at a node (1-based)
         if (node <= 0) return 0.0;
         const int lane = (node - 1) / mt, r = (node - 1) % mt;
-        auto at = [&](int a) { return st[((size_t)a * mt + r) * G + lane]; };
-        return (at(0) - at(2)) - (at(1) - at(3));
+        return (at(0, r, lane) - at(2, r, lane)) - (at(1, r, lane) - at(3, r, lane));
       };
       const double uHm = D.hw0 * prev(D.hn0) + D.hw1 * prev(D.hn1);
-      S.uH_nm1 = uHm;
-      S.uH_n = uHm + D.k * e[i].v_H;
-      S.eta_nm1 = 0.0;
-      S.touched = 0;
+      S[i].uH_nm1 = uHm;
+      S[i].uH_n = uHm + D.k * e[i].v_H;
+      S[i].eta_nm1 = 0.0;
+      S[i].touched = 0;
     }
-    std::vector<char> bt;
     if (b->precision == SB_FP32C)
-      to_prec<float>(P.tabf, bt);
+      to_prec<float>(plans[i].tabf, tabs[i]);
     else
-      to_prec<double>(P.tabf, bt);
-    he = hipMemcpy(const_cast<void *>(D.tabf), bt.data(), bt.size(), hipMemcpyHostToDevice);
-    if (he == hipSuccess) he = hipMemcpy(b->d_desc + first + i, &D, sizeof(Desc), hipMemcpyHostToDevice);
-    if (he == hipSuccess) he = hipMemcpy(b->d_status + first + i, &S, sizeof(Status), hipMemcpyHostToDevice);
-    if (he != hipSuccess) break;
-    s.plan = P;
+      to_prec<double>(plans[i].tabf, tabs[i]);
+  }
+  for (int i = 0; i < count && he == hipSuccess; ++i) {
+    const Desc &D = plans[i].desc;
+    he = hipMemcpyAsync(const_cast<void *>(D.tabf), tabs[i].data(), tabs[i].size(), hipMemcpyHostToDevice, b->stream);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(b->d_desc + slots[i], &plans[i].desc, sizeof(Desc), hipMemcpyHostToDevice, b->stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(b->d_status + slots[i], &S[i], sizeof(Status), hipMemcpyHostToDevice, b->stream);
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(b->stream);   // host buffers are released after this
+  if (he != hipSuccess) return hip_fail(b, he, "restrike upload");
+  for (int i = 0; i < count; ++i) {
+    Slot &s = b->slots[slots[i]];
+    s.plan = plans[i];
     s.restruck = true;
   }
-  if (he != hipSuccess) return hip_fail(b, he, "restrike upload");
   ++b->epoch;
   b->work_dirty = true;
   return SB_OK;
+}
+
+extern "C" int string_batch_restrike(sb_batch *b, int first, int count, const sb_excitation *e) {
+  if (!b) return SB_EINVAL;
+  if (!range_ok(b, first, count)) return fail(b, SB_EINVAL, "bad slot range");
+  std::vector<int32_t> slots(count);
+  for (int i = 0; i < count; ++i) slots[i] = first + i;
+  return string_batch_restrike_list(b, count, slots.data(), e);
 }
 
 extern "C" int string_batch_rewind(sb_batch *b, int first, int count) {
