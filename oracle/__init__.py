@@ -33,7 +33,7 @@ class OrcString(C.Structure):
         ("sigma0_l", C.c_double), ("sigma1_l", C.c_double), ("x_out", C.c_double),
         ("n_samples", C.c_int64), ("mod_type", C.c_int32), ("grid_t", C.c_int32),
         ("mod_depth_cents", C.c_double), ("mod_rate_hz", C.c_double),
-        ("glide_semitones", C.c_double), ("grid_l", C.c_int32), ("pad0", C.c_int32),
+        ("glide_semitones", C.c_double), ("grid_l", C.c_int32), ("boundary", C.c_int32),
     ]
 
 
@@ -104,7 +104,7 @@ def _load():
 
 STRING_KEYS = ("fs", "f0", "B", "alpha", "theta", "sigma0_t", "sigma1_t", "sigma0_l", "sigma1_l",
                "x_out", "n_samples", "mod_type", "mod_depth_cents", "mod_rate_hz",
-               "glide_semitones", "grid_t", "grid_l")
+               "glide_semitones", "grid_t", "grid_l", "boundary")
 EXC_KEYS = ("type", "x", "c0", "v_H", "M_H", "K_H", "alpha_H", "rhoA", "x_end", "v_B", "F_B", "attack",
             "fric_a", "fric_eps")
 

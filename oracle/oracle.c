@@ -311,12 +311,15 @@ double orc_gamma_at(const orc_string *s, int64_t n) {
     return 2.0 * f;
 }
 
+static int clamped_stable(int Nt, double th, double gamma, double kappa, double k);
+
 int orc_grid_plan(const orc_string *s, orc_grid *g) {
     if (!s || !g) return ORC_EINVAL;
     if (!(s->fs > 0.0) || !(s->f0 > 0.0) || !(s->B >= 0.0) || !(s->alpha >= 1.0)) return ORC_EINVAL;
     if (!isfinite(s->fs) || !isfinite(s->f0) || !isfinite(s->B) || !isfinite(s->alpha)) return ORC_EINVAL;
     double th = theta_of(s);
     if (!(th > 0.5) || !(th <= 1.0)) return ORC_EINVAL;
+    if (s->boundary != 0 && s->boundary != 1) return ORC_EINVAL;
     double k = 1.0 / s->fs;
     double gamma0 = 2.0 * s->f0;
     /* Sec. 4.1: K = (pi kappa / gamma)^2, with K read as the inharmonicity B */
@@ -332,6 +335,8 @@ int orc_grid_plan(const orc_string *s, orc_grid *g) {
     double gk2 = gmax * gmax * k * k;
     double h2 = (gk2 + sqrt(gk2 * gk2 + 16.0 * (2.0 * th - 1.0) * kappa * kappa * k * k)) / (2.0 * (2.0 * th - 1.0));
     int Nt = s->grid_t > 0 ? s->grid_t : (int)floor(1.0 / sqrt(h2));
+    if (s->boundary == 1 && s->grid_t <= 0)
+        while (Nt >= 2 && !clamped_stable(Nt, th, gmax, kappa, k)) --Nt;
     int Nl = 0;
     if (s->alpha != 1.0) {
         /* Sec. 3.2: h^(l) = gamma alpha k (bound), N_l = floor(1/h^(l)) */
@@ -366,6 +371,33 @@ static csr op_Dminus(int N, double h) {
     return A;
 }
 
+/* delta_xxxx of a clamped string: (N-1) x (N-1), the five-point difference
+ * (u_{l+2} - 4u_{l+1} + 6u_l - 4u_{l-1} + u_{l-2})/h^4 on the interior nodes,
+ * with the ends fixed (u_0 = u_N = 0) and of zero slope, (u_1 - u_{-1})/(2h)
+ * = (u_{N+1} - u_{N-1})/(2h) = 0, so the ghost nodes mirror: u_{-1} = u_1 and
+ * u_{N+1} = u_{N-1}.  (Sec. 4.1 names the clamped string whose partials eq.
+ * (10) gives.) */
+static csr op_D4_clamped(int N, double h) {
+    static const double stencil[5] = {1.0, -4.0, 6.0, -4.0, 1.0};
+    int n = 5 * (N - 1), t = 0;
+    int *r = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int *c = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    double *v = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double h4 = h * h * h * h;
+    for (int l = 1; l <= N - 1; ++l) {
+        for (int d = -2; d <= 2; ++d) {
+            int m = l + d;
+            if (m == -1) m = 1;              /* ghost u_{-1} = u_1 */
+            if (m == N + 1) m = N - 1;       /* ghost u_{N+1} = u_{N-1} */
+            if (m == 0 || m == N) continue;  /* fixed ends */
+            r[t] = l - 1; c[t] = m - 1; v[t] = stencil[d + 2] / h4; ++t;   /* duplicates add up */
+        }
+    }
+    csr A = csr_from_coo(N - 1, N - 1, t, r, c, v);
+    free(r); free(c); free(v);
+    return A;
+}
+
 /* mu_{x.}: (N-1) x (N-1), (u_{l+1} + u_{l-1})/2 with u_0 = u_N = 0. */
 static csr op_Mx(int N) {
     int n = 2 * (N - 1), t = 0;
@@ -379,6 +411,47 @@ static csr op_Mx(int N) {
     csr A = csr_from_coo(N - 1, N - 1, t, r, c, v);
     free(r); free(c); free(v);
     return A;
+}
+
+/* READING of the transverse spacing with clamped ends: the bound in
+ * orc_grid_plan comes from the sine modes of simply supported ends.  For any
+ * ends, eq. (4a) without loss and nonlinearity keeps a non-negative energy
+ * exactly when 4 Theta - k^2 (gamma^2 (-D_xx) + kappa^2 D_xxxx) is positive
+ * semi-definite (energy method), so a clamped grid takes the largest N_t, not
+ * above the simply supported one, for which that matrix is positive
+ * definite: all pivots of its LDL^T factorisation positive (Sylvester). */
+static double csr_at(const csr *A, int i, int j) {
+    for (int p = A->rp[i]; p < A->rp[i + 1]; ++p)
+        if (A->ci[p] == j) return A->v[p];
+    return 0.0;
+}
+
+static int clamped_stable(int Nt, double th, double gamma, double kappa, double k) {
+    int n = Nt - 1;
+    double h = 1.0 / Nt;
+    csr Dm = op_Dminus(Nt, h);
+    csr DmT = csr_transpose(&Dm);
+    csr L = csr_mul(&DmT, &Dm);                       /* -D_xx */
+    csr D4 = op_D4_clamped(Nt, h);
+    csr Kop = csr_add(gamma * gamma, &L, kappa * kappa, &D4);
+    csr I = csr_eye(n, 1.0), Mx = op_Mx(Nt);
+    csr Th = csr_add(th, &I, 1.0 - th, &Mx);
+    csr M = csr_add(4.0, &Th, -k * k, &Kop);
+    /* band LDL^T, half-bandwidth 2: l1[i] = L(i, i-1), l2[i] = L(i, i-2) */
+    double *d = (double *)calloc((size_t)n + 2, sizeof(double));
+    double *l1 = (double *)calloc((size_t)n + 2, sizeof(double));
+    int ok = 1;
+    for (int i = 0; i < n && ok; ++i) {
+        double a2 = i >= 2 ? csr_at(&M, i, i - 2) / d[i - 2] : 0.0;
+        double a1 = i >= 1 ? (csr_at(&M, i, i - 1) - (i >= 2 ? a2 * l1[i - 1] * d[i - 2] : 0.0)) / d[i - 1] : 0.0;
+        d[i] = csr_at(&M, i, i) - (i >= 1 ? a1 * a1 * d[i - 1] : 0.0) - (i >= 2 ? a2 * a2 * d[i - 2] : 0.0);
+        l1[i] = a1;
+        ok = d[i] > 0.0;
+    }
+    free(d); free(l1);
+    csr_free(&Dm); csr_free(&DmT); csr_free(&L); csr_free(&D4); csr_free(&Kop);
+    csr_free(&I); csr_free(&Mx); csr_free(&Th); csr_free(&M);
+    return ok;
 }
 
 /* I_(l)->(t): N_t x N_l.  READING of Sec. 3.1 ("p-th order upsampling
@@ -449,7 +522,10 @@ static void ops_build(const orc_string *s, const orc_grid *g, ops_t *o) {
     o->Dp_t = csr_transpose(&o->Dm_t);                   /* D_{x+} = -D_{x-}^T */
     { csr t = csr_scale(-1.0, &o->Dp_t); csr_free(&o->Dp_t); o->Dp_t = t; }
     o->Dxx_t = csr_mul(&o->Dp_t, &o->Dm_t);              /* delta_xx = delta_x+ delta_x- */
-    o->Dxxxx_t = csr_mul(&o->Dxx_t, &o->Dxx_t);          /* READING: simply supported, D_xxxx = D_xx^2 */
+    if (s->boundary == 1)
+        o->Dxxxx_t = op_D4_clamped(Nt, g->h_t);
+    else
+        o->Dxxxx_t = csr_mul(&o->Dxx_t, &o->Dxx_t);      /* READING: simply supported, D_xxxx = D_xx^2 */
     o->I_t = csr_eye(o->nt, 1.0);
     {   /* Theta = theta I + (1-theta) M_x (eq. 9) */
         csr M = op_Mx(Nt);
@@ -716,7 +792,14 @@ static double energy_half(const orc_string *s, const ops_t *o, double gamma,
     csr_matvec(&o->Dxx_t, u1, c1, NULL);
     csr_matvec(&o->Dxx_t, u0, c0, NULL);
     double kin = 0.0, pot = 0.0, stiff = 0.0;
-    for (int i = 0; i < nt; ++i) { kin += du[i] * tdu[i]; stiff += c1[i] * c0[i]; }
+    if (s->boundary == 1) {
+        /* clamped: the stiffness energy is u^{n+1} . D_xxxx u^n (D_xxxx is
+         * symmetric; with simply supported ends it equals D_xx u^{n+1} . D_xx u^n) */
+        csr_matvec(&o->Dxxxx_t, u0, c0, NULL);
+        for (int i = 0; i < nt; ++i) { kin += du[i] * tdu[i]; stiff += u1[i] * c0[i]; }
+    } else {
+        for (int i = 0; i < nt; ++i) { kin += du[i] * tdu[i]; stiff += c1[i] * c0[i]; }
+    }
     for (int i = 0; i < Nt; ++i) pot += q1[i] * q0[i];
     double H = ht / (2.0 * k * k) * kin + gamma * gamma * ht / 2.0 * pot + g->kappa * g->kappa * ht / 2.0 * stiff;
     if (o->has_l) {

@@ -39,7 +39,7 @@ typedef struct {
     int32_t grid_t;       /* 0: N_t from the stability bound; else forced N_t */
     double mod_depth_cents, mod_rate_hz, glide_semitones;
     int32_t grid_l;       /* 0: N_l from h_l >= gamma alpha k; else forced N_l */
-    int32_t pad0;
+    int32_t boundary;     /* transverse ends: 0 simply supported, 1 clamped (Sec. 4.1, eq. 10) */
 } orc_string;
 
 typedef struct {

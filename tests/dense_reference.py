@@ -44,6 +44,26 @@ def point_row(x, N):
     return row
 
 
+def clamped_curvature(N, h):
+    """Curvature at the nodes 0..N of a clamped string, (N+1) x (N-1), and the
+    trapezoid weights of its energy: with u_0 = u_N = 0 and zero end slope the
+    second difference at an end node is 2 u_1 / h^2 (resp. 2 u_{N-1} / h^2).
+    The stiffness energy (h/2) sum_i w_i c_i^2 has the gradient h C^T W C u,
+    so D_xxxx = C^T W C."""
+    C = np.zeros((N + 1, N - 1))
+    for i in range(1, N):
+        C[i, i - 1] = -2.0
+        if i - 2 >= 0:
+            C[i, i - 2] = 1.0
+        if i <= N - 2:
+            C[i, i] = 1.0
+    C[0, 0] = 2.0
+    C[N, N - 2] = 2.0
+    w = np.ones(N + 1)
+    w[0] = w[N] = 0.5
+    return C / h ** 2, w
+
+
 class Dense:
     def __init__(self, p, g):
         self.p, self.g = p, g
@@ -56,7 +76,11 @@ class Dense:
         self.Dxx_t = self.Dp_t @ self.Dm_t
         Mx = 0.5 * (np.eye(self.nt, k=1) + np.eye(self.nt, k=-1))
         self.Theta = th * np.eye(self.nt) + (1 - th) * Mx
-        self.S = g["kappa"] ** 2 * k ** 2 * (self.Dxx_t @ self.Dxx_t)
+        if p.get("boundary", 0) == 1:
+            C, w = clamped_curvature(Nt, ht)
+            self.S = g["kappa"] ** 2 * k ** 2 * (C.T @ (w[:, None] * C))
+        else:
+            self.S = g["kappa"] ** 2 * k ** 2 * (self.Dxx_t @ self.Dxx_t)
         if Nl > 0:
             hl = g["h_l"]
             self.Dm_l = dmin(Nl, hl)
@@ -159,8 +183,12 @@ def energy(p, g, u1, u0, z1, z0, gamma):
     dpad = np.concatenate([[0.0], du, [0.0]])
     theta_du = th * du + (1 - th) * 0.5 * (dpad[2:] + dpad[:-2])
     q1, q0 = half_diff(u1, ht), half_diff(u0, ht)
-    H = ht / (2 * k * k) * np.dot(du, theta_du) + gamma ** 2 * ht / 2 * np.dot(q1, q0) \
-        + kap ** 2 * ht / 2 * np.dot(lap(u1, ht), lap(u0, ht))
+    if p.get("boundary", 0) == 1:
+        C, w = clamped_curvature(Nt, ht)
+        stiff = np.dot(w * (C @ u1), C @ u0)
+    else:
+        stiff = np.dot(lap(u1, ht), lap(u0, ht))
+    H = ht / (2 * k * k) * np.dot(du, theta_du) + gamma ** 2 * ht / 2 * np.dot(q1, q0) + kap ** 2 * ht / 2 * stiff
     if Nl > 0:
         hl = g["h_l"]
         a2 = p["alpha"] ** 2

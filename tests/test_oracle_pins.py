@@ -478,3 +478,147 @@ def test_pr2_restrike_is_time_invariant(kind):
     b = oracle.run(q, None, schedule=[(m, x)])["y_u"]
     assert np.all(b[:m] == 0.0)
     np.testing.assert_allclose(b[m - 1:], a, rtol=0, atol=1e-12 * np.max(np.abs(a)))
+
+
+# ---------------------------------------------------------------------------
+# Clamped ends (Sec. 4.1: the clamped stiff string whose partials eq. (10)
+# gives).  The dense reference builds D_xxxx from the end-node curvatures
+# and their trapezoid-weighted energy (C^T W C); the oracle builds it from
+# the five-point stencil with mirrored ghost nodes.
+# ---------------------------------------------------------------------------
+def _clamped_operators(g):
+    N, h, th = g["N_t"], g["h_t"], g["theta"]
+    Dm = DR.dmin(N, h)
+    C, w = DR.clamped_curvature(N, h)
+    K = g["gamma0"] ** 2 * (Dm.T @ Dm) + g["kappa"] ** 2 * (C.T @ (w[:, None] * C))
+    n = N - 1
+    Th = th * np.eye(n) + (1 - th) * 0.5 * (np.eye(n, k=1) + np.eye(n, k=-1))
+    return K, Th
+
+
+def _clamped_modes(g):
+    """mu_m and Theta-orthonormal modes of Theta^{-1} K; eigenvalues refined
+    by Rayleigh quotients in extended precision."""
+    import scipy.linalg as sl
+    K, Th = _clamped_operators(g)
+    _, V = sl.eigh(K, Th)
+    L = np.longdouble
+    VL = V.astype(L)
+    mu = np.einsum("im,im->m", VL, K.astype(L) @ VL) / np.einsum("im,im->m", VL, Th.astype(L) @ VL)
+    return mu, V, Th
+
+
+def _clamped_freqs(g):
+    mu, _, _ = _clamped_modes(g)
+    k = g["k"]
+    return np.sort(np.arccos(1 - np.asarray(mu, np.float64) * k * k / 2) / (2 * np.pi * k))
+
+
+@pytest.mark.parametrize("theta", [0.0, 1.0])
+def test_pc1_clamped_linear_matches_modal_closed_form(theta):
+    # lossless linear pluck: each generalized mode of (K, Theta) follows
+    # xi^{n+1} = (2 - mu k^2) xi^n - xi^{n-1} with xi^0 = xi^1, whose solution
+    # is xi^0 cos((n - 1/2) phi) / cos(phi / 2), cos(phi) = 1 - mu k^2 / 2
+    p, e = W.single_linear(seconds=0.1, theta=theta)
+    p = dict(p, boundary=1, sigma0_t=0.0, sigma1_t=0.0)
+    res = oracle.run(p, e, want=("y_u",))
+    g = res["grid"]
+    N, k = g["N_t"], g["k"]
+    mu, V, Th = _clamped_modes(g)
+    x = np.arange(1, N) / N
+    tri = np.where(x <= e["x"], e["c0"] * x / e["x"], e["c0"] * (1 - x) / (1 - e["x"]))
+    L = np.longdouble
+    xi0 = (V.T @ Th @ tri).astype(L)
+    lo = int(math.floor(p["x_out"] * N))
+    w = p["x_out"] * N - lo
+    r = ((1 - w) * V[lo - 1] + w * V[lo]).astype(L)
+    phi = np.arccos(1 - mu * L(k) * L(k) / 2)
+    n = np.arange(p["n_samples"]).astype(L)
+    y = (np.cos(np.outer(n - L(0.5), phi)) / np.cos(phi / 2)) @ (xi0 * r)
+    y = np.asarray(y, np.float64)
+    err = np.max(np.abs(res["y_u"] - y)) / np.max(np.abs(y))
+    assert err < 1e-14 * p["n_samples"], err
+    # the ends matter: simply supported ends give another output
+    ss = oracle.run(dict(p, boundary=0), e, want=("y_u",))["y_u"]
+    assert np.max(np.abs(ss - y)) > 1e3 * err * np.max(np.abs(y))
+
+
+@pytest.mark.parametrize("B", [1e-4, 1e-3])
+def test_pc2_clamped_shift_approaches_eq10(B):
+    # eq. (10): clamping raises every partial by the factor
+    # 1 + 2 sqrt(B)/pi + 4 B/pi^2 over n f0 sqrt(1 + B n^2).  The discrete
+    # raise (clamped over simply supported modes of the same grid) tends to it
+    # as the grid resolves the boundary layer (fs up, so h down)
+    fletcher = 1200 * math.log2(1 + 2 * math.sqrt(B) / math.pi + 4 * B / math.pi ** 2)
+    errs = []
+    for fs in (48000.0, 192000.0, 768000.0):
+        p = dict(W.string(110.0, B, 1.0, 0.0, 0.0, 10), fs=fs, theta=1.0)
+        g = oracle.grid(dict(p, boundary=1))
+        assert g["N_t"] == oracle.grid(p)["N_t"]
+        N, k = g["N_t"], g["k"]
+        m = np.arange(1, 4)
+        s = np.sin(m * np.pi / (2 * N)) ** 2
+        b = 4 * (g["gamma0"] * k * N) ** 2 * s + 16 * (g["kappa"] * k * N * N) ** 2 * s ** 2
+        f_ss = np.arccos(1 - b / 2) / (2 * np.pi * k)    # theta = 1: mu_m = 1
+        shift = cents(_clamped_freqs(g)[:3], f_ss)
+        errs.append(np.max(np.abs(shift - fletcher)))
+        assert np.all(shift > 0.6 * fletcher)
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.3
+
+
+def test_pc2_oracle_clamped_partials_match_the_modes():
+    # the oracle's measured partials equal the clamped discrete modes
+    p, e = W.single_linear(seconds=1.0)
+    p = dict(p, boundary=1, sigma0_t=0.0, sigma1_t=0.0)
+    res = oracle.run(p, e, want=("y_u",))
+    f_disc = _clamped_freqs(res["grid"])
+    modes = np.array([1, 2, 3, 4])
+    f_est, _, _ = fit_partials(res["y_u"], p["fs"], f_disc[modes - 1], decay_guess=0.0, max_samples=24000)
+    assert np.max(np.abs(cents(f_est, f_disc[modes - 1]))) < 0.01
+
+
+@pytest.mark.parametrize("alpha", [2.0, 3.5])
+def test_pc3_clamped_nonlinear_energy_is_conserved(alpha):
+    p = dict(W.string(300.0, 1e-3, alpha, 0.0, 0.0, 1500), boundary=1)
+    e = W.pluck(0.14, 0.02)
+    res = oracle.run(p, e, want=("traj_u", "traj_z", "energy"))
+    g = res["grid"]
+    H = np.array([DR.energy(p, g, res["traj_u"][n + 1], res["traj_u"][n],
+                            res["traj_z"][n + 1], res["traj_z"][n], 2 * p["f0"])
+                  for n in range(p["n_samples"] - 1)])
+    assert np.max(np.abs(H - H[0])) / abs(H[0]) < 1e-12
+    assert np.allclose(res["energy"][:-1], H, rtol=1e-11, atol=0)
+    # the simply supported energy formula is not conserved by the clamped run
+    Hs = np.array([DR.energy(dict(p, boundary=0), g, res["traj_u"][n + 1], res["traj_u"][n],
+                             res["traj_z"][n + 1], res["traj_z"][n], 2 * p["f0"])
+                   for n in range(p["n_samples"] - 1)])
+    assert np.max(np.abs(Hs - Hs[0])) / abs(Hs[0]) > 1e-6
+
+
+def test_pc4_clamped_grid_is_energy_stable_and_sharp():
+    import scipy.linalg as sl
+    cases = [W.single_linear(), W.single_nonlinear(), W.single_linear(theta=1.0)] + W.random_batch(8, seed=5)
+    for p, _ in cases:
+        p = dict(p, boundary=1)
+        g = oracle.grid(p)
+        for N, stable in ((g["N_t"], True), (g["N_t"] + 1, False)):
+            gg = dict(g, N_t=N, h_t=1.0 / N)
+            K, Th = _clamped_operators(dict(gg, gamma0=g["gamma_max"]))
+            top = sl.eigh(K, Th, eigvals_only=True)[-1] * g["k"] ** 2
+            assert (top < 4.0) == stable, (p["f0"], N, top)
+
+
+@pytest.mark.parametrize("exc", ["pluck", "hammer"])
+def test_pc5_clamped_dense_brute_force(exc):
+    p = dict(_tiny(), boundary=1)
+    g = oracle.grid(p)
+    e = W.pluck(0.3, 0.02) if exc == "pluck" else W.hammer(0.3, 30.0, rhoA=0.002)
+    r = oracle.run(p, e, want=("traj_u", "traj_z", "u_H"))
+    U, Z, UH = DR.run_dense(p, e, g, p["n_samples"])
+    scale = np.max(np.abs(U))
+    assert np.max(np.abs(r["traj_u"] - U)) < 1e-12 * scale
+    assert np.max(np.abs(r["traj_z"] - Z)) < 1e-12 * scale
+    # and it differs from the simply supported run
+    U0, _, _ = DR.run_dense(dict(p, boundary=0), e, g, p["n_samples"])
+    assert np.max(np.abs(U0 - U)) > 1e-6 * scale
