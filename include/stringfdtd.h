@@ -57,6 +57,15 @@ extern "C" {
 #define SB_MOD_VIBRATO 1   /* f0 * 2^{(depth/1200) sin(2 pi rate t)}                  */
 #define SB_MOD_GLIDE   2   /* f0 * 2^{(semitones/12) t/T}, T = n_samples/fs           */
 
+/* Transverse end conditions (zeta is always fixed at both ends).  Simply
+ * supported: u = u_xx = 0, D_xxxx = D_xx^2, partials n f0 sqrt(1 + B n^2).
+ * Clamped: u = u_x = 0 (the string of Sec. 4.1, whose partials eq. (10)
+ * gives); D_xxxx takes mirrored ghost nodes u_{-1} = u_1, u_{N+1} = u_{N-1},
+ * and N_t is lowered below the simply supported bound when needed until
+ * 4 Theta - k^2 (gamma^2 (-D_xx) + kappa^2 D_xxxx) is positive definite. */
+#define SB_BOUNDARY_SIMPLE  0
+#define SB_BOUNDARY_CLAMPED 1
+
 typedef struct sb_batch sb_batch;   /* opaque; owns all device memory of the batch */
 
 /* Physical and control parameters of one string (Table 1; Sec. 3.2, 4.1).
@@ -83,7 +92,7 @@ typedef struct {
     double mod_rate_hz;        /* vibrato rate                                    */
     double glide_semitones;    /* glide interval over the duration                */
     int32_t grid_l;            /* 0 or a forced N_l                               */
-    int32_t reserved;
+    int32_t boundary;          /* SB_BOUNDARY_*: transverse end condition         */
 } sb_string_params;
 
 /* Excitation (Sec. 3.3).  Pluck: initial triangle of peak c0 at x, released

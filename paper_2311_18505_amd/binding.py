@@ -32,7 +32,7 @@ class SbStringParams(C.Structure):
         ("sigma0_l", C.c_double), ("sigma1_l", C.c_double), ("x_out", C.c_double),
         ("n_samples", C.c_int64), ("mod_type", C.c_int32), ("grid_t", C.c_int32),
         ("mod_depth_cents", C.c_double), ("mod_rate_hz", C.c_double), ("glide_semitones", C.c_double),
-        ("grid_l", C.c_int32), ("reserved", C.c_int32),
+        ("grid_l", C.c_int32), ("boundary", C.c_int32),
     ]
 
 

@@ -549,7 +549,8 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
     const int64_t st = std::min<int64_t>(n_steps, s.plan.desc.n_samples - s.samples_host);
     const double cost = (double)st * (double)(s.plan.desc.nt + s.plan.desc.nl + 8);
     const int c = b->precision == SB_FP64_PLAIN ? 0 : s.plan.desc.cls;
-    cls[s.plan.desc.bow_on ? 1 : 0][c].push_back({cost, i});
+    // bowed and clamped strings run in the instantiation that carries their code
+    cls[(s.plan.desc.bow_on || s.plan.desc.clamped) ? 1 : 0][c].push_back({cost, i});
   }
   if (!any) return fail(b, SB_ESTATE, "no excited slot");
   std::vector<int32_t> work;

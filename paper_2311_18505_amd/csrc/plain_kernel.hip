@@ -64,7 +64,7 @@ __global__ __launch_bounds__(64) void plain_kernel(PlainArgs a) {
   double *q = Zm + (Nl + 1);          // D- u^n at halves 1..Nt
   double *pt = q + (Nt + 2);          // I_(l)->(t) D- zeta^n
   double *ptm = pt + (Nt + 2);        // I_(l)->(t) D- zeta^{n-1}
-  double *cxx = ptm + (Nt + 2);       // D_xx u^n at nodes 0..Nt (0 at the ends)
+  double *cxx = ptm + (Nt + 2);       // D_xx u^n at nodes 0..Nt (ends: from the boundary condition)
   double *gz = cxx + (Nt + 2);        // I_(t)->(l) (q D- u^{n-1}) at l-halves 1..Nl
   double *rhs2 = gz + (Nl + 2);       // bow: n (+1 trash), becomes A^{-1} [J_p(x_B); 0]
   const bool bow = D.bow_on != 0;
@@ -119,10 +119,14 @@ __global__ __launch_bounds__(64) void plain_kernel(PlainArgs a) {
       const int ic = nv ? h : 1;
       const double cx = Ntd * Ntd * (U[ic + 1] - 2.0 * U[ic] + U[ic - 1]);
       const bool in = h < Nt + 2;
+      // clamped ends: mirrored ghost nodes give D_xx u = 2 u_1 / h^2 at node 0
+      // (2 u_{Nt-1} / h^2 at node Nt); simply supported ends give 0
+      const bool end = D.clamped != 0 && (h == 0 || h == Nt);
+      const double cend = end ? 2.0 * Ntd * Ntd * U[h == 0 ? 1 : Nt - 1] : 0.0;
       put_or_trash(q + h, in, trash, hv ? qq : 0.0);
       put_or_trash(pt + h, in, trash, hv && nl > 0 ? p1 : 0.0);
       put_or_trash(ptm + h, in, trash, hv && nl > 0 ? p0 : 0.0);
-      put_or_trash(cxx + h, in, trash, nv ? cx : 0.0);
+      put_or_trash(cxx + h, in, trash, nv ? cx : cend);
     }
     for (int b = 0; b < n * W; b += 64) put_or_trash(band + b + lane(), b + lane() < n * W, trash, 0.0);
     for (int b = 0; b <= n; b += 64) put_or_trash(rhs + b + lane(), b + lane() <= n, trash, 0.0);

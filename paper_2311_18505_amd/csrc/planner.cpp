@@ -20,6 +20,28 @@ double theta_of(const sb_string_params &p) {
   return p.theta > 0.0 ? p.theta : 0.5 * (1.0 + 4.0 / (M_PI * M_PI));
 }
 
+// Positive definiteness of the pentadiagonal 4 Theta - (gk)^2 (-D_xx) -
+// (kk)^2 D_xxxx (clamped D_xxxx) on N-1 nodes, by the pivots of its LDL^T
+// factorisation.
+static bool clamped_energy_positive(int N, double th, double gk, double kk) {
+  const int n = N - 1;
+  const double h2 = 1.0 / ((double)N * N), g2 = gk * gk / h2, s2 = kk * kk / (h2 * h2);
+  const double off1 = 2.0 * (1.0 - th) + g2 + 4.0 * s2, off2 = -s2;
+  double d1 = 0.0, d2 = 0.0, l1p = 0.0;   // pivots of rows i-1, i-2; L(i-1, i-2)
+  for (int i = 0; i < n; ++i) {
+    // each end node adds its mirrored ghost to the diagonal of D_xxxx
+    const double diag = 4.0 * th - 2.0 * g2 - (6.0 + (i == 0) + (i == n - 1)) * s2;
+    const double a2 = i >= 2 ? off2 / d2 : 0.0;
+    const double a1 = i >= 1 ? (off1 - (i >= 2 ? a2 * l1p * d2 : 0.0)) / d1 : 0.0;
+    const double d = diag - (i >= 1 ? a1 * a1 * d1 : 0.0) - (i >= 2 ? a2 * a2 * d2 : 0.0);
+    if (!(d > 0.0)) return false;
+    d2 = d1;
+    d1 = d;
+    l1p = a1;
+  }
+  return true;
+}
+
 int plan_grid(const sb_string_params &p, GridPlan &g, std::string &err) {
   if (!finite_all({p.fs, p.f0, p.B, p.alpha, p.theta, p.sigma0_t, p.sigma1_t, p.sigma0_l, p.sigma1_l,
                    p.x_out, p.mod_depth_cents, p.mod_rate_hz, p.glide_semitones})) {
@@ -51,6 +73,10 @@ int plan_grid(const sb_string_params &p, GridPlan &g, std::string &err) {
     err = "bad mod_type or grid override";
     return SB_EINVAL;
   }
+  if (p.boundary != SB_BOUNDARY_SIMPLE && p.boundary != SB_BOUNDARY_CLAMPED) {
+    err = "boundary must be SB_BOUNDARY_SIMPLE or SB_BOUNDARY_CLAMPED";
+    return SB_EINVAL;
+  }
   const double k = 1.0 / p.fs;
   const double gamma0 = 2.0 * p.f0;                      // Sec. 4.1: f0 = gamma/2
   const double kappa = gamma0 * std::sqrt(p.B) / M_PI;    // Sec. 4.1: K = (pi kappa/gamma)^2, K := B
@@ -63,7 +89,14 @@ int plan_grid(const sb_string_params &p, GridPlan &g, std::string &err) {
   const double gk2 = gmax * gmax * k * k;
   const double h2 = (gk2 + std::sqrt(gk2 * gk2 + 16.0 * (2.0 * th - 1.0) * kappa * kappa * k * k)) /
                     (2.0 * (2.0 * th - 1.0));
-  const int Nt = p.grid_t > 0 ? p.grid_t : (int)std::floor(1.0 / std::sqrt(h2));
+  int Nt = p.grid_t > 0 ? p.grid_t : (int)std::floor(1.0 / std::sqrt(h2));
+  // The bound above comes from the sine modes of simply supported ends.  With
+  // clamped ends the scheme's energy (eq. (4a) without loss and
+  // nonlinearity) stays non-negative exactly when 4 Theta - k^2 (gamma^2
+  // (-D_xx) + kappa^2 D_xxxx) is positive semi-definite; lower N_t until it
+  // is positive definite.
+  if (p.boundary == SB_BOUNDARY_CLAMPED && p.grid_t <= 0)
+    while (Nt >= 2 && !clamped_energy_positive(Nt, th, gmax * k, kappa * k)) --Nt;
   int Nl = 0;
   if (p.alpha != 1.0) Nl = p.grid_l > 0 ? p.grid_l : (int)std::floor(1.0 / (gmax * p.alpha * k));
   if (Nt < 2 || (p.alpha != 1.0 && Nl < 2)) {
@@ -184,6 +217,7 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
   }
 
   D.mod_type = p.mod_type;
+  D.clamped = p.boundary == SB_BOUNDARY_CLAMPED ? 1 : 0;
   D.f0 = p.f0;
   D.fs = p.fs;
   if (p.mod_type == 1) {

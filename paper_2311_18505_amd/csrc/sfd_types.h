@@ -56,7 +56,8 @@ struct Desc {
   double rho_t, itk_t;        // Toeplitz factor of T_u0: rho, 1/kappa_T
   double rho_l, itk_l;        // same for T_z
   // f0 modulation
-  int32_t mod_type, pad0;     // 0 none, 1 vibrato, 2 glide
+  int32_t mod_type;           // 0 none, 1 vibrato, 2 glide
+  int32_t clamped;            // 1: clamped transverse ends (mirrored ghost nodes in D_xxxx)
   double f0, fs, mod_a, mod_b;   // vibrato: a = depth/1200, b = rate; glide: a = semis/12, b = 1/T
   // hammer
   int32_t ham_on;             // 1 if the excitation is a hammer

@@ -502,7 +502,7 @@ __device__ __forceinline__ void energy_fill(double *sD, const T (&u)[MM], const 
 // plus the nonlinear potential (gamma^2 (alpha^2-1)/2)(p q^2/2 + q^4/8) in
 // the time-paired form of the scheme.  Streams over the lane's points
 // (runs once per monitor period).
-template <int G, int MM, typename T>
+template <int G, int MM, typename T, bool CLAMP>
 __device__ __forceinline__ double energy_fp64(const Desc &D, double g2k2, const double *sD, int li) {
   using E = EnergyLds<G, MM>;
   const double *U1 = sD, *U0 = sD + E::kArr, *Z1 = sD + 2 * E::kArr, *Z0 = sD + 3 * E::kArr;
@@ -522,6 +522,9 @@ __device__ __forceinline__ double energy_fp64(const Desc &D, double g2k2, const 
     const double c1 = (q1p - q1) * Ntd, c0 = (q0p - q0) * Ntd;
     kin += node ? du * (th * du + 0.5 * (1.0 - th) * (dm + dp)) : 0.0;
     stf += node ? c1 * c0 : 0.0;
+    // clamped ends: the end nodes' curvatures 2 q_1 Nt and -2 q_Nt Nt enter
+    // with trapezoid weight 1/2
+    if constexpr (CLAMP) stf += (D.clamped != 0 && half && (i == 1 || i == Nt)) ? 2.0 * Ntd * Ntd * q1 * q0 : 0.0;
     pot += half ? q1 * q0 : 0.0;
     const bool on = half && nl > 0;
     const uint32_t jab = ld_if<uint32_t>(D.tab, r * G + li, on);
@@ -609,6 +612,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   wsteps = uni(wsteps);
 
   const bool any_mod = __ballot(D.mod_type != 0) != 0;
+  // clamped ends, like the bow, exist only in the BOW instantiation
+  const bool clamped = BOW && D.clamped != 0;
+  const bool any_clamp = BOW && __ballot(clamped) != 0;
   const int hn0 = D.hn0, hn1 = D.hn1, on0 = D.on0, on1 = D.on1;
   const double hw0 = D.hw0, hw1 = D.hw1, ow0 = D.ow0, ow1 = D.ow1;
   const double omega_pow = D.omega_pow, alpha_H = D.alpha_H, Mr = D.Mr, IHs = D.IHs;
@@ -791,7 +797,20 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
         const T qn = (r + 1 < MM && r + 1 < mt) ? q[r + 1 < MM ? r + 1 : r] : qr;
         c[r] = (qn - q[r]) * Ntd * mask_t[r];
       }
-      const T cl = grp_prev<G>(last_of<T, MM>(c, mt)), cr = grp_next<G>(c[0]);
+      // Curvature at the end nodes 0 and Nt: zero for simply supported ends;
+      // for clamped ends the mirrored ghost slopes (q_0 = -q_1, q_{Nt+1} =
+      // -q_Nt) give 2 q_1 Nt and -2 q_Nt Nt.  Slot nt holds q_Nt and stands
+      // for node Nt; slots past it only feed rows the solve keeps at zero.
+      T cl = grp_prev<G>(last_of<T, MM>(c, mt));
+      if constexpr (BOW) {
+        if (any_clamp) {
+          const T e = clamped ? T(2) * Ntd : T(0);
+#pragma unroll
+          for (int r = 0; r < MM; ++r) c[r] = tb + r == nt ? -e * q[r] : c[r];
+          cl = li == 0 ? e * q[0] : cl;
+        }
+      }
+      const T cr = grp_next<G>(c[0]);
       const T fr = grp_next<G>(f[0]);
       const T vl = grp_prev<G>(last_of<T, MM>(vu, mt)), vr = grp_next<G>(vu[0]);
 #pragma unroll
@@ -1122,7 +1141,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
       }
       energy_fill<G, MM, T>(gE, u, vu, cu, cvu, z, vz, cz, cvz, mt, ml, li);
       __syncthreads();
-      const double H = energy_fp64<G, MM, T>(D, g2k2, gE, li);
+      const double H = energy_fp64<G, MM, T, BOW>(D, g2k2, gE, li);
       __syncthreads();
       H_last = mon_now ? H : H_last;
       H_step = mon_now ? n : H_step;
@@ -1174,8 +1193,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
 template <int MM, typename T>
 constexpr int kWavesPerEU = (sizeof(T) == 4 && MM <= 4) ? 2 : 1;
 
-// BOW: the instantiation for tasks with bowed strings (the host keeps them
-// in work lists of their own); the other instantiation has no bow code.
+// BOW: the instantiation for tasks with bowed or clamped strings (the host
+// keeps them in work lists of their own); the other instantiation has no
+// code for either.
 template <int G, int MM, typename T, bool KAHAN, bool BOW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<MM, T>))) void step_kernel(
     LaunchArgs a) {

@@ -39,6 +39,8 @@ def _grid_cases():
     cases = [W.single_linear(), W.single_nonlinear(), W.single_linear(theta=1.0)]
     cases += W.random_batch(200)
     cases += W.random_batch(100, durations=("uniform", 0.5, 4.0), modulation=True, seed=7)
+    cases += [(dict(p, boundary=1), e) for p, e in W.random_batch(100, modulation=True, seed=9)]
+    cases += [(dict(p, boundary=1), e) for p, e in (W.single_linear(), W.single_nonlinear())]
     return cases
 
 
@@ -51,6 +53,7 @@ def test_planned_grids_match_oracle():
 @pytest.mark.parametrize("bad", [
     dict(f0=-1.0), dict(f0=float("nan")), dict(alpha=0.5), dict(theta=0.4), dict(B=-1e-4),
     dict(x_out=1.0), dict(n_samples=1), dict(sigma0_t=-1.0), dict(fs=0.0), dict(mod_type=3),
+    dict(boundary=2), dict(boundary=-1),
 ])
 def test_plan_grid_rejects_invalid(bad):
     p, _ = W.single_nonlinear()
