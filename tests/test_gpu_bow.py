@@ -12,7 +12,9 @@ Stick/slip motion amplifies rounding differences: over longer runs the
 element-wise distance between two FP64 implementations grows at the rate the
 problem itself sets.  The longer FP64 case therefore bounds the GPU's
 distance to the oracle by the oracle's own spread under a 1e-13 relative
-change of the bow force (or 1e-10, whichever is larger).
+change of the bow force (or 1e-10, whichever is larger).  In FP32 a few
+bowed strings are that sensitive within 0.05 s already; those are bounded
+by 3x the oracle's spread under 1e-7 relative changes of their parameters.
 """
 from __future__ import annotations
 
@@ -72,7 +74,28 @@ def test_bowed_strings_match_oracle(precision, tol):
              infos[worst]["size_class"], infos[worst]["max_sweeps"]), flush=True)
     assert infos[-1]["size_class"] == 5
     assert all(inf["flags"] == 0 and inf["samples_done"] == p["n_samples"] for (p, _), inf in zip(items, infos))
-    assert max(errs) <= tol
+    if precision == "fp64":
+        assert max(errs) <= tol
+        return
+    # FP32: a few bowed strings are ill-conditioned already over 0.05 s (a
+    # 1e-7 relative change of f0 or v_B moves the oracle's output by O(1));
+    # bound each string by 3x the oracle's spread under such changes
+    bowed = [i for i, (_, e) in enumerate(items) if e.get("type") == 3 and errs[i] > tol]
+    nudged = []
+    for i in bowed:
+        p, e = items[i]
+        for rel in (1e-7, -1e-7):
+            nudged += [(dict(p, **{key: p[key] * (1 + rel)}), e) for key in ("f0", "B", "alpha")]
+            nudged += [(p, dict(e, **{key: e[key] * (1 + rel)})) for key in ("x", "v_B", "F_B")]
+    print("[cpu] oracle: %d nudged runs for %d strings above %.0e" % (len(nudged), len(bowed), tol), flush=True)
+    spread_runs = oracle.run_many(nudged) if nudged else []
+    ratio = {}
+    for j, i in enumerate(bowed):
+        spread = max(rel_l2(q["y_u"], refs[i]["y_u"]) for q in spread_runs[12 * j:12 * j + 12])
+        ratio[i] = errs[i] / max(tol, 3 * spread)
+        print("[gpu] bow fp32c string %d: rel-L2 %.2e, oracle spread %.2e" % (i, errs[i], spread), flush=True)
+    assert all(errs[i] <= tol for i in range(len(items)) if i not in ratio)
+    assert all(r <= 1.0 for r in ratio.values())
 
 
 def test_bowed_fp64_within_the_problems_conditioning():
