@@ -162,6 +162,42 @@ def bow_leg(W, binding, hiptime, n, seconds):
             "workload": "%d bowed nonlinear strings of %.1f s (seeded draws), FP32 compensated" % (n, seconds)}
 
 
+def clamped_leg(W, binding, hiptime, n, seconds):
+    """Clamped ends (Sec. 4.1) in FP32 compensated: a seeded batch of n
+    nonlinear strings (plucks and hammers), clamped and simply supported, one
+    launch each (HIP events).  Clamped strings run in the kernel instantiation
+    that also carries the bow; the ratio is what that costs."""
+    items = W.random_batch(n, seconds=seconds, seed=W.SEED + 31)
+    res = {}
+    for name, bnd in (("clamped", 1), ("simply_supported", 0)):
+        b = binding.StringBatch(n, "fp32c")
+        b.set_params(0, [dict(p, boundary=bnd) for p, _ in items])
+        b.excite(0, [e for _, e in items])
+        infos = [b.info(i) for i in range(n)]
+        steps = max(p["n_samples"] for p, _ in items)
+        b.step(480)                     # first launch of the kernels, not timed
+        b.rewind()
+        hiptime.synchronize()
+        ev0, ev1 = hiptime.Event(), hiptime.Event()
+        ev0.record(0)
+        b.step(steps)
+        ev1.record(0)
+        ev1.synchronize()
+        ms = ev0.elapsed_ms(ev1)
+        bad = sum(1 for i in range(n) if b.info(i)["flags"] != 0 or b.info(i)["samples_done"] != infos[i]["n_samples"])
+        b.close()
+        upd = sum(unknowns(inf) * (inf["n_samples"] - 2) for inf in infos)
+        res[name] = {"value": upd / (ms / 1e3), "ms": ms, "audio_s_per_s": n * seconds / (ms / 1e3),
+                     "strings_not_finished": bad}
+    return {"value": res["clamped"]["value"], "unit": "grid-point updates/s",
+            "audio_s_per_s": res["clamped"]["audio_s_per_s"], "ms": res["clamped"]["ms"],
+            "strings_not_finished": res["clamped"]["strings_not_finished"],
+            "simply_supported_same_strings": res["simply_supported"],
+            "clamped_vs_simply_supported": res["clamped"]["value"] / res["simply_supported"]["value"],
+            "workload": "%d nonlinear strings of %.1f s (seeded draws, plucks and hammers), FP32 compensated"
+                        % (n, seconds)}
+
+
 def dataset_leg(hiptime, n, seconds):
     """The dataset generator: n labelled notes of U(seconds) s, a third each
     plucked, hammered and bowed, half of them given one or two more hammers
@@ -210,6 +246,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--bow-strings", type=int, default=4096, help="strings of the bowed-batch leg")
     ap.add_argument("--no-bow", action="store_true")
+    ap.add_argument("--clamped-strings", type=int, default=4096, help="strings of the clamped-ends leg")
+    ap.add_argument("--no-clamped", action="store_true")
     ap.add_argument("--dataset-notes", type=int, default=16384, help="notes of the dataset-generator leg")
     ap.add_argument("--no-dataset", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=60.0, help="arrival window of the serving run")
@@ -326,6 +364,11 @@ def main():
         print("[bench] bow: %.1f ms, %.3e updates/s (%.2f x the same strings plucked)"
               % (bw["ms"], bw["value"], bw["bowed_vs_plucked"]), file=sys.stderr, flush=True)
         out["bow_fp32c"] = bw
+    if not args.no_clamped:
+        cl = clamped_leg(W, binding, hiptime, args.clamped_strings, 1.0)
+        print("[bench] clamped: %.1f ms, %.3e updates/s (%.2f x the same strings simply supported)"
+              % (cl["ms"], cl["value"], cl["clamped_vs_simply_supported"]), file=sys.stderr, flush=True)
+        out["clamped_fp32c"] = cl
     if not args.no_dataset:
         ds = dataset_leg(hiptime, args.dataset_notes, (0.5, 2.0))
         print("[bench] dataset: %d notes (%d re-excitations) in %.2f s, %.0f audio-s/s"
