@@ -272,8 +272,9 @@ int string_batch_set_monitor(sb_batch *b, int period, double growth_tol);
 int string_batch_set_solver(sb_batch *b, double tol, int max_sweeps);
 
 /* Grid sizes the library plans for p (host only, needs no device): N_t from
- * the stability bound of the theta-scheme, N_l from h_l >= gamma alpha k.
- * Errors: SB_EINVAL. */
+ * the stability bound of the theta-scheme (for clamped ends lowered further
+ * if the energy test of SB_BOUNDARY_CLAMPED fails), N_l from
+ * h_l >= gamma alpha k.  Errors: SB_EINVAL. */
 int string_plan_grid(const sb_string_params *p, int32_t *N_t, int32_t *N_l);
 
 /* Free every resource of the batch (synchronises its stream first). */
