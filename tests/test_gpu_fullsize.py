@@ -134,3 +134,66 @@ def test_dataset16384_sampled_notes_fp32c():
                   % (i, r, level[j][0], level[j][1]), flush=True)
             assert level[j][0] <= r <= level[j][1]
     assert worst <= 1.0
+
+
+def _one_launch(items, pick):
+    """Steps the whole batch in one call (as the benchmark's legs do) and
+    returns the outputs of the picked strings."""
+    b = binding.StringBatch(len(items), "fp32c")
+    try:
+        b.set_params(0, [p for p, _ in items])
+        b.excite(0, [e for _, e in items])
+        b.step(max(p["n_samples"] for p, _ in items))
+        outs = [b.read_output(i) for i in pick]
+        infos = [b.info(i) for i in range(len(items))]
+    finally:
+        b.close()
+    assert all(inf["flags"] == 0 and inf["samples_done"] == inf["n_samples"] for inf in infos)
+    return outs, infos
+
+
+def test_clamped4096_sampled_strings_fp32c():
+    """The benchmark's clamped leg (4096 nonlinear strings x 1 s, clamped
+    ends), 12 seeded strings against the oracle, rel-L2 <= 1e-3."""
+    _gpu()
+    items = [(dict(p, boundary=1), e) for p, e in W.random_batch(4096, seconds=1.0, seed=W.SEED + 31)]
+    pick = sorted(int(i) for i in np.random.default_rng(W.SEED + 8).choice(len(items), 12, replace=False))
+    outs, infos = _one_launch(items, pick)
+    refs = oracle.run_many([items[i] for i in pick], threads=16)
+    errs = [rel_l2(y, r["y_u"]) for y, r in zip(outs, refs)]
+    for i, err in zip(pick, errs):
+        print("[gpu] clamped string %d class %d: rel-L2 %.3e" % (i, infos[i]["size_class"], err), flush=True)
+    assert max(errs) <= 1e-3
+
+
+def test_bowed4096_sampled_strings_fp32c():
+    """The benchmark's bow leg (4096 bowed nonlinear strings x 1 s), 12
+    seeded strings against the oracle, each within max(1e-3, 3x the oracle's
+    spread under 1e-7 changes of f0, B, alpha, x_B, v_B and F_B); where that
+    spread exceeds 0.1 (chaotic stick/slip) the RMS level must also lie
+    within the nudged runs' range, widened by 25 %."""
+    _gpu()
+    items = W.bowed_batch(4096, seconds=1.0)
+    pick = sorted(int(i) for i in np.random.default_rng(W.SEED + 9).choice(len(items), 12, replace=False))
+    outs, infos = _one_launch(items, pick)
+    runs = [(items[i][0], items[i][1], []) for i in pick]
+    nudges = [r for run in runs for r in _nudged(*run)]
+    print("[cpu] oracle: %d strings, %d nudged runs" % (len(runs), len(nudges)), flush=True)
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        refs = list(ex.map(lambda r: oracle.run(r[0], r[1]), runs + nudges))
+    rms = lambda y: float(np.sqrt(np.mean(np.asarray(y, np.float64) ** 2)))
+    worst = 0.0
+    for j, (i, y) in enumerate(zip(pick, outs)):
+        ens = refs[len(runs) + 12 * j:len(runs) + 12 * j + 12]
+        spread = max(rel_l2(r["y_u"], refs[j]["y_u"]) for r in ens)
+        err = rel_l2(y, refs[j]["y_u"])
+        print("[gpu] bowed string %d class %d: rel-L2 %.3e, oracle spread %.2e"
+              % (i, infos[i]["size_class"], err, spread), flush=True)
+        worst = max(worst, err / max(1e-3, 3 * spread))
+        if spread > 0.1:
+            ratios = [1.0] + [rms(r["y_u"]) / rms(refs[j]["y_u"]) for r in ens]
+            r = rms(y) / rms(refs[j]["y_u"])
+            print("[gpu] bowed string %d: level ratio %.3f, oracle ensemble [%.3f, %.3f]"
+                  % (i, r, min(ratios), max(ratios)), flush=True)
+            assert 0.8 * min(ratios) <= r <= 1.25 * max(ratios)
+    assert worst <= 1.0
