@@ -93,6 +93,8 @@ typedef struct {
     double glide_semitones;    /* glide interval over the duration                */
     int32_t grid_l;            /* 0 or a forced N_l                               */
     int32_t boundary;          /* SB_BOUNDARY_*: transverse end condition         */
+    int32_t readout_zeta;      /* 1: also record zeta at x_out (second channel)   */
+    int32_t reserved;
 } sb_string_params;
 
 /* Excitation (Sec. 3.3).  Pluck: initial triangle of peak c0 at x, released
@@ -234,6 +236,15 @@ int string_batch_set_blocks_per_cu(sb_batch *b, const int32_t *blocks);
  * the batch stream and synchronous with it when dst_is_device == 0.
  * Errors: SB_EINVAL (range beyond n_samples), SB_EDEVICE. */
 int string_batch_read_output(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst, int dst_is_device);
+
+/* The second readout channel: zeta at x_out, interpolated on the
+ * longitudinal grid like u (Sec. 3.4 shows both u and zeta outputs; zero for
+ * alpha = 1), recorded only for strings set with readout_zeta = 1 on the
+ * batched paths; same arguments and ordering as string_batch_read_output.
+ * Errors: SB_EINVAL (range beyond n_samples), SB_ESTATE (slot not excited or
+ * set without the channel), SB_EDEVICE. */
+int string_batch_read_output_zeta(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst,
+                                  int dst_is_device);
 
 /* Device pointer of slot idx's output samples (n_samples elements of the
  * batch precision); the batch owns the memory. */

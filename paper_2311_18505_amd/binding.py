@@ -33,6 +33,7 @@ class SbStringParams(C.Structure):
         ("n_samples", C.c_int64), ("mod_type", C.c_int32), ("grid_t", C.c_int32),
         ("mod_depth_cents", C.c_double), ("mod_rate_hz", C.c_double), ("glide_semitones", C.c_double),
         ("grid_l", C.c_int32), ("boundary", C.c_int32),
+        ("readout_zeta", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -65,6 +66,7 @@ SIGNATURES = [
     ("string_batch_step_range", C.c_int, [_P, C.c_int, C.c_int, C.c_int64]),
     ("string_batch_rewind", C.c_int, [_P, C.c_int, C.c_int]),
     ("string_batch_read_output", C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, _P, C.c_int]),
+    ("string_batch_read_output_zeta", C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, _P, C.c_int]),
     ("string_batch_output_ptr", C.c_int, [_P, C.c_int, C.POINTER(_P)]),
     ("string_batch_gather_output", C.c_int, [_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_int64,
                                              _P, C.c_int]),
@@ -211,6 +213,15 @@ class StringBatch:
         out = np.empty(count, dtype=self.dtype)
         self._check(self.lib.string_batch_read_output(self.h, idx, offset, count,
                                                       out.ctypes.data_as(C.c_void_p), 0), "read_output")
+        return out
+
+    def read_output_zeta(self, idx: int, offset: int = 0, count: int | None = None) -> np.ndarray:
+        """The zeta channel of a slot set with readout_zeta = 1."""
+        if count is None:
+            count = self.n_samples[idx] - offset
+        out = np.empty(count, dtype=self.dtype)
+        self._check(self.lib.string_batch_read_output_zeta(self.h, idx, offset, count,
+                                                           out.ctypes.data_as(C.c_void_p), 0), "read_output_zeta")
         return out
 
     def restrike(self, first: int, excs):

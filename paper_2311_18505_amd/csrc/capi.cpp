@@ -330,7 +330,14 @@ static size_t region_size(const sb_batch *b, const Desc &D, size_t *off_st0, siz
   *off_tabf = 2 * st;
   *off_out = 2 * st + tf;
   *off_tab = 2 * st + tf + ou;
-  return 2 * st + tf + ou + tb;
+  // the zeta channel, when asked for, follows with the output's size
+  return 2 * st + tf + ou + tb + (D.zeta_out ? ou : 0);
+}
+
+// Offset of the zeta channel in a slot's region (batched paths).
+static size_t zeta_out_offset(const sb_batch *b, const Desc &D) {
+  size_t a0, a, o, t;
+  return region_size(b, D, &a0, &a, &o, &t) - align256(b->esz * (size_t)(D.n_samples + kWave));
 }
 
 extern "C" int string_batch_set_params(sb_batch *b, int first, int count, const sb_string_params *p) {
@@ -341,6 +348,8 @@ extern "C" int string_batch_set_params(sb_batch *b, int first, int count, const 
     std::string err;
     int st = plan_string(p[i], plans[i], err);
     if (st) return fail(b, st, "slot " + std::to_string(first + i) + ": " + err);
+    if (b->precision == SB_FP64_PLAIN && p[i].readout_zeta)
+      return fail(b, SB_EINVAL, "slot " + std::to_string(first + i) + ": the zeta channel needs a batched precision");
   }
   // queued launches may still read the memory released below
   hipError_t es = hipStreamSynchronize(b->stream);
@@ -436,6 +445,7 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     D.st_elems = plain ? 2 * (D.nt + D.nl) : G * 4 * (D.mt + D.ml);
     D.tabf = s.dmem + otf;
     D.out = s.dmem + oout;
+    D.out_z = (!plain && D.zeta_out) ? s.dmem + zeta_out_offset(b, D) : nullptr;
     D.tab = (const uint32_t *)(s.dmem + otab);
     // initial state, lane-major: u, v, cu, cv (transverse), same for zeta
     std::vector<double> u0;
@@ -474,6 +484,12 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     put(bs.data(), bs.size(), s.dmem + ost0);
     put(bt.data(), bt.size(), s.dmem + otf);
     put(bh.data(), bh.size(), s.dmem + oout);
+    if (!plain && D.zeta_out) {
+      // zeta^0 = zeta^1 = 0 for every excitation (on the plain path out_z
+      // shares its storage with the position tables: never test it there)
+      const std::vector<char> zero(bh.size(), 0);
+      put(zero.data(), zero.size(), D.out_z);
+    }
     if (plain)
       put(s.plan.ptab.data(), s.plan.ptab.size() * sizeof(int32_t), s.dmem + otab);
     else
@@ -549,8 +565,10 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
     const int64_t st = std::min<int64_t>(n_steps, s.plan.desc.n_samples - s.samples_host);
     const double cost = (double)st * (double)(s.plan.desc.nt + s.plan.desc.nl + 8);
     const int c = b->precision == SB_FP64_PLAIN ? 0 : s.plan.desc.cls;
-    // bowed and clamped strings run in the instantiation that carries their code
-    cls[(s.plan.desc.bow_on || s.plan.desc.clamped) ? 1 : 0][c].push_back({cost, i});
+    // bowed and clamped strings and the zeta channel run in the instantiation
+    // that carries their code
+    const Desc &d = s.plan.desc;
+    cls[(d.bow_on || d.clamped || d.zeta_out) ? 1 : 0][c].push_back({cost, i});
   }
   if (!any) return fail(b, SB_ESTATE, "no excited slot");
   std::vector<int32_t> work;
@@ -878,6 +896,25 @@ extern "C" int string_batch_read_output(sb_batch *b, int idx, int64_t offset, in
                                 b->stream);
   if (e == hipSuccess && !dst_is_device) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(b, e, "read_output");
+  return SB_OK;
+}
+
+extern "C" int string_batch_read_output_zeta(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst,
+                                             int dst_is_device) {
+  if (!b) return SB_EINVAL;
+  if (idx < 0 || idx >= b->capacity || !dst || offset < 0 || count < 0) return fail(b, SB_EINVAL, "bad arguments");
+  Slot &s = b->slots[idx];
+  if (!s.excited) return fail(b, SB_ESTATE, "slot not excited");
+  // (on the plain path out_z shares its storage with the position tables)
+  if (b->precision == SB_FP64_PLAIN || !s.plan.desc.zeta_out || !s.plan.desc.out_z)
+    return fail(b, SB_ESTATE, "slot set without the zeta channel");
+  if (offset + count > s.plan.desc.n_samples) return fail(b, SB_EINVAL, "range beyond n_samples");
+  if (count == 0) return SB_OK;
+  const char *src = (const char *)s.plan.desc.out_z + offset * b->esz;
+  hipError_t e = hipMemcpyAsync(dst, src, count * b->esz, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                b->stream);
+  if (e == hipSuccess && !dst_is_device) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(b, e, "read_output_zeta");
   return SB_OK;
 }
 

@@ -73,6 +73,10 @@ int plan_grid(const sb_string_params &p, GridPlan &g, std::string &err) {
     err = "bad mod_type or grid override";
     return SB_EINVAL;
   }
+  if (p.readout_zeta != 0 && p.readout_zeta != 1) {
+    err = "readout_zeta must be 0 or 1";
+    return SB_EINVAL;
+  }
   if (p.boundary != SB_BOUNDARY_SIMPLE && p.boundary != SB_BOUNDARY_CLAMPED) {
     err = "boundary must be SB_BOUNDARY_SIMPLE or SB_BOUNDARY_CLAMPED";
     return SB_EINVAL;
@@ -218,6 +222,12 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
 
   D.mod_type = p.mod_type;
   D.clamped = p.boundary == SB_BOUNDARY_CLAMPED ? 1 : 0;
+  D.zeta_out = p.readout_zeta ? 1 : 0;
+  if (Nl > 0) {
+    double w0, w1;
+    point_interp(p.x_out, Nl, D.zon0, D.zon1, w0, w1);
+    D.zw = D.zon1 ? w1 : 1.0 - w0;
+  }
   D.f0 = p.f0;
   D.fs = p.fs;
   if (p.mod_type == 1) {

@@ -62,13 +62,14 @@ struct Desc {
   // hammer
   int32_t ham_on;             // 1 if the excitation is a hammer
   int32_t hn0, hn1;           // nodes of I_H (1-based; 0 = absent)
-  int32_t pad1;
+  int32_t zeta_out;           // 1: the string also records zeta at x_out (batched paths)
   double hw0, hw1;            // weights of I_H
   double omega_pow, alpha_H, Mr, IHs;   // K_H/M_H, exponent, M_H/(rho A), I_H T_u0^{-1} J_H
   // bow (eq. 5), set on the string at time bt0: position bx0 -> bx1 over bT
   // seconds, bow speed and force rising over bta seconds, friction curve
   // sign(v) (beps + (1-beps) e^{-ba|v|})
-  int32_t bow_on, pad3;       // 1 if the excitation is a bow
+  int32_t bow_on;             // 1 if the excitation is a bow
+  int32_t zon0;               // zeta channel: first l-grid node of I(x_out) (0 = absent)
   double bx0, bx1, bT, bvB, bFB, bta, ba, beps, bt0;
   // readout
   int32_t on0, on1;           // nodes of I(x_out)
@@ -78,9 +79,18 @@ struct Desc {
   void *st0;                  // copy of the state block right after excitation
   // plain FP64 path (eq. (7), merged-order banded LU): unknowns, half
   // bandwidth, position of the hammer unknown (-1: none), and its tables
-  int32_t pn, pbw, ph, pad2;
-  const int32_t *ptab;        // pos_t[nt] | pos_l[nl] | ja|jb<<16 per t-half [Nt] | sa|na<<16, sb|nb<<16 per l-half [Nl] each
-  const double *pw;           // interpolation weight w per t-half [Nt]
+  int32_t pn, pbw, ph;
+  int32_t zon1;               // zeta channel: second l-grid node of I(x_out) (0 = absent)
+  // the plain path's tables, or (batched paths, which never read them) the
+  // zeta channel's output and interpolation weight: zon0 takes 1 - zw, zon1 zw
+  union {
+    const int32_t *ptab;      // pos_t[nt] | pos_l[nl] | ja|jb<<16 per t-half [Nt] | sa|na<<16, sb|nb<<16 per l-half [Nl] each
+    void *out_z;              // zeta samples, kernel precision (null without the channel)
+  };
+  union {
+    const double *pw;         // interpolation weight w per t-half [Nt]
+    double zw;
+  };
 };
 
 constexpr int kPlainMaxBw = 16;             // half bandwidth the plain kernel accepts

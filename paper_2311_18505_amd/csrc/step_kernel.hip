@@ -612,9 +612,12 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   wsteps = uni(wsteps);
 
   const bool any_mod = __ballot(D.mod_type != 0) != 0;
-  // clamped ends, like the bow, exist only in the BOW instantiation
+  // clamped ends and the zeta channel, like the bow, exist only in the BOW
+  // instantiation
   const bool clamped = BOW && D.clamped != 0;
   const bool any_clamp = BOW && __ballot(clamped) != 0;
+  const bool zout = BOW && D.zeta_out != 0;
+  const bool any_zout = BOW && __ballot(zout) != 0;
   const int hn0 = D.hn0, hn1 = D.hn1, on0 = D.on0, on1 = D.on1;
   const double hw0 = D.hw0, hw1 = D.hw1, ow0 = D.ow0, ow1 = D.ow1;
   const double omega_pow = D.omega_pow, alpha_H = D.alpha_H, Mr = D.Mr, IHs = D.IHs;
@@ -727,7 +730,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   // this launch; a lane with nothing to write stores into the padding after n_samples
   T *out = (T *)D.out;
   const int64_t first_m = done;
-  T ring = T(0);
+  T ring = T(0), ring_z = T(0);
   double g2blk = g2k2_0;
   T *trash = (T *)a.trash_st;
   // (n + 1) mod mon_period of the current step
@@ -1128,6 +1131,14 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     const double y = point_eval<G, T, MM>(u, cu, on0, ow0, on1, ow1);
     const int slot = (int)((m - first_m) & (G - 1));
     ring = (act && li == slot) ? (T)y : ring;
+    // second channel: zeta^{n+1} at x_out on the longitudinal grid
+    if constexpr (BOW) {
+      if (any_zout) {
+        const double yz = point_eval<G, T, MM>(z, cz, D.zon0, D.zon0 ? 1.0 - D.zw : 0.0, D.zon1,
+                                               D.zon1 ? D.zw : 0.0);
+        ring_z = (act && li == slot) ? (T)yz : ring_z;
+      }
+    }
 
     // ---- FP64 energy monitor ----
     bool bad = false;
@@ -1157,6 +1168,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     if (__ballot(flush) != 0) {
       const int64_t idx = flush ? first_m + ((m - first_m) & ~(int64_t)(G - 1)) + li : n_samples + li;
       out[idx] = ring;
+      if constexpr (BOW) {
+        if (zout) ((T *)D.out_z)[idx] = ring_z;   // same samples and padding as out
+      }
     }
     steps_done += act ? 1 : 0;
     nsteps = bad ? it + 1 : nsteps;      // a flagged string stops here
