@@ -884,38 +884,32 @@ extern "C" int string_batch_step_range(sb_batch *b, int first, int count, int64_
   return do_step(b, first, count, n_steps);
 }
 
-extern "C" int string_batch_read_output(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst, int dst_is_device) {
-  if (!b) return SB_EINVAL;
-  if (idx < 0 || idx >= b->capacity || !dst || offset < 0 || count < 0) return fail(b, SB_EINVAL, "bad arguments");
-  Slot &s = b->slots[idx];
-  if (!s.excited) return fail(b, SB_ESTATE, "slot not excited");
-  if (offset + count > s.plan.desc.n_samples) return fail(b, SB_EINVAL, "range beyond n_samples");
-  if (count == 0) return SB_OK;
-  const char *src = (const char *)s.plan.desc.out + offset * b->esz;
-  hipError_t e = hipMemcpyAsync(dst, src, count * b->esz, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                                b->stream);
-  if (e == hipSuccess && !dst_is_device) e = hipStreamSynchronize(b->stream);
-  if (e != hipSuccess) return hip_fail(b, e, "read_output");
-  return SB_OK;
-}
-
-extern "C" int string_batch_read_output_zeta(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst,
-                                             int dst_is_device) {
+// Samples offset.. of one output channel of slot idx (u, or zeta) into dst.
+static int read_channel(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst, int dst_is_device, bool zeta) {
   if (!b) return SB_EINVAL;
   if (idx < 0 || idx >= b->capacity || !dst || offset < 0 || count < 0) return fail(b, SB_EINVAL, "bad arguments");
   Slot &s = b->slots[idx];
   if (!s.excited) return fail(b, SB_ESTATE, "slot not excited");
   // (on the plain path out_z shares its storage with the position tables)
-  if (b->precision == SB_FP64_PLAIN || !s.plan.desc.zeta_out || !s.plan.desc.out_z)
+  if (zeta && (b->precision == SB_FP64_PLAIN || !s.plan.desc.zeta_out || !s.plan.desc.out_z))
     return fail(b, SB_ESTATE, "slot set without the zeta channel");
   if (offset + count > s.plan.desc.n_samples) return fail(b, SB_EINVAL, "range beyond n_samples");
   if (count == 0) return SB_OK;
-  const char *src = (const char *)s.plan.desc.out_z + offset * b->esz;
+  const char *src = (const char *)(zeta ? s.plan.desc.out_z : s.plan.desc.out) + offset * b->esz;
   hipError_t e = hipMemcpyAsync(dst, src, count * b->esz, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                                 b->stream);
   if (e == hipSuccess && !dst_is_device) e = hipStreamSynchronize(b->stream);
-  if (e != hipSuccess) return hip_fail(b, e, "read_output_zeta");
+  if (e != hipSuccess) return hip_fail(b, e, zeta ? "read_output_zeta" : "read_output");
   return SB_OK;
+}
+
+extern "C" int string_batch_read_output(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst, int dst_is_device) {
+  return read_channel(b, idx, offset, count, dst, dst_is_device, false);
+}
+
+extern "C" int string_batch_read_output_zeta(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst,
+                                             int dst_is_device) {
+  return read_channel(b, idx, offset, count, dst, dst_is_device, true);
 }
 
 extern "C" int string_batch_gather_output(sb_batch *b, int n, const int32_t *slots, const int64_t *offsets,
