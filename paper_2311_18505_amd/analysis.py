@@ -129,3 +129,35 @@ def phantom_partials(y, fs: float, f0: float, B: float, n_max: int = 12, tol_cen
 def analyze(y, fs: float, n_max: int = 12) -> dict:
     f0, B, matched = f0_estimate(y, fs)
     return {"f0": f0, "B": B, "partials": matched, "phantoms": phantom_partials(y, fs, f0, B, n_max)}
+
+
+def main(argv=None) -> None:
+    """Analyse rows of .npy files (one note per row, as the dataset generator
+    writes them) and print one JSON line per note: f0, B, the matched
+    partials and the phantom partials."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="f0, inharmonicity and phantom partials of synthesised notes")
+    ap.add_argument("files", nargs="+", help=".npy arrays, one note per row (or one 1-D note)")
+    ap.add_argument("--fs", type=float, default=48000.0)
+    ap.add_argument("--n-max", type=int, default=12)
+    ap.add_argument("--labels", help="labels.json of the dataset generator: trims each row to its length")
+    args = ap.parse_args(argv)
+    lengths = None
+    if args.labels:
+        with open(args.labels) as f:
+            lengths = [int(x["samples"]) for x in json.load(f)]
+    k = 0
+    for path in args.files:
+        rows = np.atleast_2d(np.load(path))
+        for row in rows:
+            y = row[:lengths[k]] if lengths is not None else row
+            r = analyze(np.asarray(y, np.float64), args.fs, args.n_max)
+            print(json.dumps({"file": path, "row": k, "f0": r["f0"], "B": r["B"],
+                              "partials": {str(n): f for n, f in sorted(r["partials"].items())},
+                              "phantoms": [[f, lv, list(ij)] for f, lv, ij in r["phantoms"]]}), flush=True)
+            k += 1
+
+
+if __name__ == "__main__":
+    main()

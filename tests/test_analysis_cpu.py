@@ -49,3 +49,16 @@ def test_nonlinear_string_shows_phantoms_and_linear_does_not():
     assert abs(1200 * np.log2(a_lin["f0"] / 110.0)) < 5.0
     assert len(a_nl["phantoms"]) >= 1
     assert a_lin["phantoms"] == []
+
+
+def test_command_line_reads_rows(tmp_path, capsys):
+    import json
+    fs = 48000.0
+    rows = np.stack([_tone(110.0, 5e-3, fs, 1.0), _tone(220.0, 1e-3, fs, 1.0)])
+    path = tmp_path / "audio.npy"
+    np.save(path, rows)
+    analysis.main([str(path), "--fs", "48000"])
+    out = [json.loads(l) for l in capsys.readouterr().out.splitlines()]
+    assert [o["row"] for o in out] == [0, 1]
+    assert abs(1200 * np.log2(out[0]["f0"] / 110.0)) < 0.05
+    assert abs(1200 * np.log2(out[1]["f0"] / 220.0)) < 0.05
