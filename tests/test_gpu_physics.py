@@ -153,3 +153,31 @@ def test_theta_one_and_largest_class_fp64():
         print("[gpu] N=(%d,%d) class %d: rel-L2 %.3e" % (inf["N_t"], inf["N_l"], inf["size_class"], err), flush=True)
         assert err <= 1e-10
     assert infos[1]["size_class"] == 5 and infos[2]["size_class"] == 5
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-3)])
+def test_maximum_grid_sizes(precision, tol):
+    """The largest grids the batched paths accept (1024 intervals, the top of
+    size class 5): N_l = 1024 (hammered, nonlinear) and N_t = 1024 (plucked,
+    linear), beside a small string in the same batch; one interval more is
+    refused with SB_EBUDGET."""
+    _gpu()
+    long_l = (W.string(20.0, 1e-6, 1.1713, 0.5, 1e-4, 2400), W.hammer(0.12, 2.0))
+    long_t = (W.string(14.88, 1e-8, 1.0, 0.5, 1e-4, 2400), W.pluck(0.2, 1e-3))
+    small = W.random_batch(1, seconds=0.05)[0]
+    items = [long_l, long_t, small]
+    refs = oracle.run_many(items)
+    outs, infos, _ = _run(items, precision)
+    assert (infos[0]["N_l"], infos[1]["N_t"]) == (1024, 1024)
+    for y, r, inf in zip(outs, refs, infos):
+        err = rel_l2(y, r["y_u"])
+        print("[gpu] %s N=(%d,%d) class %d: rel-L2 %.3e" % (precision, inf["N_t"], inf["N_l"], inf["size_class"], err),
+              flush=True)
+        assert inf["flags"] == 0 and err <= tol
+    b = binding.StringBatch(1, precision)
+    try:
+        with pytest.raises(binding.SbError) as ex:
+            b.set_params(0, [W.string(14.87, 1e-8, 1.0, 0.5, 1e-4, 2400)])
+        assert ex.value.code == binding.SB_EBUDGET
+    finally:
+        b.close()
