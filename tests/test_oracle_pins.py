@@ -622,3 +622,18 @@ def test_pc5_clamped_dense_brute_force(exc):
     # and it differs from the simply supported run
     U0, _, _ = DR.run_dense(dict(p, boundary=0), e, g, p["n_samples"])
     assert np.max(np.abs(U0 - U)) > 1e-6 * scale
+
+
+def test_zeta_readout_is_the_interpolated_trajectory():
+    # the second output channel: zeta at x_out, linear between the two
+    # l-grid nodes around it (fixed ends count as zero)
+    p = W.string(300.0, 1e-3, 3.0, 1.0, 3e-4, 400)
+    e = W.pluck(0.14, 0.02)
+    r = oracle.run(p, e, want=("y_z", "traj_z"))
+    Nl = r["grid"]["N_l"]
+    Z = np.concatenate([np.zeros((p["n_samples"], 1)), r["traj_z"], np.zeros((p["n_samples"], 1))], axis=1)
+    xi = p["x_out"] * Nl
+    lo = int(math.floor(xi))
+    y = (lo + 1 - xi) * Z[:, lo] + (xi - lo) * Z[:, lo + 1]
+    assert np.max(np.abs(r["y_z"] - y)) <= 1e-15 * np.max(np.abs(y))
+    assert np.max(np.abs(y)) > 0
