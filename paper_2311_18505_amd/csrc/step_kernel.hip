@@ -1207,9 +1207,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
 template <int MM, typename T>
 constexpr int kWavesPerEU = (sizeof(T) == 4 && MM <= 4) ? 2 : 1;
 
-// BOW: the instantiation for tasks with bowed or clamped strings (the host
-// keeps them in work lists of their own); the other instantiation has no
-// code for either.
+// BOW: the instantiation for tasks with bowed or clamped strings or the
+// zeta channel (the host keeps them in work lists of their own); the other
+// instantiation has no code for any of them.
 template <int G, int MM, typename T, bool KAHAN, bool BOW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<MM, T>))) void step_kernel(
     LaunchArgs a) {
