@@ -97,8 +97,20 @@ def cpu_baseline(items, seconds_cap, threads):
     rec = {"value": upd / dt, "unit": "grid-point updates/s", "cores": threads, "kind": "oracle",
            "sample": "first %d strings of the workload, each cut to %.2f s (%d updates), FP64, "
                      "one string per thread" % (len(sample), seconds_cap, upd),
-           "seconds": dt}
+           "seconds": dt, "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
     return rec, flops / upd
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def plain_leg(W, binding, hiptime, seconds):
