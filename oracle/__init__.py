@@ -39,7 +39,7 @@ class OrcString(C.Structure):
 
 class OrcExcitation(C.Structure):
     _fields_ = [
-        ("type", C.c_int32), ("pad0", C.c_int32), ("x", C.c_double), ("c0", C.c_double),
+        ("type", C.c_int32), ("interp_order", C.c_int32), ("x", C.c_double), ("c0", C.c_double),
         ("v_H", C.c_double), ("M_H", C.c_double), ("K_H", C.c_double),
         ("alpha_H", C.c_double), ("rhoA", C.c_double),
         ("x_end", C.c_double), ("v_B", C.c_double), ("F_B", C.c_double), ("attack", C.c_double),
@@ -105,7 +105,7 @@ def _load():
 STRING_KEYS = ("fs", "f0", "B", "alpha", "theta", "sigma0_t", "sigma1_t", "sigma0_l", "sigma1_l",
                "x_out", "n_samples", "mod_type", "mod_depth_cents", "mod_rate_hz",
                "glide_semitones", "grid_t", "grid_l", "boundary")
-EXC_KEYS = ("type", "x", "c0", "v_H", "M_H", "K_H", "alpha_H", "rhoA", "x_end", "v_B", "F_B", "attack",
+EXC_KEYS = ("type", "interp_order", "x", "c0", "v_H", "M_H", "K_H", "alpha_H", "rhoA", "x_end", "v_B", "F_B", "attack",
             "fric_a", "fric_eps")
 
 

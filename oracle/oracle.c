@@ -490,6 +490,40 @@ static void interp_row(double x, int N, int *idx, double *wt) {
     idx[1] = (l + 1 >= 1 && l + 1 <= N - 1) ? l : -1;        wt[1] = w;
 }
 
+/* Cubic I_3(x) of Sec. 3.3 (the p-th order interpolant with p = 3): Lagrange
+ * interpolation through the nodes l-1, l, l+1, l+2 around x = (l + a) h,
+ * written on the N-1 interior nodes.  The fixed end nodes contribute zero;
+ * a node outside the string stands for its mirror image, u_{-1} = s u_1 and
+ * u_{N+1} = s u_{N-1} (s = -1 for simply supported ends, +1 for clamped
+ * ones: the same ghosts the boundary conditions give).  Entries of idx are
+ * -1 where absent; a node reached twice gets the sum of its weights. */
+static void interp_row_cubic(double x, int N, double s, int *idx, double *wt) {
+    int l = (int)floor(x * N);
+    double a = x * N - l;
+    double w[4] = {-a * (a - 1.0) * (a - 2.0) / 6.0, (a + 1.0) * (a - 1.0) * (a - 2.0) / 2.0,
+                   -(a + 1.0) * a * (a - 2.0) / 2.0, (a + 1.0) * a * (a - 1.0) / 6.0};
+    for (int k = 0; k < 4; ++k) { idx[k] = -1; wt[k] = 0.0; }
+    int used = 0;
+    for (int k = 0; k < 4; ++k) {
+        int m = l - 1 + k;
+        double c = w[k];
+        if (m == -1) { m = 1; c *= s; }
+        if (m == N + 1) { m = N - 1; c *= s; }
+        if (m < 1 || m > N - 1) continue;
+        int j = 0;
+        while (j < used && idx[j] != m - 1) ++j;
+        if (j == used) { idx[used] = m - 1; wt[used] = 0.0; ++used; }
+        wt[j] += c;
+    }
+}
+
+static double interp_apply4(const int *idx, const double *wt, const double *u) {
+    double s = 0.0;
+    for (int k = 0; k < 4; ++k)
+        if (idx[k] >= 0) s += wt[k] * u[idx[k]];
+    return s;
+}
+
 static double interp_apply(const int *idx, const double *wt, const double *u) {
     double s = 0.0;
     if (idx[0] >= 0) s += wt[0] * u[idx[0]];
@@ -653,7 +687,7 @@ static void system_free(system_t *sy) { csr_free(&sy->A); csr_free(&sy->B); csr_
 
 typedef struct {
     int on;
-    int iH[2]; double wH[2];       /* I_p(x_H) on the transverse nodes */
+    int iH[4]; double wH[4];       /* I_p(x_H) on the transverse nodes (-1: absent) */
     double omega_pow;              /* omega_H^{1+alpha_H} = K_H / M_H   */
     double Mr;                     /* mass ratio M = M_H / (rho A L), L = 1 */
     double aH;
@@ -662,6 +696,7 @@ typedef struct {
 static int exc_validate(const orc_excitation *e) {
     if (!e) return ORC_OK;
     if (e->type < 0 || e->type > 3) return ORC_EINVAL;
+    if (e->interp_order != 0 && e->interp_order != 1 && e->interp_order != 3) return ORC_EINVAL;
     if (e->type == 0) return ORC_OK;
     if (!(e->x > 0.0 && e->x < 1.0)) return ORC_EINVAL;
     if (e->type == 1 && !isfinite(e->c0)) return ORC_EINVAL;
@@ -879,22 +914,22 @@ static csr joint_build(const ops_t *o, const system_t *sy, const hammer_t *hm, d
     if (!hm->on) return csr_scale(1.0, &sy->A);
 
     double ht = o->g.h_t;
-    double eta_nm1 = uH_nm1 - interp_apply(hm->iH, hm->wH, w_nm1);
+    double eta_nm1 = uH_nm1 - interp_apply4(hm->iH, hm->wH, w_nm1);
     double kc = k * k * c_n;
     /* extra entries: column n (u_H) in the string rows, row n (hammer) */
-    int cap = sy->A.nnz + 16;          /* 2 x (1 + 2) string-row entries + 3 hammer-row entries */
+    int cap = sy->A.nnz + 32;          /* 4 x (1 + 4) string-row entries + 5 hammer-row entries */
     int *r = (int *)malloc(sizeof(int) * (size_t)cap);
     int *c = (int *)malloc(sizeof(int) * (size_t)cap);
     double *v = (double *)malloc(sizeof(double) * (size_t)cap);
     int t = 0;
     for (int i = 0; i < sy->A.nr; ++i)
         for (int p = sy->A.rp[i]; p < sy->A.rp[i + 1]; ++p) { r[t] = i; c[t] = sy->A.ci[p]; v[t] = sy->A.v[p]; ++t; }
-    for (int a = 0; a < 2; ++a) {
+    for (int a = 0; a < 4; ++a) {
         if (hm->iH[a] < 0) continue;
         double J = hm->wH[a] / ht;
         /* -k^2 M J c (u_H^{n+1} - I u^{n+1}) moved to the left-hand side */
         r[t] = hm->iH[a]; c[t] = n; v[t] = -k * k * hm->Mr * J * c_n; ++t;
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < 4; ++b) {
             if (hm->iH[b] < 0) continue;
             r[t] = hm->iH[a]; c[t] = hm->iH[b]; v[t] = k * k * hm->Mr * J * c_n * hm->wH[b]; ++t;
         }
@@ -902,7 +937,7 @@ static csr joint_build(const ops_t *o, const system_t *sy, const hammer_t *hm, d
     }
     /* hammer row: (1 + k^2 c) u_H^{n+1} - k^2 c I u^{n+1} = 2u_H^n - u_H^{n-1} - k^2 c eta^{n-1} */
     r[t] = n; c[t] = n; v[t] = 1.0 + kc; ++t;
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < 4; ++b) {
         if (hm->iH[b] < 0) continue;
         r[t] = n; c[t] = hm->iH[b]; v[t] = -kc * hm->wH[b]; ++t;
     }
@@ -916,12 +951,15 @@ static csr joint_build(const ops_t *o, const system_t *sy, const hammer_t *hm, d
 /* Driver                                                                    */
 /* ------------------------------------------------------------------------ */
 
-static int hammer_setup(const orc_excitation *e, const orc_grid *g, hammer_t *hm) {
+static int hammer_setup(const orc_excitation *e, const orc_string *s, const orc_grid *g, hammer_t *hm) {
     memset(hm, 0, sizeof(*hm));
-    for (int a = 0; a < 2; ++a) hm->iH[a] = -1;
+    for (int a = 0; a < 4; ++a) hm->iH[a] = -1;
     if (!e || e->type != 2) return ORC_OK;
     hm->on = 1;
-    interp_row(e->x, g->N_t, hm->iH, hm->wH);
+    if (e->interp_order == 3)
+        interp_row_cubic(e->x, g->N_t, s->boundary == 1 ? 1.0 : -1.0, hm->iH, hm->wH);
+    else
+        interp_row(e->x, g->N_t, hm->iH, hm->wH);
     hm->omega_pow = e->K_H / e->M_H;         /* omega_H^{1+alpha_H} */
     hm->Mr = e->M_H / e->rhoA;               /* READING: M = M_H / (rho A L), L = 1 */
     hm->aH = e->alpha_H;
@@ -951,7 +989,7 @@ int orc_run_schedule(const orc_string *s, const orc_excitation *e, int n_re, con
     ops_t o;
     ops_build(s, &g, &o);
     hammer_t hm;
-    hammer_setup(e, &g, &hm);
+    hammer_setup(e, s, &g, &hm);
     bow_t bw;
     bow_setup(e, s, 0, &bw);
     int n = o.n, nt = o.nt, nl = o.nl, Ns = (int)s->n_samples;
@@ -1013,10 +1051,10 @@ int orc_run_schedule(const orc_string *s, const orc_excitation *e, int n_re, con
              * rests); a bow's controls restart from level n-1, so that its
              * first step is n, as step 1 is for the initial bow. */
             const orc_excitation *x = &re_exc[next_re++];
-            hammer_setup(x, &g, &hm);
+            hammer_setup(x, s, &g, &hm);
             bow_setup(x, s, step - 1, &bw);
             if (hm.on) {
-                uH0 = interp_apply(hm.iH, hm.wH, w0);
+                uH0 = interp_apply4(hm.iH, hm.wH, w0);
                 uH1 = uH0 + g.k * x->v_H;
             }
             free(perm);
@@ -1026,7 +1064,7 @@ int orc_run_schedule(const orc_string *s, const orc_excitation *e, int n_re, con
         system_t sy;
         system_build(s, &o, gamma, w1, &sy);
         double c_n = 0.0;
-        if (hm.on) c_n = hammer_c(&hm, uH1 - interp_apply(hm.iH, hm.wH, w1));
+        if (hm.on) c_n = hammer_c(&hm, uH1 - interp_apply4(hm.iH, hm.wH, w1));
         csr M = joint_build(&o, &sy, &hm, c_n, w1, w0, uH1, uH0, rhs, &flops);
         status = band_solve(&M, perm, rhs, w2, &flops);
         if (!status && bw.on) {
@@ -1082,11 +1120,11 @@ int orc_dump_system(const orc_string *s, const orc_excitation *e, int64_t step,
     ops_t o;
     ops_build(s, &g, &o);
     hammer_t hm;
-    hammer_setup(e, &g, &hm);
+    hammer_setup(e, s, &g, &hm);
     system_t sy;
     double gamma = orc_gamma_at(s, step);
     system_build(s, &o, gamma, w_n, &sy);
-    double c_n = hm.on ? hammer_c(&hm, uH_n - interp_apply(hm.iH, hm.wH, w_n)) : 0.0;
+    double c_n = hm.on ? hammer_c(&hm, uH_n - interp_apply4(hm.iH, hm.wH, w_n)) : 0.0;
     int n = o.n, na = n + (hm.on ? 1 : 0);
     double *r = (double *)calloc((size_t)na, sizeof(double));
     csr M = joint_build(&o, &sy, &hm, c_n, w_n, w_nm1, uH_n, uH_nm1, r, NULL);

@@ -44,7 +44,7 @@ typedef struct {
 
 typedef struct {
     int32_t type;         /* 0 none, 1 pluck (initial condition), 2 hammer (eq. 6), 3 bow (eq. 5) */
-    int32_t pad0;
+    int32_t interp_order; /* hammer's I_p: 0 or 1 linear, 3 cubic (Sec. 3.3's p-th order interpolant) */
     double x;             /* excitation position in (0,1); the bow's position at t = 0 */
     double c0;            /* pluck peak displacement [m] */
     double v_H;           /* hammer initial velocity [m/s] */

@@ -33,6 +33,24 @@ def interp_matrix(x_src, x_dst):
     return M
 
 
+def point_row_cubic(x, N, s):
+    """Row of the cubic interpolant at x: for each interior node's unit vector,
+    the cubic through the four nodes around x (ghost nodes u_{-1} = s u_1,
+    u_{N+1} = s u_{N-1}, end nodes zero), fitted with numpy and evaluated."""
+    h = 1.0 / N
+    l = int(np.floor(x * N))
+    m = np.arange(l - 1, l + 3)
+    row = np.zeros(N - 1)
+    for j in range(N - 1):
+        ext = np.zeros(N + 3)               # nodes -1 .. N+1
+        ext[j + 2] = 1.0
+        ext[0] = s * ext[2]
+        ext[N + 2] = s * ext[N]
+        coef = np.polyfit(m * h, ext[m + 1], 3)
+        row[j] = np.polyval(coef, x)
+    return row
+
+
 def point_row(x, N):
     """Row interpolating the interior nodes 1..N-1 at x (end nodes are zero)."""
     nodes = np.arange(N + 1) / N
@@ -143,7 +161,10 @@ def run_dense(p, e, g, n_samples):
     traj[0], traj[1] = w0, w1
     if e["type"] == 2:
         uH[1] = k * e["v_H"]
-        Ih = point_row(e["x"], Nt)
+        if e.get("interp_order", 0) == 3:
+            Ih = point_row_cubic(e["x"], Nt, 1.0 if p.get("boundary", 0) == 1 else -1.0)
+        else:
+            Ih = point_row(e["x"], Nt)
         Jh = Ih / g["h_t"]
         Mr = e["M_H"] / e["rhoA"]
         wpow = e["K_H"] / e["M_H"]

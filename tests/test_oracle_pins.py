@@ -637,3 +637,35 @@ def test_zeta_readout_is_the_interpolated_trajectory():
     y = (lo + 1 - xi) * Z[:, lo] + (xi - lo) * Z[:, lo + 1]
     assert np.max(np.abs(r["y_z"] - y)) <= 1e-15 * np.max(np.abs(y))
     assert np.max(np.abs(y)) > 0
+
+
+def test_ph1_cubic_hammer_row_reproduces_cubics():
+    # the dense reference's cubic row is exact on cubic polynomials that
+    # vanish at the ends when x is away from them (the ghosts do not enter)
+    N = 20
+    x = 0.37
+    row = DR.point_row_cubic(x, N, -1.0)
+    nodes = np.arange(1, N) / N
+    for c in ([1.0, 0, 0, 0], [0, 1.0, 0, 0], [0.3, -0.2, 0.5, 0.1]):
+        f = lambda t: (c[0] + c[1] * t + c[2] * t ** 2 + c[3] * t ** 3)
+        assert abs(row @ f(nodes) - f(x)) < 1e-12
+    assert abs(row.sum() - 1.0) < 1e-12 and np.count_nonzero(row) == 4
+
+
+@pytest.mark.parametrize("boundary", [0, 1])
+@pytest.mark.parametrize("x", [0.33, 0.04])
+def test_ph2_cubic_hammer_dense_brute_force(boundary, x):
+    # the hammer's 4-node interpolant and spreading (Sec. 3.3 with p = 3),
+    # including a position in the first interval where a mirrored ghost
+    # enters, against the dense assembly
+    p = dict(_tiny(), boundary=boundary)
+    g = oracle.grid(p)
+    e = dict(W.hammer(x, 30.0, rhoA=0.002), interp_order=3)
+    r = oracle.run(p, e, want=("traj_u", "traj_z", "u_H"))
+    U, Z, UH = DR.run_dense(p, e, g, p["n_samples"])
+    scale = np.max(np.abs(U))
+    assert np.max(np.abs(r["traj_u"] - U)) < 1e-12 * scale
+    assert np.max(np.abs(r["u_H"] - UH)) < 1e-12 * np.max(np.abs(UH))
+    lin = oracle.run(p, dict(e, interp_order=1), want=("traj_u",))["traj_u"]
+    assert np.max(np.abs(lin - U)) > 1e-6 * scale
+
