@@ -110,10 +110,14 @@ typedef struct {
  * (n_samples / fs).  Each step solves the coupled system for its right-hand
  * side and for the bow's unit force, then the step's stick/slip problem
  * exactly (as a direct solve of eq. (7) would); SB_FP64_PLAIN carries the
- * unit force through its band elimination as a second right-hand side. */
+ * unit force through its band elimination as a second right-hand side.
+ * interp_order = 3 gives the hammer the cubic interpolant of Sec. 3.3
+ * (p = 3): four nodes around x, nodes past an end mirrored with the sign of
+ * the end condition, spreading J = I^T / h (batched precisions only;
+ * SB_FP64_PLAIN refuses it). */
 typedef struct {
     int32_t type;              /* SB_EXC_*                                        */
-    int32_t reserved;
+    int32_t interp_order;      /* hammer's I_p: 0 or 1 linear, 3 cubic (below)   */
     double x;                  /* position in (0,1); the bow's at t = 0           */
     double c0;                 /* pluck peak [m]                                  */
     double v_H, M_H, K_H, alpha_H, rhoA;

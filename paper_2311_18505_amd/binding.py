@@ -39,7 +39,7 @@ class SbStringParams(C.Structure):
 
 class SbExcitation(C.Structure):
     _fields_ = [
-        ("type", C.c_int32), ("reserved", C.c_int32), ("x", C.c_double), ("c0", C.c_double),
+        ("type", C.c_int32), ("interp_order", C.c_int32), ("x", C.c_double), ("c0", C.c_double),
         ("v_H", C.c_double), ("M_H", C.c_double), ("K_H", C.c_double), ("alpha_H", C.c_double),
         ("rhoA", C.c_double), ("x_end", C.c_double), ("v_B", C.c_double), ("F_B", C.c_double),
         ("attack", C.c_double), ("fric_a", C.c_double), ("fric_eps", C.c_double),

@@ -565,10 +565,11 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
     const int64_t st = std::min<int64_t>(n_steps, s.plan.desc.n_samples - s.samples_host);
     const double cost = (double)st * (double)(s.plan.desc.nt + s.plan.desc.nl + 8);
     const int c = b->precision == SB_FP64_PLAIN ? 0 : s.plan.desc.cls;
-    // bowed and clamped strings and the zeta channel run in the instantiation
-    // that carries their code
+    // bowed and clamped strings, the zeta channel and cubic hammers run in
+    // the instantiation that carries their code
     const Desc &d = s.plan.desc;
-    cls[(d.bow_on || d.clamped || d.zeta_out) ? 1 : 0][c].push_back({cost, i});
+    const bool cubic_hammer = d.ham_on && (d.hn2 || d.hn3);
+    cls[(d.bow_on || d.clamped || d.zeta_out || cubic_hammer) ? 1 : 0][c].push_back({cost, i});
   }
   if (!any) return fail(b, SB_ESTATE, "no excited slot");
   std::vector<int32_t> work;
@@ -1091,7 +1092,7 @@ extern "C" int string_batch_restrike_list(sb_batch *b, int count, const int32_t 
         const int lane = (node - 1) / mt, r = (node - 1) % mt;
         return (at(0, r, lane) - at(2, r, lane)) - (at(1, r, lane) - at(3, r, lane));
       };
-      const double uHm = D.hw0 * prev(D.hn0) + D.hw1 * prev(D.hn1);
+      const double uHm = D.hw0 * prev(D.hn0) + D.hw1 * prev(D.hn1) + D.hw2 * prev(D.hn2) + D.hw3 * prev(D.hn3);
       S[i].uH_nm1 = uHm;
       S[i].uH_n = uHm + D.k * e[i].v_H;
       S[i].eta_nm1 = 0.0;

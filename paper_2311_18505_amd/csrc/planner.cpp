@@ -299,10 +299,46 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
   return SB_OK;
 }
 
+// Cubic Lagrange interpolant at x (Sec. 3.3 with p = 3) on the nodes l-1 ..
+// l+2 around x = (l + a) h, as up to four distinct interior nodes (1-based,
+// 0 = absent) and weights: end nodes are fixed, a node past an end stands
+// for its mirror image with sign s (-1 simply supported, +1 clamped).
+static void cubic_interp(double x, int N, double s, int n[4], double w[4]) {
+  const int l = (int)std::floor(x * N);
+  const double a = x * N - l;
+  const double lw[4] = {-a * (a - 1.0) * (a - 2.0) / 6.0, (a + 1.0) * (a - 1.0) * (a - 2.0) / 2.0,
+                        -(a + 1.0) * a * (a - 2.0) / 2.0, (a + 1.0) * a * (a - 1.0) / 6.0};
+  for (int k = 0; k < 4; ++k) {
+    n[k] = 0;
+    w[k] = 0.0;
+  }
+  int used = 0;
+  for (int k = 0; k < 4; ++k) {
+    int m = l - 1 + k;
+    double c = lw[k];
+    if (m == -1) {
+      m = 1;
+      c *= s;
+    } else if (m == N + 1) {
+      m = N - 1;
+      c *= s;
+    }
+    if (m < 1 || m > N - 1) continue;
+    int j = 0;
+    while (j < used && n[j] != m) ++j;
+    if (j == used) n[used++] = m;
+    w[j] += c;
+  }
+}
+
 int plan_excitation(const sb_excitation &e, Plan &P, std::string &err) {
   Desc &D = P.desc;
   if (e.type < 0 || e.type > 3) {
     err = "bad excitation type";
+    return SB_EINVAL;
+  }
+  if (e.interp_order != 0 && e.interp_order != 1 && e.interp_order != 3) {
+    err = "interp_order must be 0, 1 or 3";
     return SB_EINVAL;
   }
   if (!finite_all({e.x, e.c0, e.v_H, e.M_H, e.K_H, e.alpha_H}) ||
@@ -342,11 +378,29 @@ int plan_excitation(const sb_excitation &e, Plan &P, std::string &err) {
   D.ham_on = e.type == 2;
   D.hn0 = D.hn1 = 0;
   D.hw0 = D.hw1 = 0.0;
+  if (e.type == 2) {
+    D.hn2 = D.hn3 = 0;
+    D.hw2 = D.hw3 = 0.0;
+  }
   D.omega_pow = D.alpha_H = D.Mr = D.IHs = 0.0;
   double *sm = P.tabf.data() + (size_t)G * (2 * mt + ml);
   std::fill(sm, sm + (size_t)G * mt, 0.0);
   if (e.type == 2) {
-    point_interp(e.x, Nt, D.hn0, D.hn1, D.hw0, D.hw1);
+    if (e.interp_order == 3) {
+      int n[4];
+      double w[4];
+      cubic_interp(e.x, Nt, D.clamped ? 1.0 : -1.0, n, w);
+      D.hn0 = n[0];
+      D.hn1 = n[1];
+      D.hn2 = n[2];
+      D.hn3 = n[3];
+      D.hw0 = w[0];
+      D.hw1 = w[1];
+      D.hw2 = w[2];
+      D.hw3 = w[3];
+    } else {
+      point_interp(e.x, Nt, D.hn0, D.hn1, D.hw0, D.hw1);
+    }
     D.omega_pow = e.K_H / e.M_H;       // omega_H^{1 + alpha_H}
     D.alpha_H = e.alpha_H;
     D.Mr = e.M_H / e.rhoA;             // mass ratio for a string of length 1
@@ -356,6 +410,8 @@ int plan_excitation(const sb_excitation &e, Plan &P, std::string &err) {
     std::vector<double> rhs(nt + 1, 0.0), cp(nt + 1, 0.0), x(nt + 2, 0.0);
     if (D.hn0) rhs[D.hn0] += D.hw0 * Nt;
     if (D.hn1) rhs[D.hn1] += D.hw1 * Nt;
+    if (D.hn2) rhs[D.hn2] += D.hw2 * Nt;
+    if (D.hn3) rhs[D.hn3] += D.hw3 * Nt;
     double den = d;
     std::vector<double> dp(nt + 1, 0.0);
     cp[1] = c / d;
@@ -367,7 +423,8 @@ int plan_excitation(const sb_excitation &e, Plan &P, std::string &err) {
     }
     x[nt] = dp[nt];
     for (int i = nt - 1; i >= 1; --i) x[i] = dp[i] - cp[i] * x[i + 1];
-    D.IHs = (D.hn0 ? D.hw0 * x[D.hn0] : 0.0) + (D.hn1 ? D.hw1 * x[D.hn1] : 0.0);
+    D.IHs = (D.hn0 ? D.hw0 * x[D.hn0] : 0.0) + (D.hn1 ? D.hw1 * x[D.hn1] : 0.0) +
+            (D.hn2 ? D.hw2 * x[D.hn2] : 0.0) + (D.hn3 ? D.hw3 * x[D.hn3] : 0.0);
     for (int lane = 0; lane < G; ++lane)
       for (int r = 0; r < mt; ++r) {
         const int i = lane * mt + r + 1;
@@ -401,6 +458,10 @@ int plan_plain(Plan &P, std::string &err) {
   Desc &D = P.desc;
   const int Nt = D.Nt, Nl = D.Nl, nt = D.nt, nl = D.nl;
   const bool ham = D.ham_on != 0;
+  if (ham && (D.hn2 || D.hn3)) {
+    err = "the plain path takes the hammer's linear interpolant only";
+    return SB_EINVAL;
+  }
   struct Item {
     double x;
     int kind, idx;

@@ -70,7 +70,17 @@ struct Desc {
   // sign(v) (beps + (1-beps) e^{-ba|v|})
   int32_t bow_on;             // 1 if the excitation is a bow
   int32_t zon0;               // zeta channel: first l-grid node of I(x_out) (0 = absent)
-  double bx0, bx1, bT, bvB, bFB, bta, ba, beps, bt0;
+  union {
+    struct {
+      double bx0, bx1, bT, bvB, bFB, bta, ba, beps, bt0;
+    };
+    // a hammer's cubic interpolant (p = 3) has two more nodes and weights
+    // (0 = absent); a string has either a hammer or a bow, never both
+    struct {
+      int32_t hn2, hn3;
+      double hw2, hw3;
+    };
+  };
   // readout
   int32_t on0, on1;           // nodes of I(x_out)
   double ow0, ow1;

@@ -623,21 +623,30 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   const double omega_pow = D.omega_pow, alpha_H = D.alpha_H, Mr = D.Mr, IHs = D.IHs;
   const bool ham = D.ham_on != 0;
   const bool any_ham = __ballot(ham) != 0;
+  // a cubic hammer interpolant (two more nodes) exists only in the BOW
+  // instantiation; its fields share storage with the bow's and are read
+  // where used (holding them would crowd the registers of every BOW task)
+  const bool any_hc = BOW && __ballot(ham && (D.hn2 != 0 || D.hn3 != 0)) != 0;
+  auto hc_eval = [&](const T (&x)[MM], const T (&c)[MM]) -> double {
+    return ham ? point_eval<G, T, MM>(x, c, D.hn2, D.hw2, D.hn3, D.hw3) : point_eval<G, T, MM>(x, c, 0, 0.0, 0, 0.0);
+  };
   const bool bowed = BOW && D.bow_on != 0;
   // the bow's code exists only in the BOW instantiation (its registers would
   // crowd every other task's)
   const bool any_bow = BOW && __ballot(bowed) != 0;
   double *bR = sB + gi * kBowRec;   // this group's bow record
   if (any_bow) {
-    bR[kBowX0] = D.bx0;
-    bR[kBowX1] = D.bx1;
-    bR[kBowT] = D.bT;
+    // groups without a bow get zeros (their descriptor's bow fields may hold
+    // a cubic hammer's nodes)
+    bR[kBowX0] = bowed ? D.bx0 : 0.0;
+    bR[kBowX1] = bowed ? D.bx1 : 0.0;
+    bR[kBowT] = bowed ? D.bT : 0.0;
     bR[kBowVB] = bowed ? D.bvB : 0.0;
     bR[kBowFB] = bowed ? D.bFB : 0.0;
-    bR[kBowTa] = D.bta;
-    bR[kBowA] = D.ba;
-    bR[kBowEps] = D.beps;
-    bR[kBowT0] = D.bt0;
+    bR[kBowTa] = bowed ? D.bta : 0.0;
+    bR[kBowA] = bowed ? D.ba : 0.0;
+    bR[kBowEps] = bowed ? D.beps : 0.0;
+    bR[kBowT0] = bowed ? D.bt0 : 0.0;
   }
   const bool any_l = __ballot(D.nl > 0) != 0;
   int gmax = D.gmax;
@@ -858,7 +867,10 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     double eta_n = 0.0, cH = 0.0, beta = 0.0;
     if (any_ham) {
       if constexpr (kSide) side_load<G, MM, T>(cu, side, 0, li);
-      const double Iu = point_eval<G, T, MM>(u, cu, hn0, hw0, hn1, hw1);
+      double Iu = point_eval<G, T, MM>(u, cu, hn0, hw0, hn1, hw1);
+      if constexpr (BOW) {
+        if (any_hc) Iu += hc_eval(u, cu);
+      }
       eta_n = ham ? uH_n - Iu : 0.0;
       const bool contact = eta_n > 0.0;
       if (__ballot(contact) != 0) {
@@ -873,6 +885,19 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
         const int i = tb + r + 1;
         ru[r] += (i == hn0) ? add0 : T(0);
         ru[r] += (i == hn1) ? add1 : T(0);
+      }
+      if constexpr (BOW) {
+        if (any_hc) {
+          const int hn2 = ham ? D.hn2 : 0, hn3 = ham ? D.hn3 : 0;
+          const T add2 = (T)(2.0 * beta * (ham ? D.hw2 : 0.0) * Ntdd * eta_n);
+          const T add3 = (T)(2.0 * beta * (ham ? D.hw3 : 0.0) * Ntdd * eta_n);
+#pragma unroll
+          for (int r = 0; r < MM; ++r) {
+            const int i = tb + r + 1;
+            ru[r] += (i == hn2) ? add2 : T(0);
+            ru[r] += (i == hn3) ? add3 : T(0);
+          }
+        }
       }
     }
     const bool sm_on = beta != 0.0;
@@ -965,7 +990,11 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
         toeplitz_solve<G, T, MM>(nu, bu, wbu, mask_t, rho_t, itk_t, spt);
         if (hammer && any_sm) {
           // Sherman-Morrison for the rank-one hammer term beta J I
-          const T Iy = (T)point_eval<G, T, MM>(nu, zero, hn0, hw0, hn1, hw1);
+          double Iyd = point_eval<G, T, MM>(nu, zero, hn0, hw0, hn1, hw1);
+          if constexpr (BOW) {
+            if (any_hc) Iyd += hc_eval(nu, zero);
+          }
+          const T Iy = (T)Iyd;
           const T fac = smfac * Iy;
   #pragma unroll
           for (int r = 0; r < MM; ++r) nu[r] = fma(-fac, kTL ? (sm_on ? smt[r] : T(0)) : smr[r], nu[r]);
@@ -1118,7 +1147,10 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
 
     // ---- hammer lumped mass (eq. 6) ----
     if (any_ham) {
-      const double Iu1 = point_eval<G, T, MM>(u, cu, hn0, hw0, hn1, hw1);
+      double Iu1 = point_eval<G, T, MM>(u, cu, hn0, hw0, hn1, hw1);
+      if constexpr (BOW) {
+        if (any_hc) Iu1 += hc_eval(u, cu);
+      }
       const double uH_np1 = (2.0 * uH_n - uH_nm1 - kk * cH * (eta_nm1 - Iu1)) / (1.0 + kk * cH);
       const bool upd = act && ham;
       uH_nm1 = upd ? uH_n : uH_nm1;
