@@ -62,7 +62,7 @@ class OrcOutputs(C.Structure):
     _fields_ = [
         ("y_u", _DP), ("y_z", _DP), ("energy", _DP), ("traj_u", _DP), ("traj_z", _DP),
         ("u_H", _DP), ("flops", C.c_double), ("steps_done", C.c_int64),
-        ("bow_phi", _DP), ("bow_vrel", _DP),
+        ("bow_phi", _DP), ("bow_vrel", _DP), ("flops_nofill", C.c_double),
     ]
 
 
@@ -185,6 +185,7 @@ def run(p: dict, e: dict | None, want=("y_u",), allow_fail: bool = False, schedu
         res[key] = arrs[key]
     res["status"] = st
     res["flops"] = out.flops
+    res["flops_nofill"] = out.flops_nofill
     res["steps_done"] = out.steps_done
     return res
 

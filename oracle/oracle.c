@@ -224,8 +224,12 @@ static csr csr_block2(int n1, int n2, const csr *A11, const csr *A12, const csr 
 /* Solve M x = rhs.  perm[new] = old gives an ordering of the unknowns in which
  * M is banded; the band is formed from the stored entries and factored by
  * Gaussian elimination with partial pivoting (row interchanges inside the
- * band, fill up to kl above the upper bandwidth).  Adds its arithmetic to *fl. */
-static int band_solve(const csr *M, const int *perm, const double *rhs, double *x, double *fl) {
+ * band, fill up to kl above the upper bandwidth).  Adds its arithmetic to *fl,
+ * and to *fl_nf what the same elimination costs without the interchanges'
+ * fill (row updates and back substitution over the upper bandwidth ku only):
+ * W A is symmetric positive definite, so no pivoting is needed in exact
+ * arithmetic and that is the method's own count. */
+static int band_solve(const csr *M, const int *perm, const double *rhs, double *x, double *fl, double *fl_nf) {
     int n = M->nr;
     int *inv = (int *)malloc(sizeof(int) * (size_t)n);
     for (int i = 0; i < n; ++i) inv[perm[i]] = i;
@@ -246,10 +250,11 @@ static int band_solve(const csr *M, const int *perm, const double *rhs, double *
         for (int p = M->rp[i]; p < M->rp[i + 1]; ++p) AB(ni, inv[M->ci[p]]) += M->v[p];
     }
     int status = ORC_OK;
-    double flops = 0.0;
+    double flops = 0.0, flops_nf = 0.0;
     for (int kk = 0; kk < n; ++kk) {
         int last = kk + kl < n - 1 ? kk + kl : n - 1;
         int cmax = kk + ku + kl < n - 1 ? kk + ku + kl : n - 1;
+        int umax = kk + ku < n - 1 ? kk + ku : n - 1;
         int piv = kk; double best = fabs(AB(kk, kk));
         for (int r = kk + 1; r <= last; ++r)
             if (fabs(AB(r, kk)) > best) { best = fabs(AB(r, kk)); piv = r; }
@@ -262,11 +267,13 @@ static int band_solve(const csr *M, const int *perm, const double *rhs, double *
         for (int r = kk + 1; r <= last; ++r) {
             double m = AB(r, kk) / pv;
             flops += 1.0;
+            flops_nf += 1.0;
             if (m == 0.0) continue;
             AB(r, kk) = 0.0;
             for (int c = kk + 1; c <= cmax; ++c) AB(r, c) -= m * AB(kk, c);
             b[r] -= m * b[kk];
             flops += 2.0 * (cmax - kk) + 2.0;
+            flops_nf += 2.0 * (umax - kk) + 2.0;
         }
     }
     if (status == ORC_OK) {
@@ -277,12 +284,14 @@ static int band_solve(const csr *M, const int *perm, const double *rhs, double *
             for (int c = i + 1; c <= cmax; ++c) s -= AB(i, c) * y[c];
             y[i] = s / AB(i, i);
             flops += 2.0 * (cmax - i) + 1.0;
+            flops_nf += 2.0 * ((i + ku < n - 1 ? i + ku : n - 1) - i) + 1.0;
         }
         for (int i = 0; i < n; ++i) x[i] = y[inv[i]];
         free(y);
     }
 #undef AB
     if (fl) *fl += flops;
+    if (fl_nf) *fl_nf += flops_nf;
     free(inv); free(a); free(b);
     return status;
 }
@@ -745,9 +754,10 @@ static void bow_controls(const bow_t *bw, double t, double *x, double *vB, doubl
  * curve's jump at v_rel = 0, and writes eta for v_rel in phi): phi(0) is any
  * value in [-1, 1] (static friction).  If |b| <= c the string sticks to the
  * bow: v_rel = 0, phi = b/c.  Otherwise it slips with v_rel = sign(b) x, where
- * x in (0, |b|) is the one root of x + c (eps + (1-eps) e^{-a x}) = |b| (the
- * left side is convex in x and below |b| at 0), found by Newton's method
- * kept inside a shrinking bracket. */
+ * x in (0, |b|) is the root of h(x) = x + c (eps + (1-eps) e^{-a x}) - |b|.
+ * h(0) = c - |b| < 0 and h(|b|) = c (eps + (1-eps) e^{-a|b|}) > 0, and h is
+ * convex, so the root is unique; it is found by plain bisection of that
+ * bracket until the midpoint no longer moves (full FP64 precision). */
 double orc_bow_solve(double b, double c, double a, double eps, double *v) {
     if (!(c > 0.0)) {            /* no bow force */
         *v = b;
@@ -758,18 +768,16 @@ double orc_bow_solve(double b, double c, double a, double eps, double *v) {
         return b / c;
     }
     double sg = b > 0.0 ? 1.0 : -1.0, ab = fabs(b);
-    double lo = 0.0, hi = ab, x = ab;
-    for (int it = 0; it < 200; ++it) {
-        double ex = exp(-a * x);
-        double h = x + c * (eps + (1.0 - eps) * ex) - ab;
-        if (h == 0.0) break;
-        if (h > 0.0) hi = x; else lo = x;
-        double dh = 1.0 - c * (1.0 - eps) * a * ex;
-        double xn = dh > 0.0 ? x - h / dh : 0.5 * (lo + hi);
-        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-        if (fabs(xn - x) <= 4e-16 * ab || hi - lo <= 4e-16 * ab) { x = xn; break; }
-        x = xn;
+    double lo = 0.0, hi = ab;    /* h(lo) < 0 < h(hi) */
+    for (int it = 0; it < 2000; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;     /* adjacent doubles */
+        double h = mid + c * (eps + (1.0 - eps) * exp(-a * mid)) - ab;
+        if (h > 0.0) hi = mid;
+        else if (h < 0.0) lo = mid;
+        else { lo = hi = mid; break; }
     }
+    double x = 0.5 * (lo + hi);
     *v = sg * x;
     return sg * (eps + (1.0 - eps) * exp(-a * x));
 }
@@ -1024,7 +1032,7 @@ int orc_run_schedule(const orc_string *s, const orc_excitation *e, int n_re, con
     /* the bow starts on the string at rest (w^0 = w^1 = 0) */
     int *perm = position_order(&o, hm.on, e && e->type == 2 ? e->x : 0.0);
 
-    double flops = 0.0;
+    double flops = 0.0, flops_nf = 0.0;
     /* samples 0 and 1 */
     for (int m = 0; m < 2 && m < Ns; ++m) {
         const double *w = m == 0 ? w0 : w1;
@@ -1065,8 +1073,11 @@ int orc_run_schedule(const orc_string *s, const orc_excitation *e, int n_re, con
         system_build(s, &o, gamma, w1, &sy);
         double c_n = 0.0;
         if (hm.on) c_n = hammer_c(&hm, uH1 - interp_apply4(hm.iH, hm.wH, w1));
-        csr M = joint_build(&o, &sy, &hm, c_n, w1, w0, uH1, uH0, rhs, &flops);
-        status = band_solve(&M, perm, rhs, w2, &flops);
+        double mv = 0.0;
+        csr M = joint_build(&o, &sy, &hm, c_n, w1, w0, uH1, uH0, rhs, &mv);
+        flops += mv;
+        flops_nf += mv;
+        status = band_solve(&M, perm, rhs, w2, &flops, &flops_nf);
         if (!status && bw.on) {
             /* eq. (5): Gamma^n = k^2 [J_B F_B phi; 0] (friction against v_rel) */
             double xB, vB, FB;
@@ -1076,7 +1087,7 @@ int orc_run_schedule(const orc_string *s, const orc_excitation *e, int n_re, con
             memset(rb, 0, sizeof(double) * (size_t)(n + 1));
             for (int a = 0; a < 2; ++a)
                 if (iB[a] >= 0) rb[iB[a]] += wB[a] / g.h_t;
-            status = band_solve(&M, perm, rb, gb, &flops);
+            status = band_solve(&M, perm, rb, gb, &flops, &flops_nf);
             if (!status) {
                 double c = g.k * FB * interp_apply(iB, wB, gb) / 2.0;
                 double b = (interp_apply(iB, wB, w2) - interp_apply(iB, wB, w0)) / (2.0 * g.k) - vB;
@@ -1104,6 +1115,7 @@ int orc_run_schedule(const orc_string *s, const orc_excitation *e, int n_re, con
         ++steps;
     }
     out->flops = flops;
+    out->flops_nofill = flops_nf;
     out->steps_done = steps;
     free(perm); free(w0); free(w1); free(w2); free(rhs); free(gb); free(rb);
     ops_free(&o);

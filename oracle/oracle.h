@@ -12,7 +12,8 @@
  *     A^n w^{n+1} + B^n w^n + C^n w^{n-1} + Gamma^n = 0,
  * with the blocks of eq. (8)-(9) assembled literally from sparse operator
  * matrices each step, and solves for w^{n+1} with a banded LU (partial
- * pivoting) after ordering the unknowns of both grids by position.
+ * pivoting) after ordering the unknowns of both grids by position.  The
+ * bow's scalar stick/slip problem is solved by bisection.
  *
  * Units: the string is normalised to length L = 1 (positions are fractions
  * of L), displacements are in metres, time in seconds.
@@ -78,6 +79,9 @@ typedef struct {
     int64_t steps_done;   /* out: number of recursion steps taken                      */
     double *bow_phi;      /* [n_samples]  bow: friction value phi used at step n        */
     double *bow_vrel;     /* [n_samples]  bow: relative velocity v_rel at step n        */
+    double flops_nofill;  /* out: the same arithmetic with the banded elimination kept
+                             inside the band (no row interchanges, which W A being
+                             symmetric positive definite makes unnecessary)          */
 } orc_outputs;
 
 /* status codes */

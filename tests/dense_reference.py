@@ -145,43 +145,57 @@ def gamma_at(p, n):
     return 2.0 * f
 
 
-def run_dense(p, e, g, n_samples):
-    """Step eq. (7) with dense solves; returns (traj_u, traj_z, u_H)."""
+def run_dense(p, e, g, n_samples, schedule=None):
+    """Step eq. (7) with dense solves; returns (traj_u, traj_z, u_H).
+
+    schedule: optional [(m, hammer)] of hammers set on the sounding string
+    before the step that computes w^{m+1}: the hammer takes the string's
+    displacement at level m-1 under it and moves on with its speed,
+    u_H^{m-1} = I_H u^{m-1}, u_H^m = u_H^{m-1} + k v_H."""
     D = Dense(p, g)
     nt, nl = D.nt, D.nl
     Nt, k = g["N_t"], g["k"]
     w0 = np.zeros(nt + nl)
     uH = np.zeros(n_samples)
-    if e["type"] == 1:
+    if e is not None and e["type"] == 1:
         x = np.arange(1, Nt) / Nt
         tri = np.where(x <= e["x"], e["c0"] * x / e["x"], e["c0"] * (1 - x) / (1 - e["x"]))
         w0[:nt] = tri
     w1 = w0.copy()
     traj = np.zeros((n_samples, nt + nl))
     traj[0], traj[1] = w0, w1
-    if e["type"] == 2:
-        uH[1] = k * e["v_H"]
-        if e.get("interp_order", 0) == 3:
-            Ih = point_row_cubic(e["x"], Nt, 1.0 if p.get("boundary", 0) == 1 else -1.0)
+    events = dict(schedule or [])
+    hm = None
+
+    def hammer_of(x):
+        if x.get("interp_order", 0) == 3:
+            Ih = point_row_cubic(x["x"], Nt, 1.0 if p.get("boundary", 0) == 1 else -1.0)
         else:
-            Ih = point_row(e["x"], Nt)
-        Jh = Ih / g["h_t"]
-        Mr = e["M_H"] / e["rhoA"]
-        wpow = e["K_H"] / e["M_H"]
+            Ih = point_row(x["x"], Nt)
+        return dict(Ih=Ih, Jh=Ih / g["h_t"], Mr=x["M_H"] / x["rhoA"], wpow=x["K_H"] / x["M_H"], aH=x["alpha_H"])
+
+    if e is not None and e["type"] == 2:
+        uH[1] = k * e["v_H"]
+        hm = hammer_of(e)
     for n in range(1, n_samples - 1):
+        if n in events:
+            hm = hammer_of(events[n])
+            uH[n - 1] = hm["Ih"] @ w0[:nt]
+            uH[n] = uH[n - 1] + k * events[n]["v_H"]
         gam = gamma_at(p, n)
         A, Bm, Cm = D.blocks(w1[:nt], gam)
         rhs = -Bm @ w1 - Cm @ w0
-        if e["type"] == 2:
+        if hm is not None:
+            Ih, Jh = hm["Ih"], hm["Jh"]
             eta_n = uH[n] - Ih @ w1[:nt]
             eta_m = uH[n - 1] - Ih @ w0[:nt]
-            c = 0.5 * wpow * eta_n ** (e["alpha_H"] - 1) if eta_n > 0 else 0.0
-            beta = k * k * Mr * c / (1 + k * k * c)
+            c = 0.5 * hm["wpow"] * eta_n ** (hm["aH"] - 1) if eta_n > 0 else 0.0
+            beta = k * k * hm["Mr"] * c / (1 + k * k * c)
             A = A.copy()
             A[:nt, :nt] += beta * np.outer(Jh, Ih)
             rhs[:nt] += beta * Jh * (2 * uH[n] - uH[n - 1] + eta_m)
         w2 = np.linalg.solve(A, rhs)
-        if e["type"] == 2:
+        if hm is not None:
             uH[n + 1] = (2 * uH[n] - uH[n - 1] - k * k * c * (eta_m - Ih @ w2[:nt])) / (1 + k * k * c)
         traj[n + 1] = w2
         w0, w1 = w1, w2

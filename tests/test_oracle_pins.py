@@ -311,6 +311,182 @@ def test_glide_shifts_pitch_by_the_requested_interval():
     assert abs(cents(f_end, f_start) - s * 100 * 0.9) < 10.0
 
 
+def _modal_readout_modulated(p, e, g, n_samples, gamma_n):
+    """The DST-I closed form of the linear simply supported string (as in
+    _modal_readout) with the stiffness-free part of b taken at gamma^n of each
+    step: every operator stays diagonal in the sine modes while gamma varies,
+    so the modes stay uncoupled and only b_m changes from step to step."""
+    N, k, h, th = g["N_t"], g["k"], g["h_t"], g["theta"]
+    m = np.arange(1, N)
+    s = np.sin(m * np.pi / (2 * N)) ** 2
+    mu = 1 - 2 * (1 - th) * s
+    nu2 = (g["kappa"] * k / h ** 2) ** 2
+    loss = p["sigma0_t"] * k + 4 * p["sigma1_t"] * k * s / h ** 2
+    L = np.longdouble
+    al, cl = (mu + loss).astype(L), (mu - loss).astype(L)
+    x = np.arange(1, N) / N
+    tri = np.where(x <= e["x"], e["c0"] * x / e["x"], e["c0"] * (1 - x) / (1 - e["x"]))
+    xi = scipy.fft.dst(tri, type=1) / N
+    lo = int(math.floor(p["x_out"] * N))
+    w = p["x_out"] * N - lo
+    rl = ((1 - w) * np.sin(m * np.pi * lo / N) + w * np.sin(m * np.pi * (lo + 1) / N)).astype(L)
+    y = np.zeros(n_samples)
+    x0, x1 = xi.astype(L), xi.astype(L)
+    y[0] = y[1] = float(x1 @ rl)
+    for n in range(1, n_samples - 1):
+        bl = (-2 * mu + 4 * (gamma_n(n) * k / h) ** 2 * s + 16 * nu2 * s ** 2).astype(L)
+        x2 = -(bl * x1 + cl * x0) / al
+        y[n + 1] = float(x2 @ rl)
+        x0, x1 = x1, x2
+    return y
+
+
+def _inst_cents(y, fs, band):
+    """Instantaneous frequency (cents re 1 Hz) of the partial inside `band`
+    (Hz): FFT band-pass, analytic signal, phase advance per sample."""
+    import scipy.signal
+    Y = np.fft.rfft(y)
+    f = np.fft.rfftfreq(len(y), 1.0 / fs)
+    Y[(f < band[0]) | (f > band[1])] = 0.0
+    ph = np.unwrap(np.angle(scipy.signal.hilbert(np.fft.irfft(Y, len(y)))))
+    t = (np.arange(len(y) - 1) + 0.5) / fs
+    return t, 1200.0 * np.log2(np.diff(ph) * fs / (2 * np.pi))
+
+
+def test_vibrato_follows_its_depth_and_rate():
+    """Vibrato (the f0 modulation named in Sec. 1): the fundamental of a
+    lossless, nearly ideal linear string plucked at its centre swings by the
+    stated depth in cents, at the stated rate, in sine phase from t = 0."""
+    from scipy.optimize import least_squares
+    d, fv = 50.0, 5.0
+    p = W.string(220.0, 1e-5, 1.0, 0.0, 0.0, 48000, mod_type=1, mod_depth_cents=d, mod_rate_hz=fv)
+    y = oracle.run(p, W.pluck(0.5, 1e-3), want=("y_u",))["y_u"]
+    t, c = _inst_cents(y, p["fs"], (150.0, 300.0))
+    sel = (t > 0.05) & (t < 0.95)        # away from the band-pass edges
+    t, c = t[sel], c[sel]
+    sol = least_squares(lambda x: x[0] + x[1] * np.sin(2 * np.pi * x[3] * t + x[2]) - c, [c.mean(), d, 0.0, fv])
+    C, A, ph, rate = sol.x
+    assert abs(A - d) < 0.5, A
+    assert abs(rate - fv) < 1e-3 * fv, rate
+    assert abs(ph) < 0.02, ph
+    # the centre is the unmodulated string's fundamental
+    assert abs(C - 1200.0 * np.log2(220.0 * math.sqrt(1 + 1e-5))) < 6.0
+
+
+@pytest.mark.parametrize("kind", ["vibrato", "glide"])
+def test_modulated_linear_string_matches_the_modal_closed_form(kind):
+    """Under f0 modulation the sine modes of the linear simply supported
+    string stay uncoupled; each follows its three-term recurrence with gamma
+    of its step (f0 at t = n k).  Pins where the modulated gamma enters the
+    oracle's step n and its time origin."""
+    ns = 4800
+    if kind == "vibrato":
+        p = W.string(150.0, 1e-4, 1.0, 0.5, 2e-4, ns, mod_type=1, mod_depth_cents=40.0, mod_rate_hz=6.0)
+        gam = lambda n: 2 * 150.0 * 2.0 ** ((40.0 / 1200.0) * math.sin(2 * math.pi * 6.0 * n / p["fs"]))
+    else:
+        p = W.string(150.0, 1e-4, 1.0, 0.5, 2e-4, ns, mod_type=2, glide_semitones=-1.5)
+        gam = lambda n: 2 * 150.0 * 2.0 ** ((-1.5 / 12.0) * (n / p["fs"]) / (ns / p["fs"]))
+    e = W.pluck(0.23, 1e-3)
+    r = oracle.run(p, e, want=("y_u",))
+    y_ref = _modal_readout_modulated(p, e, r["grid"], ns, gam)
+    err = np.max(np.abs(r["y_u"] - y_ref)) / np.max(np.abs(y_ref))
+    assert err < 1e-14 * ns, err
+
+
+def _max_root_at(g, N, gamma):
+    k, h, th = g["k"], 1.0 / N, g["theta"]
+    m = np.arange(1, N)
+    s = np.sin(m * np.pi / (2 * N)) ** 2
+    mu = 1 - 2 * (1 - th) * s
+    b = -2 * mu + 4 * (gamma * k / h) ** 2 * s + 16 * (g["kappa"] * k / h ** 2) ** 2 * s ** 2
+    return max(np.abs(np.roots([mu[i], b[i], mu[i]])).max() for i in range(len(m)))
+
+
+@pytest.mark.parametrize("mod", [(1, 50.0, 0.0), (1, 13.0, 0.0), (2, 0.0, 2.0), (2, 0.0, -2.0)])
+def test_modulated_grids_are_sized_at_the_highest_f0(mod):
+    """A modulated string's grids are sized at the highest f0 it reaches
+    (f0 2^{d/1200} for vibrato, f0 2^{max(s,0)/12} for a glide): the
+    transverse grid is stable (P3 per-mode roots) at that gamma, one point
+    finer is at best marginal (the bound takes the top mode at s = 1) and two
+    points finer unstable; the longitudinal grid is the one of h_l >= gamma
+    alpha k at that gamma; a glide down keeps the base f0's grids."""
+    mt, dc, st = mod
+    f0, B, alpha = 180.0, 3e-4, 2.5
+    p = W.string(f0, B, alpha, 1.0, 1e-4, 1000, mod_type=mt, mod_depth_cents=dc, mod_rate_hz=5.0,
+                 glide_semitones=st)
+    f_max = f0 * 2.0 ** (dc / 1200.0) if mt == 1 else f0 * 2.0 ** (max(st, 0.0) / 12.0)
+    g = oracle.grid(p)
+    gam = 2.0 * f_max
+    assert abs(g["gamma_max"] - gam) < 1e-12 * gam
+    assert _max_root_at(g, g["N_t"], gam) <= 1 + 1e-12
+    assert _max_root_at(g, g["N_t"] + 1, gam) > 1 - 1e-12
+    assert _max_root_at(g, g["N_t"] + 2, gam) > 1 + 1e-3
+    # the same grids as the unmodulated string at the highest f0 with the
+    # same kappa (kappa follows B at the base f0 and stays fixed)
+    q = W.string(f_max, B * (f0 / f_max) ** 2, alpha, 1.0, 1e-4, 1000)
+    gq = oracle.grid(q)
+    assert (gq["N_t"], gq["N_l"]) == (g["N_t"], g["N_l"])
+    base = oracle.grid(W.string(f0, B, alpha, 1.0, 1e-4, 1000))
+    if f_max > f0 * 1.01:
+        assert g["N_t"] < base["N_t"] and g["N_l"] < base["N_l"]
+    if mt == 2 and st < 0:
+        assert (g["N_t"], g["N_l"]) == (base["N_t"], base["N_l"])
+
+
+def test_glide_up_on_a_grid_one_point_finer_diverges():
+    """The glide reaches its highest f0 at the end: the oracle's grid stays
+    bounded over the whole note, one point finer blows up before the end."""
+    p = W.string(300.0, 1e-4, 1.0, 0.0, 0.0, 9600, mod_type=2, glide_semitones=2.0)
+    e = W.pluck(0.3, 1e-3)
+    good = oracle.run(p, e, want=("y_u",))
+    assert np.all(np.isfinite(good["y_u"])) and np.max(np.abs(good["y_u"])) < 2e-3
+    bad = oracle.run(dict(p, grid_t=good["grid"]["N_t"] + 1), e, want=("y_u",), allow_fail=True)["y_u"]
+    y = bad[np.isfinite(bad)]
+    assert (not np.all(np.isfinite(bad))) or np.max(np.abs(y)) > 1e3
+
+
+@pytest.mark.parametrize("second", ["linear", "cubic"])
+def test_restrike_of_a_sounding_string_matches_dense_brute_force(second):
+    """Several excitations per note on a string that is already sounding (a
+    plucked nonlinear string struck twice more): the oracle's schedule
+    against the dense numpy stepping with the hammers set as R18 reads it."""
+    p = _tiny()
+    g = oracle.grid(p)
+    e = W.pluck(0.3, 0.02)
+    h1 = W.hammer(0.41, 20.0, rhoA=0.002)
+    h2 = dict(W.hammer(0.17, 25.0, rhoA=0.002), interp_order=3 if second == "cubic" else 0)
+    sched = [(120, h1), (260, h2)]
+    r = oracle.run(p, e, want=("traj_u", "traj_z", "u_H"), schedule=sched)
+    U, Z, UH = DR.run_dense(p, e, g, p["n_samples"], schedule=sched)
+    scale = np.max(np.abs(U))
+    assert np.max(np.abs(U[120:])) > 0.1 * scale
+    assert np.max(np.abs(r["traj_u"] - U)) < 1e-12 * scale
+    assert np.max(np.abs(r["traj_z"] - Z)) < 1e-12 * scale
+    # the hammer displacement between and after the restrikes (levels m-1
+    # and m of an event hold the new hammer in the dense run, the old one in
+    # the oracle's record)
+    keep = np.r_[121:259, 261:p["n_samples"]]
+    assert np.max(np.abs(r["u_H"][keep] - UH[keep])) < 1e-12 * np.max(np.abs(UH[keep]))
+    # both hammers touched the string: the sounding string was struck
+    free = DR.run_dense(p, e, g, p["n_samples"])[0]
+    assert np.abs(U[150] - free[150]).max() > 1e-2 * scale
+    assert np.abs(U[300] - free[300]).max() > 1e-2 * scale
+
+
+def test_flop_count_of_the_banded_solve():
+    """The oracle's arithmetic count: on a linear string the system is
+    tridiagonal (kl = ku = 1); the elimination kept inside the band costs
+    4(n-2) flops per step fewer than with the interchanges' fill (one more
+    column in each row update and each back substitution row but the last
+    two), and the whole step costs a few tens of flops per unknown."""
+    p, e = W.single_linear(seconds=0.01)
+    r = oracle.run(p, e)
+    n = r["grid"]["N_t"] - 1
+    steps = r["steps_done"]
+    assert r["flops"] - r["flops_nofill"] == 4 * (n - 2) * steps
+    assert 15 < r["flops_nofill"] / (n * steps) < 40
+
+
 def test_golden_paper_constants():
     with open(os.path.join(GOLDEN, "paper_constants.json")) as fh:
         gold = json.load(fh)
