@@ -237,16 +237,23 @@ int string_batch_set_blocks_per_cu(sb_batch *b, const int32_t *blocks);
 
 /* Copy samples offset .. offset+count-1 of slot idx to dst (count elements
  * of the batch precision: float for SB_FP32C, double otherwise), ordered on
- * the batch stream and synchronous with it when dst_is_device == 0.
- * Errors: SB_EINVAL (range beyond n_samples), SB_EDEVICE. */
+ * the batch stream.  A host destination (dst_is_device == 0) is written
+ * synchronously with the stream; samples the slot has not produced yet (at
+ * or past its samples_done, e.g. after the energy monitor stopped it) are
+ * written as zero, and a flagged slot returns SB_EUNSTABLE after the copy.
+ * A device destination is an asynchronous copy of the buffer as it stands.
+ * Errors: SB_EINVAL (range beyond n_samples), SB_ESTATE (slot not excited),
+ * SB_EUNSTABLE, SB_EDEVICE. */
 int string_batch_read_output(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst, int dst_is_device);
 
 /* The second readout channel: zeta at x_out, interpolated on the
- * longitudinal grid like u (Sec. 3.4 shows both u and zeta outputs; zero for
+ * longitudinal grid like u (the paper's Fig. 2 shows the transverse and the
+ * longitudinal outputs and their spectra, discussed in Sec. 4.2; zero for
  * alpha = 1), recorded only for strings set with readout_zeta = 1 on the
- * batched paths; same arguments and ordering as string_batch_read_output.
- * Errors: SB_EINVAL (range beyond n_samples), SB_ESTATE (slot not excited or
- * set without the channel), SB_EDEVICE. */
+ * batched paths; same arguments, ordering and zero filling as
+ * string_batch_read_output.  Errors: SB_EINVAL (range beyond n_samples),
+ * SB_ESTATE (slot not excited or set without the channel), SB_EUNSTABLE,
+ * SB_EDEVICE. */
 int string_batch_read_output_zeta(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst,
                                   int dst_is_device);
 
@@ -254,17 +261,22 @@ int string_batch_read_output_zeta(sb_batch *b, int idx, int64_t offset, int64_t 
  * batch precision); the batch owns the memory. */
 int string_batch_output_ptr(sb_batch *b, int idx, void **dev_ptr);
 
-/* Streaming readout of many slots at once (Sec. 3.4's output signal, one
- * chunk per string): row i of dst (count elements of the batch precision)
- * receives samples offsets[i] .. offsets[i]+count-1 of slot slots[i],
- * clipped at that slot's n_samples (the rest of the row is left as is).
- * One gather kernel and one copy, ordered on the batch stream and
- * synchronous with it when dst_is_device == 0.  slots/offsets are host
- * arrays of n entries, copied before the call returns.
- * Errors: SB_EINVAL (bad slot, offset outside [0, n_samples)), SB_ESTATE
- * (slot not excited), SB_ENOMEM, SB_EDEVICE. */
+/* Streaming readout of many slots at once (the output signal of Sec. 3.4's
+ * recursion, one chunk per string): row i of dst (count elements of the
+ * batch precision) receives samples offsets[i] .. offsets[i]+count-1 of slot
+ * slots[i]; samples the slot has not produced (at or past its samples_done
+ * or n_samples) are written as zero, so a row never holds stale audio.  One
+ * gather kernel and one copy, ordered on the batch stream.  slots/offsets
+ * are host arrays of n entries, copied before the call returns.
+ * samples_done and flags (host arrays of n entries, or NULL) receive each
+ * listed slot's progress and flags (as string_batch_info reports them).
+ * Unless dst is on the device and both are NULL, the call is synchronous
+ * with the batch stream and returns SB_EUNSTABLE when any listed slot is
+ * flagged (the rows and arrays are written either way; last_error names the
+ * slots).  Errors: SB_EINVAL (bad slot, offset outside [0, n_samples)),
+ * SB_ESTATE (slot not excited), SB_EUNSTABLE, SB_ENOMEM, SB_EDEVICE. */
 int string_batch_gather_output(sb_batch *b, int n, const int32_t *slots, const int64_t *offsets, int64_t count,
-                               void *dst, int dst_is_device);
+                               void *dst, int dst_is_device, int64_t *samples_done, int32_t *flags);
 
 /* Energy H^{n+1/2} of slot idx at its last monitor check (FP64, computed on
  * the GPU), and the step n of that check (-1 if none).  Synchronises the

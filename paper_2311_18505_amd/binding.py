@@ -69,7 +69,7 @@ SIGNATURES = [
     ("string_batch_read_output_zeta", C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, _P, C.c_int]),
     ("string_batch_output_ptr", C.c_int, [_P, C.c_int, C.POINTER(_P)]),
     ("string_batch_gather_output", C.c_int, [_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_int64,
-                                             _P, C.c_int]),
+                                             _P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     ("string_batch_graph_capture", C.c_int, [_P, C.c_int64, C.c_int]),
     ("string_batch_graph_launch", C.c_int, [_P]),
     ("string_batch_autotune", C.c_int, [_P, C.c_int64, C.POINTER(C.c_int32)]),
@@ -257,16 +257,24 @@ class StringBatch:
         self._check(self.lib.string_batch_autotune(self.h, probe_steps, chosen), "autotune")
         return list(chosen)
 
-    def gather_output(self, slots, offsets, count: int) -> np.ndarray:
+    def gather_output(self, slots, offsets, count: int, status: bool = False):
         """Rows of `count` samples: row i holds samples offsets[i].. of slots[i]
-        (clipped at that slot's n_samples; the rest of the row is undefined)."""
+        (zero where the slot has not produced them).  With status=True returns
+        (rows, samples_done, flags) and does not raise for flagged slots;
+        otherwise a flagged slot raises SbError(SB_EUNSTABLE)."""
         sl = np.ascontiguousarray(slots, dtype=np.int32)
         of = np.ascontiguousarray(offsets, dtype=np.int64)
         out = np.empty((len(sl), count), dtype=self.dtype)
-        self._check(self.lib.string_batch_gather_output(
+        done = np.zeros(len(sl), dtype=np.int64)
+        flags = np.zeros(len(sl), dtype=np.int32)
+        st = self.lib.string_batch_gather_output(
             self.h, len(sl), sl.ctypes.data_as(C.POINTER(C.c_int32)), of.ctypes.data_as(C.POINTER(C.c_int64)),
-            count, out.ctypes.data_as(C.c_void_p), 0), "gather_output")
-        return out
+            count, out.ctypes.data_as(C.c_void_p), 0, done.ctypes.data_as(C.POINTER(C.c_int64)),
+            flags.ctypes.data_as(C.POINTER(C.c_int32)))
+        if status and st == SB_EUNSTABLE:
+            return out, done, flags
+        self._check(st, "gather_output")
+        return (out, done, flags) if status else out
 
     def read_output_device(self, idx: int, dst_ptr: int, offset: int, count: int):
         self._check(self.lib.string_batch_read_output(self.h, idx, offset, count, C.c_void_p(dst_ptr), 1),

@@ -15,17 +15,22 @@ constexpr int kBowStepVB = 8, kBowStepK2F = 9, kBowStepIv = 10, kBowStepW0 = 11,
               kBowStepN1 = 14, kBowT0 = 15;
 constexpr int kBowRec = 16;
 
-// Bow of eq. (5).  Controls at time t: force and bow speed rise linearly
-// over the attack, the position moves linearly over the note, both counted
-// from the time the bow was set on the string.
+// Bow of eq. (5).  Controls at time t from the record: kBowX0 the start
+// position, kBowX1 its rate of change (zero when it stays) until kBowT
+// seconds after the bow was set (kBowT0), kBowTa the rate at which force and
+// bow speed ramp up to kBowFB and kBowVB (zero: no attack).
 __device__ __forceinline__ void bow_controls(const double *R, double t, double &x, double &vB, double &FB) {
-  t -= R[kBowT0];
-  const double r = R[kBowTa] > 0.0 ? (t < R[kBowTa] ? t / R[kBowTa] : 1.0) : 1.0;
-  const double q = R[kBowT] > 0.0 ? (t < R[kBowT] ? t / R[kBowT] : 1.0) : 0.0;
-  x = R[kBowX0] + (R[kBowX1] - R[kBowX0]) * q;
-  vB = R[kBowVB] * r;
-  FB = R[kBowFB] * r;
+  const double s = t - R[kBowT0];
+  const double ramp = R[kBowTa] > 0.0 ? fmin(s * R[kBowTa], 1.0) : 1.0;
+  x = fma(R[kBowX1], fmin(s, R[kBowT]), R[kBowX0]);
+  vB = R[kBowVB] * ramp;
+  FB = R[kBowFB] * ramp;
 }
+
+// Record entries kBowX1 and kBowTa from a descriptor's end position x1 after
+// T seconds and attack time ta.
+__device__ __forceinline__ double bow_x_rate(double x0, double x1, double T) { return T > 0.0 ? (x1 - x0) / T : 0.0; }
+__device__ __forceinline__ double bow_ramp_rate(double ta) { return ta > 0.0 ? 1.0 / ta : 0.0; }
 
 // Nodes (1-based, 0 = absent) and weights of the linear interpolant at x.
 __device__ __forceinline__ void bow_interp(double x, int N, int &n0, int &n1, double &w0, double &w1) {

@@ -22,8 +22,9 @@ hipError_t launch_delay(uint64_t ticks, hipStream_t st);
 hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
                          hipStream_t st);
 hipError_t launch_scatter(const void *src, const UploadSeg *segs, int n, hipStream_t st);
-hipError_t launch_gather(int precision, const Desc *desc, const int32_t *slots, const int64_t *offs, int n,
-                         int64_t count, void *dst, hipStream_t st);
+hipError_t launch_gather(int precision, const Desc *desc, const Status *status, const int32_t *slots,
+                         const int64_t *offs, int n, int64_t count, void *dst, int64_t *row_done, int32_t *row_flags,
+                         hipStream_t st);
 hipError_t launch_plain(const Desc *d_desc, Status *d_status, int slot, int64_t n_steps, size_t lds_bytes,
                         hipStream_t st);
 }  // namespace sfd
@@ -142,6 +143,8 @@ struct sb_batch {
   size_t segs_cap = 0;
   int32_t *d_gslots = nullptr;
   int64_t *d_goffs = nullptr;
+  int64_t *d_gdone = nullptr;     // per gathered row: the slot's samples_done and flags
+  int32_t *d_gflags = nullptr;
   void *d_gbuf = nullptr;
   size_t gbuf_bytes = 0;
   std::vector<int32_t> h_work;
@@ -282,6 +285,8 @@ extern "C" int string_batch_destroy(sb_batch *b) {
   hipFree(b->d_trash_status);
   hipFree(b->d_gslots);
   hipFree(b->d_goffs);
+  hipFree(b->d_gdone);
+  hipFree(b->d_gflags);
   hipFree(b->d_gbuf);
   hipFree(b->d_stage);
   hipFree(b->d_segs);
@@ -885,7 +890,19 @@ extern "C" int string_batch_step_range(sb_batch *b, int first, int count, int64_
   return do_step(b, first, count, n_steps);
 }
 
+static int read_status(sb_batch *b, int idx, Status *S);
+
+// Describes the flagged slots among n (for last_error) and returns SB_EUNSTABLE.
+static int unstable(sb_batch *b, const std::vector<int> &bad) {
+  std::string m = "flagged by the energy monitor or the solver (output stops at samples_done): slot";
+  for (size_t i = 0; i < bad.size() && i < 16; ++i) m += " " + std::to_string(bad[i]);
+  if (bad.size() > 16) m += " ... (" + std::to_string(bad.size()) + " slots)";
+  return fail(b, SB_EUNSTABLE, m);
+}
+
 // Samples offset.. of one output channel of slot idx (u, or zeta) into dst.
+// Host destinations get zeros for the samples the slot has not produced, and
+// SB_EUNSTABLE when the slot is flagged.
 static int read_channel(sb_batch *b, int idx, int64_t offset, int64_t count, void *dst, int dst_is_device, bool zeta) {
   if (!b) return SB_EINVAL;
   if (idx < 0 || idx >= b->capacity || !dst || offset < 0 || count < 0) return fail(b, SB_EINVAL, "bad arguments");
@@ -897,10 +914,21 @@ static int read_channel(sb_batch *b, int idx, int64_t offset, int64_t count, voi
   if (offset + count > s.plan.desc.n_samples) return fail(b, SB_EINVAL, "range beyond n_samples");
   if (count == 0) return SB_OK;
   const char *src = (const char *)(zeta ? s.plan.desc.out_z : s.plan.desc.out) + offset * b->esz;
-  hipError_t e = hipMemcpyAsync(dst, src, count * b->esz, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                                b->stream);
-  if (e == hipSuccess && !dst_is_device) e = hipStreamSynchronize(b->stream);
-  if (e != hipSuccess) return hip_fail(b, e, zeta ? "read_output_zeta" : "read_output");
+  if (dst_is_device) {
+    hipError_t e = hipMemcpyAsync(dst, src, count * b->esz, hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, zeta ? "read_output_zeta" : "read_output");
+    return SB_OK;
+  }
+  Status S;
+  int st = read_status(b, idx, &S);    // synchronises the stream
+  if (st) return st;
+  const int64_t have = std::max<int64_t>(0, std::min<int64_t>(count, S.samples_done - offset));
+  if (have > 0) {
+    hipError_t e = hipMemcpy(dst, src, have * b->esz, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(b, e, zeta ? "read_output_zeta" : "read_output");
+  }
+  std::memset((char *)dst + have * b->esz, 0, (count - have) * b->esz);
+  if (S.flags) return unstable(b, {idx});
   return SB_OK;
 }
 
@@ -914,11 +942,12 @@ extern "C" int string_batch_read_output_zeta(sb_batch *b, int idx, int64_t offse
 }
 
 extern "C" int string_batch_gather_output(sb_batch *b, int n, const int32_t *slots, const int64_t *offsets,
-                                          int64_t count, void *dst, int dst_is_device) {
+                                          int64_t count, void *dst, int dst_is_device, int64_t *samples_done,
+                                          int32_t *flags) {
   if (!b) return SB_EINVAL;
   if (n < 0 || n > b->capacity || count < 0 || (n > 0 && (!slots || !offsets || !dst)))
     return fail(b, SB_EINVAL, "bad arguments");
-  if (n == 0 || count == 0) return SB_OK;
+  if (n == 0) return SB_OK;
   for (int i = 0; i < n; ++i) {
     if (slots[i] < 0 || slots[i] >= b->capacity) return fail(b, SB_EINVAL, "bad slot");
     const Slot &s = b->slots[slots[i]];
@@ -929,11 +958,13 @@ extern "C" int string_batch_gather_output(sb_batch *b, int n, const int32_t *slo
   if (!b->d_gslots) {
     e = hipMalloc(&b->d_gslots, sizeof(int32_t) * b->capacity);
     if (e == hipSuccess) e = hipMalloc(&b->d_goffs, sizeof(int64_t) * b->capacity);
+    if (e == hipSuccess) e = hipMalloc(&b->d_gdone, sizeof(int64_t) * b->capacity);
+    if (e == hipSuccess) e = hipMalloc(&b->d_gflags, sizeof(int32_t) * b->capacity);
     if (e != hipSuccess) return hip_fail(b, e, "gather buffers");
   }
   const size_t bytes = (size_t)n * (size_t)count * b->esz;
   void *rows = dst;
-  if (!dst_is_device) {
+  if (!dst_is_device && bytes > 0) {
     if (bytes > b->gbuf_bytes) {
       // the previous buffer may still be read by queued copies
       e = hipStreamSynchronize(b->stream);
@@ -950,12 +981,34 @@ extern "C" int string_batch_gather_output(sb_batch *b, int n, const int32_t *slo
   e = hipStreamSynchronize(b->stream);
   if (e == hipSuccess) e = hipMemcpy(b->d_gslots, slots, sizeof(int32_t) * n, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_goffs, offsets, sizeof(int64_t) * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_gather(b->precision, b->d_desc, b->d_gslots, b->d_goffs, n, count, rows, b->stream);
-  if (e == hipSuccess && !dst_is_device) {
+  // (with count 0 the kernel only records progress and flags: rows is never touched)
+  if (e == hipSuccess)
+    e = launch_gather(b->precision, b->d_desc, b->d_status, b->d_gslots, b->d_goffs, n, count, rows, b->d_gdone,
+                      b->d_gflags, b->stream);
+  if (e == hipSuccess && !dst_is_device && bytes > 0)
     e = hipMemcpyAsync(dst, rows, bytes, hipMemcpyDeviceToHost, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  const bool want_status = !dst_is_device || samples_done || flags;
+  if (!want_status) {
+    if (e != hipSuccess) return hip_fail(b, e, "gather_output");
+    return SB_OK;
   }
+  // progress and flags of the listed slots
+  std::vector<int64_t> hd(n);
+  std::vector<int32_t> hf(n);
+  if (e == hipSuccess) e = hipMemcpyAsync(hd.data(), b->d_gdone, sizeof(int64_t) * n, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hf.data(), b->d_gflags, sizeof(int32_t) * n, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(b, e, "gather_output");
+  std::vector<int> bad;
+  for (int i = 0; i < n; ++i) {
+    if (samples_done) samples_done[i] = hd[i];
+    if (flags) flags[i] = hf[i];
+    if (hf[i]) {
+      bad.push_back(slots[i]);
+      b->slots[slots[i]].flagged = true;
+    }
+  }
+  if (!bad.empty()) return unstable(b, bad);
   return SB_OK;
 }
 

@@ -68,7 +68,8 @@ __global__ __launch_bounds__(64) void plain_kernel(PlainArgs a) {
   double *gz = cxx + (Nt + 2);        // I_(t)->(l) (q D- u^{n-1}) at l-halves 1..Nl
   double *rhs2 = gz + (Nl + 2);       // bow: n (+1 trash), becomes A^{-1} [J_p(x_B); 0]
   const bool bow = D.bow_on != 0;
-  const double bR[kBowRec] = {D.bx0, D.bx1, D.bT, D.bvB, D.bFB, D.bta, D.ba, D.beps, 0, 0, 0, 0, 0, 0, 0, D.bt0};
+  const double bR[kBowRec] = {D.bx0, bow_x_rate(D.bx0, D.bx1, D.bT), D.bT, D.bvB, D.bFB, bow_ramp_rate(D.bta),
+                             D.ba, D.beps, 0, 0, 0, 0, 0, 0, 0, D.bt0};
 
   const int32_t *pos_t = D.ptab, *pos_l = pos_t + nt, *jab = pos_l + nl;
   const int32_t *rga = jab + Nt, *rgb = rga + Nl;

@@ -639,11 +639,11 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     // groups without a bow get zeros (their descriptor's bow fields may hold
     // a cubic hammer's nodes)
     bR[kBowX0] = bowed ? D.bx0 : 0.0;
-    bR[kBowX1] = bowed ? D.bx1 : 0.0;
+    bR[kBowX1] = bowed ? bow_x_rate(D.bx0, D.bx1, D.bT) : 0.0;
     bR[kBowT] = bowed ? D.bT : 0.0;
     bR[kBowVB] = bowed ? D.bvB : 0.0;
     bR[kBowFB] = bowed ? D.bFB : 0.0;
-    bR[kBowTa] = bowed ? D.bta : 0.0;
+    bR[kBowTa] = bowed ? bow_ramp_rate(D.bta) : 0.0;
     bR[kBowA] = bowed ? D.ba : 0.0;
     bR[kBowEps] = bowed ? D.beps : 0.0;
     bR[kBowT0] = bowed ? D.bt0 : 0.0;
@@ -1331,26 +1331,37 @@ __global__ void rewind_kernel(const Desc *desc, Status *status, const Status *st
 }
 
 // Row i of dst receives samples offs[i] .. offs[i]+count-1 of slot slots[i]'s
-// output, clipped at its n_samples: one block per row.
+// output; samples the slot has not produced (at or past its samples_done, or
+// past n_samples) are written as zero.  The slot's samples_done and flags go
+// to row_done[i] and row_flags[i].  One block per row.
 template <typename T>
-__global__ void gather_kernel(const Desc *desc, const int32_t *slots, const int64_t *offs, int n, int64_t count,
-                              T *dst) {
+__global__ void gather_kernel(const Desc *desc, const Status *status, const int32_t *slots, const int64_t *offs,
+                              int n, int64_t count, T *dst, int64_t *row_done, int32_t *row_flags) {
   const int i = (int)blockIdx.x;
   if (i >= n) return;
-  const Desc &D = desc[slots[i]];
-  const int64_t left = D.n_samples - offs[i];
-  const int64_t c = count < left ? count : left;
+  const int s = slots[i];
+  const Desc &D = desc[s];
+  const int64_t done = status[s].samples_done;
+  const int64_t avail = (done < D.n_samples ? done : D.n_samples) - offs[i];
+  const int64_t c = count < avail ? count : (avail > 0 ? avail : 0);
   const T *src = (const T *)D.out + offs[i];
-  for (int64_t s = threadIdx.x; s < c; s += blockDim.x) dst[(int64_t)i * count + s] = src[s];
+  for (int64_t t = threadIdx.x; t < count; t += blockDim.x) dst[(int64_t)i * count + t] = t < c ? src[t] : T(0);
+  if (threadIdx.x == 0) {
+    row_done[i] = done;
+    row_flags[i] = status[s].flags;
+  }
 }
 
-hipError_t launch_gather(int precision, const Desc *desc, const int32_t *slots, const int64_t *offs, int n,
-                         int64_t count, void *dst, hipStream_t st) {
+hipError_t launch_gather(int precision, const Desc *desc, const Status *status, const int32_t *slots,
+                         const int64_t *offs, int n, int64_t count, void *dst, int64_t *row_done, int32_t *row_flags,
+                         hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (precision == 1)
-    hipLaunchKernelGGL(gather_kernel<float>, dim3(n), dim3(256), 0, st, desc, slots, offs, n, count, (float *)dst);
+    hipLaunchKernelGGL(gather_kernel<float>, dim3(n), dim3(256), 0, st, desc, status, slots, offs, n, count,
+                       (float *)dst, row_done, row_flags);
   else
-    hipLaunchKernelGGL(gather_kernel<double>, dim3(n), dim3(256), 0, st, desc, slots, offs, n, count, (double *)dst);
+    hipLaunchKernelGGL(gather_kernel<double>, dim3(n), dim3(256), 0, st, desc, status, slots, offs, n, count,
+                       (double *)dst, row_done, row_flags);
   return hipGetLastError();
 }
 

@@ -67,7 +67,9 @@ def draw_notes(n: int, seed: int = W.SEED + 21, seconds=(0.5, 2.0), restrike_pro
 
 
 def synthesize(notes: list, precision: str = "fp32c", capacity: int = 4096, log=None) -> list:
-    """Audio of every note (numpy arrays of the batch precision), in order."""
+    """Audio of every note (numpy arrays of the batch precision), in order;
+    None for a note whose string the device flagged (energy monitor or
+    solver), which the dataset leaves out."""
     out = [None] * len(notes)
     for first in range(0, len(notes), capacity):
         part = notes[first:first + capacity]
@@ -90,7 +92,12 @@ def synthesize(notes: list, precision: str = "fp32c", capacity: int = 4096, log=
                     b.restrike_list([i for i, _ in live], [ex for _, ex in live])
             b.step(ns - done)
             for i in range(len(part)):
-                out[first + i] = b.read_output(i)
+                try:
+                    out[first + i] = b.read_output(i)
+                except binding.SbError as err:
+                    if err.code != binding.SB_EUNSTABLE:
+                        raise
+                    out[first + i] = None
         finally:
             b.close()
         if log:
@@ -121,14 +128,17 @@ def main():
     t = time.perf_counter()
     audio = synthesize(notes, args.precision, args.capacity, log=lambda m: print("[dataset] " + m, flush=True))
     dt = time.perf_counter() - t
-    for first in range(0, len(audio), args.capacity):
-        part = audio[first:first + args.capacity]
+    kept = [(x, a) for x, a in zip(notes, audio) if a is not None]
+    for first in range(0, len(kept), args.capacity):
+        part = [a for _, a in kept[first:first + args.capacity]]
         rows = np.zeros((len(part), max(len(a) for a in part)), dtype=part[0].dtype)
         for i, a in enumerate(part):
             rows[i, :len(a)] = a
         np.save(os.path.join(args.out, "audio_%06d.npy" % first), rows)   # zero-padded rows
     with open(os.path.join(args.out, "labels.json"), "w") as f:
-        json.dump([dict(labels(x), samples=len(a)) for x, a in zip(notes, audio)], f)
+        json.dump([dict(labels(x), samples=len(a)) for x, a in kept], f)
+    if len(kept) < len(notes):
+        print("[dataset] %d notes flagged by the device and left out" % (len(notes) - len(kept)), flush=True)
     secs = sum(x["params"]["n_samples"] for x in notes) / 48000.0
     print("[dataset] %d notes, %.0f audio-s in %.1f s (%.0f audio-s/s)" % (len(notes), secs, dt, secs / dt), flush=True)
 

@@ -11,7 +11,9 @@ being stepped join the next launch and overlap with them on the GPU.
 
 Latencies are measured on the host clock from a request's arrival: the first
 chunk (its first samples on the host) and completion (its last samples on the
-host).
+host).  A request whose string the device flags (energy monitor or solver)
+fails alone: its slot is freed, its audio is not delivered past the last
+sample it produced, and it counts neither as done nor in the latencies.
 """
 from __future__ import annotations
 
@@ -40,6 +42,7 @@ class ServeStats:
     first_chunk_s: dict
     completion_s: dict
     refused: list
+    failed: list
     wall_s: float
     audio_s: float
     chunks: int
@@ -53,6 +56,7 @@ class ServeStats:
         return {
             "requests_done": len(self.completion_s),
             "refused": len(self.refused),
+            "failed": len(self.failed),
             "first_chunk_ms": {"p50": pct(self.first_chunk_s, 50), "p99": pct(self.first_chunk_s, 99)},
             "completion_ms": {"p50": pct(self.completion_s, 50), "p99": pct(self.completion_s, 99)},
             "audio_s_per_s": self.audio_s / self.wall_s if self.wall_s > 0 else None,
@@ -63,17 +67,21 @@ class ServeStats:
         }
 
 
-def _estimate_bytes(params: dict) -> int:
-    """Device bytes of one FP32 request: its output dominates (state and
-    tables are a few tens of bytes per grid point)."""
+def _estimate_bytes(params: dict, esz: int) -> int:
+    """Device bytes of one request in a batch of element size esz (4 for
+    FP32C, 8 for FP64): its output (two channels with the zeta readout) plus
+    state, its excitation copy and tables (at most ~16 elements and 12 bytes
+    of indices per grid point, lane padding included) and alignment."""
     nt, nl = binding.plan_grid(params)
-    return 4 * (int(params["n_samples"]) + 64) + 96 * (nt + nl) + 4096
+    channels = 2 if params.get("readout_zeta", 0) else 1
+    return channels * esz * (int(params["n_samples"]) + 64) + (16 * esz + 12) * (nt + nl) + 8 * 256
 
 
 class Server:
     def __init__(self, capacity: int = 8192, precision: str = "fp32c", chunk: int = CHUNK,
                  mem_budget: int = 32 << 30):
         self.b = binding.StringBatch(capacity, precision)
+        self.esz = 4 if precision == "fp32c" else 8
         self.capacity = capacity
         self.chunk = chunk
         self.mem_budget = mem_budget
@@ -110,7 +118,8 @@ class Server:
     def run(self, requests, keep=(), clock=time.perf_counter, on_chunk=None, log=None,
             log_every: float = 10.0) -> tuple:
         """Serve `requests` (arrival times relative to the start) in real time.
-        Returns (ServeStats, {rid: samples} for the rids in `keep`).  `log`, if
+        Returns (ServeStats, {rid: samples} for the rids in `keep` that did not
+        fail).  `log`, if
         given, receives a progress line every `log_every` seconds."""
         reqs = {r.rid: r for r in requests}
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
@@ -118,7 +127,7 @@ class Server:
         active = {}        # slot -> [request, samples_done, samples delivered]
         keep = set(keep)
         outputs = {rid: [] for rid in keep}
-        first, done, refused, step_ms = {}, {}, [], []
+        first, done, refused, failed, step_ms = {}, {}, [], [], []
         mem_used, max_active, chunks = 0, 0, 0
         t0 = clock()
         next_log = log_every
@@ -133,7 +142,7 @@ class Server:
             new = []
             while waiting and self.free:
                 r = waiting[0]
-                need = _estimate_bytes(r.params)
+                need = _estimate_bytes(r.params, self.esz)
                 if mem_used + need > self.mem_budget and (active or new):
                     break
                 waiting.popleft()
@@ -156,14 +165,23 @@ class Server:
             ts = clock()
             self.b.step(self.chunk)
             slots = sorted(active)
-            rows = self.b.gather_output(slots, [active[s][2] for s in slots], self.chunk + 2)
+            rows, sdone, flags = self.b.gather_output(slots, [active[s][2] for s in slots], self.chunk + 2,
+                                                      status=True)
             t_avail = clock() - t0
             step_ms.append((clock() - ts) * 1e3)
             chunks += 1
             for i, s in enumerate(slots):
                 r, sd, dl = active[s]
                 ns = int(r.params["n_samples"])
-                sd = min(ns, sd + self.chunk)
+                if flags[i]:
+                    # the device stopped this string: the request fails alone
+                    failed.append(r.rid)
+                    outputs.pop(r.rid, None)
+                    del active[s]
+                    self.free.append(s)
+                    mem_used -= r.nbytes
+                    continue
+                sd = min(ns, int(sdone[i]))
                 cnt = sd - dl
                 if r.rid in outputs:
                     outputs[r.rid].append(rows[i, :cnt].copy())
@@ -180,7 +198,7 @@ class Server:
             self.free.sort(reverse=True)
         wall = clock() - t0
         audio = sum(int(reqs[rid].params["n_samples"]) / reqs[rid].params["fs"] for rid in done)
-        stats = ServeStats(first, done, refused, wall, audio, chunks, max_active, step_ms)
+        stats = ServeStats(first, done, refused, failed, wall, audio, chunks, max_active, step_ms)
         return stats, {rid: np.concatenate(v) if v else np.empty(0) for rid, v in outputs.items()}
 
 

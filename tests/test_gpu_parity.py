@@ -58,10 +58,6 @@ def _report(tag, err, info=None):
     print("%s rel-L2 %.3e %s" % (tag, err, "" if info is None else info), flush=True)
 
 
-@pytest.mark.skip(reason="hung on the GPU with an earlier step kernel whose lane-0-only status stores were compiled "
-                         "into a divergent loop exit; a first fix did not clear it, so this exact case stays off the "
-                         "GPU until the cause of that hang is shown on the CPU (the same string runs inside the "
-                         "other cases)")
 def test_tiny_first():
     _gpu()
     p, e = W.single_linear(seconds=0.01)
