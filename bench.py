@@ -2,15 +2,19 @@
 """Benchmark of batched FP32 string synthesis on one MI355X.
 
 One bench step synthesises a whole batch of strings from their excitation to
-their last sample through the C ABI (rewind on the device, then one replay of
-a HIP graph holding a launch over the longest duration, every size class
-forked onto its own stream), with every input already in device memory.
-Prints one JSON line: grid-point updates per second (the sum over strings of
+their last sample through the C ABI: a rewind on the device, then one eager
+string_batch_step over the longest duration (the size classes' launches
+forked onto their own streams and joined), with every input already in
+device memory.  The same step replayed from a captured HIP graph, and the
+same batch stepped in 480-sample chunks, are timed beside it.  Prints one
+JSON line: grid-point updates per second (the sum over strings of
 (N_t - 1 + N_l - 1) per time step), audio seconds per second, the roofline
-position of each size-class kernel (the longest one reported as `roofline`),
-the FP64 CPU oracle timed on a sample of the same workload, the plain FP64
-per-string method on the single nonlinear string, and a real-time serving
-run with Poisson arrivals (p50/p99 latencies).
+position of each launch's kernel (the one with the most updates reported as
+`roofline`), the FP64 CPU oracle timed on a sample of the same workload and
+the GPU output's error against it on that sample (rel-L2 and partial offsets
+in cents), the uniform 4096-string batch, the plain FP64 per-string method
+on the single nonlinear string, and a real-time serving run with Poisson
+arrivals (p50/p99 latencies).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -77,28 +81,62 @@ def measured_traffic():
 
 def cpu_baseline(items, seconds_cap, threads):
     """The FP64 oracle on a bounded sample of the workload, one string per
-    host thread.  Returns the baseline record and the oracle's arithmetic per
-    grid-point update (its RHS matvecs and banded LU)."""
+    host thread.  Returns the baseline record, the oracle's arithmetic per
+    grid-point update (its RHS matvecs and banded elimination, without and
+    with partial pivoting's fill) and the sample's outputs."""
     import oracle
     sample = []
     for p, e in items[:threads * 4]:
-        q = dict(p, n_samples=min(p["n_samples"], int(seconds_cap * p["fs"])))
+        # the note cut to its first seconds_cap: a glide keeps the full
+        # note's rate (its interval scales with the cut) and both grids stay
+        # those planned for the full note, so the cut oracle run computes the
+        # same samples as the first ones of the GPU's full-length run
+        ns = min(p["n_samples"], int(seconds_cap * p["fs"]))
+        g = oracle.grid(p)
+        q = dict(p, n_samples=ns, grid_t=g["N_t"], grid_l=g["N_l"])
+        if p.get("mod_type", 0) == 2:
+            q["glide_semitones"] = p["glide_semitones"] * ns / p["n_samples"]
         sample.append((q, e))
     t0 = time.perf_counter()
     res = oracle.run_many(sample, threads=threads)
     dt = time.perf_counter() - t0
     upd = 0
-    flops = 0.0
+    flops = flops_nf = 0.0
     for r in res:
         g = r["grid"]
         n = (g["N_t"] - 1) + max(g["N_l"] - 1, 0)
         upd += n * r["steps_done"]
         flops += r["flops"]
+        flops_nf += r["flops_nofill"]
     rec = {"value": upd / dt, "unit": "grid-point updates/s", "cores": threads, "kind": "oracle",
-           "sample": "first %d strings of the workload, each cut to %.2f s (%d updates), FP64, "
-                     "one string per thread" % (len(sample), seconds_cap, upd),
+           "sample": "first %d strings of the workload, each cut to its first %.2f s (%d updates; glides keep "
+                     "their rate, grids those of the full note), FP64, one string per thread"
+                     % (len(sample), seconds_cap, upd),
            "seconds": dt, "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
-    return rec, flops / upd
+    return rec, flops_nf / upd, flops / upd, [r["y_u"] for r in res]
+
+
+def accuracy(outs, refs, fs):
+    """Error of each GPU output against the oracle's on the same samples:
+    rel-L2, and the offset in cents of the GPU output's spectral peaks from
+    the oracle's (the six strongest peaks within 40 dB of each reference,
+    both located by the same estimator on the same window)."""
+    from paper_2311_18505_amd import analysis
+    rel, cts = [], []
+    for y, ref in zip(outs, refs):
+        y = np.asarray(y, dtype=np.float64)[:len(ref)]
+        rel.append(float(np.linalg.norm(y - ref) / np.linalg.norm(ref)))
+        fr, lr = analysis.find_peaks(ref, fs, floor_db=-40.0)
+        fy, _ = analysis.find_peaks(y, fs, floor_db=-60.0)
+        for f in fr[np.argsort(lr)[::-1][:6]]:
+            if len(fy):
+                c = 1200.0 * np.log2(fy / f)
+                j = int(np.argmin(np.abs(c)))
+                cts.append(abs(float(c[j])))
+    return {"strings": len(refs), "rel_l2_max": max(rel), "rel_l2_median": float(np.median(rel)),
+            "partial_offset_cents_max": max(cts) if cts else None,
+            "partial_offset_cents_median": float(np.median(cts)) if cts else None,
+            "partials_compared": len(cts)}
 
 
 def cpu_model() -> str:
@@ -135,6 +173,34 @@ def plain_leg(W, binding, hiptime, seconds):
             "ms": ms, "workload": "single nonlinear hammered string, %.1f s (N_t=%d, N_l=%d), FP64, "
                                   "one string per launch" % (seconds, inf["N_t"], inf["N_l"]),
             "finished": done["samples_done"] == p["n_samples"] and done["flags"] == 0}
+
+
+def uniform_leg(W, binding, hiptime):
+    """The uniform batch: 4096 nonlinear strings of 2 s, FP32 compensated,
+    autotuned, one eager step of the whole batch after a warm-up (HIP
+    events)."""
+    items = W.uniform_batch_4096()
+    b = binding.StringBatch(len(items), "fp32c")
+    b.set_params(0, [p for p, _ in items])
+    b.excite(0, [e for _, e in items])
+    infos = [b.info(i) for i in range(len(items))]
+    steps = max(p["n_samples"] for p, _ in items)
+    tuned = b.autotune(480)
+    b.step(steps)                       # warm-up
+    b.rewind()
+    hiptime.synchronize()
+    ev0, ev1 = hiptime.Event(), hiptime.Event()
+    ev0.record(0)
+    b.step(steps)
+    ev1.record(0)
+    ev1.synchronize()
+    ms = ev0.elapsed_ms(ev1)
+    bad = sum(1 for i in range(len(items)) if b.info(i)["flags"] != 0 or b.info(i)["samples_done"] != infos[i]["n_samples"])
+    b.close()
+    upd = sum(unknowns(inf) * (inf["n_samples"] - 2) for inf in infos)
+    return {"value": upd / (ms / 1e3), "unit": "grid-point updates/s", "audio_s_per_s": len(items) * 2.0 / (ms / 1e3),
+            "ms": ms, "updates": upd, "blocks_per_cu": tuned, "strings_not_finished": bad,
+            "workload": "4096 nonlinear strings of 2.0 s (seeded draws), FP32 compensated"}
 
 
 def bow_leg(W, binding, hiptime, n, seconds):
@@ -226,7 +292,8 @@ def dataset_leg(hiptime, n, seconds):
     secs = sum(x["params"]["n_samples"] for x in notes) / 48000.0
     return {"value": secs / wall, "unit": "audio-s/s", "notes_per_s": n / wall, "wall_s": wall,
             "notes": n, "events": sum(len(x["events"]) for x in notes),
-            "finite": bool(all(np.isfinite(a).all() for a in audio)),
+            "finite": bool(all(np.isfinite(a).all() for a in audio if a is not None)),
+            "flagged_notes": sum(1 for a in audio if a is None),
             "workload": "%d notes of U(%.1f, %.1f) s, pluck/hammer/bow, half re-excited mid-note once or twice, "
                         "FP32 compensated" % (n, seconds[0], seconds[1])}
 
@@ -254,8 +321,10 @@ def main():
     ap.add_argument("--workload", default="uneven16384", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=0.25, help="duration cap of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--plain-seconds", type=float, default=0.5, help="duration of the plain FP64 comparator run")
+    ap.add_argument("--plain-seconds", type=float, default=2.0, help="duration of the plain FP64 comparator run")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-uniform", action="store_true", help="skip the uniform 4096-string batch leg")
+    ap.add_argument("--no-chunked", action="store_true", help="skip timing the batch in 480-sample chunks")
     ap.add_argument("--bow-strings", type=int, default=4096, help="strings of the bowed-batch leg")
     ap.add_argument("--no-bow", action="store_true")
     ap.add_argument("--clamped-strings", type=int, default=4096, help="strings of the clamped-ends leg")
@@ -325,6 +394,24 @@ def main():
     g1.synchronize()
     graph_ms = g0.elapsed_ms(g1)
     print("[bench] graph replay: %.3f ms" % graph_ms, file=sys.stderr, flush=True)
+    # the oracle's sample: the first strings' first samples (read after the
+    # replay, which recomputes the same outputs)
+    n_cpu = min(len(items), 4 * min(16, os.cpu_count() or 1))
+    cut = int(args.cpu_seconds * 48000)
+    gpu_sample = [b.read_output(i, 0, min(params[i]["n_samples"], cut)) for i in range(n_cpu)]
+    chunked_ms = None
+    if not args.no_chunked:
+        # the same batch stepped in 480-sample chunks (one step call each)
+        b.rewind()
+        hiptime.synchronize()
+        c0, c1 = hiptime.Event(), hiptime.Event()
+        c0.record(0)
+        for _ in range(0, n_max, 480):
+            b.step(480)
+        c1.record(0)
+        c1.synchronize()
+        chunked_ms = c0.elapsed_ms(c1)
+        print("[bench] 480-sample chunks: %.3f ms" % chunked_ms, file=sys.stderr, flush=True)
 
     # every string must have finished cleanly
     bad = 0
@@ -365,12 +452,17 @@ def main():
         "strings_not_finished": bad,
         "gpu_ms_per_step": gpu_ms / args.steps,
         "graph_replay_ms": graph_ms,
+        "chunked_480_ms": chunked_ms,
     }
     if not args.no_plain:
         pl = plain_leg(W, binding, hiptime, args.plain_seconds)
         print("[bench] plain FP64: %.1f ms, %.3e updates/s" % (pl["ms"], pl["value"]), file=sys.stderr, flush=True)
         out["plain_fp64"] = pl
         out["batched_vs_plain"] = value / pl["value"]
+    if not args.no_uniform and args.workload != "uniform4096":
+        un = uniform_leg(W, binding, hiptime)
+        print("[bench] uniform 4096: %.1f ms, %.3e updates/s" % (un["ms"], un["value"]), file=sys.stderr, flush=True)
+        out["uniform4096_fp32c"] = un
     if not args.no_bow:
         bw = bow_leg(W, binding, hiptime, args.bow_strings, 1.0)
         print("[bench] bow: %.1f ms, %.3e updates/s (%.2f x the same strings plucked)"
@@ -400,11 +492,15 @@ def main():
             out["serving"]["plain_fp64_max_rate_hz"] = out["plain_fp64"]["audio_s_per_s"] / mean_T
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
-        rec, flops_per_update = cpu_baseline(items, args.cpu_seconds, threads)
+        rec, flops_per_update, flops_fill, refs = cpu_baseline(items, args.cpu_seconds, threads)
         out["cpu_baseline"] = {k: v for k, v in rec.items() if k != "seconds"}
+        out["accuracy_vs_oracle"] = dict(accuracy(gpu_sample, refs, 48000.0),
+                                         sample=rec["sample"], precision="FP32 compensated vs FP64 oracle")
+        print("[bench] accuracy vs oracle: %s" % json.dumps(out["accuracy_vs_oracle"]), file=sys.stderr, flush=True)
         # roofline of each launch's kernel: the oracle's arithmetic per
-        # grid-point update times the updates of that launch's strings, over
-        # the kernel's own duration (HIP events on its stream, last timed step)
+        # grid-point update (banded elimination without pivoting's fill) times
+        # the updates of that launch's strings, over the kernel's own duration
+        # (HIP events on its stream, last timed step)
         by_launch = []
         for u in range(binding.NUM_LAUNCHES):
             if launch_ms[u] <= 0:
@@ -421,6 +517,7 @@ def main():
                            "traffic": measured_traffic() if dom["kernel"] == TRAFFIC["kernel"] else None,
                            "kernel": dom["kernel"], "kernel_ms_per_launch": dom["ms"],
                            "flops_per_update": flops_per_update,
+                           "flops_per_update_with_pivoting_fill": flops_fill,
                            "whole_step_frac": flops_per_update * updates / (gpu_ms / args.steps / 1e3) / PEAK_FP32_VECTOR}
         out["roofline_by_launch"] = by_launch
     print(json.dumps(out), flush=True)
