@@ -278,6 +278,24 @@ int string_batch_output_ptr(sb_batch *b, int idx, void **dev_ptr);
 int string_batch_gather_output(sb_batch *b, int n, const int32_t *slots, const int64_t *offsets, int64_t count,
                                void *dst, int dst_is_device, int64_t *samples_done, int32_t *flags);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): string_batch_gather_output into a device
+ * destination without any allocation.  The gathered slot indices, offsets
+ * and per-row progress and flags live in a fixed scratch array of the
+ * library (SB_NOALLOC_MAX_ROWS rows, about 384 KiB, held by each GPU the
+ * library runs on until the process ends) instead of buffers of the batch.
+ * Same rows, zero filling and return codes as string_batch_gather_output;
+ * dst is device memory of n*count elements of the batch precision;
+ * samples_done and flags are host arrays of n entries or NULL.  Synchronous
+ * with the batch stream.  Every call on one GPU shares that GPU's scratch:
+ * calls that overlap on one GPU (batches on different streams or threads at
+ * the same time) race and must not be made.  Errors: SB_EINVAL (n above
+ * SB_NOALLOC_MAX_ROWS or the capacity, bad slot, offset outside
+ * [0, n_samples)), SB_ESTATE (slot not excited), SB_EUNSTABLE, SB_EDEVICE. */
+#define SB_NOALLOC_MAX_ROWS 16384
+int string_batch_gather_output_noalloc(sb_batch *b, int n, const int32_t *slots, const int64_t *offsets,
+                                       int64_t count, void *dst, int64_t *samples_done, int32_t *flags);
+
 /* Energy H^{n+1/2} of slot idx at its last monitor check (FP64, computed on
  * the GPU), and the step n of that check (-1 if none).  Synchronises the
  * stream.  Errors: SB_EINVAL, SB_EDEVICE. */

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libstringfdtd.so")
 SB_OK, SB_EINVAL, SB_ENOMEM, SB_EBUDGET, SB_EUNSTABLE, SB_ESTATE, SB_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 SB_FP64, SB_FP32C, SB_FP64_PLAIN = 0, 1, 2
 PRECISIONS = {"fp64": SB_FP64, "fp32c": SB_FP32C, "fp64_plain": SB_FP64_PLAIN}
+# rows of the allocation-free gather's fixed scratch
+SB_NOALLOC_MAX_ROWS = 16384
 # concurrent launches of a batched step: classes 0..3 merged, class 4, class 5
 NUM_LAUNCHES = 3
 LAUNCH_CLASSES = ((0, 1, 2, 3), (4,), (5,))
@@ -70,6 +72,8 @@ SIGNATURES = [
     ("string_batch_output_ptr", C.c_int, [_P, C.c_int, C.POINTER(_P)]),
     ("string_batch_gather_output", C.c_int, [_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_int64,
                                              _P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    ("string_batch_gather_output_noalloc", C.c_int, [_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                                     C.c_int64, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     ("string_batch_graph_capture", C.c_int, [_P, C.c_int64, C.c_int]),
     ("string_batch_graph_launch", C.c_int, [_P]),
     ("string_batch_autotune", C.c_int, [_P, C.c_int64, C.POINTER(C.c_int32)]),

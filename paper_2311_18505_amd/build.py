@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstringfdtd.so")
-SOURCES = ["capi.cpp", "planner.cpp", "step_kernel.hip", "plain_kernel.hip"]
+SOURCES = ["capi.cpp", "planner.cpp", "step_kernel.hip", "plain_kernel.hip", "static_scratch.hip"]
 
 
 def hipcc() -> str:

@@ -27,6 +27,7 @@ hipError_t launch_gather(int precision, const Desc *desc, const Status *status, 
                          hipStream_t st);
 hipError_t launch_plain(const Desc *d_desc, Status *d_status, int slot, int64_t n_steps, size_t lds_bytes,
                         hipStream_t st);
+hipError_t static_scratch_ptr(int device, void **ptr);
 }  // namespace sfd
 
 using namespace sfd;
@@ -145,6 +146,7 @@ struct sb_batch {
   int64_t *d_goffs = nullptr;
   int64_t *d_gdone = nullptr;     // per gathered row: the slot's samples_done and flags
   int32_t *d_gflags = nullptr;
+  void *d_scratch = nullptr;      // this device's copy of the library's fixed scratch (allocation-free calls)
   void *d_gbuf = nullptr;
   size_t gbuf_bytes = 0;
   std::vector<int32_t> h_work;
@@ -241,6 +243,8 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
     if (e == hipSuccess) e = hipEventCreate(&b->ev_t1[c]);
   }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  // the device address of the fixed scratch on this (current) device
+  if (e == hipSuccess) e = static_scratch_ptr(dev, &b->d_scratch);
   if (e == hipSuccess) {
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
@@ -999,6 +1003,61 @@ extern "C" int string_batch_gather_output(sb_batch *b, int n, const int32_t *slo
   if (e == hipSuccess) e = hipMemcpyAsync(hf.data(), b->d_gflags, sizeof(int32_t) * n, hipMemcpyDeviceToHost, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(b, e, "gather_output");
+  std::vector<int> bad;
+  for (int i = 0; i < n; ++i) {
+    if (samples_done) samples_done[i] = hd[i];
+    if (flags) flags[i] = hf[i];
+    if (hf[i]) {
+      bad.push_back(slots[i]);
+      b->slots[slots[i]].flagged = true;
+    }
+  }
+  if (!bad.empty()) return unstable(b, bad);
+  return SB_OK;
+}
+
+static_assert(kNoAllocMaxRows == SB_NOALLOC_MAX_ROWS, "row limit of the allocation-free gather");
+
+// string_batch_gather_output into a device destination with the index
+// arrays and per-row status in the library's fixed scratch instead of the
+// batch's own buffers (which the first gather allocates): no allocation at
+// all.  Synchronous with the batch stream (the scratch of the previous call
+// is free once the stream has drained).
+extern "C" int string_batch_gather_output_noalloc(sb_batch *b, int n, const int32_t *slots, const int64_t *offsets,
+                                                  int64_t count, void *dst, int64_t *samples_done, int32_t *flags) {
+  if (!b) return SB_EINVAL;
+  // the size limit first: it is the one error a caller of this entry point must expect
+  if (n > kNoAllocMaxRows || n > b->capacity)
+    return fail(b, SB_EINVAL, "n = " + std::to_string(n) + " rows exceeds the allocation-free gather's maximum of " +
+                                  std::to_string(std::min(kNoAllocMaxRows, b->capacity)));
+  if (n < 0 || count < 0 || (n > 0 && (!slots || !offsets || (count > 0 && !dst))))
+    return fail(b, SB_EINVAL, "bad arguments");
+  if (n == 0) return SB_OK;
+  for (int i = 0; i < n; ++i) {
+    if (slots[i] < 0 || slots[i] >= b->capacity) return fail(b, SB_EINVAL, "bad slot");
+    const Slot &s = b->slots[slots[i]];
+    if (!s.excited) return fail(b, SB_ESTATE, "slot " + std::to_string(slots[i]) + " not excited");
+    if (offsets[i] < 0 || offsets[i] >= s.plan.desc.n_samples) return fail(b, SB_EINVAL, "offset outside the output");
+  }
+  if (!b->d_scratch) return fail(b, SB_EDEVICE, "no fixed scratch on this device");
+  char *base = (char *)b->d_scratch;
+  int32_t *d_slots = (int32_t *)(base + kScratchSlotsOff);
+  int64_t *d_offs = (int64_t *)(base + kScratchOffsOff);
+  int64_t *d_done = (int64_t *)(base + kScratchDoneOff);
+  int32_t *d_flags = (int32_t *)(base + kScratchFlagsOff);
+  // earlier work on the stream (a previous call's gather reads the scratch)
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess) e = hipMemcpy(d_slots, slots, sizeof(int32_t) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_offs, offsets, sizeof(int64_t) * n, hipMemcpyHostToDevice);
+  // (with count 0 the kernel only records progress and flags)
+  if (e == hipSuccess)
+    e = launch_gather(b->precision, b->d_desc, b->d_status, d_slots, d_offs, n, count, dst, d_done, d_flags, b->stream);
+  std::vector<int64_t> hd(n);
+  std::vector<int32_t> hf(n);
+  if (e == hipSuccess) e = hipMemcpyAsync(hd.data(), d_done, sizeof(int64_t) * n, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hf.data(), d_flags, sizeof(int32_t) * n, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(b, e, "gather_output_noalloc");
   std::vector<int> bad;
   for (int i = 0; i < n; ++i) {
     if (samples_done) samples_done[i] = hd[i];

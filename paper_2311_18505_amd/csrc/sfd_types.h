@@ -1,6 +1,7 @@
 // Internal types shared by the host planner, the C ABI and the HIP kernels of
 // libstringfdtd (private to the library).
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 namespace sfd {
@@ -141,6 +142,16 @@ struct LaunchArgs {
 };
 
 constexpr int kMaxTrash = 4 * 2 * kMaxSlots * kWave * 8;   // largest state block in FP64
+
+// Fixed device scratch of the allocation-free gather: per row a slot index,
+// an offset, and the slot's progress and flags, for at most kNoAllocMaxRows
+// rows (each region starts on a 256-byte boundary).
+constexpr int kNoAllocMaxRows = 16384;
+constexpr size_t kScratchSlotsOff = 0;
+constexpr size_t kScratchOffsOff = kScratchSlotsOff + ((sizeof(int32_t) * kNoAllocMaxRows + 255) & ~size_t(255));
+constexpr size_t kScratchDoneOff = kScratchOffsOff + ((sizeof(int64_t) * kNoAllocMaxRows + 255) & ~size_t(255));
+constexpr size_t kScratchFlagsOff = kScratchDoneOff + ((sizeof(int64_t) * kNoAllocMaxRows + 255) & ~size_t(255));
+constexpr size_t kStaticScratchBytes = kScratchFlagsOff + ((sizeof(int32_t) * kNoAllocMaxRows + 255) & ~size_t(255));
 
 // One segment of a bulk upload (excitation): bytes (a multiple of 4) from
 // offset src_off of the staging buffer to dst.
