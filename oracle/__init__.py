@@ -34,6 +34,7 @@ class OrcString(C.Structure):
         ("n_samples", C.c_int64), ("mod_type", C.c_int32), ("grid_t", C.c_int32),
         ("mod_depth_cents", C.c_double), ("mod_rate_hz", C.c_double),
         ("glide_semitones", C.c_double), ("grid_l", C.c_int32), ("boundary", C.c_int32),
+        ("grid_interp", C.c_int32),
     ]
 
 
@@ -96,6 +97,8 @@ def _load():
         lib.orc_dump_system.restype = C.c_int
         lib.orc_gamma_at.argtypes = [C.POINTER(OrcString), C.c_int64]
         lib.orc_gamma_at.restype = C.c_double
+        lib.orc_apply_I_lt.argtypes = [C.c_int, C.c_int, C.c_int, _DP, _DP]
+        lib.orc_apply_I_lt.restype = C.c_int
         lib.orc_bow_solve.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _DP]
         lib.orc_bow_solve.restype = C.c_double
         _lib = lib
@@ -104,7 +107,7 @@ def _load():
 
 STRING_KEYS = ("fs", "f0", "B", "alpha", "theta", "sigma0_t", "sigma1_t", "sigma0_l", "sigma1_l",
                "x_out", "n_samples", "mod_type", "mod_depth_cents", "mod_rate_hz",
-               "glide_semitones", "grid_t", "grid_l", "boundary")
+               "glide_semitones", "grid_t", "grid_l", "boundary", "grid_interp")
 EXC_KEYS = ("type", "interp_order", "x", "c0", "v_H", "M_H", "K_H", "alpha_H", "rhoA", "x_end", "v_B", "F_B", "attack",
             "fric_a", "fric_eps")
 
@@ -188,6 +191,16 @@ def run(p: dict, e: dict | None, want=("y_u",), allow_fail: bool = False, schedu
     res["flops_nofill"] = out.flops_nofill
     res["steps_done"] = out.steps_done
     return res
+
+
+def apply_I_lt(Nt: int, Nl: int, order: int, p) -> np.ndarray:
+    """I_(l)->(t) p of the scheme (order 1 or 3) on grids of Nt and Nl intervals."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.zeros(Nt)
+    st = _load().orc_apply_I_lt(Nt, Nl, order, _ptr(p), _ptr(out))
+    if st != 0:
+        raise OracleError("orc_apply_I_lt failed with status %d" % st)
+    return out
 
 
 def run_many(items, want=("y_u",), threads: int | None = None) -> list:

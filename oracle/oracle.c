@@ -329,6 +329,7 @@ int orc_grid_plan(const orc_string *s, orc_grid *g) {
     double th = theta_of(s);
     if (!(th > 0.5) || !(th <= 1.0)) return ORC_EINVAL;
     if (s->boundary != 0 && s->boundary != 1) return ORC_EINVAL;
+    if (s->grid_interp != 0 && s->grid_interp != 1 && s->grid_interp != 3) return ORC_EINVAL;
     double k = 1.0 / s->fs;
     double gamma0 = 2.0 * s->f0;
     /* Sec. 4.1: K = (pi kappa / gamma)^2, with K read as the inharmonicity B */
@@ -464,13 +465,18 @@ static int clamped_stable(int Nt, double th, double gamma, double kappa, double 
 }
 
 /* I_(l)->(t): N_t x N_l.  READING of Sec. 3.1 ("p-th order upsampling
- * interpolant", order unstated): first-order Lagrange interpolation from the
- * longitudinal half points (j-1/2)h_l to the transverse half points
- * (i-1/2)h_t, with the end values held constant outside the outermost half
- * points.  The fractional index xi = x/h_l + 1/2 is formed as the exact ratio
- * ((2i-1) N_l + N_t) / (2 N_t). */
-static csr op_I_lt(int Nt, int Nl) {
-    int n = 2 * Nt, t = 0;
+ * interpolant", order unstated): Lagrange interpolation of order p = 1
+ * (default) or p = 3 from the longitudinal half points (j-1/2)h_l to the
+ * transverse half points (i-1/2)h_t.  In units of h_l the t-half point sits
+ * at xi = x/h_l + 1/2 (l-half j at xi = j), formed as the exact ratio
+ * ((2i-1) N_l + N_t) / (2 N_t); with j0 = floor(xi) and a = xi - j0, p = 1
+ * takes j0, j0+1 with weights 1-a, a and p = 3 takes j0-1 .. j0+2 with the
+ * cubic Lagrange weights.  Half points past an end stand for their mirror
+ * images (p_0 = p_1, p_{-1} = p_2, p_{N_l+1} = p_{N_l}, ...): p = D_x- zeta
+ * is even about a fixed end of zeta.  For p = 1 this holds the end values
+ * constant outside the outermost half points. */
+static csr op_I_lt(int Nt, int Nl, int order) {
+    int n = 4 * Nt, t = 0;
     int *r = (int *)malloc(sizeof(int) * (size_t)n);
     int *c = (int *)malloc(sizeof(int) * (size_t)n);
     double *v = (double *)malloc(sizeof(double) * (size_t)n);
@@ -478,15 +484,38 @@ static csr op_I_lt(int Nt, int Nl) {
         long long num = (long long)(2 * i - 1) * Nl + Nt;
         long long den = 2LL * Nt;
         int j0 = (int)(num / den);
-        double w = (double)(num % den) / (double)den;
-        int ja = j0 < 1 ? 1 : (j0 > Nl ? Nl : j0);
-        int jb = j0 + 1 < 1 ? 1 : (j0 + 1 > Nl ? Nl : j0 + 1);
-        r[t] = i - 1; c[t] = ja - 1; v[t] = 1.0 - w; ++t;
-        r[t] = i - 1; c[t] = jb - 1; v[t] = w; ++t;
+        double a = (double)(num % den) / (double)den;
+        int nk = order == 3 ? 4 : 2;
+        int first = order == 3 ? j0 - 1 : j0;
+        double w[4];
+        if (order == 3) {
+            w[0] = -a * (a - 1.0) * (a - 2.0) / 6.0;
+            w[1] = (a + 1.0) * (a - 1.0) * (a - 2.0) / 2.0;
+            w[2] = -(a + 1.0) * a * (a - 2.0) / 2.0;
+            w[3] = (a + 1.0) * a * (a - 1.0) / 6.0;
+        } else {
+            w[0] = 1.0 - a;
+            w[1] = a;
+        }
+        for (int k = 0; k < nk; ++k) {
+            int j = first + k;
+            if (j < 1) j = 1 - j;                 /* mirror about x = 0 */
+            if (j > Nl) j = 2 * Nl + 1 - j;       /* mirror about x = 1 */
+            r[t] = i - 1; c[t] = j - 1; v[t] = w[k]; ++t;   /* repeated entries add up */
+        }
     }
     csr A = csr_from_coo(Nt, Nl, t, r, c, v);
     free(r); free(c); free(v);
     return A;
+}
+
+/* For tests: pt = I_(l)->(t) p (order 1 or 3) on grids of N_t and N_l intervals. */
+int orc_apply_I_lt(int Nt, int Nl, int order, const double *p, double *pt) {
+    if (Nt < 2 || Nl < 2 || (order != 1 && order != 3) || !p || !pt) return ORC_EINVAL;
+    csr A = op_I_lt(Nt, Nl, order);
+    csr_matvec(&A, p, pt, NULL);
+    csr_free(&A);
+    return ORC_OK;
 }
 
 /* Interpolation row I_p(x) of Sec. 3.3 on the N-1 interior nodes: READING:
@@ -592,7 +621,7 @@ static void ops_build(const orc_string *s, const orc_grid *g, ops_t *o) {
         { csr t = csr_scale(-1.0, &o->Dp_l); csr_free(&o->Dp_l); o->Dp_l = t; }
         o->Dxx_l = csr_mul(&o->Dp_l, &o->Dm_l);
         o->I_l = csr_eye(o->nl, 1.0);
-        o->I_lt = op_I_lt(Nt, Nl);
+        o->I_lt = op_I_lt(Nt, Nl, s->grid_interp == 3 ? 3 : 1);
         /* READING: I_(t)->(l) = (h_t/h_l) I_(l)->(t)^T, the weighted adjoint */
         csr tr = csr_transpose(&o->I_lt);
         o->I_tl = csr_scale(g->h_t / g->h_l, &tr);
@@ -732,6 +761,8 @@ typedef struct {
     double x0, x1, T;              /* position x0 -> x1 over T seconds from t0 */
     double vB, FB, ta;             /* bow velocity and force, attack time */
     double a, eps;                 /* friction curve */
+    int order;                     /* I_p: 1 linear, 3 cubic (Sec. 3.3's p-th order interpolant) */
+    double ghost;                  /* sign of the mirrored ghost nodes of the cubic I_p */
 } bow_t;
 
 /* Control values at time t.  READING: the paper gives the controls as
@@ -798,6 +829,8 @@ static void bow_setup(const orc_excitation *e, const orc_string *s, int64_t n0, 
     bw->ta = e->attack;
     bw->a = e->fric_a;
     bw->eps = e->fric_eps;
+    bw->order = e->interp_order == 3 ? 3 : 1;
+    bw->ghost = s->boundary == 1 ? 1.0 : -1.0;
 }
 
 /* Contact coefficient at time n of eq. (6): F_H = c_n (eta^{n+1} + eta^{n-1})
@@ -1082,15 +1115,21 @@ int orc_run_schedule(const orc_string *s, const orc_excitation *e, int n_re, con
             /* eq. (5): Gamma^n = k^2 [J_B F_B phi; 0] (friction against v_rel) */
             double xB, vB, FB;
             bow_controls(&bw, step * g.k, &xB, &vB, &FB);
-            int iB[2]; double wB[2];
-            interp_row(xB, g.N_t, iB, wB);
+            /* I_p(x_B) and J_p(x_B) = I_p^T / h_t: linear, or the cubic of the
+             * hammer's R21 reading (four nodes, ghosts mirrored with the end
+             * condition's sign) */
+            int iB[4] = {-1, -1, -1, -1}; double wB[4] = {0.0, 0.0, 0.0, 0.0};
+            if (bw.order == 3)
+                interp_row_cubic(xB, g.N_t, bw.ghost, iB, wB);
+            else
+                interp_row(xB, g.N_t, iB, wB);
             memset(rb, 0, sizeof(double) * (size_t)(n + 1));
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 4; ++a)
                 if (iB[a] >= 0) rb[iB[a]] += wB[a] / g.h_t;
             status = band_solve(&M, perm, rb, gb, &flops, &flops_nf);
             if (!status) {
-                double c = g.k * FB * interp_apply(iB, wB, gb) / 2.0;
-                double b = (interp_apply(iB, wB, w2) - interp_apply(iB, wB, w0)) / (2.0 * g.k) - vB;
+                double c = g.k * FB * interp_apply4(iB, wB, gb) / 2.0;
+                double b = (interp_apply4(iB, wB, w2) - interp_apply4(iB, wB, w0)) / (2.0 * g.k) - vB;
                 double vrel;
                 double phi = orc_bow_solve(b, c, bw.a, bw.eps, &vrel);
                 for (int i = 0; i < n; ++i) w2[i] -= g.k * g.k * FB * phi * gb[i];

@@ -41,11 +41,12 @@ typedef struct {
     double mod_depth_cents, mod_rate_hz, glide_semitones;
     int32_t grid_l;       /* 0: N_l from h_l >= gamma alpha k; else forced N_l */
     int32_t boundary;     /* transverse ends: 0 simply supported, 1 clamped (Sec. 4.1, eq. 10) */
+    int32_t grid_interp;  /* order p of I_(l)->(t) (Sec. 3.1's p-th order interpolant): 0 or 1 linear, 3 cubic */
 } orc_string;
 
 typedef struct {
     int32_t type;         /* 0 none, 1 pluck (initial condition), 2 hammer (eq. 6), 3 bow (eq. 5) */
-    int32_t interp_order; /* hammer's I_p: 0 or 1 linear, 3 cubic (Sec. 3.3's p-th order interpolant) */
+    int32_t interp_order; /* I_p of the hammer or the bow: 0 or 1 linear, 3 cubic (Sec. 3.3's p-th order interpolant) */
     double x;             /* excitation position in (0,1); the bow's position at t = 0 */
     double c0;            /* pluck peak displacement [m] */
     double v_H;           /* hammer initial velocity [m/s] */
@@ -107,6 +108,10 @@ int orc_run_schedule(const orc_string *s, const orc_excitation *e, int n_re, con
 int orc_dump_system(const orc_string *s, const orc_excitation *e, int64_t n,
                     const double *w_n, const double *w_nm1, double uH_n, double uH_nm1,
                     double *A, double *Bm, double *C, double *rhs);
+
+/* For tests: pt[0..N_t) = I_(l)->(t) p[0..N_l) (Sec. 3.1's p-th order
+ * interpolant, order 1 or 3, the same operator the scheme assembles). */
+int orc_apply_I_lt(int Nt, int Nl, int order, const double *p, double *pt);
 
 /* gamma^n = 2 f0(n k) under the modulation of the string (Sec. 1 abstract). */
 double orc_gamma_at(const orc_string *s, int64_t n);

@@ -33,6 +33,43 @@ def interp_matrix(x_src, x_dst):
     return M
 
 
+_CUBIC_HALVES = {}
+
+
+def interp_matrix_cubic_halves(Nl, x_dst):
+    key = (Nl, tuple(np.round(np.asarray(x_dst, dtype=np.float64), 15)))
+    if key not in _CUBIC_HALVES:
+        _CUBIC_HALVES[key] = _interp_matrix_cubic_halves(Nl, x_dst)
+    return _CUBIC_HALVES[key]
+
+
+def _interp_matrix_cubic_halves(Nl, x_dst):
+    """Cubic interpolation from the longitudinal half points (j - 1/2)/Nl,
+    j = 1..Nl, to the positions x_dst: for each unit vector, the cubic through
+    the four half points around x, those past an end taking the value of their
+    mirror image about that end (p_0 = p_1, p_{-1} = p_2, p_{Nl+1} = p_{Nl},
+    ...), fitted with numpy and evaluated."""
+    h = 1.0 / Nl
+    M = np.zeros((len(x_dst), Nl))
+
+    def fold(j):
+        if j < 1:
+            return 1 - j
+        if j > Nl:
+            return 2 * Nl + 1 - j
+        return j
+
+    for col in range(Nl):
+        e = np.zeros(Nl)
+        e[col] = 1.0
+        for r, x in enumerate(x_dst):
+            j0 = int(np.floor(x / h + 0.5))
+            js = np.arange(j0 - 1, j0 + 3)
+            coef = np.polyfit((js - 0.5) * h, [e[fold(j) - 1] for j in js], 3)
+            M[r, col] = np.polyval(coef, x)
+    return M
+
+
 def point_row_cubic(x, N, s):
     """Row of the cubic interpolant at x: for each interior node's unit vector,
     the cubic through the four nodes around x (ghost nodes u_{-1} = s u_1,
@@ -41,7 +78,10 @@ def point_row_cubic(x, N, s):
     l = int(np.floor(x * N))
     m = np.arange(l - 1, l + 3)
     row = np.zeros(N - 1)
-    for j in range(N - 1):
+    # only the nodes of the four-point stencil and the two next to the ends
+    # (the ghosts' mirrors) can get a weight; every other column fits zeros
+    cand = sorted({j for j in range(l - 2, l + 2) if 0 <= j < N - 1} | {0, N - 2})
+    for j in cand:
         ext = np.zeros(N + 3)               # nodes -1 .. N+1
         ext[j + 2] = 1.0
         ext[0] = s * ext[2]
@@ -106,7 +146,10 @@ class Dense:
             self.Dxx_l = self.Dp_l @ self.Dm_l
             xt = (np.arange(1, Nt + 1) - 0.5) * ht
             xl = (np.arange(1, Nl + 1) - 0.5) * hl
-            self.I_lt = interp_matrix(xl, xt)
+            if p.get("grid_interp", 0) == 3:
+                self.I_lt = interp_matrix_cubic_halves(Nl, xt)
+            else:
+                self.I_lt = interp_matrix(xl, xt)
             self.I_tl = (ht / hl) * self.I_lt.T
 
     def blocks(self, u_n, gamma):
@@ -230,7 +273,11 @@ def energy(p, g, u1, u0, z1, z0, gamma):
         p1, p0 = half_diff(z1, hl), half_diff(z0, hl)
         xt = (np.arange(1, Nt + 1) - 0.5) * ht
         xl = (np.arange(1, Nl + 1) - 0.5) * hl
-        pt1, pt0 = np.interp(xt, xl, p1), np.interp(xt, xl, p0)
+        if p.get("grid_interp", 0) == 3:
+            I = interp_matrix_cubic_halves(Nl, xt)
+            pt1, pt0 = I @ p1, I @ p0
+        else:
+            pt1, pt0 = np.interp(xt, xl, p1), np.interp(xt, xl, p0)
         qq = q1 * q0
         H += hl / (2 * k * k) * np.dot(z1 - z0, z1 - z0) + gamma ** 2 * a2 * hl / 2 * np.dot(p1, p0) \
             + gamma ** 2 * (a2 - 1) / 2 * ht * np.sum(qq * qq / 4 + qq * (pt1 + pt0) / 2)

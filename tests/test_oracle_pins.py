@@ -845,3 +845,109 @@ def test_ph2_cubic_hammer_dense_brute_force(boundary, x):
     lin = oracle.run(p, dict(e, interp_order=1), want=("traj_u",))["traj_u"]
     assert np.max(np.abs(lin - U)) > 1e-6 * scale
 
+
+
+# ---------------------------------------------------------------------------
+# Cubic (p = 3) interpolants: the grid interpolant I_(l)->(t) of Sec. 3.1
+# with its adjoint, and the bow's I_p / J_p of Sec. 3.3.1 (reading R22)
+# ---------------------------------------------------------------------------
+
+def test_pi1_cubic_grid_interpolant_is_exact_on_cubics():
+    """I_(l)->(t) of order 3 reproduces cubic polynomials at every t-half
+    point whose four l-half points lie inside the string, even polynomials
+    about an end up to that end (the mirrored half points are those of an
+    even function), and sums each row to 1; order 1 reproduces lines."""
+    Nt, Nl = 37, 23
+    xt = (np.arange(1, Nt + 1) - 0.5) / Nt
+    xl = (np.arange(1, Nl + 1) - 0.5) / Nl
+    inner = (xt > 1.5 / Nl) & (xt < 1.0 - 1.5 / Nl)
+    for c in ([1.0, 0, 0, 0], [0.2, 1.0, 0, 0], [0.3, -0.2, 0.5, 0.1], [0, 0, 0, 1.0]):
+        f = lambda x: c[0] + c[1] * x + c[2] * x ** 2 + c[3] * x ** 3
+        pt = oracle.apply_I_lt(Nt, Nl, 3, f(xl))
+        assert np.max(np.abs(pt[inner] - f(xt[inner]))) < 1e-13
+    # even about x = 0 (left end) and about x = 1 (right end)
+    left, right = xt < 0.5, xt > 0.5
+    pt = oracle.apply_I_lt(Nt, Nl, 3, 0.4 - 2.0 * xl ** 2)
+    assert np.max(np.abs(pt[left] - (0.4 - 2.0 * xt[left] ** 2))) < 1e-13
+    pt = oracle.apply_I_lt(Nt, Nl, 3, 0.1 + 3.0 * (1 - xl) ** 2)
+    assert np.max(np.abs(pt[right] - (0.1 + 3.0 * (1 - xt[right]) ** 2))) < 1e-13
+    assert np.max(np.abs(oracle.apply_I_lt(Nt, Nl, 3, np.ones(Nl)) - 1.0)) < 1e-14
+    lin = oracle.apply_I_lt(Nt, Nl, 1, 0.5 + xl)
+    mid = (xt > 0.5 / Nl) & (xt < 1.0 - 0.5 / Nl)
+    assert np.max(np.abs(lin[mid] - (0.5 + xt[mid]))) < 1e-14
+    # the cubic differs from the linear one where the data curve
+    assert np.max(np.abs(oracle.apply_I_lt(Nt, Nl, 3, xl ** 3) - oracle.apply_I_lt(Nt, Nl, 1, xl ** 3))) > 1e-5
+
+
+@pytest.mark.parametrize("exc", ["pluck", "hammer"])
+def test_pi2_cubic_grid_interpolant_dense_brute_force(exc):
+    """The coupled system with the cubic I_(l)->(t) and its adjoint against
+    the dense numpy assembly, whose cubic interpolant is fitted with
+    numpy.polyfit through the mirrored half points."""
+    p = dict(_tiny(), grid_interp=3)
+    g = oracle.grid(p)
+    e = W.pluck(0.3, 0.02) if exc == "pluck" else W.hammer(0.3, 30.0, rhoA=0.002)
+    r = oracle.run(p, e, want=("traj_u", "traj_z", "u_H"))
+    U, Z, UH = DR.run_dense(p, e, g, p["n_samples"])
+    scale = np.max(np.abs(U))
+    assert np.max(np.abs(r["traj_u"] - U)) < 1e-12 * scale
+    assert np.max(np.abs(r["traj_z"] - Z)) < 1e-12 * scale
+    lin = oracle.run(dict(p, grid_interp=0), e, want=("traj_z",))["traj_z"]
+    assert np.max(np.abs(lin - Z)) > 1e-6 * np.max(np.abs(Z))
+
+
+def test_pi3_cubic_grid_interpolant_keeps_w_a_symmetric_definite():
+    p = W.string(300.0, 1e-3, 3.5, 1.0, 3e-4, 10, grid_t=23, grid_l=17, )
+    p = dict(p, grid_interp=3)
+    g = oracle.grid(p)
+    rng = np.random.default_rng(5)
+    nt, nl = g["N_t"] - 1, g["N_l"] - 1
+    x = np.arange(1, g["N_t"]) / g["N_t"]
+    u = 0.05 * np.sin(np.pi * x) + 0.01 * rng.standard_normal(nt)
+    z = 0.01 * rng.standard_normal(nl)
+    w = np.concatenate([u, z])
+    A = oracle.dump_system(p, None, 1, w, w)["A"]
+    Wt = np.diag(np.concatenate([np.full(nt, g["h_t"]), np.full(nl, g["h_l"])]))
+    WA = Wt @ A
+    assert np.max(np.abs(WA - WA.T)) <= 1e-15 * np.max(np.abs(WA))
+    assert np.linalg.eigvalsh(0.5 * (WA + WA.T)).min() > 0
+
+
+@pytest.mark.parametrize("alpha", [2.0, 3.5])
+def test_pi4_cubic_grid_interpolant_conserves_energy(alpha):
+    """Lossless nonlinear pluck with the cubic I_(l)->(t): the discrete energy
+    (its nonlinear term built from the same cubic interpolant) is conserved."""
+    p = dict(W.string(300.0, 1e-3, alpha, 0.0, 0.0, 1500), grid_interp=3)
+    e = W.pluck(0.14, 0.02)
+    res = oracle.run(p, e, want=("traj_u", "traj_z", "energy"))
+    g = res["grid"]
+    H = np.array([DR.energy(p, g, res["traj_u"][n + 1], res["traj_u"][n],
+                            res["traj_z"][n + 1], res["traj_z"][n], 2 * p["f0"])
+                  for n in range(p["n_samples"] - 1)])
+    assert np.max(np.abs(H - H[0])) / abs(H[0]) < 1e-12
+    assert np.allclose(res["energy"][:-1], H, rtol=1e-11, atol=0)
+    assert np.max(np.abs(res["traj_z"])) > 1e-3 * np.max(np.abs(res["traj_u"]))
+
+
+@pytest.mark.parametrize("boundary", [0, 1])
+def test_pb5_cubic_bow_energy_balance(boundary):
+    """The bow with the cubic I_p (four nodes, mirrored ghosts near an end)
+    and J_p = I_p^T / h: on a lossless string the energy changes exactly by
+    the friction work, with I_p the dense reference's own cubic row."""
+    p = dict(W.string(110.0, 1e-4, 2.0, 0.0, 0.0, 4800), boundary=boundary)
+    e = dict(W.bow(0.02, 0.1, 100.0, x_end=0.14), interp_order=3)
+    r = oracle.run(p, e, want=("traj_u", "energy", "bow_phi"))
+    g = r["grid"]
+    k, N = g["k"], g["N_t"]
+    U, H, phi = r["traj_u"], r["energy"], r["bow_phi"]
+    s = 1.0 if boundary == 1 else -1.0
+    worst = 0.0
+    for n in range(1, len(H) - 1):
+        xB, _, FB = _bow_controls(e, p, n * k)
+        row = DR.point_row_cubic(xB, N, s)
+        work = k * FB * phi[n] * (row @ (U[n + 1] - U[n - 1])) / (2 * k)
+        worst = max(worst, abs((H[n] - H[n - 1]) + work))
+    assert np.max(np.abs(H)) > 1e-4
+    assert worst <= 1e-12 * np.max(np.abs(H))
+    lin = oracle.run(p, dict(e, interp_order=1), want=("traj_u",))["traj_u"]
+    assert np.max(np.abs(lin - U)) > 1e-6 * np.max(np.abs(U))
