@@ -309,10 +309,16 @@ int string_batch_info(sb_batch *b, int idx, sb_string_info *info);
 int string_batch_set_monitor(sb_batch *b, int period, double growth_tol);
 
 /* Coupled-solve controls of the batched paths (block Gauss-Seidel between
- * the transverse and longitudinal grids, eq. (8)): a string's step has
- * converged when no node's acceleration changed by more than tol times the
- * string's largest acceleration after the first sweep (default 1e-13 FP64,
- * 1e-5 FP32C: below the FP32 rounding of the accumulated state); max_sweeps caps the sweeps per step (default 64; a step that
+ * the transverse and longitudinal grids, eq. (8)).  A string's step has
+ * converged when the estimated error of its accelerations -- the largest
+ * update of the last sweep times that sweep's contraction, the ratio of the
+ * last two sweeps' largest updates -- or the update itself is below tol
+ * times the string's largest acceleration after the first sweep (default
+ * 1e-13 FP64, 1e-7 FP32C: the FP32 rounding of the acceleration).  Strings
+ * in the kernels that carry bows, clamped ends or the zeta channel stop on
+ * the update alone, below tol (FP64) or 100 tol (FP32C) times that value
+ * (the stick/slip decision of a chaotic bowed string amplifies the solve's
+ * error).  max_sweeps caps the sweeps per step (default 64; a step that
  * reaches it flags the string with 2). */
 int string_batch_set_solver(sb_batch *b, double tol, int max_sweeps);
 

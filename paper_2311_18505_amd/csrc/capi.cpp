@@ -203,7 +203,7 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
   b->esz = precision == SB_FP32C ? 4 : 8;
   b->stream = (hipStream_t)hip_stream;
   b->mon_tol = precision == SB_FP32C ? 1e-4 : 1e-9;
-  b->tol = precision == SB_FP32C ? 1e-5 : 1e-13;
+  b->tol = precision == SB_FP32C ? 1e-7 : 1e-13;
   b->slots.resize(capacity);
   int dev = 0;
   hipDeviceProp_t prop;
