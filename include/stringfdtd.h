@@ -94,7 +94,7 @@ typedef struct {
     int32_t grid_l;            /* 0 or a forced N_l                               */
     int32_t boundary;          /* SB_BOUNDARY_*: transverse end condition         */
     int32_t readout_zeta;      /* 1: also record zeta at x_out (second channel)   */
-    int32_t reserved;
+    int32_t grid_interp;       /* order p of I_(l)->(t): 0 or 1 linear, 3 cubic   */
 } sb_string_params;
 
 /* Excitation (Sec. 3.3).  Pluck: initial triangle of peak c0 at x, released

@@ -35,7 +35,7 @@ class SbStringParams(C.Structure):
         ("n_samples", C.c_int64), ("mod_type", C.c_int32), ("grid_t", C.c_int32),
         ("mod_depth_cents", C.c_double), ("mod_rate_hz", C.c_double), ("glide_semitones", C.c_double),
         ("grid_l", C.c_int32), ("boundary", C.c_int32),
-        ("readout_zeta", C.c_int32), ("reserved", C.c_int32),
+        ("readout_zeta", C.c_int32), ("grid_interp", C.c_int32),
     ]
 
 

@@ -13,7 +13,9 @@ namespace sfd {
 constexpr int kBowX0 = 0, kBowX1 = 1, kBowT = 2, kBowVB = 3, kBowFB = 4, kBowTa = 5, kBowA = 6, kBowEps = 7;
 constexpr int kBowStepVB = 8, kBowStepK2F = 9, kBowStepIv = 10, kBowStepW0 = 11, kBowStepW1 = 12, kBowStepN0 = 13,
               kBowStepN1 = 14, kBowT0 = 15;
-constexpr int kBowRec = 16;
+// the cubic I_p's two further nodes and weights (zero for the linear one)
+constexpr int kBowStepW2 = 16, kBowStepW3 = 17, kBowStepN2 = 18, kBowStepN3 = 19;
+constexpr int kBowRec = 20;
 
 // Bow of eq. (5).  Controls at time t from the record: kBowX0 the start
 // position, kBowX1 its rate of change (zero when it stays) until kBowT

@@ -331,10 +331,11 @@ static size_t region_size(const sb_batch *b, const Desc &D, size_t *off_st0, siz
     return 2 * st + tf + ou + tb;
   }
   const size_t G = (size_t)kClassLanes[D.cls];
+  const bool cubic = D.grid_interp == 3;   // three more weights per t-slot, two more ranges per l-slot
   const size_t st = align256(b->esz * G * 4 * (D.mt + D.ml));
-  const size_t tf = align256(b->esz * G * (3 * D.mt + D.ml));
+  const size_t tf = align256(b->esz * G * (3 * D.mt + D.ml + (cubic ? 3 * D.mt : 0)));
   const size_t ou = align256(b->esz * (size_t)(D.n_samples + kWave));
-  const size_t tb = align256(sizeof(uint32_t) * G * (D.mt + 2 * D.ml));
+  const size_t tb = align256(sizeof(uint32_t) * G * (D.mt + 2 * D.ml + (cubic ? 2 * D.ml : 0)));
   *off_st0 = st;
   *off_tabf = 2 * st;
   *off_out = 2 * st + tf;
@@ -578,7 +579,7 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
     // the instantiation that carries their code
     const Desc &d = s.plan.desc;
     const bool cubic_hammer = d.ham_on && (d.hn2 || d.hn3);
-    cls[(d.bow_on || d.clamped || d.zeta_out || cubic_hammer) ? 1 : 0][c].push_back({cost, i});
+    cls[(d.bow_on || d.clamped || d.zeta_out || cubic_hammer || d.grid_interp == 3) ? 1 : 0][c].push_back({cost, i});
   }
   if (!any) return fail(b, SB_ESTATE, "no excited slot");
   std::vector<int32_t> work;

@@ -2,6 +2,7 @@
 // tables for the GPU stepping kernel (FP64 on the host, rounded once to the
 // kernel precision on upload).
 #include "planner.h"
+#include "interp.h"
 
 #include <algorithm>
 #include <cmath>
@@ -81,6 +82,10 @@ int plan_grid(const sb_string_params &p, GridPlan &g, std::string &err) {
     err = "boundary must be SB_BOUNDARY_SIMPLE or SB_BOUNDARY_CLAMPED";
     return SB_EINVAL;
   }
+  if (p.grid_interp != 0 && p.grid_interp != 1 && p.grid_interp != 3) {
+    err = "grid_interp must be 0, 1 or 3";
+    return SB_EINVAL;
+  }
   const double k = 1.0 / p.fs;
   const double gamma0 = 2.0 * p.f0;                      // Sec. 4.1: f0 = gamma/2
   const double kappa = gamma0 * std::sqrt(p.B) / M_PI;    // Sec. 4.1: K = (pi kappa/gamma)^2, K := B
@@ -105,6 +110,10 @@ int plan_grid(const sb_string_params &p, GridPlan &g, std::string &err) {
   if (p.alpha != 1.0) Nl = p.grid_l > 0 ? p.grid_l : (int)std::floor(1.0 / (gmax * p.alpha * k));
   if (Nt < 2 || (p.alpha != 1.0 && Nl < 2)) {
     err = "grid has fewer than 2 intervals";
+    return SB_EINVAL;
+  }
+  if (p.grid_interp == 3 && Nl > 0 && Nl < 4) {
+    err = "the cubic grid interpolant needs N_l >= 4";
     return SB_EINVAL;
   }
   g.Nt = Nt;
@@ -239,20 +248,31 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
   }
   point_interp(p.x_out, Nt, D.on0, D.on1, D.ow0, D.ow1);
 
-  // tables, lane-major [slot][lane]
+  // tables, lane-major [slot][lane]; the cubic grid interpolant (p = 3)
+  // appends two more range tables and three more weights per t-slot
+  const bool cubic = p.grid_interp == 3 && Nl > 0;
+  D.grid_interp = cubic ? 3 : 1;
   const int mt = D.mt, ml = D.ml;
-  P.tab.assign((size_t)G * (mt + 2 * ml), 0u);
-  P.tabf.assign((size_t)G * (3 * mt + ml), 0.0);
+  P.tab.assign((size_t)G * (mt + 2 * ml + (cubic ? 2 * ml : 0)), 0u);
+  P.tabf.assign((size_t)G * (3 * mt + ml + (cubic ? 3 * mt : 0)), 0.0);
   uint32_t *jab = P.tab.data();
   uint32_t *rga = jab + (size_t)G * mt;
   uint32_t *rgb = rga + (size_t)G * ml;
+  uint32_t *rgc = rgb + (size_t)G * ml;   // cubic only
+  uint32_t *rgd = rgc + (size_t)G * ml;
   double *wi = P.tabf.data();
   double *wbu = wi + (size_t)G * mt;
   double *wbz = wbu + (size_t)G * mt;
   double *sm = wbz + (size_t)G * ml;
+  double *wc = sm + (size_t)G * mt;       // cubic only: weights 1..3 of each t-half point
   P.ja.assign(Nt + 1, 1);
   P.jb.assign(Nt + 1, 1);
   P.w.assign(Nt + 1, 0.0);
+  // cubic: base l-half point b of each t-half point (its four taps sit at
+  // b .. b+3) and their weights, half points past an end folded onto their
+  // mirror images (p_0 = p_1, p_{-1} = p_2, ...), as the scheme reads it
+  std::vector<int> base(Nt + 1, 1);
+  std::vector<double> cw((size_t)4 * (Nt + 1), 0.0);
   for (int lane = 0; lane < G; ++lane)
     for (int r = 0; r < mt; ++r) {
       const int i = lane * mt + r + 1;   // half point i / node i
@@ -269,66 +289,73 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
         P.ja[i] = (int)a;
         P.jb[i] = (int)b;
         P.w[i] = w;
+        if (cubic) {
+          const double t = w;
+          const double lw[4] = {-t * (t - 1.0) * (t - 2.0) / 6.0, (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0,
+                                -(t + 1.0) * t * (t - 2.0) / 2.0, (t + 1.0) * t * (t - 1.0) / 6.0};
+          const int bb = std::min(std::max(j0 - 1, 1), Nl - 3);
+          base[i] = bb;
+          for (int k = 0; k < 4; ++k) {
+            int j = j0 - 1 + k;
+            if (j < 1) j = 1 - j;
+            if (j > Nl) j = 2 * Nl + 1 - j;
+            cw[(size_t)4 * i + (j - bb)] += lw[k];
+          }
+        }
       }
-      jab[(size_t)r * G + lane] = a | (b << 16);
-      wi[(size_t)r * G + lane] = w;
+      if (cubic) {
+        jab[(size_t)r * G + lane] = (uint32_t)base[std::min(i, Nt)] | ((uint32_t)base[std::min(i, Nt)] << 16);
+        wi[(size_t)r * G + lane] = i <= Nt ? cw[(size_t)4 * i] : 0.0;
+        for (int k = 1; k < 4; ++k) wc[(size_t)(k - 1) * G * mt + (size_t)r * G + lane] = i <= Nt ? cw[(size_t)4 * i + k] : 0.0;
+      } else {
+        jab[(size_t)r * G + lane] = a | (b << 16);
+        wi[(size_t)r * G + lane] = w;
+      }
       if (i <= Nt - 1) wbu[(size_t)r * G + lane] = wbt[i];
     }
   if (Nl > 0) {
-    // ranges of t-half points whose first (second) tap lands on l-half j
-    std::vector<int> sa(Nl + 2, 0), na(Nl + 2, 0), sb(Nl + 2, 0), nb(Nl + 2, 0);
+    // ranges of t-half points whose taps land on l-half j: linear, first
+    // (second) tap; cubic, tap k of the t-half points with base j - k
+    std::vector<int> s0(Nl + 2, 0), n0(Nl + 2, 0), s1(Nl + 2, 0), n1(Nl + 2, 0);
+    std::vector<int> sbase(Nl + 2, 0), nbase(Nl + 2, 0);
     for (int i = Nt; i >= 1; --i) {
-      sa[P.ja[i]] = i - 1;
-      na[P.ja[i]]++;
-      sb[P.jb[i]] = i - 1;
-      nb[P.jb[i]]++;
+      s0[P.ja[i]] = i - 1;
+      n0[P.ja[i]]++;
+      s1[P.jb[i]] = i - 1;
+      n1[P.jb[i]]++;
+      sbase[base[i]] = i - 1;
+      nbase[base[i]]++;
     }
+    auto packed = [&](int j, int k) -> uint32_t {   // cubic: t-half points with base j - k
+      const int b = j - k;
+      return (b >= 1 && b <= Nl) ? ((uint32_t)sbase[b] | ((uint32_t)nbase[b] << 16)) : 0u;
+    };
     D.gmax = 0;
-    for (int j = 1; j <= Nl; ++j) D.gmax = std::max(D.gmax, std::max(na[j], nb[j]));
+    for (int j = 1; j <= Nl; ++j) {
+      if (cubic)
+        for (int k = 0; k < 4; ++k) D.gmax = std::max(D.gmax, (int)(packed(j, k) >> 16));
+      else
+        D.gmax = std::max(D.gmax, std::max(n0[j], n1[j]));
+    }
     for (int lane = 0; lane < G; ++lane)
       for (int r = 0; r < ml; ++r) {
         const int j = lane * ml + r + 1;
         if (j <= Nl) {
-          rga[(size_t)r * G + lane] = (uint32_t)sa[j] | ((uint32_t)na[j] << 16);
-          rgb[(size_t)r * G + lane] = (uint32_t)sb[j] | ((uint32_t)nb[j] << 16);
+          if (cubic) {
+            rga[(size_t)r * G + lane] = packed(j, 0);
+            rgb[(size_t)r * G + lane] = packed(j, 1);
+            rgc[(size_t)r * G + lane] = packed(j, 2);
+            rgd[(size_t)r * G + lane] = packed(j, 3);
+          } else {
+            rga[(size_t)r * G + lane] = (uint32_t)s0[j] | ((uint32_t)n0[j] << 16);
+            rgb[(size_t)r * G + lane] = (uint32_t)s1[j] | ((uint32_t)n1[j] << 16);
+          }
         }
         if (j <= Nl - 1) wbz[(size_t)r * G + lane] = wbl[j];
       }
   }
   (void)sm;
   return SB_OK;
-}
-
-// Cubic Lagrange interpolant at x (Sec. 3.3 with p = 3) on the nodes l-1 ..
-// l+2 around x = (l + a) h, as up to four distinct interior nodes (1-based,
-// 0 = absent) and weights: end nodes are fixed, a node past an end stands
-// for its mirror image with sign s (-1 simply supported, +1 clamped).
-static void cubic_interp(double x, int N, double s, int n[4], double w[4]) {
-  const int l = (int)std::floor(x * N);
-  const double a = x * N - l;
-  const double lw[4] = {-a * (a - 1.0) * (a - 2.0) / 6.0, (a + 1.0) * (a - 1.0) * (a - 2.0) / 2.0,
-                        -(a + 1.0) * a * (a - 2.0) / 2.0, (a + 1.0) * a * (a - 1.0) / 6.0};
-  for (int k = 0; k < 4; ++k) {
-    n[k] = 0;
-    w[k] = 0.0;
-  }
-  int used = 0;
-  for (int k = 0; k < 4; ++k) {
-    int m = l - 1 + k;
-    double c = lw[k];
-    if (m == -1) {
-      m = 1;
-      c *= s;
-    } else if (m == N + 1) {
-      m = N - 1;
-      c *= s;
-    }
-    if (m < 1 || m > N - 1) continue;
-    int j = 0;
-    while (j < used && n[j] != m) ++j;
-    if (j == used) n[used++] = m;
-    w[j] += c;
-  }
 }
 
 int plan_excitation(const sb_excitation &e, Plan &P, std::string &err) {
@@ -362,6 +389,7 @@ int plan_excitation(const sb_excitation &e, Plan &P, std::string &err) {
   const int Nt = D.Nt, mt = D.mt, ml = D.ml, nt = D.nt;
   const int G = kClassLanes[D.cls];
   D.bow_on = e.type == 3;
+  D.bow_cubic = e.type == 3 && e.interp_order == 3;
   D.bx0 = D.bx1 = D.bT = D.bvB = D.bFB = D.bta = D.ba = D.beps = D.bt0 = 0.0;
   if (e.type == 3) {
     D.bx0 = e.x;
@@ -460,6 +488,14 @@ int plan_plain(Plan &P, std::string &err) {
   const bool ham = D.ham_on != 0;
   if (ham && (D.hn2 || D.hn3)) {
     err = "the plain path takes the hammer's linear interpolant only";
+    return SB_EINVAL;
+  }
+  if (D.bow_cubic) {
+    err = "the plain path takes the bow's linear interpolant only";
+    return SB_EINVAL;
+  }
+  if (D.grid_interp == 3) {
+    err = "the plain path takes the linear grid interpolant only";
     return SB_EINVAL;
   }
   struct Item {

@@ -71,6 +71,8 @@ struct Desc {
   // sign(v) (beps + (1-beps) e^{-ba|v|})
   int32_t bow_on;             // 1 if the excitation is a bow
   int32_t zon0;               // zeta channel: first l-grid node of I(x_out) (0 = absent)
+  int32_t bow_cubic;          // 1: the bow's I_p is the cubic interpolant (four nodes)
+  int32_t grid_interp;        // order of I_(l)->(t): 1 linear, 3 cubic (extra tables, see the planner)
   union {
     struct {
       double bx0, bx1, bT, bvB, bFB, bta, ba, beps, bt0;

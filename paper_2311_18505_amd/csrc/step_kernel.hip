@@ -24,6 +24,7 @@
 
 #include "sfd_types.h"
 #include "bow.h"
+#include "interp.h"
 
 namespace sfd {
 
@@ -344,12 +345,17 @@ __device__ __forceinline__ double to_d(T hi, T c) {
 // t-half contribution arrays of I_(t)->(l), each MM*G values plus one trash
 // entry per lane (writes a lane must not make go there, without bank
 // conflicts).
-template <int G, int MM>
+template <int G, int MM, int NARR = 3>
 struct Lds {
   static constexpr int kArr = MM * G + G;
   static constexpr int kTrash = MM * G;   // + lane in group
-  static constexpr int kStride = 3 * kArr;
+  static constexpr int kStride = NARR * kArr;
 };
+
+// Arrays per group: p and two tap arrays; the instantiation that carries the
+// bow also holds the cubic grid interpolant's two further tap arrays.
+template <bool BOW>
+constexpr int kLdsArrays = BOW ? 5 : 3;
 
 // MM per-lane values of a group: in registers, or (largest class) in LDS at
 // [r G] from the lane's entry, read where they are used.  With 16 slots per
@@ -594,7 +600,23 @@ __device__ __forceinline__ double energy_fp64(const Desc &D, double g2k2, const 
     const double w = ld_if<double>(tf, r * G + li, on);
     const double pa1 = (Z1[ja] - Z1[ja - 1]) * Nld, pa0 = (Z0[ja] - Z0[ja - 1]) * Nld;
     const double pb1 = (Z1[jb] - Z1[jb - 1]) * Nld, pb0 = (Z0[jb] - Z0[jb - 1]) * Nld;
-    const double pt1 = (1.0 - w) * pa1 + w * pb1, pt0 = (1.0 - w) * pa0 + w * pb0;
+    double pt1 = (1.0 - w) * pa1 + w * pb1, pt0 = (1.0 - w) * pa0 + w * pb0;
+    if constexpr (CLAMP) {
+      // the cubic grid interpolant (same instantiation): taps ja .. ja+3
+      if (D.grid_interp == 3 && on) {
+        const T *tfc = tf + (3 * mt + ml) * G;
+        const double wc[4] = {w, (double)tfc[r * G + li], (double)tfc[(mt + r) * G + li],
+                              (double)tfc[(2 * mt + r) * G + li]};
+        double s1 = 0.0, s0 = 0.0;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          s1 += wc[x] * ((Z1[ja + x] - Z1[ja + x - 1]) * Nld);
+          s0 += wc[x] * ((Z0[ja + x] - Z0[ja + x - 1]) * Nld);
+        }
+        pt1 = s1;
+        pt0 = s0;
+      }
+    }
     const double qq = q1 * q0;
     nlt += on ? qq * qq / 4.0 + qq * (pt1 + pt0) / 2.0 : 0.0;
   }
@@ -732,6 +754,13 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     }
     gmax = __builtin_amdgcn_readfirstlane(gmax);
   }
+  // cubic grid interpolant (p = 3), only in the instantiation that carries the
+  // bow: a string's jab holds the base l-half point b of each t-half point
+  // (taps b .. b+3) and wi the first tap's weight; the other three weights and
+  // the ranges of taps 2 and 3 follow the linear tables and are read from
+  // memory where used
+  const bool cub = BOW && D.grid_interp == 3;
+  const bool any_cub = BOW && __ballot(cub) != 0;
   const double g2k2_0 = D.g2k2_0, a2m1_4 = D.a2m1_4, a2d = D.a2, Ntdd = D.Ntd, kk = D.k * D.k;
   const int mon_check = D.mon_check;
 
@@ -821,8 +850,61 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   // (n + 1) mod mon_period of the current step
   int mon_ctr = a.mon_period > 0 ? (int)(done % a.mon_period) : 1;
 
-  using L = Lds<G, MM>;
+  using L = Lds<G, MM, kLdsArrays<BOW>>;
   T *gP = sS + gi * L::kStride, *gA = gP + L::kArr, *gB = gA + L::kArr;
+  T *gC = BOW ? gB + L::kArr : gB, *gD = BOW ? gC + L::kArr : gB;   // cubic taps 2 and 3
+  const T *tfc = tf + (3 * mt + ml) * G;          // cubic grid interpolant: weights 1..3 per t-slot
+  const uint32_t *tabc = tab + (mt + 2 * ml) * G; // and the ranges of taps 2 and 3 per l-slot
+  // weight k (1..3) of the cubic grid interpolant at t-slot r (0 elsewhere)
+  auto cw = [&](int k, int r) -> T { return ld_if<T>(tfc, ((k - 1) * mt + r) * G + li, cub && r < mt); };
+  // I_(l)->(t) at this lane's t-half point r of the group's l-half values sX
+  auto interp_lt = [&](const T *sX, int r) -> T {
+    const int ja = (int)(jab[r] & 0xffffu), jb = (int)(jab[r] >> 16);
+    const T w = wi[r];
+    T v = (T(1) - w) * sX[ja - 1] + w * sX[jb - 1];
+    if constexpr (BOW) {
+      if (any_cub) {
+        // taps b .. b+3 from the base b = ja; index ja + 2 stays inside the
+        // group's array for every group
+        const T vc = ((w * sX[ja - 1] + cw(1, r) * sX[ja]) + cw(2, r) * sX[ja + 1]) + cw(3, r) * sX[ja + 2];
+        v = cub ? vc : v;
+      }
+    }
+    return v;
+  };
+  // the tap contributions of x at this lane's t-half points (the
+  // instantiation that carries the bow sums them directly over the ranges)
+  auto tap_store = [&](const T (&x)[MM]) {
+#pragma unroll
+    for (int r = 0; r < MM; ++r) {
+      const T w = wi[r];
+      if (BOW && any_cub) {
+        gA[tb + r] = (cub ? w : T(1) - w) * x[r];
+        gB[tb + r] = (cub ? cw(1, r) : w) * x[r];
+        gC[tb + r] = cw(2, r) * x[r];
+        gD[tb + r] = cw(3, r) * x[r];
+      } else {
+        gA[tb + r] = (T(1) - w) * x[r];
+        gB[tb + r] = w * x[r];
+      }
+    }
+  };
+  // I_(t)->(l) up to h_t/h_l at this lane's l-half points, summed directly
+  auto tap_gather = [&](T (&g)[MM]) {
+    gather_lt<MM, T>(g, gA, gB, rga, rgb, gmax);
+    if (BOW && any_cub) {
+      uint32_t rc[MM], rd[MM];
+#pragma unroll
+      for (int r = 0; r < MM; ++r) {
+        rc[r] = ld_if<uint32_t>(tabc, r * G + li, cub && r < ml);
+        rd[r] = ld_if<uint32_t>(tabc, (ml + r) * G + li, cub && r < ml);
+      }
+      T g2[MM];
+      gather_lt<MM, T>(g2, gC, gD, rc, rd, gmax);
+#pragma unroll
+      for (int r = 0; r < MM; ++r) g[r] += g2[r];
+    }
+  };
   double *gE = sE + gi * EnergyLds<G, MM>::kStride;
 
   for (int64_t it = 0; it < wsteps; ++it) {
@@ -865,17 +947,14 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < MM; ++r) {
-      const int ja = (int)(jab[r] & 0xffffu), jb = (int)(jab[r] >> 16);
-      const T w = wi[r];
-      const T pt = (T(1) - w) * gP[ja - 1] + w * gP[jb - 1];
+      const T pt = interp_lt(gP, r);
       q2[r] = q[r] * q[r];
       f[r] = q[r] * (q2[r] + T(2) * pt);
-      if constexpr (BOW) {
-        gA[tb + r] = (T(1) - w) * q2[r];
-        gB[tb + r] = w * q2[r];
-      }
     }
-    if constexpr (!BOW) prefix_store<G, MM, T>(gA, gB, q2, wi, tb, li, L::kTrash);
+    if constexpr (BOW)
+      tap_store(q2);
+    else
+      prefix_store<G, MM, T>(gA, gB, q2, wi, tb, li, L::kTrash);
     __syncthreads();
 
     // ---- right-hand side, transverse ----
@@ -923,7 +1002,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     {
       T g[MM];
       if constexpr (BOW)
-        gather_lt<MM, T>(g, gA, gB, rga, rgb, gmax);
+        tap_gather(g);
       else
         prefix_gather<MM, T>(g, gA, gB, rga, rgb);
 #pragma unroll
@@ -971,19 +1050,40 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     if (any_bow) {
       double xB, vB, FB;
       bow_controls(bR, (double)n * D.k, xB, vB, FB);
-      int bn0, bn1;
-      double bw0, bw1;
+      // I_p(x_B): linear, or the cubic interpolant (four nodes, ghosts
+      // mirrored with the end condition's sign)
+      int bn0, bn1, bn2 = 0, bn3 = 0;
+      double bw0, bw1, bw2 = 0.0, bw3 = 0.0;
       bow_interp(xB, nt + 1, bn0, bn1, bw0, bw1);
+      if (__ballot(bowed && D.bow_cubic != 0) != 0) {
+        int cn[4];
+        double cwt[4];
+        cubic_interp(xB, nt + 1, D.clamped ? 1.0 : -1.0, cn, cwt);
+        const bool c3 = bowed && D.bow_cubic != 0;
+        bn0 = c3 ? cn[0] : bn0;
+        bn1 = c3 ? cn[1] : bn1;
+        bn2 = c3 ? cn[2] : 0;
+        bn3 = c3 ? cn[3] : 0;
+        bw0 = c3 ? cwt[0] : bw0;
+        bw1 = c3 ? cwt[1] : bw1;
+        bw2 = c3 ? cwt[2] : 0.0;
+        bw3 = c3 ? cwt[3] : 0.0;
+      }
       const double kk = D.k * D.k;
       bR[kBowStepVB] = vB;
       bR[kBowStepK2F] = kk * FB;
       if constexpr (kSide) {
         T cv[MM];
         side_load<G, MM, T>(cv, side, 1, li);
-        bR[kBowStepIv] = point_eval<G, T, MM>(vu, cv, bn0, bw0, bn1, bw1);
+        bR[kBowStepIv] = point_eval<G, T, MM>(vu, cv, bn0, bw0, bn1, bw1) + point_eval<G, T, MM>(vu, cv, bn2, bw2, bn3, bw3);
       } else {
-        bR[kBowStepIv] = point_eval<G, T, MM>(vu, cvu, bn0, bw0, bn1, bw1);
+        bR[kBowStepIv] =
+            point_eval<G, T, MM>(vu, cvu, bn0, bw0, bn1, bw1) + point_eval<G, T, MM>(vu, cvu, bn2, bw2, bn3, bw3);
       }
+      bR[kBowStepW2] = bw2;
+      bR[kBowStepW3] = bw3;
+      bR[kBowStepN2] = (double)bn2;
+      bR[kBowStepN3] = (double)bn3;
       bR[kBowStepW0] = bw0;
       bR[kBowStepW1] = bw1;
       bR[kBowStepN0] = (double)bn0;
@@ -1038,9 +1138,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
           for (int r = 0; r < MM; ++r) {
             const T am = r == 0 ? al : au[r > 0 ? r - 1 : 0];
             const T d = (au[r] - am) * Ntd;
-            const int ja = (int)(jab[r] & 0xffffu), jb = (int)(jab[r] >> 16);
-            const T w = wi[r];
-            const T idz = (T(1) - w) * gP[ja - 1] + w * gP[jb - 1];
+            const T idz = interp_lt(gP, r);
             e[r] = q[r] * fma(q[r], d, idz);
           }
           __syncthreads();
@@ -1071,14 +1169,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
             fq[r] = q[r] * ((nu[r] - am) * Ntd);
           }
           if constexpr (BOW) {
-  #pragma unroll
-            for (int r = 0; r < MM; ++r) {
-              const T w = wi[r];
-              gA[tb + r] = (T(1) - w) * fq[r];
-              gB[tb + r] = w * fq[r];
-            }
+            tap_store(fq);
             __syncthreads();
-            gather_lt<MM, T>(gg, gA, gB, rga, rgb, gmax);
+            tap_gather(gg);
           } else {
             prefix_store<G, MM, T>(gA, gB, fq, wi, tb, li, L::kTrash);
             __syncthreads();
@@ -1159,18 +1252,23 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
         // v_rel = b - c phi with b = I_p(a_u + 2 v^{n-1/2}) / 2k - v_B and
         // c = k F_B I_p d_u / 2, and a -= k^2 F_B phi d
         const int bn0 = (int)bR[kBowStepN0], bn1 = (int)bR[kBowStepN1];
-        const double bw0 = bR[kBowStepW0], bw1 = bR[kBowStepW1];
+        const int bn2 = (int)bR[kBowStepN2], bn3 = (int)bR[kBowStepN3];
+        const double bw0 = bR[kBowStepW0], bw1 = bR[kBowStepW1], bw2 = bR[kBowStepW2], bw3 = bR[kBowStepW3];
         T fb[MM], du[MM], dz[MM];
 #pragma unroll
         for (int r = 0; r < MM; ++r) {
+          // J_p = I_p^T / h_t (a node listed once, cubic ghosts folded in by the weights)
           const int i = tb + r + 1;
-          fb[r] = (i == bn0 ? (T)(bw0 * (nt + 1)) : T(0)) + (i == bn1 ? (T)(bw1 * (nt + 1)) : T(0));
+          fb[r] = ((i == bn0 ? (T)(bw0 * (nt + 1)) : T(0)) + (i == bn1 ? (T)(bw1 * (nt + 1)) : T(0))) +
+                  ((i == bn2 ? (T)(bw2 * (nt + 1)) : T(0)) + (i == bn3 ? (T)(bw3 * (nt + 1)) : T(0)));
         }
         bool convd;
         sweeps += gs_solve(fb, zero, false, du, dz, convd);
         conv = conv && convd;
-        const double Ia = point_eval<G, T, MM>(au, zero, bn0, bw0, bn1, bw1);
-        const double Id = point_eval<G, T, MM>(du, zero, bn0, bw0, bn1, bw1);
+        const double Ia =
+            point_eval<G, T, MM>(au, zero, bn0, bw0, bn1, bw1) + point_eval<G, T, MM>(au, zero, bn2, bw2, bn3, bw3);
+        const double Id =
+            point_eval<G, T, MM>(du, zero, bn0, bw0, bn1, bw1) + point_eval<G, T, MM>(du, zero, bn2, bw2, bn3, bw3);
         const double bb = (Ia + 2.0 * bR[kBowStepIv]) / (2.0 * D.k) - bR[kBowStepVB];
         const double c = 0.5 * bR[kBowStepK2F] / D.k * Id;
         const double phi = bow_phi(bb, c, bR[kBowA], bR[kBowEps]);
@@ -1326,7 +1424,7 @@ template <int G, int MM, typename T, bool KAHAN, bool BOW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<MM, T>))) void step_kernel(
     LaunchArgs a) {
   constexpr int kGroups = kWave / G;
-  using L = Lds<G, MM>;
+  using L = Lds<G, MM, kLdsArrays<BOW>>;
   // the energy monitor's scratch overlays the stepping arrays (never live together)
   constexpr int kStepDoubles = (kGroups * L::kStride * (int)sizeof(T) + 7) / 8;
   constexpr int kEnergyDoubles = kGroups * EnergyLds<G, MM>::kStride;
@@ -1358,12 +1456,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
 // over their tasks in the order the host chose (estimated work, longest
 // first), so that the short tasks fill the tail.  They share the occupancy
 // target and need neither LDS tables nor LDS compensation.
-template <typename T>
+template <typename T, bool BOW>
 constexpr int small_lds_doubles() {
-  constexpr int a = (Lds<64, 4>::kStride * (int)sizeof(T) + 7) / 8, ae = EnergyLds<64, 4>::kStride;
-  constexpr int b = (2 * Lds<32, 4>::kStride * (int)sizeof(T) + 7) / 8, be = 2 * EnergyLds<32, 4>::kStride;
-  constexpr int c = (4 * Lds<16, 4>::kStride * (int)sizeof(T) + 7) / 8, ce = 4 * EnergyLds<16, 4>::kStride;
-  constexpr int d = (4 * Lds<16, 2>::kStride * (int)sizeof(T) + 7) / 8, de = 4 * EnergyLds<16, 2>::kStride;
+  constexpr int n = kLdsArrays<BOW>;
+  constexpr int a = (Lds<64, 4, n>::kStride * (int)sizeof(T) + 7) / 8, ae = EnergyLds<64, 4>::kStride;
+  constexpr int b = (2 * Lds<32, 4, n>::kStride * (int)sizeof(T) + 7) / 8, be = 2 * EnergyLds<32, 4>::kStride;
+  constexpr int c = (4 * Lds<16, 4, n>::kStride * (int)sizeof(T) + 7) / 8, ce = 4 * EnergyLds<16, 4>::kStride;
+  constexpr int d = (4 * Lds<16, 2, n>::kStride * (int)sizeof(T) + 7) / 8, de = 4 * EnergyLds<16, 2>::kStride;
   constexpr int m1 = a > ae ? a : ae, m2 = b > be ? b : be, m3 = c > ce ? c : ce, m4 = d > de ? d : de;
   constexpr int m12 = m1 > m2 ? m1 : m2, m34 = m3 > m4 ? m3 : m4;
   return m12 > m34 ? m12 : m34;
@@ -1374,7 +1473,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
     LaunchArgs a) {
   static_assert(kWavesPerEU<2, T> == kWavesPerEU<4, T>, "one occupancy target for the merged classes");
   static_assert(!kSideComp<4, T, KAHAN> && !kTabLds<4>, "no LDS tables in the merged classes");
-  __shared__ double lds[small_lds_doubles<T>()];
+  __shared__ double lds[small_lds_doubles<T, BOW>()];
   __shared__ double lds_bow[BOW ? 4 * kBowRec : 1];   // up to four groups per wavefront
   __shared__ T lds_w[2 * 4 * kWave];                    // per-slot weights of the point interpolants
   T *sS = (T *)lds;

@@ -9,7 +9,8 @@ it gives them.
 
 String dictionary keys: fs, f0, B, alpha, theta, sigma0_t, sigma1_t, sigma0_l,
 sigma1_l, x_out, n_samples, mod_type (0 none, 1 vibrato, 2 glide),
-mod_depth_cents, mod_rate_hz, glide_semitones, grid_t, grid_l.
+mod_depth_cents, mod_rate_hz, glide_semitones, grid_t, grid_l, grid_interp
+(order of the grid interpolant: 0 or 1 linear, 3 cubic).
 Excitation keys: type (0 none, 1 pluck, 2 hammer), x, c0, v_H, M_H, K_H,
 alpha_H, rhoA.
 """
@@ -29,8 +30,9 @@ HAMMER = dict(M_H=0.008, K_H=1e8, alpha_H=2.5, rhoA=0.05)
 
 def string(f0, B, alpha, sigma0, sigma1, n_samples, theta=0.0, fs=FS, x_out=X_OUT,
            mod_type=0, mod_depth_cents=0.0, mod_rate_hz=0.0, glide_semitones=0.0,
-           grid_t=0, grid_l=0, sigma0_l=None, sigma1_l=None) -> dict:
+           grid_t=0, grid_l=0, sigma0_l=None, sigma1_l=None, grid_interp=0) -> dict:
     return dict(fs=float(fs), f0=float(f0), B=float(B), alpha=float(alpha), theta=float(theta),
+                grid_interp=int(grid_interp),
                 sigma0_t=float(sigma0), sigma1_t=float(sigma1),
                 sigma0_l=float(sigma0 if sigma0_l is None else sigma0_l),
                 sigma1_l=float(sigma1 if sigma1_l is None else sigma1_l),

@@ -53,7 +53,7 @@ def test_planned_grids_match_oracle():
 @pytest.mark.parametrize("bad", [
     dict(f0=-1.0), dict(f0=float("nan")), dict(alpha=0.5), dict(theta=0.4), dict(B=-1e-4),
     dict(x_out=1.0), dict(n_samples=1), dict(sigma0_t=-1.0), dict(fs=0.0), dict(mod_type=3),
-    dict(boundary=2), dict(boundary=-1), dict(readout_zeta=2),
+    dict(boundary=2), dict(boundary=-1), dict(readout_zeta=2), dict(grid_interp=2), dict(grid_interp=3, grid_l=3),
 ])
 def test_plan_grid_rejects_invalid(bad):
     p, _ = W.single_nonlinear()
