@@ -42,9 +42,10 @@ PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 2.4 GHz x 25
 TRAFFIC = {"kernel": "step_kernel_small<float, true>", "source_sha256": "bc9d5ff483ce2a72",
            "fetch_bytes": 234.42e9, "write_bytes": 751.18e9}
 
-# the kernels of the three launches of a step (size classes 0..3 merged, 4, 5)
+# the kernels of the three launch units of a step (size classes 0..3 merged,
+# 4, then 5 and 6 on one stream)
 LAUNCH_KERNELS = ["step_kernel_small<float, true>", "step_kernel<64, 8, float, true>",
-                  "step_kernel<64, 16, float, true>"]
+                  "step_kernel<64, 10 and 16, float, true>"]
 
 WORKLOADS = {
     # 16384 nonlinear strings, durations U(0.5, 4) s, vibrato or glide, FP32
@@ -58,7 +59,7 @@ def unknowns(info):
     return (info["N_t"] - 1) + max(info["N_l"] - 1, 0)
 
 
-KERNEL_SOURCES = ("step_kernel.hip", "bow.h", "sfd_types.h")
+KERNEL_SOURCES = ("step_kernel.hip", "bow.h", "interp.h", "sfd_types.h")
 
 
 def kernel_source_hash() -> str:

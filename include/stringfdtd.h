@@ -205,12 +205,14 @@ int string_batch_rewind(sb_batch *b, int first, int count);
 int string_batch_graph_capture(sb_batch *b, int64_t steps_per_launch, int n_launches);
 int string_batch_graph_launch(sb_batch *b);
 
-/* A batched step runs as SB_NUM_LAUNCHES concurrent kernel launches, each on
- * its own stream, forked from and joined back to the batch stream:
+/* A batched step runs as SB_NUM_LAUNCHES concurrent units of kernel
+ * launches, each on its own stream, forked from and joined back to the batch
+ * stream:
  *   0: size classes 0..3 (up to 256 points), one persistent launch with one
- *      work queue, tasks of class 3 first and class 0 last;
+ *      work queue, the classes' tasks dealt out in proportion;
  *   1: size class 4 (up to 512 points);
- *   2: size class 5 (up to 1024 points). */
+ *   2: size classes 5 (up to 640 points) and 6 (up to 1024), one launch
+ *      after the other. */
 #define SB_NUM_LAUNCHES 3
 
 /* Durations of the launches of the last batched step (string_batch_step or a

@@ -15,9 +15,9 @@
 #include "sfd_types.h"
 
 namespace sfd {
-hipError_t launch_unit(int precision, int unit, bool bow, const LaunchArgs &a, int blocks, hipStream_t st);
+hipError_t launch_kernel(int precision, int kernel, bool bow, const LaunchArgs &a, int blocks, hipStream_t st);
 hipError_t launch_zero(int32_t *c, int n, hipStream_t st);
-int max_blocks_per_cu(int precision, int unit, bool bow);
+int max_blocks_per_cu(int precision, int kernel, bool bow);
 hipError_t launch_delay(uint64_t ticks, hipStream_t st);
 hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
                          hipStream_t st);
@@ -641,7 +641,8 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
 // forked onto their own streams and joined back.  Issues no synchronisation
 // and no copy, so it can be captured.
 static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t n_steps) {
-  hipError_t e = launch_zero(b->d_counters, 2 * kNumUnits, st);
+  static_assert(2 * kNumClasses <= 16, "queue heads of every class and variant");
+  hipError_t e = launch_zero(b->d_counters, 2 * kNumClasses, st);
   if (e == hipSuccess) e = hipEventRecord(b->ev_fork, st);
   if (e != hipSuccess) return hip_fail(b, e, "fork");
   // largest strings first: their launches hold the longest per-step latency
@@ -650,54 +651,57 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
     hipStream_t cs = b->unit_stream[u];
     b->unit_strings[u] = 0;
     bool forked = false;
-    // the bowed variant follows the other on the same stream
-    for (int v = 0; v < 2; ++v) {
-      LaunchArgs a;
-      a.desc = b->d_desc;
-      a.status = b->d_status;
-      int lo, hi;
-      if (u == 0) {
-        for (int c = 0; c < kNumSmall; ++c) a.part_work[c] = b->d_work + wp.off[v][c];
-        a.tickets = b->d_work + wp.tickets_off[v];
-        a.work = b->d_work + wp.off[v][0];
-        a.n_work = wp.n_tickets[v];
-        lo = wp.off[v][0];
-        hi = wp.off[v][kNumSmall];
-      } else {
-        const int c = kNumSmall + u - 1;
-        a.work = b->d_work + wp.off[v][c];
-        a.n_work = (wp.off[v][c + 1] - wp.off[v][c]) / (kWave / kClassLanes[c]);
-        for (int p = 0; p < kNumSmall; ++p) a.part_work[p] = nullptr;
-        a.tickets = nullptr;
-        lo = wp.off[v][c];
-        hi = wp.off[v][c + 1];
-      }
-      for (int k = lo; k < hi; ++k) b->unit_strings[u] += b->h_work[k] >= 0 ? 1 : 0;
-      if (a.n_work == 0) continue;
-      a.counter = b->d_counters + 2 * u + v;
-      a.n_steps = n_steps;
-      a.mon_period = b->mon_period;
-      a.max_sweeps = b->max_sweeps;
-      a.tol = b->tol;
-      a.mon_tol = b->mon_tol;
-      a.trash_st = b->d_trash;
-      a.trash_status = b->d_trash_status;
-      int per_cu = b->blocks_per_cu[u];
-      if (per_cu <= 0 || v == 1) {
-        const int occ = std::max(1, max_blocks_per_cu(b->precision, u, v == 1));
+    // the unit's classes one after the other (unit 0: the merged launch of
+    // classes 0..3); the bowed variant follows the other on the same stream
+    const int c_lo = u == 0 ? 0 : (u == 1 ? kNumSmall : kNumSmall + 1);
+    const int c_hi = u == 0 ? 1 : (u == 1 ? kNumSmall + 1 : kNumClasses);
+    for (int c = c_lo; c < c_hi; ++c) {
+      const int kernel = u == 0 ? 0 : kernel_of_class(c);
+      for (int v = 0; v < 2; ++v) {
+        LaunchArgs a;
+        a.desc = b->d_desc;
+        a.status = b->d_status;
+        int lo, hi;
+        if (u == 0) {
+          for (int p = 0; p < kNumSmall; ++p) a.part_work[p] = b->d_work + wp.off[v][p];
+          a.tickets = b->d_work + wp.tickets_off[v];
+          a.work = b->d_work + wp.off[v][0];
+          a.n_work = wp.n_tickets[v];
+          lo = wp.off[v][0];
+          hi = wp.off[v][kNumSmall];
+        } else {
+          a.work = b->d_work + wp.off[v][c];
+          a.n_work = (wp.off[v][c + 1] - wp.off[v][c]) / (kWave / kClassLanes[c]);
+          for (int p = 0; p < kNumSmall; ++p) a.part_work[p] = nullptr;
+          a.tickets = nullptr;
+          lo = wp.off[v][c];
+          hi = wp.off[v][c + 1];
+        }
+        for (int k = lo; k < hi; ++k) b->unit_strings[u] += b->h_work[k] >= 0 ? 1 : 0;
+        if (a.n_work == 0) continue;
+        a.counter = b->d_counters + 2 * c + v;
+        a.n_steps = n_steps;
+        a.mon_period = b->mon_period;
+        a.max_sweeps = b->max_sweeps;
+        a.tol = b->tol;
+        a.mon_tol = b->mon_tol;
+        a.trash_st = b->d_trash;
+        a.trash_status = b->d_trash_status;
+        int per_cu = b->blocks_per_cu[u];
+        const int occ = std::max(1, max_blocks_per_cu(b->precision, kernel, v == 1));
         per_cu = per_cu > 0 ? std::min(per_cu, occ) : occ;
+        const int blocks = std::min(a.n_work, b->num_cu * per_cu);
+        if (!forked) {
+          e = hipStreamWaitEvent(cs, b->ev_fork, 0);
+          // the merged launch starts a little after the large classes (their
+          // wavefronts need whole SIMDs; the merged one's would fill them first)
+          if (e == hipSuccess && u == 0 && big_launched) e = launch_delay(b->delay_ticks, cs);
+          if (e == hipSuccess) e = hipEventRecord(b->ev_t0[u], cs);
+          forked = true;
+        }
+        if (e == hipSuccess) e = launch_kernel(b->precision, kernel, v == 1, a, blocks, cs);
+        if (e != hipSuccess) return hip_fail(b, e, "step launch");
       }
-      const int blocks = std::min(a.n_work, b->num_cu * per_cu);
-      if (!forked) {
-        e = hipStreamWaitEvent(cs, b->ev_fork, 0);
-        // the merged launch starts a little after the large classes (their
-        // wavefronts need whole SIMDs; the merged one's would fill them first)
-        if (e == hipSuccess && u == 0 && big_launched) e = launch_delay(b->delay_ticks, cs);
-        if (e == hipSuccess) e = hipEventRecord(b->ev_t0[u], cs);
-        forked = true;
-      }
-      if (e == hipSuccess) e = launch_unit(b->precision, u, v == 1, a, blocks, cs);
-      if (e != hipSuccess) return hip_fail(b, e, "step launch");
     }
     if (!forked) continue;
     big_launched = big_launched || u > 0;
@@ -817,7 +821,9 @@ extern "C" int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *
     for (int c = 0; c < kNumClasses; ++c)
       nw[unit_of_class(c)] += (wp.off[v][c + 1] - wp.off[v][c]) / (kWave / kClassLanes[c]);
   for (int u = 0; u < kNumUnits; ++u) {
-    occ[u] = std::max(1, max_blocks_per_cu(b->precision, u, false));
+    occ[u] = 1;
+    for (int c = 0; c < kNumClasses; ++c)
+      if (unit_of_class(c) == u) occ[u] = std::max(occ[u], max_blocks_per_cu(b->precision, kernel_of_class(c), false));
     b->blocks_per_cu[u] = occ[u];
     if (chosen) chosen[u] = 0;
   }

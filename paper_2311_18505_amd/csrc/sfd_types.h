@@ -14,17 +14,21 @@ constexpr int kMaxN = kWave * kMaxSlots;   // N_t, N_l <= 1024
 // (a wavefront holds 64/G strings) and every lane owns up to MM consecutive
 // points of each grid; a string runs in the smallest class with
 // G * MM >= max(N_t, N_l).
-constexpr int kNumClasses = 6;
-constexpr int kClassLanes[kNumClasses] = {16, 16, 32, 64, 64, 64};
-constexpr int kClassSlots[kNumClasses] = {2, 4, 4, 4, 8, 16};
+constexpr int kNumClasses = 7;
+constexpr int kClassLanes[kNumClasses] = {16, 16, 32, 64, 64, 64, 64};
+constexpr int kClassSlots[kNumClasses] = {2, 4, 4, 4, 8, 10, 16};
 
 // Launches of one step.  The classes up to 256 points share one occupancy
 // profile and run as one persistent launch with one work queue (unit 0);
-// the two largest classes run as launches of their own (units 1, 2), each on
-// its own stream, so the three run concurrently.
+// class 4 runs as a launch of its own (unit 1) and classes 5 and 6 one after
+// the other on a third stream (unit 2; no string of the benchmark workloads
+// needs class 6), so the three units run concurrently.
 constexpr int kNumSmall = 4;        // classes 0..3
 constexpr int kNumUnits = 3;
-constexpr int unit_of_class(int c) { return c < kNumSmall ? 0 : c - kNumSmall + 1; }
+constexpr int unit_of_class(int c) { return c < kNumSmall ? 0 : (c == kNumSmall ? 1 : 2); }
+// kernel of a class: 0 the merged classes, then one per large class
+constexpr int kernel_of_class(int c) { return c < kNumSmall ? 0 : c - kNumSmall + 1; }
+constexpr int kNumKernels = kNumClasses - kNumSmall + 1;
 
 enum : int32_t {
   kFlagUnstable = 1,      // energy monitor: non-finite or growing energy

@@ -361,7 +361,7 @@ constexpr int kLdsArrays = BOW ? 5 : 3;
 // [r G] from the lane's entry, read where they are used.  With 16 slots per
 // lane the tables would otherwise take a third of the register file.
 template <int MM>
-constexpr bool kTabLds = MM >= 16;
+constexpr bool kTabLds = MM >= 10;
 
 template <int G, int MM, typename V, bool IN_LDS>
 struct LaneTab {
@@ -411,7 +411,7 @@ struct TabLds {
 // uses (4 MM G values per group) instead of in registers: with 16 slots per
 // lane they would otherwise crowd the register file and spill the state.
 template <int MM, typename T, bool KAHAN>
-constexpr bool kSideComp = KAHAN && MM >= 16;
+constexpr bool kSideComp = KAHAN && MM >= 10;
 
 template <int G, int MM, typename T>
 __device__ __forceinline__ void side_load(T (&x)[MM], const T *side, int k, int li) {
@@ -1574,20 +1574,23 @@ hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const 
 }
 
 template <typename T, bool KAHAN, bool BOW>
-static hipError_t launch_unit_t(int unit, const LaunchArgs &a, int blocks, hipStream_t st) {
-  switch (unit) {
+static hipError_t launch_kernel_t(int kernel, const LaunchArgs &a, int blocks, hipStream_t st) {
+  switch (kernel) {
     case 0: hipLaunchKernelGGL((step_kernel_small<T, KAHAN, BOW>), dim3(blocks), dim3(64), 0, st, a); break;
     case 1: hipLaunchKernelGGL((step_kernel<64, 8, T, KAHAN, BOW>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((step_kernel<64, 10, T, KAHAN, BOW>), dim3(blocks), dim3(64), 0, st, a); break;
     default: hipLaunchKernelGGL((step_kernel<64, 16, T, KAHAN, BOW>), dim3(blocks), dim3(64), 0, st, a); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_unit(int precision, int unit, bool bow, const LaunchArgs &a, int blocks, hipStream_t st) {
+// kernel: 0 the merged classes 0..3, 1..3 the classes 4..6 (kernel_of_class)
+hipError_t launch_kernel(int precision, int kernel, bool bow, const LaunchArgs &a, int blocks, hipStream_t st) {
   if (precision == 1)
-    return bow ? launch_unit_t<float, true, true>(unit, a, blocks, st) : launch_unit_t<float, true, false>(unit, a, blocks, st);
-  return bow ? launch_unit_t<double, false, true>(unit, a, blocks, st)
-             : launch_unit_t<double, false, false>(unit, a, blocks, st);
+    return bow ? launch_kernel_t<float, true, true>(kernel, a, blocks, st)
+               : launch_kernel_t<float, true, false>(kernel, a, blocks, st);
+  return bow ? launch_kernel_t<double, false, true>(kernel, a, blocks, st)
+             : launch_kernel_t<double, false, false>(kernel, a, blocks, st);
 }
 
 // Holds its stream for `ticks` of the constant-rate wall clock and exits
@@ -1612,12 +1615,13 @@ hipError_t launch_zero(int32_t *c, int n, hipStream_t st) {
 }
 
 template <typename T, bool KAHAN, bool BOW>
-static int blocks_per_cu(int unit) {
+static int blocks_per_cu(int kernel) {
   int n = 0;
   hipError_t e;
-  switch (unit) {
+  switch (kernel) {
     case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_small<T, KAHAN, BOW>, 64, 0); break;
     case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 8, T, KAHAN, BOW>, 64, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 10, T, KAHAN, BOW>, 64, 0); break;
     default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 16, T, KAHAN, BOW>, 64, 0); break;
   }
   if (e != hipSuccess) {
@@ -1627,9 +1631,9 @@ static int blocks_per_cu(int unit) {
   return n;
 }
 
-int max_blocks_per_cu(int precision, int unit, bool bow) {
-  if (precision == 1) return bow ? blocks_per_cu<float, true, true>(unit) : blocks_per_cu<float, true, false>(unit);
-  return bow ? blocks_per_cu<double, false, true>(unit) : blocks_per_cu<double, false, false>(unit);
+int max_blocks_per_cu(int precision, int kernel, bool bow) {
+  if (precision == 1) return bow ? blocks_per_cu<float, true, true>(kernel) : blocks_per_cu<float, true, false>(kernel);
+  return bow ? blocks_per_cu<double, false, true>(kernel) : blocks_per_cu<double, false, false>(kernel);
 }
 
 }  // namespace sfd

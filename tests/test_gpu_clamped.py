@@ -1,7 +1,7 @@
 """Clamped string ends (Sec. 4.1, eq. (10)) on the GPU through the C ABI.
 
 * mixed batches (every third string simply supported, the rest clamped, so
-  waves hold both; clamped strings in all six size classes) against the FP64
+  waves hold both; clamped strings in all seven size classes) against the FP64
   oracle: FP64 rel-L2 <= 1e-10, FP32
   compensated <= 1e-3;
 * the plain FP64 comparator with clamped ends, <= 1e-10;
@@ -51,9 +51,10 @@ def _run(items, precision):
 def _mixed(n, seconds, seed):
     items = W.random_batch(n, seconds=seconds, seed=seed)
     items = [(dict(p, boundary=0 if i % 3 == 2 else 1), e) for i, (p, e) in enumerate(items)]
-    # a low clamped string in the largest size class, hammered
+    # low clamped strings in the two largest size classes, hammered and plucked
     low = W.string(20.7, 1e-5, 1.2, 0.5, 1e-4, int(seconds * 48000))
-    return items + [(dict(low, boundary=1), W.hammer(0.12, 2.0))]
+    mid = W.string(40.0, 1e-5, 1.1, 0.5, 1e-4, int(seconds * 48000))
+    return items + [(dict(low, boundary=1), W.hammer(0.12, 2.0)), (dict(mid, boundary=1), W.pluck(0.2, 1e-3))]
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-3)])
@@ -65,7 +66,7 @@ def test_clamped_mixed_batch(precision, tol):
     errs = [rel_l2(y, r) for y, r in zip(outs, refs)]
     print("[gpu] %s clamped batch: worst rel-L2 %.3e" % (precision, max(errs)), flush=True)
     assert all(i["flags"] == 0 for i in infos)
-    assert set(i["size_class"] for (p, _), i in zip(items, infos) if p["boundary"] == 1) == set(range(6))
+    assert set(i["size_class"] for (p, _), i in zip(items, infos) if p["boundary"] == 1) == set(range(7))
     assert max(errs) <= tol
 
 

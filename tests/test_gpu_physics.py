@@ -166,7 +166,7 @@ def test_theta_one_and_largest_class_fp64():
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-3)])
 def test_maximum_grid_sizes(precision, tol):
     """The largest grids the batched paths accept (1024 intervals, the top of
-    size class 5): N_l = 1024 (hammered, nonlinear) and N_t = 1024 (plucked,
+    size class 6): N_l = 1024 (hammered, nonlinear) and N_t = 1024 (plucked,
     linear), beside a small string in the same batch; one interval more is
     refused with SB_EBUDGET."""
     _gpu()
