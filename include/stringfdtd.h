@@ -134,7 +134,7 @@ typedef struct {
     int32_t flags;             /* 1: unstable (energy monitor), 2: no convergence */
     int32_t max_sweeps;        /* largest number of coupled-solve sweeps in a step */
     int64_t total_sweeps;      /* total sweeps                                    */
-    int32_t size_class;        /* kernel size class 0..5 of the batched paths      */
+    int32_t size_class;        /* kernel size class 0..6 of the batched paths      */
     int32_t lanes;             /* lanes per string in that class (16, 32 or 64)   */
 } sb_string_info;
 
@@ -191,6 +191,35 @@ int string_batch_restrike_list(sb_batch *b, int count, const int32_t *slots, con
  * a device copy of the excited state is kept for this.  Asynchronous on the
  * batch stream.  Errors: SB_EINVAL, SB_EDEVICE. */
 int string_batch_rewind(sb_batch *b, int first, int count);
+
+/* Checkpoint and resume of one slot.  The recursion of eq. (7) carries its
+ * whole past in the two latest grid levels (Sec. 3.2), so a slot's stepping
+ * state is small and self-contained: both grids at levels n and n-1 (as
+ * value and velocity, with their compensations on the FP32 compensated
+ * path), the hammer's lumped state, the energy monitor's reference and the
+ * progress counters.  A snapshot copies exactly that; restoring it onto the
+ * same slot makes the next steps reproduce, bit for bit, what they computed
+ * after the snapshot was taken (output samples from samples_done on are
+ * written again).  Output already written, the parameters and the
+ * excitation tables are not part of it: a snapshot restores only onto the
+ * slot it was taken from, and only while that slot keeps the excitation it
+ * had (excite or restrike in between: SB_ESTATE).
+ *
+ * string_batch_snapshot_bytes: size in bytes of slot idx's snapshot (a
+ *   256-byte header, then the state block).
+ * string_batch_snapshot: waits for the batch's queued work, then copies the
+ *   snapshot to dst (caller-owned, at least that many bytes; host memory, or
+ *   device memory when dst_is_device) and returns when the copy is complete.
+ * string_batch_restore: checks the snapshot's header against the slot
+ *   (SB_EINVAL when it is not a snapshot of this slot's string or bytes
+ *   differs from its size), waits for the batch's queued work, copies it back
+ *   and returns when the copy is complete; the slot's samples_done and flags
+ *   become the snapshot's.  A captured graph must be captured again.
+ * Errors: SB_EINVAL, SB_ESTATE (slot not excited, or re-excited since the
+ * snapshot), SB_EDEVICE. */
+int string_batch_snapshot_bytes(sb_batch *b, int idx, int64_t *bytes);
+int string_batch_snapshot(sb_batch *b, int idx, void *dst, int64_t bytes, int dst_is_device);
+int string_batch_restore(sb_batch *b, int idx, const void *src, int64_t bytes, int src_is_device);
 
 /* Launch capture (batched paths).  Records n_launches consecutive launches
  * of steps_per_launch steps each, of every slot excited at the time of the

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libstringfdtd.so")
+# STRINGFDTD_LIB names another build of the library (the LDS-poisoning debug
+# build, libstringfdtd_poison.so, in its test)
+LIB_PATH = os.environ.get("STRINGFDTD_LIB") or os.path.join(HERE, "libstringfdtd.so")
 
 SB_OK, SB_EINVAL, SB_ENOMEM, SB_EBUDGET, SB_EUNSTABLE, SB_ESTATE, SB_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 SB_FP64, SB_FP32C, SB_FP64_PLAIN = 0, 1, 2
@@ -68,6 +70,9 @@ SIGNATURES = [
     ("string_batch_step", C.c_int, [_P, C.c_int64]),
     ("string_batch_step_range", C.c_int, [_P, C.c_int, C.c_int, C.c_int64]),
     ("string_batch_rewind", C.c_int, [_P, C.c_int, C.c_int]),
+    ("string_batch_snapshot_bytes", C.c_int, [_P, C.c_int, C.POINTER(C.c_int64)]),
+    ("string_batch_snapshot", C.c_int, [_P, C.c_int, _P, C.c_int64, C.c_int]),
+    ("string_batch_restore", C.c_int, [_P, C.c_int, _P, C.c_int64, C.c_int]),
     ("string_batch_read_output", C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, _P, C.c_int]),
     ("string_batch_read_output_zeta", C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, _P, C.c_int]),
     ("string_batch_output_ptr", C.c_int, [_P, C.c_int, C.POINTER(_P)]),
@@ -211,6 +216,30 @@ class StringBatch:
     def rewind(self, first: int = 0, count: int | None = None):
         count = self.capacity - first if count is None else count
         self._check(self.lib.string_batch_rewind(self.h, first, count), "rewind")
+
+    def snapshot_bytes(self, idx: int) -> int:
+        n = C.c_int64()
+        self._check(self.lib.string_batch_snapshot_bytes(self.h, idx, C.byref(n)), "snapshot_bytes")
+        return n.value
+
+    def snapshot(self, idx: int) -> np.ndarray:
+        """Slot idx's stepping state as a byte array (host)."""
+        buf = np.zeros(self.snapshot_bytes(idx), dtype=np.uint8)
+        self._check(self.lib.string_batch_snapshot(self.h, idx, buf.ctypes.data_as(C.c_void_p), buf.nbytes, 0),
+                    "snapshot")
+        return buf
+
+    def restore(self, idx: int, snap) -> None:
+        """Puts back a snapshot of slot idx taken by snapshot()."""
+        buf = np.ascontiguousarray(snap, dtype=np.uint8)
+        self._check(self.lib.string_batch_restore(self.h, idx, buf.ctypes.data_as(C.c_void_p), buf.nbytes, 0),
+                    "restore")
+
+    def snapshot_device(self, idx: int, dst_ptr: int, nbytes: int) -> None:
+        self._check(self.lib.string_batch_snapshot(self.h, idx, C.c_void_p(dst_ptr), nbytes, 1), "snapshot")
+
+    def restore_device(self, idx: int, src_ptr: int, nbytes: int) -> None:
+        self._check(self.lib.string_batch_restore(self.h, idx, C.c_void_p(src_ptr), nbytes, 1), "restore")
 
     def read_output(self, idx: int, offset: int = 0, count: int | None = None) -> np.ndarray:
         if count is None:

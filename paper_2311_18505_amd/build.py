@@ -18,24 +18,45 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source for gfx950 into one shared library (always rebuilds)."""
+# the library, and its debug twin whose step kernel poisons dead LDS with NaN
+VARIANTS = {"": [], "_poison": ["-DSFD_POISON_LDS=1"]}
+
+
+def _command(variant: str, out: str) -> list:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           # packed FP32 arithmetic stays off on this hardware pool
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           # host-side planning reproduces FP64 grid sizes bit for bit
-           "-Xarch_host", "-ffp-contract=off",
-           "-I", os.path.join(os.path.dirname(HERE), "include"),
-           "-o", tmp] + srcs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libstringfdtd.so")
-    os.replace(tmp, LIB)
+    return [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+            # packed FP32 arithmetic stays off on the test machines
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # host-side planning reproduces FP64 grid sizes bit for bit
+            "-Xarch_host", "-ffp-contract=off",
+            "-I", os.path.join(os.path.dirname(HERE), "include")] + VARIANTS[variant] + ["-o", out] + srcs
+
+
+def lib_path(variant: str = "") -> str:
+    return os.path.join(HERE, "libstringfdtd%s.so" % variant)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source for gfx950 into libstringfdtd.so and its LDS-poisoning
+    debug twin libstringfdtd_poison.so, side by side (always rebuilds)."""
+    procs = []
+    for variant in VARIANTS:
+        out = lib_path(variant)
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = _command(variant, tmp)
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((out, tmp, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    failed = []
+    for out, tmp, proc in procs:
+        log, _ = proc.communicate()
+        if proc.returncode != 0:
+            sys.stderr.write(log)
+            failed.append(os.path.basename(out))
+        else:
+            os.replace(tmp, out)
+    if failed:
+        raise RuntimeError("hipcc failed building %s" % ", ".join(failed))
     return LIB
 
 

@@ -108,6 +108,7 @@ struct Slot {
   int64_t samples_host = 0;   // samples expected after the launches issued so far
   bool flagged = false;       // a flag was observed on the device
   bool restruck = false;      // re-excited since string_batch_excite (no rewind)
+  int64_t gen = 0;            // excitation generation (excite or restrike), names the slot's tables
 };
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
@@ -153,6 +154,7 @@ struct sb_batch {
   std::vector<int32_t> h_plain;   // plain path: slots in launch order
   bool work_dirty = true;
   int64_t epoch = 0;               // bumped whenever slots change (invalidates a captured graph)
+  int64_t next_gen = 0;            // last excitation generation handed to a slot
   int blocks_per_cu[kNumUnits] = {};   // persistent blocks per CU per launch (0: occupancy limit)
   // captured launches (string_batch_graph_capture)
   hipStream_t cap_stream = nullptr;
@@ -516,6 +518,7 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
     s.restruck = false;
     s.flagged = false;
     s.samples_host = S.samples_done;
+    s.gen = ++b->next_gen;
   }
   // staging buffers of the batch (the previous upload has completed: the
   // stream was synchronised above)
@@ -1235,6 +1238,7 @@ extern "C" int string_batch_restrike_list(sb_batch *b, int count, const int32_t 
     Slot &s = b->slots[slots[i]];
     s.plan = plans[i];
     s.restruck = true;
+    s.gen = ++b->next_gen;
   }
   ++b->epoch;
   b->work_dirty = true;
@@ -1262,5 +1266,126 @@ extern "C" int string_batch_rewind(sb_batch *b, int first, int count) {
   }
   hipError_t e = launch_rewind(b->precision, b->d_desc, b->d_status, b->d_status0, first, count, b->stream);
   if (e != hipSuccess) return hip_fail(b, e, "rewind");
+  return SB_OK;
+}
+
+// Snapshot of one slot: this header, the slot's Status at kSnapStatusOff and
+// its state block (both grids, velocities and compensations, in the batch's
+// precision and layout) at kSnapStateOff.
+namespace {
+struct SnapHeader {
+  char magic[8];
+  int32_t precision, slot, cls, esz;
+  int64_t gen, st_elems, n_samples, bytes;
+  int32_t nt, nl;
+};
+constexpr char kSnapMagic[8] = {'S', 'B', 'S', 'N', 'A', 'P', '1', 0};
+constexpr int64_t kSnapStatusOff = 128, kSnapStateOff = 256;
+static_assert(sizeof(SnapHeader) <= (size_t)kSnapStatusOff, "snapshot header");
+static_assert(kSnapStatusOff + (int64_t)sizeof(Status) <= kSnapStateOff, "snapshot status");
+
+SnapHeader snap_header(const sb_batch *b, int idx) {
+  const Slot &s = b->slots[idx];
+  const Desc &D = s.plan.desc;
+  SnapHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kSnapMagic, sizeof(h.magic));
+  h.precision = b->precision;
+  h.slot = idx;
+  h.cls = D.cls;
+  h.esz = (int32_t)b->esz;
+  h.gen = s.gen;
+  h.st_elems = D.st_elems;
+  h.n_samples = D.n_samples;
+  h.bytes = kSnapStateOff + (int64_t)D.st_elems * (int64_t)b->esz;
+  h.nt = D.nt;
+  h.nl = D.nl;
+  return h;
+}
+
+// Queued launches and copies of the batch finish first.
+hipError_t sync_batch(sb_batch *b) {
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess && b->cap_stream) e = hipStreamSynchronize(b->cap_stream);
+  return e;
+}
+}  // namespace
+
+extern "C" int string_batch_snapshot_bytes(sb_batch *b, int idx, int64_t *bytes) {
+  if (!b) return SB_EINVAL;
+  if (!bytes || idx < 0 || idx >= b->capacity) return fail(b, SB_EINVAL, "bad arguments");
+  if (!b->slots[idx].excited) return fail(b, SB_ESTATE, "slot not excited");
+  *bytes = snap_header(b, idx).bytes;
+  return SB_OK;
+}
+
+extern "C" int string_batch_snapshot(sb_batch *b, int idx, void *dst, int64_t bytes, int dst_is_device) {
+  if (!b) return SB_EINVAL;
+  if (!dst || idx < 0 || idx >= b->capacity) return fail(b, SB_EINVAL, "bad arguments");
+  const Slot &s = b->slots[idx];
+  if (!s.excited) return fail(b, SB_ESTATE, "slot not excited");
+  const SnapHeader h = snap_header(b, idx);
+  if (bytes < h.bytes) return fail(b, SB_EINVAL, "buffer smaller than the snapshot (" + std::to_string(h.bytes) + " bytes)");
+  char head[kSnapStatusOff];
+  std::memset(head, 0, sizeof(head));
+  std::memcpy(head, &h, sizeof(h));
+  char *d = (char *)dst;
+  const hipMemcpyKind out = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  hipError_t e = sync_batch(b);
+  if (e == hipSuccess) {
+    if (dst_is_device)
+      e = hipMemcpyAsync(d, head, sizeof(head), hipMemcpyHostToDevice, b->stream);
+    else
+      std::memcpy(d, head, sizeof(head));
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(d + kSnapStatusOff, b->d_status + idx, sizeof(Status), out, b->stream);
+  if (e == hipSuccess && !dst_is_device)
+    std::memset(d + kSnapStatusOff + sizeof(Status), 0, kSnapStateOff - kSnapStatusOff - sizeof(Status));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d + kSnapStateOff, s.plan.desc.st, (size_t)(h.bytes - kSnapStateOff), out, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);   // `head` is released after this
+  if (e != hipSuccess) return hip_fail(b, e, "snapshot");
+  return SB_OK;
+}
+
+extern "C" int string_batch_restore(sb_batch *b, int idx, const void *src, int64_t bytes, int src_is_device) {
+  if (!b) return SB_EINVAL;
+  if (!src || idx < 0 || idx >= b->capacity) return fail(b, SB_EINVAL, "bad arguments");
+  Slot &s = b->slots[idx];
+  if (!s.excited) return fail(b, SB_ESTATE, "slot not excited");
+  const SnapHeader want = snap_header(b, idx);
+  if (bytes < kSnapStateOff) return fail(b, SB_EINVAL, "not a snapshot (too short)");
+  const char *p = (const char *)src;
+  SnapHeader h;
+  Status S;
+  hipError_t e = hipSuccess;
+  if (src_is_device) {
+    e = hipMemcpy(&h, p, sizeof(h), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&S, p + kSnapStatusOff, sizeof(S), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(b, e, "restore read");
+  } else {
+    std::memcpy(&h, p, sizeof(h));
+    std::memcpy(&S, p + kSnapStatusOff, sizeof(S));
+  }
+  if (std::memcmp(h.magic, kSnapMagic, sizeof(h.magic)) != 0) return fail(b, SB_EINVAL, "not a snapshot");
+  if (h.bytes != bytes || h.bytes != want.bytes || h.precision != want.precision || h.esz != want.esz ||
+      h.st_elems != want.st_elems || h.cls != want.cls || h.nt != want.nt || h.nl != want.nl ||
+      h.n_samples != want.n_samples)
+    return fail(b, SB_EINVAL, "the snapshot does not fit this slot's string");
+  if (h.slot != idx) return fail(b, SB_EINVAL, "the snapshot was taken from slot " + std::to_string(h.slot));
+  if (h.gen != s.gen) return fail(b, SB_ESTATE, "the slot was excited or re-excited since the snapshot");
+  const int64_t n = want.n_samples;
+  if (S.samples_done < std::min<int64_t>(2, n) || S.samples_done > n) return fail(b, SB_EINVAL, "corrupt snapshot");
+  const hipMemcpyKind in = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  e = sync_batch(b);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_status + idx, &S, sizeof(Status), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s.plan.desc.st, p + kSnapStateOff, (size_t)(h.bytes - kSnapStateOff), in, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);   // `S` is released after this
+  if (e != hipSuccess) return hip_fail(b, e, "restore");
+  s.samples_host = S.samples_done;
+  s.flagged = S.flags != 0;
+  b->work_dirty = true;
+  ++b->epoch;
   return SB_OK;
 }

@@ -662,6 +662,23 @@ __device__ __forceinline__ void store_state(T *st, T *trash, const T (&u)[MM], c
   }
 }
 
+// Debug builds (SFD_POISON_LDS=1) fill the LDS that a task or a step must
+// write before it reads with NaN: all of a group's LDS at the start of every
+// task, and the arrays every step rebuilds (slopes, taps, prefix sums, the
+// energy scratch that overlays them) at the end of every step.  A read of a
+// stale or never-written entry then makes the output NaN or trips the energy
+// monitor.  Regular builds compile none of it.
+#ifndef SFD_POISON_LDS
+#define SFD_POISON_LDS 0
+#endif
+constexpr bool kPoisonLds = SFD_POISON_LDS != 0;
+
+template <int G, typename V>
+__device__ __forceinline__ void poison_lds(V *p, int n, int li) {
+  const V nan = (V)__builtin_nan("");
+  for (int i = li; i < n; i += G) p[i] = nan;
+}
+
 // ---------------------------------------------------------------------------
 // One wavefront task: up to 64/G strings stepped together
 // ---------------------------------------------------------------------------
@@ -709,6 +726,17 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   // the readout's I(x_out) as per-slot weights of this lane, in LDS at
   // [lane][slot]: one multiply-add per slot and one group sum per use.
   T *wH = sW + lane * MM, *wO = sW + kWave * MM + lane * MM;
+  using L = Lds<G, MM, kLdsArrays<BOW>>;
+  if constexpr (kPoisonLds) {
+    poison_lds<G>(sS + gi * L::kStride, L::kStride, li);
+    poison_lds<G>(sE + gi * EnergyLds<G, MM>::kStride, EnergyLds<G, MM>::kStride, li);
+    poison_lds<1>(wH, MM, 0);
+    poison_lds<1>(wO, MM, 0);
+    if constexpr (BOW) poison_lds<G>(sB + gi * kBowRec, kBowRec, li);
+    if constexpr (kSideComp<MM, T, KAHAN>) poison_lds<G>(sC + gi * 4 * MM * G, 4 * MM * G, li);
+    if constexpr (kTabLds<MM>) poison_lds<G>(sTf + gi * TabLds<G, MM, T>::kWordsT, TabLds<G, MM, T>::kWordsT, li);
+    __syncthreads();
+  }
   {
     // (a cubic hammer's extra nodes share their storage with a bow's fields)
     const int h0 = ham ? D.hn0 : 0, h1 = ham ? D.hn1 : 0, h2 = ham ? D.hn2 : 0, h3 = ham ? D.hn3 : 0;
@@ -850,7 +878,6 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   // (n + 1) mod mon_period of the current step
   int mon_ctr = a.mon_period > 0 ? (int)(done % a.mon_period) : 1;
 
-  using L = Lds<G, MM, kLdsArrays<BOW>>;
   T *gP = sS + gi * L::kStride, *gA = gP + L::kArr, *gB = gA + L::kArr;
   T *gC = BOW ? gB + L::kArr : gB, *gD = BOW ? gC + L::kArr : gB;   // cubic taps 2 and 3
   const T *tfc = tf + (3 * mt + ml) * G;          // cubic grid interpolant: weights 1..3 per t-slot
@@ -1385,6 +1412,12 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     steps_done += act ? 1 : 0;
     nsteps = bad ? it + 1 : nsteps;      // a flagged string stops here
     mon_ctr = mon_ctr + 1 == a.mon_period ? 0 : mon_ctr + 1;
+    if constexpr (kPoisonLds) {
+      __syncthreads();
+      poison_lds<G>(gP, L::kStride, li);
+      poison_lds<G>(gE, EnergyLds<G, MM>::kStride, li);
+      __syncthreads();
+    }
   }
 
   // ---- write back: every lane stores; an empty group writes to the trash ----
