@@ -15,9 +15,9 @@
 #include "sfd_types.h"
 
 namespace sfd {
-hipError_t launch_kernel(int precision, int kernel, bool bow, const LaunchArgs &a, int blocks, hipStream_t st);
+hipError_t launch_kernel(int precision, int kernel, int variant, const LaunchArgs &a, int blocks, hipStream_t st);
 hipError_t launch_zero(int32_t *c, int n, hipStream_t st);
-int max_blocks_per_cu(int precision, int kernel, bool bow);
+int max_blocks_per_cu(int precision, int kernel, int variant);
 hipError_t launch_delay(uint64_t ticks, hipStream_t st);
 hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
                          hipStream_t st);
@@ -216,7 +216,7 @@ extern "C" int string_batch_create(int capacity, int precision, void *hip_stream
       (e = hipMalloc(&b->d_status, sizeof(Status) * capacity)) != hipSuccess ||
       (e = hipMalloc(&b->d_status0, sizeof(Status) * capacity)) != hipSuccess ||
       (e = hipMalloc(&b->d_work, sizeof(int32_t) * work_capacity(capacity))) != hipSuccess ||
-      (e = hipMalloc(&b->d_counters, sizeof(int32_t) * 16)) != hipSuccess ||
+      (e = hipMalloc(&b->d_counters, sizeof(int32_t) * kNumVariants * kNumClasses)) != hipSuccess ||
       (e = hipMalloc(&b->d_trash, kMaxTrash)) != hipSuccess ||
       (e = hipMalloc(&b->d_trash_status, sizeof(Status))) != hipSuccess) {
     g_create_error = std::string("hipMalloc: ") + hipGetErrorString(e);
@@ -309,7 +309,11 @@ static_assert(kNumUnits == SB_NUM_LAUNCHES, "launch units of the C ABI");
 
 // task lists (strings, padded per class to whole tasks) and the ticket map of
 // the merged launch (at most one ticket per string)
-static size_t work_capacity(int capacity) { return 2 * (size_t)capacity + 2 * (size_t)kNumClasses * kWave; }
+// every string once in a task list (each list padded to whole wavefronts),
+// and at most one ticket per task
+static size_t work_capacity(int capacity) {
+  return 2 * (size_t)capacity + (size_t)kNumVariants * kNumParts * (kWave + 1);
+}
 
 static bool range_ok(const sb_batch *b, int first, int count) {
   return first >= 0 && count >= 0 && (int64_t)first + count <= b->capacity;
@@ -358,7 +362,7 @@ extern "C" int string_batch_set_params(sb_batch *b, int first, int count, const 
   std::vector<Plan> plans(count);
   for (int i = 0; i < count; ++i) {
     std::string err;
-    int st = plan_string(p[i], plans[i], err);
+    int st = plan_string(p[i], plans[i], err, b->precision == SB_FP32C);
     if (st) return fail(b, st, "slot " + std::to_string(first + i) + ": " + err);
     if (b->precision == SB_FP64_PLAIN && p[i].readout_zeta)
       return fail(b, SB_EINVAL, "slot " + std::to_string(first + i) + ": the zeta channel needs a batched precision");
@@ -561,14 +565,17 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
 // Variant 1 holds the tasks with bowed strings: they run in kernels of their
 // own, which keeps the bow's code and registers out of every other task.
 struct WorkPlan {
-  int off[2][kNumClasses + 1] = {};      // per variant, start of each class's tasks
-  int tickets_off[2] = {}, n_tickets[2] = {};   // ticket maps of the merged launches
+  int off[kNumVariants][kNumParts + 1] = {};      // per variant, start of each part's tasks
+  // ticket maps of the launches of unit 0 (parts of classes 0..3) and unit 1
+  // (the shapes of class 4)
+  int tickets_off[kNumVariants][2] = {}, n_tickets[kNumVariants][2] = {};
   std::vector<int> members;   // slots stepped
 };
 
+static int part_lanes(int part) { return kClassLanes[part / kNumShapes]; }
 
 static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPlan &wp) {
-  std::vector<std::pair<double, int>> cls[2][kNumClasses];
+  std::vector<std::pair<double, int>> parts[kNumVariants][kNumParts];
   bool any = false;
   for (int i = first; i < first + count; ++i) {
     Slot &s = b->slots[i];
@@ -577,47 +584,54 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
     if (s.flagged || s.samples_host >= s.plan.desc.n_samples) continue;
     const int64_t st = std::min<int64_t>(n_steps, s.plan.desc.n_samples - s.samples_host);
     const double cost = (double)st * (double)(s.plan.desc.nt + s.plan.desc.nl + 8);
-    const int c = b->precision == SB_FP64_PLAIN ? 0 : s.plan.desc.cls;
-    // bowed and clamped strings, the zeta channel and cubic hammers run in
-    // the instantiation that carries their code
     const Desc &d = s.plan.desc;
+    const int part = b->precision == SB_FP64_PLAIN ? 0 : d.cls * kNumShapes + d.shape;
+    // bowed and clamped strings, the zeta channel and cubic hammers run in
+    // the instantiation that carries their code, strings with the cubic grid
+    // interpolant in the one that adds it
     const bool cubic_hammer = d.ham_on && (d.hn2 || d.hn3);
-    cls[(d.bow_on || d.clamped || d.zeta_out || cubic_hammer || d.grid_interp == 3) ? 1 : 0][c].push_back({cost, i});
+    const int v = d.grid_interp == 3 ? kVarCubic
+                                     : ((d.bow_on || d.clamped || d.zeta_out || cubic_hammer) ? kVarBow : kVarPlain);
+    parts[v][part].push_back({cost, i});
   }
   if (!any) return fail(b, SB_ESTATE, "no excited slot");
   std::vector<int32_t> work;
-  for (int v = 0; v < 2; ++v) {
-    for (int c = 0; c < kNumClasses; ++c) {
-      auto &L = cls[v][c];
+  for (int v = 0; v < kNumVariants; ++v) {
+    for (int q = 0; q < kNumParts; ++q) {
+      auto &L = parts[v][q];
       std::stable_sort(L.begin(), L.end(), [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
         return x.first > y.first;
       });
-      wp.off[v][c] = (int)work.size();
-      const int groups = b->precision == SB_FP64_PLAIN ? 1 : kWave / kClassLanes[c];
+      wp.off[v][q] = (int)work.size();
+      const int groups = b->precision == SB_FP64_PLAIN ? 1 : kWave / part_lanes(q);
       for (size_t i = 0; i < L.size(); i += groups)
         for (int g = 0; g < groups; ++g) work.push_back(i + g < L.size() ? L[i + g].second : -1);
       for (auto &w : L) wp.members.push_back(w.second);
     }
-    wp.off[v][kNumClasses] = (int)work.size();
+    wp.off[v][kNumParts] = (int)work.size();
     if (b->precision != SB_FP64_PLAIN) {
-      // tickets of the merged launch: the tasks of classes 0..3 dealt out in
-      // proportion to their counts (task t of a class of n tasks at t / n),
-      // each class longest first.  The mix of classes on the CUs then stays
-      // the same over the whole launch, which runs faster than one class
+      // tickets of the launches of units 0 and 1: the tasks of their parts
+      // dealt out in proportion to their counts (task t of a part of n tasks
+      // at t / n), each part longest first.  The mix of parts on the CUs then
+      // stays the same over the whole launch, which runs faster than one part
       // after another (their bottlenecks differ), and the shortest tasks of
-      // every class fill the tail.
-      std::vector<std::pair<double, int32_t>> tk;
-      for (int c = 0; c < kNumSmall; ++c) {
-        const int groups = kWave / kClassLanes[c];
-        const int nt = (int)((cls[v][c].size() + groups - 1) / groups);
-        for (int t = 0; t < nt; ++t) tk.push_back({-(double)t / (double)nt, (int32_t)((c << 24) | t)});
+      // every part fill the tail.  A ticket is part << 24 | task (unit 1: the
+      // shape of class 4).
+      for (int u = 0; u < 2; ++u) {
+        const int q_lo = u == 0 ? 0 : kNumSmall * kNumShapes, q_hi = u == 0 ? kNumSmall * kNumShapes : kShapedClasses * kNumShapes;
+        std::vector<std::pair<double, int32_t>> tk;
+        for (int q = q_lo; q < q_hi; ++q) {
+          const int groups = kWave / part_lanes(q);
+          const int nt = (int)((parts[v][q].size() + groups - 1) / groups);
+          for (int t = 0; t < nt; ++t) tk.push_back({-(double)t / (double)nt, (int32_t)(((q - q_lo) << 24) | t)});
+        }
+        std::stable_sort(tk.begin(), tk.end(), [](const std::pair<double, int32_t> &x, const std::pair<double, int32_t> &y) {
+          return x.first > y.first;
+        });
+        wp.tickets_off[v][u] = (int)work.size();
+        wp.n_tickets[v][u] = (int)tk.size();
+        for (auto &t : tk) work.push_back(t.second);
       }
-      std::stable_sort(tk.begin(), tk.end(), [](const std::pair<double, int32_t> &x, const std::pair<double, int32_t> &y) {
-        return x.first > y.first;
-      });
-      wp.tickets_off[v] = (int)work.size();
-      wp.n_tickets[v] = (int)tk.size();
-      for (auto &t : tk) work.push_back(t.second);
     }
   }
   if (work.empty() || b->precision == SB_FP64_PLAIN) {
@@ -644,8 +658,7 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
 // forked onto their own streams and joined back.  Issues no synchronisation
 // and no copy, so it can be captured.
 static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t n_steps) {
-  static_assert(2 * kNumClasses <= 16, "queue heads of every class and variant");
-  hipError_t e = launch_zero(b->d_counters, 2 * kNumClasses, st);
+  hipError_t e = launch_zero(b->d_counters, kNumVariants * kNumClasses, st);
   if (e == hipSuccess) e = hipEventRecord(b->ev_fork, st);
   if (e != hipSuccess) return hip_fail(b, e, "fork");
   // largest strings first: their launches hold the longest per-step latency
@@ -655,34 +668,39 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
     b->unit_strings[u] = 0;
     bool forked = false;
     // the unit's classes one after the other (unit 0: the merged launch of
-    // classes 0..3); the bowed variant follows the other on the same stream
+    // classes 0..3); the bow-family variants follow the plain one on the same stream
     const int c_lo = u == 0 ? 0 : (u == 1 ? kNumSmall : kNumSmall + 1);
     const int c_hi = u == 0 ? 1 : (u == 1 ? kNumSmall + 1 : kNumClasses);
     for (int c = c_lo; c < c_hi; ++c) {
       const int kernel = u == 0 ? 0 : kernel_of_class(c);
-      for (int v = 0; v < 2; ++v) {
+      for (int v = 0; v < kNumVariants; ++v) {
         LaunchArgs a;
         a.desc = b->d_desc;
         a.status = b->d_status;
         int lo, hi;
-        if (u == 0) {
-          for (int p = 0; p < kNumSmall; ++p) a.part_work[p] = b->d_work + wp.off[v][p];
-          a.tickets = b->d_work + wp.tickets_off[v];
-          a.work = b->d_work + wp.off[v][0];
-          a.n_work = wp.n_tickets[v];
-          lo = wp.off[v][0];
-          hi = wp.off[v][kNumSmall];
+        for (int p = 0; p < kNumSmall * kNumShapes; ++p) a.part_work[p] = nullptr;
+        a.tickets = nullptr;
+        if (u <= 1) {
+          // ticketed launches: unit 0 over the parts of classes 0..3, unit 1
+          // over the shapes of class 4
+          const int q0 = u == 0 ? 0 : kNumSmall * kNumShapes;
+          const int nq = u == 0 ? kNumSmall * kNumShapes : kNumShapes;
+          for (int p = 0; p < nq; ++p) a.part_work[p] = b->d_work + wp.off[v][q0 + p];
+          a.tickets = b->d_work + wp.tickets_off[v][u];
+          a.work = a.part_work[0];
+          a.n_work = wp.n_tickets[v][u];
+          lo = wp.off[v][q0];
+          hi = wp.off[v][q0 + nq];
         } else {
-          a.work = b->d_work + wp.off[v][c];
-          a.n_work = (wp.off[v][c + 1] - wp.off[v][c]) / (kWave / kClassLanes[c]);
-          for (int p = 0; p < kNumSmall; ++p) a.part_work[p] = nullptr;
-          a.tickets = nullptr;
-          lo = wp.off[v][c];
-          hi = wp.off[v][c + 1];
+          const int q = c * kNumShapes;   // classes 5 and 6: shape 0 only
+          a.work = b->d_work + wp.off[v][q];
+          a.n_work = (wp.off[v][q + 1] - wp.off[v][q]) / (kWave / kClassLanes[c]);
+          lo = wp.off[v][q];
+          hi = wp.off[v][q + 1];
         }
         for (int k = lo; k < hi; ++k) b->unit_strings[u] += b->h_work[k] >= 0 ? 1 : 0;
         if (a.n_work == 0) continue;
-        a.counter = b->d_counters + 2 * c + v;
+        a.counter = b->d_counters + kNumVariants * c + v;
         a.n_steps = n_steps;
         a.mon_period = b->mon_period;
         a.max_sweeps = b->max_sweeps;
@@ -691,7 +709,7 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
         a.trash_st = b->d_trash;
         a.trash_status = b->d_trash_status;
         int per_cu = b->blocks_per_cu[u];
-        const int occ = std::max(1, max_blocks_per_cu(b->precision, kernel, v == 1));
+        const int occ = std::max(1, max_blocks_per_cu(b->precision, kernel, v));
         per_cu = per_cu > 0 ? std::min(per_cu, occ) : occ;
         const int blocks = std::min(a.n_work, b->num_cu * per_cu);
         if (!forked) {
@@ -702,7 +720,7 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
           if (e == hipSuccess) e = hipEventRecord(b->ev_t0[u], cs);
           forked = true;
         }
-        if (e == hipSuccess) e = launch_kernel(b->precision, kernel, v == 1, a, blocks, cs);
+        if (e == hipSuccess) e = launch_kernel(b->precision, kernel, v, a, blocks, cs);
         if (e != hipSuccess) return hip_fail(b, e, "step launch");
       }
     }
@@ -820,13 +838,13 @@ extern "C" int string_batch_autotune(sb_batch *b, int64_t probe_steps, int32_t *
     return x == hipSuccess ? SB_OK : hip_fail(b, x, "autotune");
   };
   int occ[kNumUnits], nw[kNumUnits] = {};
-  for (int v = 0; v < 2; ++v)
-    for (int c = 0; c < kNumClasses; ++c)
-      nw[unit_of_class(c)] += (wp.off[v][c + 1] - wp.off[v][c]) / (kWave / kClassLanes[c]);
+  for (int v = 0; v < kNumVariants; ++v)
+    for (int q = 0; q < kNumParts; ++q)
+      nw[unit_of_class(q / kNumShapes)] += (wp.off[v][q + 1] - wp.off[v][q]) / (kWave / part_lanes(q));
   for (int u = 0; u < kNumUnits; ++u) {
     occ[u] = 1;
     for (int c = 0; c < kNumClasses; ++c)
-      if (unit_of_class(c) == u) occ[u] = std::max(occ[u], max_blocks_per_cu(b->precision, kernel_of_class(c), false));
+      if (unit_of_class(c) == u) occ[u] = std::max(occ[u], max_blocks_per_cu(b->precision, kernel_of_class(c), kVarPlain));
     b->blocks_per_cu[u] = occ[u];
     if (chosen) chosen[u] = 0;
   }

@@ -162,7 +162,7 @@ static void point_interp(double x, int N, int &n0, int &n1, double &w0, double &
   w1 = n1 ? w : 0.0;
 }
 
-int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
+int plan_string(const sb_string_params &p, Plan &P, std::string &err, bool shapes) {
   GridPlan g;
   int st = plan_grid(p, g, err);
   if (st) return st;
@@ -189,13 +189,22 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err) {
     err = "string exceeds the largest size class";
     return SB_EBUDGET;
   }
-  // every string of a class is laid out with the class's MM slots per lane
-  // (the kernel's loops run over MM slots whatever the string's length, so
-  // spreading a shorter string over fewer slots would save nothing); nodes
-  // past the string's end hold zeros
+  // a string of a class is laid out with the class's MM slots per lane on
+  // both grids (nodes past a grid's end hold zeros), or, where the kernels
+  // step half-width layouts (shapes), with MM/2 on a grid that fits in
+  // them: the stepping loops run over a grid's slots, so that grid then
+  // costs half
   const int G = kClassLanes[D.cls];
-  D.mt = kClassSlots[D.cls];
-  D.ml = kClassSlots[D.cls];
+  D.shape = 0;
+  if (shapes && D.cls < kShapedClasses) {
+    const int half = G * (kClassSlots[D.cls] / 2);
+    if (Nl <= half)
+      D.shape = 1;   // (also a string without a longitudinal grid)
+    else if (Nt <= half)
+      D.shape = 2;
+  }
+  D.mt = shape_mt(D.cls, D.shape);
+  D.ml = shape_ml(D.cls, D.shape);
   D.mon_check = p.mod_type == 0 ? 1 : 0;
   D.n_samples = p.n_samples;
   const double k = g.k, th = g.theta;

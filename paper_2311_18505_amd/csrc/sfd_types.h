@@ -30,6 +30,25 @@ constexpr int unit_of_class(int c) { return c < kNumSmall ? 0 : (c == kNumSmall 
 constexpr int kernel_of_class(int c) { return c < kNumSmall ? 0 : c - kNumSmall + 1; }
 constexpr int kNumKernels = kNumClasses - kNumSmall + 1;
 
+// Kernel instantiations by the code a string needs: plain (plucks and
+// two-node hammers), the bow family (bowed strings, clamped ends, the zeta
+// channel, cubic hammers) and the bow family with the cubic grid
+// interpolant.  Each carries only its own code, so a task pays only for the
+// registers of what its strings use.
+enum : int { kVarPlain = 0, kVarBow = 1, kVarCubic = 2, kNumVariants = 3 };
+
+// Layouts ("shapes") of a string in its class: shape 0 gives both grids the
+// class's MM slots per lane; shape 1 gives the longitudinal grid and shape 2
+// the transverse grid MM/2 slots, where that grid fits in them.  The stepping
+// loops run over a grid's slots, so a half-width grid does half the work.
+// FP32 batches, classes 0..4; FP64 batches and classes 5, 6 use shape 0.
+constexpr int kNumShapes = 3;
+constexpr int kShapedClasses = 5;
+constexpr int shape_mt(int c, int s) { return s == 2 ? kClassSlots[c] / 2 : kClassSlots[c]; }
+constexpr int shape_ml(int c, int s) { return s == 1 ? kClassSlots[c] / 2 : kClassSlots[c]; }
+// work lists are kept per part = class * kNumShapes + shape
+constexpr int kNumParts = kNumClasses * kNumShapes;
+
 enum : int32_t {
   kFlagUnstable = 1,      // energy monitor: non-finite or growing energy
   kFlagNoConverge = 2,    // coupled solve did not converge within the sweep cap
@@ -42,6 +61,8 @@ struct Desc {
   int32_t nt, nl;             // unknowns: Nt-1, Nl-1 (0)
   int32_t mt, ml;             // slots per lane of each grid (the class's MM)
   int32_t cls;                // size class index
+  int32_t shape;              // layout in the class (kNumShapes): mt, ml follow from it
+  int32_t shape_pad;
   int32_t mon_check;          // 1: energy must not grow (unforced, constant f0)
   int64_t n_samples;          // samples to produce
   void *st;                   // state block, kernel precision, lane-major [array][slot][lane]
@@ -133,9 +154,10 @@ struct LaunchArgs {
   Status *status;
   const int32_t *work;        // 64/G string indices per wavefront task (-1: empty group)
   int32_t n_work;             // number of wavefront tasks (tickets)
-  // unit 0: ticket w runs task tickets[w] & 0xffffff of class
-  // tickets[w] >> 24, whose tasks are listed at part_work[class]
-  const int32_t *part_work[kNumSmall];
+  // units 0 and 1: ticket w runs task tickets[w] & 0xffffff of part
+  // tickets[w] >> 24, whose tasks are listed at part_work[part] (unit 0:
+  // parts of classes 0..3; unit 1: the shapes of class 4)
+  const int32_t *part_work[kNumSmall * kNumShapes];
   const int32_t *tickets;
   int32_t *counter;           // work-queue head (zeroed before the launch)
   int64_t n_steps;            // steps to advance each string (clamped at n_samples)

@@ -189,13 +189,6 @@ __device__ __forceinline__ T ld_if(const P *p, int idx, bool ok) {
   return ok ? (T)v : T(0);
 }
 
-// p[idx] = v where ok, else the value goes to trash[tidx]: every lane stores.
-template <typename T>
-__device__ __forceinline__ void st_if(T *p, int idx, bool ok, T *trash, int tidx, T v) {
-  T *q = ok ? p + idx : trash + tidx;
-  *q = v;
-}
-
 // x[m-1] for a per-lane m >= 1 (no runtime register indexing).
 template <typename T, int MM>
 __device__ __forceinline__ T last_of(const T (&x)[MM], int m) {
@@ -353,9 +346,9 @@ struct Lds {
 };
 
 // Arrays per group: p and two tap arrays; the instantiation that carries the
-// bow also holds the cubic grid interpolant's two further tap arrays.
-template <bool BOW>
-constexpr int kLdsArrays = BOW ? 5 : 3;
+// cubic grid interpolant holds its two further tap arrays.
+template <bool CUB>
+constexpr int kLdsArrays = CUB ? 5 : 3;
 
 // MM per-lane values of a group: in registers, or (largest class) in LDS at
 // [r G] from the lane's entry, read where they are used.  With 16 slots per
@@ -541,11 +534,11 @@ struct EnergyLds {
 
 // Writes this lane's part of w^{n+1} = (u - cu, z - cz) and w^n = w^{n+1} - v
 // into the group's energy scratch; node 0 and the unused slots hold 0.
-template <int G, int MM, typename T>
-__device__ __forceinline__ void energy_fill(double *sD, const T (&u)[MM], const T (&vu)[MM], const T (&cu)[MM],
-                                            const T (&cvu)[MM], const T (&z)[MM], const T (&vz)[MM],
-                                            const T (&cz)[MM], const T (&cvz)[MM], int mt, int ml, int li) {
-  using E = EnergyLds<G, MM>;
+template <int G, int MT, int ML, typename T>
+__device__ __forceinline__ void energy_fill(double *sD, const T (&u)[MT], const T (&vu)[MT], const T (&cu)[MT],
+                                            const T (&cvu)[MT], const T (&z)[ML], const T (&vz)[ML],
+                                            const T (&cz)[ML], const T (&cvz)[ML], int li) {
+  using E = EnergyLds<G, (MT > ML ? MT : ML)>;
   double *U1 = sD, *U0 = sD + E::kArr, *Z1 = sD + 2 * E::kArr, *Z0 = sD + 3 * E::kArr;
   const int zero_at = li == 0 ? 0 : E::kTrash;
   U1[zero_at] = 0.0;
@@ -553,12 +546,15 @@ __device__ __forceinline__ void energy_fill(double *sD, const T (&u)[MM], const 
   Z1[zero_at] = 0.0;
   Z0[zero_at] = 0.0;
 #pragma unroll
-  for (int r = 0; r < MM; ++r) {
-    const int it = r < mt ? li * mt + r + 1 : E::kTrash;
+  for (int r = 0; r < MT; ++r) {
+    const int it = li * MT + r + 1;
     const double a1 = (double)u[r] - (double)cu[r];
     U1[it] = a1;
     U0[it] = a1 - ((double)vu[r] - (double)cvu[r]);
-    const int il = r < ml ? li * ml + r + 1 : E::kTrash;
+  }
+#pragma unroll
+  for (int r = 0; r < ML; ++r) {
+    const int il = li * ML + r + 1;
     const double b1 = (double)z[r] - (double)cz[r];
     Z1[il] = b1;
     Z0[il] = b1 - ((double)vz[r] - (double)cvz[r]);
@@ -570,7 +566,7 @@ __device__ __forceinline__ void energy_fill(double *sD, const T (&u)[MM], const 
 // plus the nonlinear potential (gamma^2 (alpha^2-1)/2)(p q^2/2 + q^4/8) in
 // the time-paired form of the scheme.  Streams over the lane's points
 // (runs once per monitor period).
-template <int G, int MM, typename T, bool CLAMP>
+template <int G, int MM, typename T, bool CLAMP, bool CUB>
 __device__ __forceinline__ double energy_fp64(const Desc &D, double g2k2, const double *sD, int li) {
   using E = EnergyLds<G, MM>;
   const double *U1 = sD, *U0 = sD + E::kArr, *Z1 = sD + 2 * E::kArr, *Z0 = sD + 3 * E::kArr;
@@ -601,8 +597,8 @@ __device__ __forceinline__ double energy_fp64(const Desc &D, double g2k2, const 
     const double pa1 = (Z1[ja] - Z1[ja - 1]) * Nld, pa0 = (Z0[ja] - Z0[ja - 1]) * Nld;
     const double pb1 = (Z1[jb] - Z1[jb - 1]) * Nld, pb0 = (Z0[jb] - Z0[jb - 1]) * Nld;
     double pt1 = (1.0 - w) * pa1 + w * pb1, pt0 = (1.0 - w) * pa0 + w * pb0;
-    if constexpr (CLAMP) {
-      // the cubic grid interpolant (same instantiation): taps ja .. ja+3
+    if constexpr (CUB) {
+      // the cubic grid interpolant: taps ja .. ja+3
       if (D.grid_interp == 3 && on) {
         const T *tfc = tf + (3 * mt + ml) * G;
         const double wc[4] = {w, (double)tfc[r * G + li], (double)tfc[(mt + r) * G + li],
@@ -640,25 +636,26 @@ __device__ __forceinline__ double energy_fp64(const Desc &D, double g2k2, const 
   return grp_reduce<G, false>(H);
 }
 
-// Stores the register state into the string's state block (slots past mt / ml
-// store into the trash block instead, so every lane stores).
-template <int G, typename T, int MM>
-__device__ __forceinline__ void store_state(T *st, T *trash, const T (&u)[MM], const T (&vu)[MM], const T (&cu)[MM],
-                                            const T (&cvu)[MM], const T (&z)[MM], const T (&vz)[MM],
-                                            const T (&cz)[MM], const T (&cvz)[MM], int mt, int ml, int li) {
-  const int zo = 4 * mt * G;
+// Stores the register state into the string's state block, laid out
+// [array][slot][lane] with MT slots per lane for u and ML for zeta.
+template <int G, typename T, int MT, int ML>
+__device__ __forceinline__ void store_state(T *st, const T (&u)[MT], const T (&vu)[MT], const T (&cu)[MT],
+                                            const T (&cvu)[MT], const T (&z)[ML], const T (&vz)[ML],
+                                            const T (&cz)[ML], const T (&cvz)[ML], int li) {
+  constexpr int zo = 4 * MT * G;
 #pragma unroll
-  for (int r = 0; r < MM; ++r) {
-    const bool ot = r < mt, ol = r < ml;
-    const int tr = r * G + li;
-    st_if<T>(st, (0 * mt + r) * G + li, ot, trash, tr, u[r]);
-    st_if<T>(st, (1 * mt + r) * G + li, ot, trash, tr, vu[r]);
-    st_if<T>(st, (2 * mt + r) * G + li, ot, trash, tr, cu[r]);
-    st_if<T>(st, (3 * mt + r) * G + li, ot, trash, tr, cvu[r]);
-    st_if<T>(st, zo + (0 * ml + r) * G + li, ol, trash, tr, z[r]);
-    st_if<T>(st, zo + (1 * ml + r) * G + li, ol, trash, tr, vz[r]);
-    st_if<T>(st, zo + (2 * ml + r) * G + li, ol, trash, tr, cz[r]);
-    st_if<T>(st, zo + (3 * ml + r) * G + li, ol, trash, tr, cvz[r]);
+  for (int r = 0; r < MT; ++r) {
+    st[(0 * MT + r) * G + li] = u[r];
+    st[(1 * MT + r) * G + li] = vu[r];
+    st[(2 * MT + r) * G + li] = cu[r];
+    st[(3 * MT + r) * G + li] = cvu[r];
+  }
+#pragma unroll
+  for (int r = 0; r < ML; ++r) {
+    st[zo + (0 * ML + r) * G + li] = z[r];
+    st[zo + (1 * ML + r) * G + li] = vz[r];
+    st[zo + (2 * ML + r) * G + li] = cz[r];
+    st[zo + (3 * ML + r) * G + li] = cvz[r];
   }
 }
 
@@ -683,9 +680,13 @@ __device__ __forceinline__ void poison_lds(V *p, int n, int li) {
 // One wavefront task: up to 64/G strings stepped together
 // ---------------------------------------------------------------------------
 
-template <int G, int MM, typename T, bool KAHAN, bool BOW>
+template <int G, int MT, int ML, typename T, bool KAHAN, bool BOW, bool CUB>
 __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *work, int task, T *sS, double *sE, T *sC,
                                          uint32_t *sTu, T *sTf, double *sB, T *sW) {
+  // MT and ML slots per lane on the transverse and longitudinal grids; LDS
+  // regions are laid out for the larger, MM
+  constexpr int MM = MT > ML ? MT : ML;
+  static_assert(MT == ML || (!kTabLds<MM> && !kSideComp<MM, T, KAHAN>), "LDS tables only with equal slot counts");
   const int lane = lane_id();
   const int li = lane & (G - 1), gi = lane / G;
   const int sidx = work[task * (kWave / G) + gi];
@@ -697,7 +698,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
 
   // ---- per-group constants (lane registers) ----
   const int nt = D.nt, nl = D.nl;
-  constexpr int mt = MM, ml = MM;   // every string is laid out with MM slots per lane
+  constexpr int mt = MT, ml = ML;   // slots per lane of the string's layout
   const int64_t n_samples = D.n_samples;
   const int64_t done = S->samples_done;
   const int64_t left = n_samples - done;
@@ -725,13 +726,13 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   // The hammer's interpolant I_H (two nodes, four with the cubic one) and
   // the readout's I(x_out) as per-slot weights of this lane, in LDS at
   // [lane][slot]: one multiply-add per slot and one group sum per use.
-  T *wH = sW + lane * MM, *wO = sW + kWave * MM + lane * MM;
-  using L = Lds<G, MM, kLdsArrays<BOW>>;
+  T *wH = sW + lane * MT, *wO = sW + kWave * MM + lane * MT;
+  using L = Lds<G, MM, kLdsArrays<CUB>>;
   if constexpr (kPoisonLds) {
     poison_lds<G>(sS + gi * L::kStride, L::kStride, li);
     poison_lds<G>(sE + gi * EnergyLds<G, MM>::kStride, EnergyLds<G, MM>::kStride, li);
-    poison_lds<1>(wH, MM, 0);
-    poison_lds<1>(wO, MM, 0);
+    poison_lds<1>(wH, MT, 0);
+    poison_lds<1>(wO, MT, 0);
     if constexpr (BOW) poison_lds<G>(sB + gi * kBowRec, kBowRec, li);
     if constexpr (kSideComp<MM, T, KAHAN>) poison_lds<G>(sC + gi * 4 * MM * G, 4 * MM * G, li);
     if constexpr (kTabLds<MM>) poison_lds<G>(sTf + gi * TabLds<G, MM, T>::kWordsT, TabLds<G, MM, T>::kWordsT, li);
@@ -744,8 +745,8 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     const int o0 = D.on0, o1 = D.on1;
     const double v0 = o0 ? D.ow0 : 0.0, v1 = o1 ? D.ow1 : 0.0;
 #pragma unroll
-    for (int r = 0; r < MM; ++r) {
-      const int node = li * MM + r + 1;
+    for (int r = 0; r < MT; ++r) {
+      const int node = li * MT + r + 1;
       wH[r] = (T)((node == h0 ? w0 : 0.0) + (node == h1 ? w1 : 0.0) + (node == h2 ? w2 : 0.0) + (node == h3 ? w3 : 0.0));
       wO[r] = (T)((node == o0 ? v0 : 0.0) + (node == o1 ? v1 : 0.0));
     }
@@ -782,23 +783,23 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     }
     gmax = __builtin_amdgcn_readfirstlane(gmax);
   }
-  // cubic grid interpolant (p = 3), only in the instantiation that carries the
-  // bow: a string's jab holds the base l-half point b of each t-half point
+  // cubic grid interpolant (p = 3), only in its own instantiation (one that
+  // also carries the bow's code): a string's jab holds the base l-half point b of each t-half point
   // (taps b .. b+3) and wi the first tap's weight; the other three weights and
   // the ranges of taps 2 and 3 follow the linear tables and are read from
   // memory where used
-  const bool cub = BOW && D.grid_interp == 3;
-  const bool any_cub = BOW && __ballot(cub) != 0;
+  const bool cub = CUB && D.grid_interp == 3;
+  const bool any_cub = CUB && __ballot(cub) != 0;
   const double g2k2_0 = D.g2k2_0, a2m1_4 = D.a2m1_4, a2d = D.a2, Ntdd = D.Ntd, kk = D.k * D.k;
   const int mon_check = D.mon_check;
 
   // ---- state and tables into registers ----
-  T u[MM], vu[MM], cu[MM], cvu[MM], z[MM], vz[MM], cz[MM], cvz[MM];
+  T u[MT], vu[MT], cu[MT], cvu[MT], z[ML], vz[ML], cz[ML], cvz[ML];
   constexpr bool kTL = kTabLds<MM>;
-  using TU = LaneTab<G, MM, uint32_t, kTL>;
-  using TF = LaneTab<G, MM, T, kTL>;
-  TU jab, rga, rgb;
-  TF wi, wbu, wbz, smt;
+  LaneTab<G, MT, uint32_t, kTL> jab;
+  LaneTab<G, ML, uint32_t, kTL> rga, rgb;
+  LaneTab<G, MT, T, kTL> wi, wbu, smt;
+  LaneTab<G, ML, T, kTL> wbz;
   if constexpr (kTL) {
     jab.p = sTu + gi * TabLds<G, MM, T>::kWordsU + li;
     rga.p = jab.p + MM * G;
@@ -813,25 +814,27 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   const uint32_t *tab = D.tab;
   const int zo = 4 * mt * G;
 #pragma unroll
-  for (int r = 0; r < MM; ++r) {
-    const bool ot = r < mt, ol = r < ml;
+  for (int r = 0; r < MT; ++r) {
     // without compensation the c arrays stay zero (constants the compiler folds)
-    u[r] = ld_if<T>(st, (0 * mt + r) * G + li, ot);
-    vu[r] = ld_if<T>(st, (1 * mt + r) * G + li, ot);
-    cu[r] = KAHAN ? ld_if<T>(st, (2 * mt + r) * G + li, ot) : T(0);
-    cvu[r] = KAHAN ? ld_if<T>(st, (3 * mt + r) * G + li, ot) : T(0);
-    z[r] = ld_if<T>(st, zo + (0 * ml + r) * G + li, ol);
-    vz[r] = ld_if<T>(st, zo + (1 * ml + r) * G + li, ol);
-    cz[r] = KAHAN ? ld_if<T>(st, zo + (2 * ml + r) * G + li, ol) : T(0);
-    cvz[r] = KAHAN ? ld_if<T>(st, zo + (3 * ml + r) * G + li, ol) : T(0);
-    jab.put(r, ot ? ld_if<uint32_t>(tab, r * G + li, ot) : 0x00010001u);
-    rga.put(r, ld_if<uint32_t>(tab, (mt + r) * G + li, ol));
-    rgb.put(r, ld_if<uint32_t>(tab, (mt + ml + r) * G + li, ol));
-    wi.put(r, ld_if<T>(tf, r * G + li, ot));
-    wbu.put(r, ld_if<T>(tf, (mt + r) * G + li, ot));
-    wbz.put(r, ld_if<T>(tf, (2 * mt + r) * G + li, ol));
+    u[r] = st[(0 * mt + r) * G + li];
+    vu[r] = st[(1 * mt + r) * G + li];
+    cu[r] = KAHAN ? st[(2 * mt + r) * G + li] : T(0);
+    cvu[r] = KAHAN ? st[(3 * mt + r) * G + li] : T(0);
+    jab.put(r, tab[r * G + li]);
+    wi.put(r, tf[r * G + li]);
+    wbu.put(r, tf[(mt + r) * G + li]);
     // Sherman-Morrison vector (zero without a hammer), kept in LDS
-    if constexpr (kTL) smt.put(r, ld_if<T>(tf, (2 * mt + ml + r) * G + li, ot));
+    if constexpr (kTL) smt.put(r, tf[(2 * mt + ml + r) * G + li]);
+  }
+#pragma unroll
+  for (int r = 0; r < ML; ++r) {
+    z[r] = st[zo + (0 * ml + r) * G + li];
+    vz[r] = st[zo + (1 * ml + r) * G + li];
+    cz[r] = KAHAN ? st[zo + (2 * ml + r) * G + li] : T(0);
+    cvz[r] = KAHAN ? st[zo + (3 * ml + r) * G + li] : T(0);
+    rga.put(r, tab[(mt + r) * G + li]);
+    rgb.put(r, tab[(mt + ml + r) * G + li]);
+    wbz.put(r, tf[(2 * mt + r) * G + li]);
   }
   const T *smv = tf + (2 * mt + ml) * G;   // Sherman-Morrison vector T_u0^{-1} J_H
   constexpr bool kSide = kSideComp<MM, T, KAHAN>;
@@ -847,7 +850,8 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   // (node masks); slopes, couplings and LDS contributions there vanish by
   // themselves, so no other predicate is needed.
   const int tb = li * mt, lb = li * ml;
-  NodeMask<MM, T, kTL> mask_t, mask_l;
+  NodeMask<MT, T, kTL> mask_t;
+  NodeMask<ML, T, kTL> mask_l;
   mask_t.init(tb, nt);
   mask_l.init(lb, nl);
 
@@ -879,7 +883,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   int mon_ctr = a.mon_period > 0 ? (int)(done % a.mon_period) : 1;
 
   T *gP = sS + gi * L::kStride, *gA = gP + L::kArr, *gB = gA + L::kArr;
-  T *gC = BOW ? gB + L::kArr : gB, *gD = BOW ? gC + L::kArr : gB;   // cubic taps 2 and 3
+  T *gC = CUB ? gB + L::kArr : gB, *gD = CUB ? gC + L::kArr : gB;   // cubic taps 2 and 3
   const T *tfc = tf + (3 * mt + ml) * G;          // cubic grid interpolant: weights 1..3 per t-slot
   const uint32_t *tabc = tab + (mt + 2 * ml) * G; // and the ranges of taps 2 and 3 per l-slot
   // weight k (1..3) of the cubic grid interpolant at t-slot r (0 elsewhere)
@@ -889,7 +893,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     const int ja = (int)(jab[r] & 0xffffu), jb = (int)(jab[r] >> 16);
     const T w = wi[r];
     T v = (T(1) - w) * sX[ja - 1] + w * sX[jb - 1];
-    if constexpr (BOW) {
+    if constexpr (CUB) {
       if (any_cub) {
         // taps b .. b+3 from the base b = ja; index ja + 2 stays inside the
         // group's array for every group
@@ -901,11 +905,11 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   };
   // the tap contributions of x at this lane's t-half points (the
   // instantiation that carries the bow sums them directly over the ranges)
-  auto tap_store = [&](const T (&x)[MM]) {
+  auto tap_store = [&](const T (&x)[MT]) {
 #pragma unroll
-    for (int r = 0; r < MM; ++r) {
+    for (int r = 0; r < MT; ++r) {
       const T w = wi[r];
-      if (BOW && any_cub) {
+      if (CUB && any_cub) {
         gA[tb + r] = (cub ? w : T(1) - w) * x[r];
         gB[tb + r] = (cub ? cw(1, r) : w) * x[r];
         gC[tb + r] = cw(2, r) * x[r];
@@ -917,19 +921,19 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     }
   };
   // I_(t)->(l) up to h_t/h_l at this lane's l-half points, summed directly
-  auto tap_gather = [&](T (&g)[MM]) {
-    gather_lt<MM, T>(g, gA, gB, rga, rgb, gmax);
-    if (BOW && any_cub) {
-      uint32_t rc[MM], rd[MM];
+  auto tap_gather = [&](T (&g)[ML]) {
+    gather_lt<ML, T>(g, gA, gB, rga, rgb, gmax);
+    if (CUB && any_cub) {
+      uint32_t rc[ML], rd[ML];
 #pragma unroll
-      for (int r = 0; r < MM; ++r) {
+      for (int r = 0; r < ML; ++r) {
         rc[r] = ld_if<uint32_t>(tabc, r * G + li, cub && r < ml);
         rd[r] = ld_if<uint32_t>(tabc, (ml + r) * G + li, cub && r < ml);
       }
-      T g2[MM];
-      gather_lt<MM, T>(g2, gC, gD, rc, rd, gmax);
+      T g2[ML];
+      gather_lt<ML, T>(g2, gC, gD, rc, rd, gmax);
 #pragma unroll
-      for (int r = 0; r < MM; ++r) g[r] += g2[r];
+      for (int r = 0; r < ML; ++r) g[r] += g2[r];
     }
   };
   double *gE = sE + gi * EnergyLds<G, MM>::kStride;
@@ -948,19 +952,22 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     const T aG = (T)(g2k2 * a2d);
 
     // ---- slopes q (t half points) and p (l half points) ----
-    T q[MM], p[MM];
+    T q[MT], p[ML];
     if constexpr (kSide) {
       side_load<G, MM, T>(cu, side, 0, li);
       side_load<G, MM, T>(cz, side, 2, li);
     }
     {
-      const T ul = grp_prev<G>(last_of<T, MM>(u, mt)), cl = grp_prev<G>(last_of<T, MM>(cu, mt));
-      const T zl = grp_prev<G>(last_of<T, MM>(z, ml)), czl = grp_prev<G>(last_of<T, MM>(cz, ml));
+      const T ul = grp_prev<G>(last_of<T, MT>(u, mt)), cl = grp_prev<G>(last_of<T, MT>(cu, mt));
+      const T zl = grp_prev<G>(last_of<T, ML>(z, ml)), czl = grp_prev<G>(last_of<T, ML>(cz, ml));
 #pragma unroll
-      for (int r = 0; r < MM; ++r) {
+      for (int r = 0; r < MT; ++r) {
         const T um = r == 0 ? ul : u[r > 0 ? r - 1 : 0];
         const T cm = r == 0 ? cl : cu[r > 0 ? r - 1 : 0];
         q[r] = ((u[r] - um) - (cu[r] - cm)) * Ntd;
+      }
+#pragma unroll
+      for (int r = 0; r < ML; ++r) {
         const T zm = r == 0 ? zl : z[r > 0 ? r - 1 : 0];
         const T czm = r == 0 ? czl : cz[r > 0 ? r - 1 : 0];
         p[r] = ((z[r] - zm) - (cz[r] - czm)) * Nld;
@@ -968,12 +975,12 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     }
 
     // ---- p~ = I_(l)->(t) p, and the transposed contributions of q^2 ----
-    T f[MM], q2[MM];
+    T f[MT], q2[MT];
 #pragma unroll
-    for (int r = 0; r < MM; ++r) gP[lb + r] = p[r];
+    for (int r = 0; r < ML; ++r) gP[lb + r] = p[r];
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < MM; ++r) {
+    for (int r = 0; r < MT; ++r) {
       const T pt = interp_lt(gP, r);
       q2[r] = q[r] * q[r];
       f[r] = q[r] * (q2[r] + T(2) * pt);
@@ -981,43 +988,43 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     if constexpr (BOW)
       tap_store(q2);
     else
-      prefix_store<G, MM, T>(gA, gB, q2, wi, tb, li, L::kTrash);
+      prefix_store<G, MT, T>(gA, gB, q2, wi, tb, li, L::kTrash);
     __syncthreads();
 
     // ---- right-hand side, transverse ----
-    T ru[MM], rz[MM];
+    T ru[MT], rz[ML];
     {
-      T c[MM];
+      T c[MT];
       const T qr = grp_next<G>(q[0]);
 #pragma unroll
-      for (int r = 0; r < MM; ++r) {
-        const T qn = (r + 1 < MM && r + 1 < mt) ? q[r + 1 < MM ? r + 1 : r] : qr;
+      for (int r = 0; r < MT; ++r) {
+        const T qn = (r + 1 < MT) ? q[r + 1 < MT ? r + 1 : r] : qr;
         c[r] = (qn - q[r]) * Ntd * mask_t[r];
       }
       // Curvature at the end nodes 0 and Nt: zero for simply supported ends;
       // for clamped ends the mirrored ghost slopes (q_0 = -q_1, q_{Nt+1} =
       // -q_Nt) give 2 q_1 Nt and -2 q_Nt Nt.  Slot nt holds q_Nt and stands
       // for node Nt; slots past it only feed rows the solve keeps at zero.
-      T cl = grp_prev<G>(last_of<T, MM>(c, mt));
+      T cl = grp_prev<G>(last_of<T, MT>(c, mt));
       if constexpr (BOW) {
         if (any_clamp) {
           const T e = clamped ? T(2) * Ntd : T(0);
 #pragma unroll
-          for (int r = 0; r < MM; ++r) c[r] = tb + r == nt ? -e * q[r] : c[r];
+          for (int r = 0; r < MT; ++r) c[r] = tb + r == nt ? -e * q[r] : c[r];
           cl = li == 0 ? e * q[0] : cl;
         }
       }
       const T cr = grp_next<G>(c[0]);
       const T fr = grp_next<G>(f[0]);
-      const T vl = grp_prev<G>(last_of<T, MM>(vu, mt)), vr = grp_next<G>(vu[0]);
+      const T vl = grp_prev<G>(last_of<T, MT>(vu, mt)), vr = grp_next<G>(vu[0]);
 #pragma unroll
-      for (int r = 0; r < MM; ++r) {
-        const bool nx = r + 1 < MM && r + 1 < mt;
+      for (int r = 0; r < MT; ++r) {
+        const bool nx = r + 1 < MT;
         const T cm = r == 0 ? cl : c[r > 0 ? r - 1 : 0];
-        const T cp = nx ? c[r + 1 < MM ? r + 1 : r] : cr;
-        const T fp = nx ? f[r + 1 < MM ? r + 1 : r] : fr;
+        const T cp = nx ? c[r + 1 < MT ? r + 1 : r] : cr;
+        const T fp = nx ? f[r + 1 < MT ? r + 1 : r] : fr;
         const T vm = r == 0 ? vl : vu[r > 0 ? r - 1 : 0];
-        const T vp = nx ? vu[r + 1 < MM ? r + 1 : r] : vr;
+        const T vp = nx ? vu[r + 1 < MT ? r + 1 : r] : vr;
         T acc = G2 * c[r] - cS * ((cp - T(2) * c[r]) + cm);
         acc = fma(T(2) * phi2 * Ntd, fp - f[r], acc);
         acc = fma(-s0t2, vu[r], acc);
@@ -1027,22 +1034,22 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     }
     // ---- right-hand side, longitudinal ----
     {
-      T g[MM];
+      T g[ML];
       if constexpr (BOW)
         tap_gather(g);
       else
-        prefix_gather<MM, T>(g, gA, gB, rga, rgb);
+        prefix_gather<ML, T>(g, gA, gB, rga, rgb);
 #pragma unroll
-      for (int r = 0; r < MM; ++r) g[r] *= ratio;
+      for (int r = 0; r < ML; ++r) g[r] *= ratio;
       const T pr = grp_next<G>(p[0]), gr = grp_next<G>(g[0]);
-      const T vl = grp_prev<G>(last_of<T, MM>(vz, ml)), vr = grp_next<G>(vz[0]);
+      const T vl = grp_prev<G>(last_of<T, ML>(vz, ml)), vr = grp_next<G>(vz[0]);
 #pragma unroll
-      for (int r = 0; r < MM; ++r) {
-        const bool nx = r + 1 < MM && r + 1 < ml;
-        const T pn = nx ? p[r + 1 < MM ? r + 1 : r] : pr;
-        const T gn = nx ? g[r + 1 < MM ? r + 1 : r] : gr;
+      for (int r = 0; r < ML; ++r) {
+        const bool nx = r + 1 < ML;
+        const T pn = nx ? p[r + 1 < ML ? r + 1 : r] : pr;
+        const T gn = nx ? g[r + 1 < ML ? r + 1 : r] : gr;
         const T vm = r == 0 ? vl : vz[r > 0 ? r - 1 : 0];
-        const T vp = nx ? vz[r + 1 < MM ? r + 1 : r] : vr;
+        const T vp = nx ? vz[r + 1 < ML ? r + 1 : r] : vr;
         T acc = aG * ((pn - p[r]) * Nld);
         acc = fma(T(2) * phi2 * Nld, gn - g[r], acc);
         acc = fma(-s0l2, vz[r], acc);
@@ -1052,22 +1059,24 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     }
 
     // ---- hammer: contact coefficient at time n, right-hand side 2 beta J eta^n ----
+    // (without contact anywhere in the wavefront the contact terms vanish:
+    // beta = 0, no right-hand side, and the lumped mass moves freely)
     double eta_n = 0.0, cH = 0.0, beta = 0.0;
     if (any_ham) {
       if constexpr (kSide) side_load<G, MM, T>(cu, side, 0, li);
-      const double Iu = (double)slot_dot<G, MM, T>(wH, u, cu);
+      const double Iu = (double)slot_dot<G, MT, T>(wH, u, cu);
       eta_n = ham ? uH_n - Iu : 0.0;
       const bool contact = eta_n > 0.0;
+      touched = (act && contact) ? 1 : touched;
       if (__ballot(contact) != 0) {
         const double cc = contact_coef(eta_n, omega_pow, alpha_H);
         cH = contact ? cc : 0.0;
-      }
-      touched = (act && contact) ? 1 : touched;
-      beta = kk * Mr * cH / (1.0 + kk * cH);
-      // right-hand side 2 beta J_H eta^n with J_H = I_H^T / h_t
-      const T addH = (T)(2.0 * beta * Ntdd * eta_n);
+        beta = kk * Mr * cH / (1.0 + kk * cH);
+        // right-hand side 2 beta J_H eta^n with J_H = I_H^T / h_t
+        const T addH = (T)(2.0 * beta * Ntdd * eta_n);
 #pragma unroll
-      for (int r = 0; r < MM; ++r) ru[r] = fma(wH[r], addH, ru[r]);
+        for (int r = 0; r < MT; ++r) ru[r] = fma(wH[r], addH, ru[r]);
+      }
     }
     const bool sm_on = beta != 0.0;
     const bool any_sm = __ballot(sm_on) != 0;
@@ -1100,12 +1109,12 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
       bR[kBowStepVB] = vB;
       bR[kBowStepK2F] = kk * FB;
       if constexpr (kSide) {
-        T cv[MM];
-        side_load<G, MM, T>(cv, side, 1, li);
-        bR[kBowStepIv] = point_eval<G, T, MM>(vu, cv, bn0, bw0, bn1, bw1) + point_eval<G, T, MM>(vu, cv, bn2, bw2, bn3, bw3);
+        T cv[MT];
+        side_load<G, MT, T>(cv, side, 1, li);
+        bR[kBowStepIv] = point_eval<G, T, MT>(vu, cv, bn0, bw0, bn1, bw1) + point_eval<G, T, MT>(vu, cv, bn2, bw2, bn3, bw3);
       } else {
         bR[kBowStepIv] =
-            point_eval<G, T, MM>(vu, cvu, bn0, bw0, bn1, bw1) + point_eval<G, T, MM>(vu, cvu, bn2, bw2, bn3, bw3);
+            point_eval<G, T, MT>(vu, cvu, bn0, bw0, bn1, bw1) + point_eval<G, T, MT>(vu, cvu, bn2, bw2, bn3, bw3);
       }
       bR[kBowStepW2] = bw2;
       bR[kBowStepW3] = bw3;
@@ -1118,27 +1127,28 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     }
 
     // ---- coupled solve: block Gauss-Seidel around T_u0 (+ hammer) and T_z ----
-    T smr[MM], zero[MM];
+    T smr[MT], zero[MT], zero_l[ML];
 #pragma unroll
-    for (int r = 0; r < MM; ++r) {
+    for (int r = 0; r < MT; ++r) {
       zero[r] = T(0);
       smr[r] = T(0);
     }
+#pragma unroll
+    for (int r = 0; r < ML; ++r) zero_l[r] = T(0);
     if (!kTL && any_sm) {
 #pragma unroll
-      for (int r = 0; r < MM; ++r) smr[r] = ld_if<T>(smv, r * G + li, sm_on);
+      for (int r = 0; r < MT; ++r) smr[r] = ld_if<T>(smv, r * G + li, sm_on);
     }
-    const T smfac = (T)(beta / (1.0 + beta * IHs));
+    const T smfac = any_sm ? (T)(beta / (1.0 + beta * IHs)) : T(0);
     // One solve of the step's coupled system A [a_u; a_z] = [f_u; f_z] (the
     // hammer's rank-one term included when `hammer`); returns this group's
     // sweeps and whether it converged.
-    auto gs_solve = [&](const T (&fu)[MM], const T (&fz)[MM], bool hammer, T (&au)[MM], T (&az)[MM],
+    auto gs_solve = [&](const T (&fu)[MT], const T (&fz)[ML], bool hammer, T (&au)[MT], T (&az)[ML],
                         bool &conv) -> int {
 #pragma unroll
-      for (int r = 0; r < MM; ++r) {
-        au[r] = T(0);
-        az[r] = T(0);
-      }
+      for (int r = 0; r < MT; ++r) au[r] = T(0);
+#pragma unroll
+      for (int r = 0; r < ML; ++r) az[r] = T(0);
       conv = false;            // this group's iterates are final
       int sweeps = 0;
       T ascale = T(0);         // tol x the group's largest value after the first sweep
@@ -1147,22 +1157,22 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
       for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
         // transverse right-hand side with the current coupling terms:
         // e = q (q D_x- a_u + I_(l)->(t) D_x- a_z), b_u = r_u + phi^2 D_x+ e
-        T bu[MM];
+        T bu[MT];
         if (sweep == 0) {
   #pragma unroll
-          for (int r = 0; r < MM; ++r) bu[r] = fu[r];
+          for (int r = 0; r < MT; ++r) bu[r] = fu[r];
         } else {
-          const T al = grp_prev<G>(last_of<T, MM>(au, mt));
-          const T zl = grp_prev<G>(last_of<T, MM>(az, ml));
+          const T al = grp_prev<G>(last_of<T, MT>(au, mt));
+          const T zl = grp_prev<G>(last_of<T, ML>(az, ml));
   #pragma unroll
-          for (int r = 0; r < MM; ++r) {
+          for (int r = 0; r < ML; ++r) {
             const T zm = r == 0 ? zl : az[r > 0 ? r - 1 : 0];
             gP[lb + r] = (az[r] - zm) * Nld;
           }
           __syncthreads();
-          T e[MM];
+          T e[MT];
   #pragma unroll
-          for (int r = 0; r < MM; ++r) {
+          for (int r = 0; r < MT; ++r) {
             const T am = r == 0 ? al : au[r > 0 ? r - 1 : 0];
             const T d = (au[r] - am) * Ntd;
             const T idz = interp_lt(gP, r);
@@ -1171,27 +1181,27 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
           __syncthreads();
           const T er = grp_next<G>(e[0]);
   #pragma unroll
-          for (int r = 0; r < MM; ++r) {
-            const T en = (r + 1 < MM && r + 1 < mt) ? e[r + 1 < MM ? r + 1 : r] : er;
+          for (int r = 0; r < MT; ++r) {
+            const T en = (r + 1 < MT) ? e[r + 1 < MT ? r + 1 : r] : er;
             bu[r] = fma(phi2 * Ntd, en - e[r], fu[r]);
           }
         }
-        T nu[MM];
-        toeplitz_solve<G, T, MM>(nu, bu, wbu, mask_t, rho_t, itk_t, spt);
+        T nu[MT];
+        toeplitz_solve<G, T, MT>(nu, bu, wbu, mask_t, rho_t, itk_t, spt);
         if (hammer && any_sm) {
           // Sherman-Morrison for the rank-one hammer term beta J I
-          const T Iy = slot_dot<G, MM, T>(wH, nu, zero);
+          const T Iy = slot_dot<G, MT, T>(wH, nu, zero);
           const T fac = smfac * Iy;
   #pragma unroll
-          for (int r = 0; r < MM; ++r) nu[r] = fma(-fac, kTL ? (sm_on ? smt[r] : T(0)) : smr[r], nu[r]);
+          for (int r = 0; r < MT; ++r) nu[r] = fma(-fac, kTL ? (sm_on ? smt[r] : T(0)) : smr[r], nu[r]);
         }
         // longitudinal right-hand side: r_z + phi^2 D_x+ I_(t)->(l) (q D_x- a_u)
-        T gg[MM];
+        T gg[ML];
         {
-          const T al = grp_prev<G>(last_of<T, MM>(nu, mt));
-          T fq[MM];
+          const T al = grp_prev<G>(last_of<T, MT>(nu, mt));
+          T fq[MT];
   #pragma unroll
-          for (int r = 0; r < MM; ++r) {
+          for (int r = 0; r < MT; ++r) {
             const T am = r == 0 ? al : nu[r > 0 ? r - 1 : 0];
             fq[r] = q[r] * ((nu[r] - am) * Ntd);
           }
@@ -1200,23 +1210,23 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
             __syncthreads();
             tap_gather(gg);
           } else {
-            prefix_store<G, MM, T>(gA, gB, fq, wi, tb, li, L::kTrash);
+            prefix_store<G, MT, T>(gA, gB, fq, wi, tb, li, L::kTrash);
             __syncthreads();
-            prefix_gather<MM, T>(gg, gA, gB, rga, rgb);
+            prefix_gather<ML, T>(gg, gA, gB, rga, rgb);
           }
           __syncthreads();
   #pragma unroll
-          for (int r = 0; r < MM; ++r) gg[r] *= ratio;
+          for (int r = 0; r < ML; ++r) gg[r] *= ratio;
         }
         const T gr = grp_next<G>(gg[0]);
-        T bz[MM];
+        T bz[ML];
   #pragma unroll
-        for (int r = 0; r < MM; ++r) {
-          const T gn = (r + 1 < MM && r + 1 < ml) ? gg[r + 1 < MM ? r + 1 : r] : gr;
+        for (int r = 0; r < ML; ++r) {
+          const T gn = (r + 1 < ML) ? gg[r + 1 < ML ? r + 1 : r] : gr;
           bz[r] = fma(phi2 * Nld, gn - gg[r], fz[r]);
         }
-        T nz[MM];
-        toeplitz_solve<G, T, MM>(nz, bz, wbz, mask_l, rho_l, itk_l, spl);
+        T nz[ML];
+        toeplitz_solve<G, T, ML>(nz, bz, wbz, mask_l, rho_l, itk_l, spl);
         // convergence of this group, from the second sweep on (a string without
         // a longitudinal grid is solved exactly by the first).  Block
         // Gauss-Seidel contracts the error by rho per sweep, and rho is
@@ -1230,7 +1240,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
           if (sweep == 0) {
             T amax = T(0);
   #pragma unroll
-            for (int r = 0; r < MM; ++r) amax = fmax(amax, fmax(fabs(nu[r]), fabs(nz[r])));
+            for (int r = 0; r < MT; ++r) amax = fmax(amax, fabs(nu[r]));
+  #pragma unroll
+            for (int r = 0; r < ML; ++r) amax = fmax(amax, fabs(nz[r]));
             const T A = grp_reduce<G, true>(amax);
             // the instantiation that carries the bow stops on the update alone,
             // at 100 tol in FP32 (an update of 1e-5 leaves an error of about
@@ -1240,7 +1252,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
           } else {
             T delta = T(0);
   #pragma unroll
-            for (int r = 0; r < MM; ++r) delta = fmax(delta, fmax(fabs(nu[r] - au[r]), fabs(nz[r] - az[r])));
+            for (int r = 0; r < MT; ++r) delta = fmax(delta, fabs(nu[r] - au[r]));
+  #pragma unroll
+            for (int r = 0; r < ML; ++r) delta = fmax(delta, fabs(nz[r] - az[r]));
             const T dmax = grp_reduce<G, true>(delta);
             const T dn = dmax * iscale;
             // (the instantiation that carries the bow stops on the update alone:
@@ -1252,16 +1266,14 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
         }
         if (__ballot(conv) != 0) {
   #pragma unroll
-          for (int r = 0; r < MM; ++r) {
-            au[r] = conv ? au[r] : nu[r];
-            az[r] = conv ? az[r] : nz[r];
-          }
+          for (int r = 0; r < MT; ++r) au[r] = conv ? au[r] : nu[r];
+  #pragma unroll
+          for (int r = 0; r < ML; ++r) az[r] = conv ? az[r] : nz[r];
         } else {
   #pragma unroll
-          for (int r = 0; r < MM; ++r) {
-            au[r] = nu[r];
-            az[r] = nz[r];
-          }
+          for (int r = 0; r < MT; ++r) au[r] = nu[r];
+  #pragma unroll
+          for (int r = 0; r < ML; ++r) az[r] = nz[r];
         }
         sweeps = conv ? sweeps : sweep + 1;
         conv = conv || now;
@@ -1269,7 +1281,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
       }
       return sweeps;
     };
-    T au[MM], az[MM];
+    T au[MT], az[ML];
     bool conv;
     int sweeps = gs_solve(ru, rz, true, au, az, conv);
     if constexpr (BOW) {
@@ -1281,30 +1293,29 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
         const int bn0 = (int)bR[kBowStepN0], bn1 = (int)bR[kBowStepN1];
         const int bn2 = (int)bR[kBowStepN2], bn3 = (int)bR[kBowStepN3];
         const double bw0 = bR[kBowStepW0], bw1 = bR[kBowStepW1], bw2 = bR[kBowStepW2], bw3 = bR[kBowStepW3];
-        T fb[MM], du[MM], dz[MM];
+        T fb[MT], du[MT], dz[ML];
 #pragma unroll
-        for (int r = 0; r < MM; ++r) {
+        for (int r = 0; r < MT; ++r) {
           // J_p = I_p^T / h_t (a node listed once, cubic ghosts folded in by the weights)
           const int i = tb + r + 1;
           fb[r] = ((i == bn0 ? (T)(bw0 * (nt + 1)) : T(0)) + (i == bn1 ? (T)(bw1 * (nt + 1)) : T(0))) +
                   ((i == bn2 ? (T)(bw2 * (nt + 1)) : T(0)) + (i == bn3 ? (T)(bw3 * (nt + 1)) : T(0)));
         }
         bool convd;
-        sweeps += gs_solve(fb, zero, false, du, dz, convd);
+        sweeps += gs_solve(fb, zero_l, false, du, dz, convd);
         conv = conv && convd;
         const double Ia =
-            point_eval<G, T, MM>(au, zero, bn0, bw0, bn1, bw1) + point_eval<G, T, MM>(au, zero, bn2, bw2, bn3, bw3);
+            point_eval<G, T, MT>(au, zero, bn0, bw0, bn1, bw1) + point_eval<G, T, MT>(au, zero, bn2, bw2, bn3, bw3);
         const double Id =
-            point_eval<G, T, MM>(du, zero, bn0, bw0, bn1, bw1) + point_eval<G, T, MM>(du, zero, bn2, bw2, bn3, bw3);
+            point_eval<G, T, MT>(du, zero, bn0, bw0, bn1, bw1) + point_eval<G, T, MT>(du, zero, bn2, bw2, bn3, bw3);
         const double bb = (Ia + 2.0 * bR[kBowStepIv]) / (2.0 * D.k) - bR[kBowStepVB];
         const double c = 0.5 * bR[kBowStepK2F] / D.k * Id;
         const double phi = bow_phi(bb, c, bR[kBowA], bR[kBowEps]);
         const T f = (T)(bR[kBowStepK2F] * phi);
 #pragma unroll
-        for (int r = 0; r < MM; ++r) {
-          au[r] = fma(-f, du[r], au[r]);
-          az[r] = fma(-f, dz[r], az[r]);
-        }
+        for (int r = 0; r < MT; ++r) au[r] = fma(-f, du[r], au[r]);
+#pragma unroll
+        for (int r = 0; r < ML; ++r) az[r] = fma(-f, dz[r], az[r]);
       }
     }
     flags |= (act && !conv) ? kFlagNoConverge : 0;
@@ -1320,25 +1331,31 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     }
     if (__ballot(!act) == 0) {
 #pragma unroll
-      for (int r = 0; r < MM; ++r) {
+      for (int r = 0; r < MT; ++r) {
         kahan_add<T, KAHAN>(vu[r], cvu[r], au[r]);
         update_pos<T, KAHAN>(u[r], cu[r], vu[r], cvu[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < ML; ++r) {
         kahan_add<T, KAHAN>(vz[r], cvz[r], az[r]);
         update_pos<T, KAHAN>(z[r], cz[r], vz[r], cvz[r]);
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < MM; ++r) {
+      for (int r = 0; r < MT; ++r) {
         T nu_ = u[r], nvu = vu[r], ncu = cu[r], ncvu = cvu[r];
         kahan_add<T, KAHAN>(nvu, ncvu, au[r]);
         update_pos<T, KAHAN>(nu_, ncu, nvu, ncvu);
-        T nz_ = z[r], nvz = vz[r], ncz = cz[r], ncvz = cvz[r];
-        kahan_add<T, KAHAN>(nvz, ncvz, az[r]);
-        update_pos<T, KAHAN>(nz_, ncz, nvz, ncvz);
         u[r] = act ? nu_ : u[r];
         vu[r] = act ? nvu : vu[r];
         cu[r] = act ? ncu : cu[r];
         cvu[r] = act ? ncvu : cvu[r];
+      }
+#pragma unroll
+      for (int r = 0; r < ML; ++r) {
+        T nz_ = z[r], nvz = vz[r], ncz = cz[r], ncvz = cvz[r];
+        kahan_add<T, KAHAN>(nvz, ncvz, az[r]);
+        update_pos<T, KAHAN>(nz_, ncz, nvz, ncvz);
         z[r] = act ? nz_ : z[r];
         vz[r] = act ? nvz : vz[r];
         cz[r] = act ? ncz : cz[r];
@@ -1355,8 +1372,11 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
 
     // ---- hammer lumped mass (eq. 6) ----
     if (any_ham) {
-      const double Iu1 = (double)slot_dot<G, MM, T>(wH, u, cu);
-      const double uH_np1 = (2.0 * uH_n - uH_nm1 - kk * cH * (eta_nm1 - Iu1)) / (1.0 + kk * cH);
+      double uH_np1 = 2.0 * uH_n - uH_nm1;
+      if (any_sm) {
+        const double Iu1 = (double)slot_dot<G, MT, T>(wH, u, cu);
+        uH_np1 = (2.0 * uH_n - uH_nm1 - kk * cH * (eta_nm1 - Iu1)) / (1.0 + kk * cH);
+      }
       const bool upd = act && ham;
       uH_nm1 = upd ? uH_n : uH_nm1;
       uH_n = upd ? uH_np1 : uH_n;
@@ -1365,13 +1385,13 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
 
     // ---- readout y^{n+1} = I(x_out) u^{n+1} into the group's ring of G samples ----
     const int64_t m = n + 1;
-    const T y = slot_dot<G, MM, T>(wO, u, cu);
+    const T y = slot_dot<G, MT, T>(wO, u, cu);
     const int slot = (int)((m - first_m) & (G - 1));
     ring = (act && li == slot) ? y : ring;
     // second channel: zeta^{n+1} at x_out on the longitudinal grid
     if constexpr (BOW) {
       if (any_zout) {
-        const double yz = point_eval<G, T, MM>(z, cz, D.zon0, D.zon0 ? 1.0 - D.zw : 0.0, D.zon1,
+        const double yz = point_eval<G, T, ML>(z, cz, D.zon0, D.zon0 ? 1.0 - D.zw : 0.0, D.zon1,
                                                D.zon1 ? D.zw : 0.0);
         ring_z = (act && li == slot) ? (T)yz : ring_z;
       }
@@ -1387,9 +1407,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
         side_load<G, MM, T>(cz, side, 2, li);
         side_load<G, MM, T>(cvz, side, 3, li);
       }
-      energy_fill<G, MM, T>(gE, u, vu, cu, cvu, z, vz, cz, cvz, mt, ml, li);
+      energy_fill<G, MT, ML, T>(gE, u, vu, cu, cvu, z, vz, cz, cvz, li);
       __syncthreads();
-      const double H = energy_fp64<G, MM, T, BOW>(D, g2k2, gE, li);
+      const double H = energy_fp64<G, MM, T, BOW, CUB>(D, g2k2, gE, li);
       __syncthreads();
       H_last = mon_now ? H : H_last;
       H_step = mon_now ? n : H_step;
@@ -1428,7 +1448,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     side_load<G, MM, T>(cz, side, 2, li);
     side_load<G, MM, T>(cvz, side, 3, li);
   }
-  store_state<G, T, MM>(present ? st : trash, trash, u, vu, cu, cvu, z, vz, cz, cvz, mt, ml, li);
+  store_state<G, T, MT, ML>(present ? st : trash, u, vu, cu, cvu, z, vz, cz, cvz, li);
   Sw->samples_done = done + steps_done;
   Sw->flags = flags;
   Sw->max_sweeps = max_sw;
@@ -1450,14 +1470,19 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
 template <int MM, typename T>
 constexpr int kWavesPerEU = (sizeof(T) == 4 && MM <= 4) ? 2 : 1;
 
+// FP32 instantiations step the half-width shapes as well (FP64 batches lay
+// every string out with shape 0)
+template <typename T>
+constexpr bool kShapes = sizeof(T) == 4;
+
 // BOW: the instantiation for tasks with bowed or clamped strings or the
 // zeta channel (the host keeps them in work lists of their own); the other
 // instantiation has no code for any of them.
-template <int G, int MM, typename T, bool KAHAN, bool BOW>
+template <int G, int MM, typename T, bool KAHAN, bool BOW, bool CUB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<MM, T>))) void step_kernel(
     LaunchArgs a) {
   constexpr int kGroups = kWave / G;
-  using L = Lds<G, MM, kLdsArrays<BOW>>;
+  using L = Lds<G, MM, kLdsArrays<CUB>>;
   // the energy monitor's scratch overlays the stepping arrays (never live together)
   constexpr int kStepDoubles = (kGroups * L::kStride * (int)sizeof(T) + 7) / 8;
   constexpr int kEnergyDoubles = kGroups * EnergyLds<G, MM>::kStride;
@@ -1481,7 +1506,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
     int w = atomicAdd(a.counter, lane_id() == 0 ? 1 : 0);
     w = __builtin_amdgcn_readfirstlane(w);
     if (w >= a.n_work) break;
-    run_task<G, MM, T, KAHAN, BOW>(a, a.work, w, sS, sE, sC, sTu, sTf, lds_bow, lds_w);
+    if constexpr (MM <= 8) {
+      // class 4: the ticket names the shape and its task
+      const int m = __builtin_amdgcn_readfirstlane(a.tickets[w]), t = m & 0xffffff;
+      switch (m >> 24) {
+        case 1:
+          if constexpr (kShapes<T>)
+            run_task<G, MM, MM / 2, T, KAHAN, BOW, CUB>(a, a.part_work[1], t, sS, sE, sC, sTu, sTf, lds_bow, lds_w);
+          break;
+        case 2:
+          if constexpr (kShapes<T>)
+            run_task<G, MM / 2, MM, T, KAHAN, BOW, CUB>(a, a.part_work[2], t, sS, sE, sC, sTu, sTf, lds_bow, lds_w);
+          break;
+        default:
+          run_task<G, MM, MM, T, KAHAN, BOW, CUB>(a, a.part_work[0], t, sS, sE, sC, sTu, sTf, lds_bow, lds_w);
+          break;
+      }
+    } else {
+      run_task<G, MM, MM, T, KAHAN, BOW, CUB>(a, a.work, w, sS, sE, sC, sTu, sTf, lds_bow, lds_w);
+    }
   }
 }
 
@@ -1489,9 +1532,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
 // over their tasks in the order the host chose (estimated work, longest
 // first), so that the short tasks fill the tail.  They share the occupancy
 // target and need neither LDS tables nor LDS compensation.
-template <typename T, bool BOW>
+template <typename T, bool CUB>
 constexpr int small_lds_doubles() {
-  constexpr int n = kLdsArrays<BOW>;
+  constexpr int n = kLdsArrays<CUB>;
   constexpr int a = (Lds<64, 4, n>::kStride * (int)sizeof(T) + 7) / 8, ae = EnergyLds<64, 4>::kStride;
   constexpr int b = (2 * Lds<32, 4, n>::kStride * (int)sizeof(T) + 7) / 8, be = 2 * EnergyLds<32, 4>::kStride;
   constexpr int c = (4 * Lds<16, 4, n>::kStride * (int)sizeof(T) + 7) / 8, ce = 4 * EnergyLds<16, 4>::kStride;
@@ -1501,12 +1544,12 @@ constexpr int small_lds_doubles() {
   return m12 > m34 ? m12 : m34;
 }
 
-template <typename T, bool KAHAN, bool BOW>
+template <typename T, bool KAHAN, bool BOW, bool CUB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<4, T>))) void step_kernel_small(
     LaunchArgs a) {
   static_assert(kWavesPerEU<2, T> == kWavesPerEU<4, T>, "one occupancy target for the merged classes");
   static_assert(!kSideComp<4, T, KAHAN> && !kTabLds<4>, "no LDS tables in the merged classes");
-  __shared__ double lds[small_lds_doubles<T, BOW>()];
+  __shared__ double lds[small_lds_doubles<T, CUB>()];
   __shared__ double lds_bow[BOW ? 4 * kBowRec : 1];   // up to four groups per wavefront
   __shared__ T lds_w[2 * 4 * kWave];                    // per-slot weights of the point interpolants
   T *sS = (T *)lds;
@@ -1516,12 +1559,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
     w = __builtin_amdgcn_readfirstlane(w);
     if (w >= a.n_work) break;
     const int m = __builtin_amdgcn_readfirstlane(a.tickets[w]), t = m & 0xffffff;
+    // part = class * kNumShapes + shape
+#define SFD_PART(P, G_, MT_, ML_)                                                                              \
+  case P:                                                                                                     \
+    if constexpr (kShapes<T> || (MT_ == ML_))                                                                 \
+      run_task<G_, MT_, ML_, T, KAHAN, BOW, CUB>(a, a.part_work[P], t, sS, sE, sS, nullptr, nullptr, lds_bow, \
+                                                 lds_w);                                                      \
+    break;
     switch (m >> 24) {
-      case 3: run_task<64, 4, T, KAHAN, BOW>(a, a.part_work[3], t, sS, sE, sS, nullptr, nullptr, lds_bow, lds_w); break;
-      case 2: run_task<32, 4, T, KAHAN, BOW>(a, a.part_work[2], t, sS, sE, sS, nullptr, nullptr, lds_bow, lds_w); break;
-      case 1: run_task<16, 4, T, KAHAN, BOW>(a, a.part_work[1], t, sS, sE, sS, nullptr, nullptr, lds_bow, lds_w); break;
-      default: run_task<16, 2, T, KAHAN, BOW>(a, a.part_work[0], t, sS, sE, sS, nullptr, nullptr, lds_bow, lds_w); break;
+      SFD_PART(9, 64, 4, 4)
+      SFD_PART(10, 64, 4, 2)
+      SFD_PART(11, 64, 2, 4)
+      SFD_PART(6, 32, 4, 4)
+      SFD_PART(7, 32, 4, 2)
+      SFD_PART(8, 32, 2, 4)
+      SFD_PART(3, 16, 4, 4)
+      SFD_PART(4, 16, 4, 2)
+      SFD_PART(5, 16, 2, 4)
+      SFD_PART(1, 16, 2, 1)
+      SFD_PART(2, 16, 1, 2)
+      default:
+        run_task<16, 2, 2, T, KAHAN, BOW, CUB>(a, a.part_work[0], t, sS, sE, sS, nullptr, nullptr, lds_bow, lds_w);
+        break;
     }
+#undef SFD_PART
   }
 }
 
@@ -1606,24 +1667,31 @@ hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const 
   return hipGetLastError();
 }
 
-template <typename T, bool KAHAN, bool BOW>
+template <typename T, bool KAHAN, bool BOW, bool CUB>
 static hipError_t launch_kernel_t(int kernel, const LaunchArgs &a, int blocks, hipStream_t st) {
   switch (kernel) {
-    case 0: hipLaunchKernelGGL((step_kernel_small<T, KAHAN, BOW>), dim3(blocks), dim3(64), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((step_kernel<64, 8, T, KAHAN, BOW>), dim3(blocks), dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((step_kernel<64, 10, T, KAHAN, BOW>), dim3(blocks), dim3(64), 0, st, a); break;
-    default: hipLaunchKernelGGL((step_kernel<64, 16, T, KAHAN, BOW>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 0: hipLaunchKernelGGL((step_kernel_small<T, KAHAN, BOW, CUB>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((step_kernel<64, 8, T, KAHAN, BOW, CUB>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((step_kernel<64, 10, T, KAHAN, BOW, CUB>), dim3(blocks), dim3(64), 0, st, a); break;
+    default: hipLaunchKernelGGL((step_kernel<64, 16, T, KAHAN, BOW, CUB>), dim3(blocks), dim3(64), 0, st, a); break;
   }
   return hipGetLastError();
 }
 
-// kernel: 0 the merged classes 0..3, 1..3 the classes 4..6 (kernel_of_class)
-hipError_t launch_kernel(int precision, int kernel, bool bow, const LaunchArgs &a, int blocks, hipStream_t st) {
-  if (precision == 1)
-    return bow ? launch_kernel_t<float, true, true>(kernel, a, blocks, st)
-               : launch_kernel_t<float, true, false>(kernel, a, blocks, st);
-  return bow ? launch_kernel_t<double, false, true>(kernel, a, blocks, st)
-             : launch_kernel_t<double, false, false>(kernel, a, blocks, st);
+template <typename T, bool KAHAN>
+static hipError_t launch_kernel_v(int kernel, int variant, const LaunchArgs &a, int blocks, hipStream_t st) {
+  switch (variant) {
+    case kVarPlain: return launch_kernel_t<T, KAHAN, false, false>(kernel, a, blocks, st);
+    case kVarBow: return launch_kernel_t<T, KAHAN, true, false>(kernel, a, blocks, st);
+    default: return launch_kernel_t<T, KAHAN, true, true>(kernel, a, blocks, st);
+  }
+}
+
+// kernel: 0 the merged classes 0..3, 1..3 the classes 4..6 (kernel_of_class);
+// variant: kVarPlain, kVarBow or kVarCubic
+hipError_t launch_kernel(int precision, int kernel, int variant, const LaunchArgs &a, int blocks, hipStream_t st) {
+  if (precision == 1) return launch_kernel_v<float, true>(kernel, variant, a, blocks, st);
+  return launch_kernel_v<double, false>(kernel, variant, a, blocks, st);
 }
 
 // Holds its stream for `ticks` of the constant-rate wall clock and exits
@@ -1647,15 +1715,15 @@ hipError_t launch_zero(int32_t *c, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T, bool KAHAN, bool BOW>
+template <typename T, bool KAHAN, bool BOW, bool CUB>
 static int blocks_per_cu(int kernel) {
   int n = 0;
   hipError_t e;
   switch (kernel) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_small<T, KAHAN, BOW>, 64, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 8, T, KAHAN, BOW>, 64, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 10, T, KAHAN, BOW>, 64, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 16, T, KAHAN, BOW>, 64, 0); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_small<T, KAHAN, BOW, CUB>, 64, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 8, T, KAHAN, BOW, CUB>, 64, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 10, T, KAHAN, BOW, CUB>, 64, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<64, 16, T, KAHAN, BOW, CUB>, 64, 0); break;
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -1664,9 +1732,18 @@ static int blocks_per_cu(int kernel) {
   return n;
 }
 
-int max_blocks_per_cu(int precision, int kernel, bool bow) {
-  if (precision == 1) return bow ? blocks_per_cu<float, true, true>(kernel) : blocks_per_cu<float, true, false>(kernel);
-  return bow ? blocks_per_cu<double, false, true>(kernel) : blocks_per_cu<double, false, false>(kernel);
+template <typename T, bool KAHAN>
+static int blocks_per_cu_v(int kernel, int variant) {
+  switch (variant) {
+    case kVarPlain: return blocks_per_cu<T, KAHAN, false, false>(kernel);
+    case kVarBow: return blocks_per_cu<T, KAHAN, true, false>(kernel);
+    default: return blocks_per_cu<T, KAHAN, true, true>(kernel);
+  }
+}
+
+int max_blocks_per_cu(int precision, int kernel, int variant) {
+  if (precision == 1) return blocks_per_cu_v<float, true>(kernel, variant);
+  return blocks_per_cu_v<double, false>(kernel, variant);
 }
 
 }  // namespace sfd
