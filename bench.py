@@ -39,8 +39,8 @@ PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 2.4 GHz x 25
 # (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a
 # 512 MiB device copy (x2.000 and x1.000); profiles/hbm_traffic_uneven16384.md.
 # Valid only for the kernel sources it was measured on (kernel_source_hash).
-TRAFFIC = {"kernel": "step_kernel_small<float, true>", "source_sha256": "bc9d5ff483ce2a72",
-           "fetch_bytes": 234.42e9, "write_bytes": 751.18e9}
+TRAFFIC = {"kernel": "step_kernel_small<float, true>", "source_sha256": "4b97fc0fa953f370",
+           "fetch_bytes": 5.924e9, "write_bytes": 17.087e9}
 
 # the kernels of the three launch units of a step (size classes 0..3 merged,
 # 4, then 5 and 6 on one stream)
