@@ -323,6 +323,22 @@ __device__ __forceinline__ double gamma2k2_at(const Desc &D, int64_t n) {
   return gam * gam * D.k * D.k;
 }
 
+// The same in FP32 for the FP32 kernels: the phase (or the glide's fraction
+// of the note) is reduced in FP64, the factor 2^{2 a sin(2 pi r t)} (or
+// 2^{2 a t/T}) of (gamma_0 k)^2 evaluated in FP32, where the result is
+// rounded anyway.
+__device__ __forceinline__ float gamma2k2_at_f(const Desc &D, int64_t n) {
+  const double t = (double)n / D.fs;
+  float e = 0.f;
+  if (D.mod_type == 1) {
+    const double cyc = D.mod_b * t;
+    e = (float)(2.0 * D.mod_a) * sinf(6.28318530717958647692f * (float)(cyc - floor(cyc)));
+  } else if (D.mod_type == 2) {
+    e = (float)(2.0 * D.mod_a * (t / D.mod_b));
+  }
+  return (float)D.g2k2_0 * exp2f(e);
+}
+
 // Contact coefficient c = omega^{1+alpha_H} (eta^+)^{alpha_H - 1} / 2 of eq. (6)
 // (power factor at time n), used only while a hammer touches.
 __device__ __forceinline__ double contact_coef(double eta, double omega_pow, double alpha_H) {
@@ -877,7 +893,12 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   T *out = (T *)D.out;
   const int64_t first_m = done;
   T ring = T(0), ring_z = T(0);
-  double g2blk = g2k2_0;
+  // per-step coefficients of an unmodulated string (and a modulated string's
+  // block of G values of (gamma^n k)^2, one per lane, in the kernel precision)
+  const bool modg = D.mod_type != 0;
+  const T G2_0 = (T)g2k2_0, phi2_0 = (T)(g2k2_0 * a2m1_4), aG_0 = (T)(g2k2_0 * a2d);
+  const T a2m1_4t = (T)a2m1_4, a2t = (T)a2d;
+  T g2blk = G2_0;
   T *trash = (T *)a.trash_st;
   // (n + 1) mod mon_period of the current step
   int mon_ctr = a.mon_period > 0 ? (int)(done % a.mon_period) : 1;
@@ -943,13 +964,20 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     const int64_t n = done - 1 + it;               // time level; the step produces sample n+1
     // ---- gamma^n (f0 modulation): one block of G steps per lane ----
     double g2k2 = g2k2_0;
+    T G2 = G2_0, phi2 = phi2_0, aG = aG_0;
     if (any_mod) {
-      if ((it & (G - 1)) == 0) g2blk = gamma2k2_at(D, n + li);
-      g2k2 = __shfl(g2blk, (lane & ~(G - 1)) + (int)(it & (G - 1)), kWave);
+      if ((it & (G - 1)) == 0) {
+        if constexpr (sizeof(T) == 4)
+          g2blk = gamma2k2_at_f(D, n + li);
+        else
+          g2blk = gamma2k2_at(D, n + li);
+      }
+      const T gm = __shfl(g2blk, (lane & ~(G - 1)) + (int)(it & (G - 1)), kWave);
+      G2 = modg ? gm : G2_0;
+      phi2 = modg ? gm * a2m1_4t : phi2_0;
+      aG = modg ? gm * a2t : aG_0;
+      g2k2 = modg ? (double)gm : g2k2_0;
     }
-    const T G2 = (T)g2k2;
-    const T phi2 = (T)(g2k2 * a2m1_4);
-    const T aG = (T)(g2k2 * a2d);
 
     // ---- slopes q (t half points) and p (l half points) ----
     T q[MT], p[ML];
