@@ -136,6 +136,9 @@ typedef struct {
     int64_t total_sweeps;      /* total sweeps                                    */
     int32_t size_class;        /* kernel size class 0..6 of the batched paths      */
     int32_t lanes;             /* lanes per string in that class (16, 32 or 64)   */
+    int32_t slots_t, slots_l;  /* slots per lane of the transverse / longitudinal
+                                  grid in the string's layout (FP32 batches halve
+                                  a grid that fits; 0 on the plain path)         */
 } sb_string_info;
 
 /* Create a batch of `capacity` (>= 1) slots computing in `precision`

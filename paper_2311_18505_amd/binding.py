@@ -55,7 +55,7 @@ class SbStringInfo(C.Structure):
     _fields_ = [
         ("N_t", C.c_int32), ("N_l", C.c_int32), ("n_samples", C.c_int64), ("samples_done", C.c_int64),
         ("flags", C.c_int32), ("max_sweeps", C.c_int32), ("total_sweeps", C.c_int64),
-        ("size_class", C.c_int32), ("lanes", C.c_int32),
+        ("size_class", C.c_int32), ("lanes", C.c_int32), ("slots_t", C.c_int32), ("slots_l", C.c_int32),
     ]
 
 

@@ -566,9 +566,10 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
 // own, which keeps the bow's code and registers out of every other task.
 struct WorkPlan {
   int off[kNumVariants][kNumParts + 1] = {};      // per variant, start of each part's tasks
-  // ticket maps of the launches of unit 0 (parts of classes 0..3) and unit 1
-  // (the shapes of class 4)
-  int tickets_off[kNumVariants][2] = {}, n_tickets[kNumVariants][2] = {};
+  // ticket maps of the merged launch (parts of classes 0..3, index 0) and of
+  // each large class's launch (its shapes, index 1 + class - 4)
+  static constexpr int kTicketLists = 1 + kNumClasses - kNumSmall;
+  int tickets_off[kNumVariants][kTicketLists] = {}, n_tickets[kNumVariants][kTicketLists] = {};
   std::vector<int> members;   // slots stepped
 };
 
@@ -610,15 +611,16 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
     }
     wp.off[v][kNumParts] = (int)work.size();
     if (b->precision != SB_FP64_PLAIN) {
-      // tickets of the launches of units 0 and 1: the tasks of their parts
-      // dealt out in proportion to their counts (task t of a part of n tasks
-      // at t / n), each part longest first.  The mix of parts on the CUs then
-      // stays the same over the whole launch, which runs faster than one part
-      // after another (their bottlenecks differ), and the shortest tasks of
-      // every part fill the tail.  A ticket is part << 24 | task (unit 1: the
-      // shape of class 4).
-      for (int u = 0; u < 2; ++u) {
-        const int q_lo = u == 0 ? 0 : kNumSmall * kNumShapes, q_hi = u == 0 ? kNumSmall * kNumShapes : kShapedClasses * kNumShapes;
+      // tickets of the merged launch and of each large class's launch: the
+      // tasks of their parts dealt out in proportion to their counts (task t
+      // of a part of n tasks at t / n), each part longest first.  The mix of
+      // parts on the CUs then stays the same over the whole launch, which
+      // runs faster than one part after another (their bottlenecks differ),
+      // and the shortest tasks of every part fill the tail.  A ticket is
+      // part << 24 | task (a large class: its shape).
+      for (int u = 0; u < WorkPlan::kTicketLists; ++u) {
+        const int q_lo = u == 0 ? 0 : (kNumSmall + u - 1) * kNumShapes;
+        const int q_hi = u == 0 ? kNumSmall * kNumShapes : q_lo + kNumShapes;
         std::vector<std::pair<double, int32_t>> tk;
         for (int q = q_lo; q < q_hi; ++q) {
           const int groups = kWave / part_lanes(q);
@@ -680,23 +682,18 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
         int lo, hi;
         for (int p = 0; p < kNumSmall * kNumShapes; ++p) a.part_work[p] = nullptr;
         a.tickets = nullptr;
-        if (u <= 1) {
-          // ticketed launches: unit 0 over the parts of classes 0..3, unit 1
-          // over the shapes of class 4
-          const int q0 = u == 0 ? 0 : kNumSmall * kNumShapes;
+        {
+          // ticketed launches: the merged one over the parts of classes
+          // 0..3, a large class's over its shapes
+          const int tl = u == 0 ? 0 : 1 + c - kNumSmall;
+          const int q0 = u == 0 ? 0 : c * kNumShapes;
           const int nq = u == 0 ? kNumSmall * kNumShapes : kNumShapes;
           for (int p = 0; p < nq; ++p) a.part_work[p] = b->d_work + wp.off[v][q0 + p];
-          a.tickets = b->d_work + wp.tickets_off[v][u];
+          a.tickets = b->d_work + wp.tickets_off[v][tl];
           a.work = a.part_work[0];
-          a.n_work = wp.n_tickets[v][u];
+          a.n_work = wp.n_tickets[v][tl];
           lo = wp.off[v][q0];
           hi = wp.off[v][q0 + nq];
-        } else {
-          const int q = c * kNumShapes;   // classes 5 and 6: shape 0 only
-          a.work = b->d_work + wp.off[v][q];
-          a.n_work = (wp.off[v][q + 1] - wp.off[v][q]) / (kWave / kClassLanes[c]);
-          lo = wp.off[v][q];
-          hi = wp.off[v][q + 1];
         }
         for (int k = lo; k < hi; ++k) b->unit_strings[u] += b->h_work[k] >= 0 ? 1 : 0;
         if (a.n_work == 0) continue;
@@ -1137,6 +1134,8 @@ extern "C" int string_batch_info(sb_batch *b, int idx, sb_string_info *info) {
   info->N_l = s.plan.desc.Nl;
   info->size_class = s.plan.desc.cls;
   info->lanes = kClassLanes[s.plan.desc.cls];
+  info->slots_t = b->precision == SB_FP64_PLAIN ? 0 : s.plan.desc.mt;
+  info->slots_l = b->precision == SB_FP64_PLAIN ? 0 : s.plan.desc.ml;
   info->n_samples = s.plan.desc.n_samples;
   if (!s.excited) return SB_OK;
   Status S;

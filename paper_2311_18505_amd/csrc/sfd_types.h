@@ -41,9 +41,9 @@ enum : int { kVarPlain = 0, kVarBow = 1, kVarCubic = 2, kNumVariants = 3 };
 // class's MM slots per lane; shape 1 gives the longitudinal grid and shape 2
 // the transverse grid MM/2 slots, where that grid fits in them.  The stepping
 // loops run over a grid's slots, so a half-width grid does half the work.
-// FP32 batches, classes 0..4; FP64 batches and classes 5, 6 use shape 0.
+// FP32 batches; FP64 batches use shape 0.
 constexpr int kNumShapes = 3;
-constexpr int kShapedClasses = 5;
+constexpr int kShapedClasses = kNumClasses;
 constexpr int shape_mt(int c, int s) { return s == 2 ? kClassSlots[c] / 2 : kClassSlots[c]; }
 constexpr int shape_ml(int c, int s) { return s == 1 ? kClassSlots[c] / 2 : kClassSlots[c]; }
 // work lists are kept per part = class * kNumShapes + shape
@@ -154,9 +154,9 @@ struct LaunchArgs {
   Status *status;
   const int32_t *work;        // 64/G string indices per wavefront task (-1: empty group)
   int32_t n_work;             // number of wavefront tasks (tickets)
-  // units 0 and 1: ticket w runs task tickets[w] & 0xffffff of part
-  // tickets[w] >> 24, whose tasks are listed at part_work[part] (unit 0:
-  // parts of classes 0..3; unit 1: the shapes of class 4)
+  // ticket w runs task tickets[w] & 0xffffff of part tickets[w] >> 24,
+  // whose tasks are listed at part_work[part] (the merged launch: the parts
+  // of classes 0..3; a large class: its shapes)
   const int32_t *part_work[kNumSmall * kNumShapes];
   const int32_t *tickets;
   int32_t *counter;           // work-queue head (zeroed before the launch)

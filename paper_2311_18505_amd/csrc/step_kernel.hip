@@ -422,15 +422,17 @@ struct TabLds {
 template <int MM, typename T, bool KAHAN>
 constexpr bool kSideComp = KAHAN && MM >= 10;
 
-template <int G, int MM, typename T>
-__device__ __forceinline__ void side_load(T (&x)[MM], const T *side, int k, int li) {
+// array k of a group's side region holds S slots per lane (S = the larger
+// grid's slot count); x has the slots of its own grid
+template <int G, int S, typename T, int M>
+__device__ __forceinline__ void side_load(T (&x)[M], const T *side, int k, int li) {
 #pragma unroll
-  for (int r = 0; r < MM; ++r) x[r] = side[(k * MM + r) * G + li];
+  for (int r = 0; r < M; ++r) x[r] = side[(k * S + r) * G + li];
 }
-template <int G, int MM, typename T>
-__device__ __forceinline__ void side_save(const T (&x)[MM], T *side, int k, int li) {
+template <int G, int S, typename T, int M>
+__device__ __forceinline__ void side_save(const T (&x)[M], T *side, int k, int li) {
 #pragma unroll
-  for (int r = 0; r < MM; ++r) side[(k * MM + r) * G + li] = x[r];
+  for (int r = 0; r < M; ++r) side[(k * S + r) * G + li] = x[r];
 }
 
 // I_(t)->(l) up to the factor h_t/h_l at one l-half point by direct sums (the
@@ -702,7 +704,6 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   // MT and ML slots per lane on the transverse and longitudinal grids; LDS
   // regions are laid out for the larger, MM
   constexpr int MM = MT > ML ? MT : ML;
-  static_assert(MT == ML || (!kTabLds<MM> && !kSideComp<MM, T, KAHAN>), "LDS tables only with equal slot counts");
   const int lane = lane_id();
   const int li = lane & (G - 1), gi = lane / G;
   const int sidx = work[task * (kWave / G) + gi];
@@ -856,10 +857,10 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   constexpr bool kSide = kSideComp<MM, T, KAHAN>;
   T *side = sC + gi * 4 * MM * G;
   if constexpr (kSide) {
-    side_save<G, MM, T>(cu, side, 0, li);
-    side_save<G, MM, T>(cvu, side, 1, li);
-    side_save<G, MM, T>(cz, side, 2, li);
-    side_save<G, MM, T>(cvz, side, 3, li);
+    side_save<G, MM>(cu, side, 0, li);
+    side_save<G, MM>(cvu, side, 1, li);
+    side_save<G, MM>(cz, side, 2, li);
+    side_save<G, MM>(cvz, side, 3, li);
   }
 
   // Nodes past the string's end hold zero state, which the solves keep
@@ -982,8 +983,8 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     // ---- slopes q (t half points) and p (l half points) ----
     T q[MT], p[ML];
     if constexpr (kSide) {
-      side_load<G, MM, T>(cu, side, 0, li);
-      side_load<G, MM, T>(cz, side, 2, li);
+      side_load<G, MM>(cu, side, 0, li);
+      side_load<G, MM>(cz, side, 2, li);
     }
     {
       const T ul = grp_prev<G>(last_of<T, MT>(u, mt)), cl = grp_prev<G>(last_of<T, MT>(cu, mt));
@@ -1091,7 +1092,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     // beta = 0, no right-hand side, and the lumped mass moves freely)
     double eta_n = 0.0, cH = 0.0, beta = 0.0;
     if (any_ham) {
-      if constexpr (kSide) side_load<G, MM, T>(cu, side, 0, li);
+      if constexpr (kSide) side_load<G, MM>(cu, side, 0, li);
       const double Iu = (double)slot_dot<G, MT, T>(wH, u, cu);
       eta_n = ham ? uH_n - Iu : 0.0;
       const bool contact = eta_n > 0.0;
@@ -1138,7 +1139,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
       bR[kBowStepK2F] = kk * FB;
       if constexpr (kSide) {
         T cv[MT];
-        side_load<G, MT, T>(cv, side, 1, li);
+        side_load<G, MM>(cv, side, 1, li);
         bR[kBowStepIv] = point_eval<G, T, MT>(vu, cv, bn0, bw0, bn1, bw1) + point_eval<G, T, MT>(vu, cv, bn2, bw2, bn3, bw3);
       } else {
         bR[kBowStepIv] =
@@ -1352,10 +1353,10 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
 
     // ---- state update: v^{n+1/2} = v^{n-1/2} + a, w^{n+1} = w^n + v^{n+1/2} ----
     if constexpr (kSide) {
-      side_load<G, MM, T>(cu, side, 0, li);
-      side_load<G, MM, T>(cvu, side, 1, li);
-      side_load<G, MM, T>(cz, side, 2, li);
-      side_load<G, MM, T>(cvz, side, 3, li);
+      side_load<G, MM>(cu, side, 0, li);
+      side_load<G, MM>(cvu, side, 1, li);
+      side_load<G, MM>(cz, side, 2, li);
+      side_load<G, MM>(cvz, side, 3, li);
     }
     if (__ballot(!act) == 0) {
 #pragma unroll
@@ -1392,10 +1393,10 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     }
 
     if constexpr (kSide) {
-      side_save<G, MM, T>(cu, side, 0, li);
-      side_save<G, MM, T>(cvu, side, 1, li);
-      side_save<G, MM, T>(cz, side, 2, li);
-      side_save<G, MM, T>(cvz, side, 3, li);
+      side_save<G, MM>(cu, side, 0, li);
+      side_save<G, MM>(cvu, side, 1, li);
+      side_save<G, MM>(cz, side, 2, li);
+      side_save<G, MM>(cvz, side, 3, li);
     }
 
     // ---- hammer lumped mass (eq. 6) ----
@@ -1430,10 +1431,10 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     const bool mon_now = act && a.mon_period > 0 && mon_ctr == 0;
     if (__ballot(mon_now) != 0) {
       if constexpr (kSide) {
-        side_load<G, MM, T>(cu, side, 0, li);
-        side_load<G, MM, T>(cvu, side, 1, li);
-        side_load<G, MM, T>(cz, side, 2, li);
-        side_load<G, MM, T>(cvz, side, 3, li);
+        side_load<G, MM>(cu, side, 0, li);
+        side_load<G, MM>(cvu, side, 1, li);
+        side_load<G, MM>(cz, side, 2, li);
+        side_load<G, MM>(cvz, side, 3, li);
       }
       energy_fill<G, MT, ML, T>(gE, u, vu, cu, cvu, z, vz, cz, cvz, li);
       __syncthreads();
@@ -1471,10 +1472,10 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   // ---- write back: every lane stores; an empty group writes to the trash ----
   Status *Sw = present ? S : a.trash_status;
   if constexpr (kSide) {
-    side_load<G, MM, T>(cu, side, 0, li);
-    side_load<G, MM, T>(cvu, side, 1, li);
-    side_load<G, MM, T>(cz, side, 2, li);
-    side_load<G, MM, T>(cvz, side, 3, li);
+    side_load<G, MM>(cu, side, 0, li);
+    side_load<G, MM>(cvu, side, 1, li);
+    side_load<G, MM>(cz, side, 2, li);
+    side_load<G, MM>(cvz, side, 3, li);
   }
   store_state<G, T, MT, ML>(present ? st : trash, u, vu, cu, cvu, z, vz, cz, cvz, li);
   Sw->samples_done = done + steps_done;
@@ -1534,8 +1535,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
     int w = atomicAdd(a.counter, lane_id() == 0 ? 1 : 0);
     w = __builtin_amdgcn_readfirstlane(w);
     if (w >= a.n_work) break;
-    if constexpr (MM <= 8) {
-      // class 4: the ticket names the shape and its task
+    {
+      // the ticket names the layout (shape) and its task
       const int m = __builtin_amdgcn_readfirstlane(a.tickets[w]), t = m & 0xffffff;
       switch (m >> 24) {
         case 1:
@@ -1550,8 +1551,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
           run_task<G, MM, MM, T, KAHAN, BOW, CUB>(a, a.part_work[0], t, sS, sE, sC, sTu, sTf, lds_bow, lds_w);
           break;
       }
-    } else {
-      run_task<G, MM, MM, T, KAHAN, BOW, CUB>(a, a.work, w, sS, sE, sC, sTu, sTf, lds_bow, lds_w);
     }
   }
 }

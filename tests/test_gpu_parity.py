@@ -139,3 +139,51 @@ def test_plain_fp64_modulated_and_chunked():
         _report("plain chunked N=(%d,%d)" % (inf["N_t"], inf["N_l"]), err, inf)
         assert inf["samples_done"] == p["n_samples"]
         assert err <= 1e-10
+
+
+# one string per (size class, layout): (f0, B, alpha); layout 1 halves the
+# longitudinal grid's slots per lane (also a string without one), layout 2
+# the transverse grid's (FP32 batches only)
+_LAYOUT_CASES = [
+    (0, 0, 193.3, 0.03, 4.0), (0, 1, 373.47, 0.01, 4.0), (0, 2, 432.33, 0.03, 2.0),
+    (1, 0, 92.99, 0.01, 4.0), (1, 1, 193.3, 0.001, 4.0), (1, 2, 124.61, 0.03, 3.0),
+    (2, 0, 48.13, 0.001, 4.0), (2, 1, 92.99, 0.0001, 4.0), (2, 2, 48.13, 0.03, 4.0),
+    (3, 0, 24.91, 0.001, 4.0), (3, 1, 48.13, 0.0001, 4.0), (3, 2, 24.91, 0.01, 4.0),
+    (4, 0, 20.0, 0.0001, 3.0), (4, 1, 24.91, 0.0001, 4.0), (4, 2, 20.0, 0.001, 3.0),
+    (5, 0, 9.42, 0.0001, 4.0), (5, 1, 8.0, 0.0001, 1.0), (5, 2, 9.42, 0.001, 4.0),
+    (6, 0, 8.0, 1e-05, 3.0), (6, 1, 8.0, 1e-05, 1.0), (6, 2, 8.0, 0.001, 3.0),
+]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-3)])
+def test_half_width_layouts(precision, tol):
+    """Every size class with a half-width layout (the smaller grid on half the
+    class's slots per lane: FP32 batches) against the oracle, plucked and
+    hammered, modulated and not; FP64 batches keep the full layout."""
+    _gpu()
+    slots = {0: 2, 1: 4, 2: 4, 3: 4, 4: 8, 5: 10, 6: 16}
+    items, want = [], []
+    for k, (c, s, f0, B, a) in enumerate(_LAYOUT_CASES):
+        p = W.string(f0, B, a, 1.0, 2e-4, 960, mod_type=1 if k % 3 == 0 else 0, mod_depth_cents=20.0,
+                     mod_rate_hz=5.0)
+        e = W.pluck(0.13 + 0.02 * k, 1e-3) if k % 2 else W.hammer(0.11 + 0.01 * k, 2.0)
+        items.append((p, e))
+        mm = slots[c]
+        half = precision == "fp32c"
+        want.append((c, mm // 2 if half and s == 2 else mm, mm // 2 if half and s == 1 else mm))
+    refs = oracle.run_many(items, want=("y_u",))
+    b = binding.StringBatch(len(items), precision)
+    try:
+        b.set_params(0, [p for p, _ in items])
+        b.excite(0, [e for _, e in items])
+        b.step(960)
+        outs = [b.read_output(i) for i in range(len(items))]
+        infos = [b.info(i) for i in range(len(items))]
+    finally:
+        b.close()
+    got = [(inf["size_class"], inf["slots_t"], inf["slots_l"]) for inf in infos]
+    errs = [rel_l2(y, r["y_u"]) for y, r in zip(outs, refs)]
+    print("[gpu] %s layouts %s, worst rel-L2 %.3e" % (precision, got, max(errs)), flush=True)
+    assert got == want
+    assert all(inf["flags"] == 0 for inf in infos)
+    assert max(errs) <= tol
