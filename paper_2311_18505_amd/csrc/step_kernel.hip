@@ -58,6 +58,20 @@ __device__ __forceinline__ double dpp(double x) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// DPP move restricted to the rows of ROWS (bit r: row r of 16 lanes); the
+// other rows read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_rows(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // value of lane l (a constant) for every lane
 __device__ __forceinline__ float lane_read(float x, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
@@ -72,6 +86,8 @@ __device__ __forceinline__ double lane_read(double x, int l) {
 constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108;
 constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
 constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138;
+// lane 15 of each row to the next row; lane 31 to rows 2 and 3
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
 
 // value of the previous / next lane of the same group (0 at the group edge)
 template <int G, typename T>
@@ -95,11 +111,18 @@ __device__ __forceinline__ T grp_reduce(T x) {
   x = op(x, dpp<kRowShr4>(x));
   x = op(x, dpp<kRowShr8>(x));
   // lane 15 of a row now holds the row total
-  const T r0 = lane_read(x, 15), r1 = lane_read(x, 31), r2 = lane_read(x, 47), r3 = lane_read(x, 63);
   const int row = lane_id() >> 4;
-  if (G == 16) return row == 0 ? r0 : row == 1 ? r1 : row == 2 ? r2 : r3;
-  if (G == 32) return row < 2 ? op(r0, r1) : op(r2, r3);
-  return op(op(r0, r1), op(r2, r3));
+  if (G == 16) {
+    const T r0 = lane_read(x, 15), r1 = lane_read(x, 31), r2 = lane_read(x, 47), r3 = lane_read(x, 63);
+    return row == 0 ? r0 : row == 1 ? r1 : row == 2 ? r2 : r3;
+  }
+  // rows 1 and 3 add the totals of rows 0 and 2 (the other rows add 0):
+  // lanes 31 and 63 hold the totals of the two halves
+  x = op(x, dpp_rows<kRowBcast15, 0xa>(x));
+  if (G == 32) return row < 2 ? lane_read(x, 31) : lane_read(x, 63);
+  // rows 2 and 3 add the first half's total: lane 63 holds the wave's
+  x = op(x, dpp_rows<kRowBcast31, 0xc>(x));
+  return lane_read(x, 63);
 }
 
 // Powers of the lane-to-lane carry factor g used by the group scans.
@@ -107,6 +130,7 @@ template <typename T>
 struct ScanPow {
   T g1, g2, g4, g8, g16;
   T gl;   // g^{(lane & 15) + 1}
+  T gl2;  // g^{(lane & 31) + 1}
   T gr;   // g^{16 - (lane & 15)}
 };
 
@@ -131,6 +155,7 @@ __device__ __forceinline__ ScanPow<T> scan_pow(T g) {
   p.g16 = p.g8 * p.g8;
   const int j = lane_id() & 15;
   p.gl = ipow(g, j + 1);
+  p.gl2 = (lane_id() & 16) ? p.gl * p.g16 : p.gl;
   p.gr = ipow(g, 16 - j);
   return p;
 }
@@ -145,16 +170,12 @@ __device__ __forceinline__ T grp_scan_fwd(T e, const ScanPow<T> &p) {
   t = fma(p.g4, dpp<kRowShr4>(t), t);
   t = fma(p.g8, dpp<kRowShr8>(t), t);
   if (G >= 32) {
-    const T R0 = lane_read(t, 15), R1 = lane_read(t, 31), R2 = lane_read(t, 47);
-    const int row = lane_id() >> 4;
-    T C;
-    if (G == 32) {
-      C = row == 1 ? R0 : row == 3 ? R2 : T(0);
-    } else {
-      const T C1 = R0, C2 = fma(p.g16, C1, R1), C3 = fma(p.g16, C2, R2);
-      C = row == 1 ? C1 : row == 2 ? C2 : row == 3 ? C3 : T(0);
-    }
-    t = fma(p.gl, C, t);
+    // rows 1 and 3 carry in the last lane of rows 0 and 2 (rows 0 and 2 add 0)
+    t = fma(p.gl, dpp_rows<kRowBcast15, 0xa>(t), t);
+  }
+  if (G == 64) {
+    // rows 2 and 3 carry in lane 31, now the scan of the first half
+    t = fma(p.gl2, dpp_rows<kRowBcast31, 0xc>(t), t);
   }
   return t;
 }
@@ -516,7 +537,7 @@ __device__ __forceinline__ void prefix_store(T *PA, T *PB, const T (&x)[MM], con
     pa[r] = ca;
     pb[r] = cb;
   }
-  const ScanPow<T> one = {T(1), T(1), T(1), T(1), T(1), T(1), T(1)};
+  const ScanPow<T> one = {T(1), T(1), T(1), T(1), T(1), T(1), T(1), T(1)};
   const T oa = grp_scan_fwd<G>(grp_prev<G>(ca), one), ob = grp_scan_fwd<G>(grp_prev<G>(cb), one);
 #pragma unroll
   for (int r = 0; r < MM; ++r) {
