@@ -86,8 +86,9 @@ __device__ __forceinline__ double lane_read(double x, int l) {
 constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108;
 constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
 constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138;
-// lane 15 of each row to the next row; lane 31 to rows 2 and 3
-constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+// lane 15 of each row to the next row; lane 31 to rows 2 and 3; lane 15 of
+// each row to its own row
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kRowNewBcast15 = 0x15F;
 
 // value of the previous / next lane of the same group (0 at the group edge)
 template <int G, typename T>
@@ -112,10 +113,7 @@ __device__ __forceinline__ T grp_reduce(T x) {
   x = op(x, dpp<kRowShr8>(x));
   // lane 15 of a row now holds the row total
   const int row = lane_id() >> 4;
-  if (G == 16) {
-    const T r0 = lane_read(x, 15), r1 = lane_read(x, 31), r2 = lane_read(x, 47), r3 = lane_read(x, 63);
-    return row == 0 ? r0 : row == 1 ? r1 : row == 2 ? r2 : r3;
-  }
+  if (G == 16) return dpp_rows<kRowNewBcast15, 0xf>(x);
   // rows 1 and 3 add the totals of rows 0 and 2 (the other rows add 0):
   // lanes 31 and 63 hold the totals of the two halves
   x = op(x, dpp_rows<kRowBcast15, 0xa>(x));
