@@ -88,7 +88,22 @@ constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0
 constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138;
 // lane 15 of each row to the next row; lane 31 to rows 2 and 3; lane 15 of
 // each row to its own row
-constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kRowNewBcast15 = 0x15F;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kRowNewBcast0 = 0x150, kRowNewBcast15 = 0x15F;
+
+// Each odd row's values in both rows of its pair (rows 0 and 1 read row 1,
+// rows 2 and 3 read row 3): the second result of v_permlane16_swap with both
+// operands x.
+__device__ __forceinline__ float odd_rows(float x) {
+  const unsigned b = __builtin_bit_cast(unsigned, x);
+  return __builtin_bit_cast(float, (unsigned)__builtin_amdgcn_permlane16_swap(b, b, false, false)[1]);
+}
+__device__ __forceinline__ double odd_rows(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  const unsigned nlo = __builtin_amdgcn_permlane16_swap(lo, lo, false, false)[1];
+  const unsigned nhi = __builtin_amdgcn_permlane16_swap(hi, hi, false, false)[1];
+  return __builtin_bit_cast(double, ((uint64_t)nhi << 32) | nlo);
+}
 
 // value of the previous / next lane of the same group (0 at the group edge)
 template <int G, typename T>
@@ -112,12 +127,12 @@ __device__ __forceinline__ T grp_reduce(T x) {
   x = op(x, dpp<kRowShr4>(x));
   x = op(x, dpp<kRowShr8>(x));
   // lane 15 of a row now holds the row total
-  const int row = lane_id() >> 4;
   if (G == 16) return dpp_rows<kRowNewBcast15, 0xf>(x);
   // rows 1 and 3 add the totals of rows 0 and 2 (the other rows add 0):
   // lanes 31 and 63 hold the totals of the two halves
   x = op(x, dpp_rows<kRowBcast15, 0xa>(x));
-  if (G == 32) return row < 2 ? lane_read(x, 31) : lane_read(x, 63);
+  // (groups of 32: each odd row spreads its lane 15 and lends it to its pair)
+  if (G == 32) return odd_rows(dpp_rows<kRowNewBcast15, 0xa>(x));
   // rows 2 and 3 add the first half's total: lane 63 holds the wave's
   x = op(x, dpp_rows<kRowBcast31, 0xc>(x));
   return lane_read(x, 63);
@@ -130,6 +145,7 @@ struct ScanPow {
   T gl;   // g^{(lane & 15) + 1}
   T gl2;  // g^{(lane & 31) + 1}
   T gr;   // g^{16 - (lane & 15)}
+  T gr2;  // g^{32 - (lane & 31)}
 };
 
 template <typename T>
@@ -155,6 +171,7 @@ __device__ __forceinline__ ScanPow<T> scan_pow(T g) {
   p.gl = ipow(g, j + 1);
   p.gl2 = (lane_id() & 16) ? p.gl * p.g16 : p.gl;
   p.gr = ipow(g, 16 - j);
+  p.gr2 = (lane_id() & 16) ? p.gr : p.gr * p.g16;
   return p;
 }
 
@@ -187,16 +204,13 @@ __device__ __forceinline__ T grp_scan_bwd(T e, const ScanPow<T> &p) {
   t = fma(p.g4, dpp<kRowShl4>(t), t);
   t = fma(p.g8, dpp<kRowShl8>(t), t);
   if (G >= 32) {
-    const T R1 = lane_read(t, 16), R2 = lane_read(t, 32), R3 = lane_read(t, 48);
-    const int row = lane_id() >> 4;
-    T C;
-    if (G == 32) {
-      C = row == 0 ? R1 : row == 2 ? R3 : T(0);
-    } else {
-      const T C3 = R3, C2 = fma(p.g16, C3, R2), C1 = fma(p.g16, C2, R1);
-      C = row == 0 ? C1 : row == 1 ? C2 : row == 2 ? C3 : T(0);
-    }
-    t = fma(p.gr, C, t);
+    // rows 0 and 2 carry in the first lane of rows 1 and 3 (rows 1 and 3 add 0)
+    t = fma(p.gr, dpp_rows<kRowNewBcast0, 0x5>(odd_rows(t)), t);
+  }
+  if (G == 64) {
+    // rows 0 and 1 carry in lane 32, now the scan of the second half
+    const T c = lane_read(t, 32);
+    t = lane_id() < 32 ? fma(p.gr2, c, t) : t;
   }
   return t;
 }
@@ -535,7 +549,7 @@ __device__ __forceinline__ void prefix_store(T *PA, T *PB, const T (&x)[MM], con
     pa[r] = ca;
     pb[r] = cb;
   }
-  const ScanPow<T> one = {T(1), T(1), T(1), T(1), T(1), T(1), T(1), T(1)};
+  const ScanPow<T> one = {T(1), T(1), T(1), T(1), T(1), T(1), T(1), T(1), T(1)};
   const T oa = grp_scan_fwd<G>(grp_prev<G>(ca), one), ob = grp_scan_fwd<G>(grp_prev<G>(cb), one);
 #pragma unroll
   for (int r = 0; r < MM; ++r) {
