@@ -59,7 +59,7 @@ def unknowns(info):
     return (info["N_t"] - 1) + max(info["N_l"] - 1, 0)
 
 
-KERNEL_SOURCES = ("step_kernel.hip", "bow.h", "interp.h", "sfd_types.h")
+KERNEL_SOURCES = ("step_kernel.h", "bow.h", "interp.h", "sfd_types.h")
 
 
 def kernel_source_hash() -> str:

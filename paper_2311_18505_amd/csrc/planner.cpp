@@ -191,17 +191,22 @@ int plan_string(const sb_string_params &p, Plan &P, std::string &err, bool shape
   }
   // a string of a class is laid out with the class's MM slots per lane on
   // both grids (nodes past a grid's end hold zeros), or, where the kernels
-  // step half-width layouts (shapes), with MM/2 on a grid that fits in
-  // them: the stepping loops run over a grid's slots, so that grid then
-  // costs half
+  // step narrower layouts (shapes), with the fewest slots per lane each grid
+  // fits in: the stepping loops run over a grid's slots, so the work follows
+  // the slot counts (the fewest in total; a string without a longitudinal
+  // grid takes the narrowest level there)
   const int G = kClassLanes[D.cls];
   D.shape = 0;
-  if (shapes && D.cls < kShapedClasses) {
-    const int half = G * (kClassSlots[D.cls] / 2);
-    if (Nl <= half)
-      D.shape = 1;   // (also a string without a longitudinal grid)
-    else if (Nt <= half)
-      D.shape = 2;
+  if (shapes) {
+    int best = 2 * kClassSlots[D.cls] + 1;
+    for (int s = 0; s < kNumShapes; ++s) {
+      if (!shape_ok(D.cls, s)) continue;
+      const int mt = shape_mt(D.cls, s), ml = shape_ml(D.cls, s);
+      if (Nt <= G * mt && Nl <= G * ml && mt + ml < best) {
+        best = mt + ml;
+        D.shape = s;
+      }
+    }
   }
   D.mt = shape_mt(D.cls, D.shape);
   D.ml = shape_ml(D.cls, D.shape);

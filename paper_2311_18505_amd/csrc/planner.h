@@ -27,8 +27,9 @@ struct Plan {
 
 double theta_of(const sb_string_params &p);
 int plan_grid(const sb_string_params &p, GridPlan &g, std::string &err);
-// shapes: lay a grid that fits in half the class's slots per lane out with
-// MM/2 of them (the FP32 kernels step those layouts)
+// shapes: lay each grid out with the fewest slots per lane of its class's
+// width levels (MM, 3MM/4, MM/2) that it fits in (the FP32 kernels step those
+// layouts)
 int plan_string(const sb_string_params &p, Plan &P, std::string &err, bool shapes = false);
 int plan_excitation(const sb_excitation &e, Plan &P, std::string &err);
 void initial_state(const sb_excitation &e, const Plan &P, std::vector<double> &u0, double &uH0, double &uH1);

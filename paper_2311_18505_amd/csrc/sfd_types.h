@@ -37,15 +37,22 @@ constexpr int kNumKernels = kNumClasses - kNumSmall + 1;
 // registers of what its strings use.
 enum : int { kVarPlain = 0, kVarBow = 1, kVarCubic = 2, kNumVariants = 3 };
 
-// Layouts ("shapes") of a string in its class: shape 0 gives both grids the
-// class's MM slots per lane; shape 1 gives the longitudinal grid and shape 2
-// the transverse grid MM/2 slots, where that grid fits in them.  The stepping
-// loops run over a grid's slots, so a half-width grid does half the work.
-// FP32 batches; FP64 batches use shape 0.
-constexpr int kNumShapes = 3;
-constexpr int kShapedClasses = kNumClasses;
-constexpr int shape_mt(int c, int s) { return s == 2 ? kClassSlots[c] / 2 : kClassSlots[c]; }
-constexpr int shape_ml(int c, int s) { return s == 1 ? kClassSlots[c] / 2 : kClassSlots[c]; }
+// Layouts ("shapes") of a string in its class: each grid gets MM, 3MM/4 or
+// MM/2 slots per lane (width levels 0, 1, 2), the fewest its points fit in;
+// shape = 3 * (transverse level) + (longitudinal level).  The stepping loops
+// run over a grid's slots, so a narrower grid does proportionally less work.
+// Level 1 exists in the classes of 4 and 8 slots; both grids at level 2 would
+// fit the next smaller class, so shape 8 is never used.  FP32 batches; FP64
+// batches use shape 0.
+constexpr int kNumShapes = 9;
+constexpr bool slots_have_quarter(int mm) { return mm == 4 || mm == 8; }
+constexpr int level_slots(int mm, int level) { return level == 0 ? mm : level == 1 ? 3 * mm / 4 : mm / 2; }
+constexpr bool shape_fits(int mm, int s) {
+  return s >= 0 && s < kNumShapes && s != 8 && (slots_have_quarter(mm) || (s / 3 != 1 && s % 3 != 1));
+}
+constexpr int shape_mt(int c, int s) { return level_slots(kClassSlots[c], s / 3); }
+constexpr int shape_ml(int c, int s) { return level_slots(kClassSlots[c], s % 3); }
+constexpr bool shape_ok(int c, int s) { return shape_fits(kClassSlots[c], s); }
 // work lists are kept per part = class * kNumShapes + shape
 constexpr int kNumParts = kNumClasses * kNumShapes;
 
@@ -59,7 +66,7 @@ enum : int32_t {
 struct Desc {
   int32_t Nt, Nl;             // intervals of the transverse / longitudinal grids (Nl = 0: no zeta)
   int32_t nt, nl;             // unknowns: Nt-1, Nl-1 (0)
-  int32_t mt, ml;             // slots per lane of each grid (the class's MM)
+  int32_t mt, ml;             // slots per lane of each grid (from the shape; FP64: the class's MM)
   int32_t cls;                // size class index
   int32_t shape;              // layout in the class (kNumShapes): mt, ml follow from it
   int32_t shape_pad;

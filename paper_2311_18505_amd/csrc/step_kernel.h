@@ -1,4 +1,5 @@
-// Batched stepping kernel of libstringfdtd for gfx950.
+// Batched stepping kernels of libstringfdtd for gfx950 (device code; each
+// instantiation family is compiled by a translation unit of its own).
 //
 // A wavefront steps 64/G strings at once: each string owns a group of G
 // lanes, and lane l of a group holds the transverse points l*mt+1 .. l*mt+mt
@@ -20,6 +21,7 @@
 // factorisation kT (1 + rho S-)(1 + rho S+) on the odd periodic extension of
 // the fixed-end grid (two first-order recurrences per lane plus group scans);
 // the hammer's rank-one term is removed exactly by Sherman-Morrison.
+#pragma once
 #include <hip/hip_runtime.h>
 
 #include "sfd_types.h"
@@ -1532,7 +1534,7 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
 template <int MM, typename T>
 constexpr int kWavesPerEU = (sizeof(T) == 4 && MM <= 4) ? 2 : 1;
 
-// FP32 instantiations step the half-width shapes as well (FP64 batches lay
+// FP32 instantiations step the narrower shapes as well (FP64 batches lay
 // every string out with shape 0)
 template <typename T>
 constexpr bool kShapes = sizeof(T) == 4;
@@ -1572,14 +1574,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
       // the ticket names the layout (shape) and its task
       const int m = __builtin_amdgcn_readfirstlane(a.tickets[w]), t = m & 0xffffff;
       switch (m >> 24) {
-        case 1:
-          if constexpr (kShapes<T>)
-            run_task<G, MM, MM / 2, T, KAHAN, BOW, CUB>(a, a.part_work[1], t, sS, sE, sC, sTu, sTf, lds_bow, lds_w);
-          break;
-        case 2:
-          if constexpr (kShapes<T>)
-            run_task<G, MM / 2, MM, T, KAHAN, BOW, CUB>(a, a.part_work[2], t, sS, sE, sC, sTu, sTf, lds_bow, lds_w);
-          break;
+#define SFD_SHAPE(S)                                                                                             \
+  case S:                                                                                                       \
+    if constexpr (kShapes<T> && shape_fits(MM, S))                                                              \
+      run_task<G, level_slots(MM, (S) / 3), level_slots(MM, (S) % 3), T, KAHAN, BOW, CUB>(                       \
+          a, a.part_work[S], t, sS, sE, sC, sTu, sTf, lds_bow, lds_w);                                          \
+    break;
+        SFD_SHAPE(1)
+        SFD_SHAPE(2)
+        SFD_SHAPE(3)
+        SFD_SHAPE(4)
+        SFD_SHAPE(5)
+        SFD_SHAPE(6)
+        SFD_SHAPE(7)
+#undef SFD_SHAPE
         default:
           run_task<G, MM, MM, T, KAHAN, BOW, CUB>(a, a.part_work[0], t, sS, sE, sC, sTu, sTf, lds_bow, lds_w);
           break;
@@ -1619,112 +1627,36 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
     w = __builtin_amdgcn_readfirstlane(w);
     if (w >= a.n_work) break;
     const int m = __builtin_amdgcn_readfirstlane(a.tickets[w]), t = m & 0xffffff;
-    // part = class * kNumShapes + shape
+    // part = class * kNumShapes + shape; FP64 batches use shape 0 only
 #define SFD_PART(P, G_, MT_, ML_)                                                                              \
   case P:                                                                                                     \
-    if constexpr (kShapes<T> || (MT_ == ML_))                                                                 \
+    if constexpr (kShapes<T> || (P) % kNumShapes == 0)                                                        \
       run_task<G_, MT_, ML_, T, KAHAN, BOW, CUB>(a, a.part_work[P], t, sS, sE, sS, nullptr, nullptr, lds_bow, \
                                                  lds_w);                                                      \
     break;
+// the shapes of a class of four slots per lane, parts P0 .. P0 + 7
+#define SFD_PARTS4(P0, G_)    \
+  SFD_PART(P0, G_, 4, 4)      \
+  SFD_PART(P0 + 1, G_, 4, 3)  \
+  SFD_PART(P0 + 2, G_, 4, 2)  \
+  SFD_PART(P0 + 3, G_, 3, 4)  \
+  SFD_PART(P0 + 4, G_, 3, 3)  \
+  SFD_PART(P0 + 5, G_, 3, 2)  \
+  SFD_PART(P0 + 6, G_, 2, 4)  \
+  SFD_PART(P0 + 7, G_, 2, 3)
     switch (m >> 24) {
-      SFD_PART(9, 64, 4, 4)
-      SFD_PART(10, 64, 4, 2)
-      SFD_PART(11, 64, 2, 4)
-      SFD_PART(6, 32, 4, 4)
-      SFD_PART(7, 32, 4, 2)
-      SFD_PART(8, 32, 2, 4)
-      SFD_PART(3, 16, 4, 4)
-      SFD_PART(4, 16, 4, 2)
-      SFD_PART(5, 16, 2, 4)
-      SFD_PART(1, 16, 2, 1)
-      SFD_PART(2, 16, 1, 2)
+      SFD_PARTS4(3 * kNumShapes, 64)
+      SFD_PARTS4(2 * kNumShapes, 32)
+      SFD_PARTS4(1 * kNumShapes, 16)
+      SFD_PART(2, 16, 2, 1)
+      SFD_PART(6, 16, 1, 2)
       default:
         run_task<16, 2, 2, T, KAHAN, BOW, CUB>(a, a.part_work[0], t, sS, sE, sS, nullptr, nullptr, lds_bow, lds_w);
         break;
     }
+#undef SFD_PARTS4
 #undef SFD_PART
   }
-}
-
-__global__ void zero_counters(int32_t *c, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) c[i] = 0;
-}
-
-// Restores slots first..first+count-1 to their state right after excitation:
-// one block per slot copies the saved state block and the saved status.
-template <typename T>
-__global__ void rewind_kernel(const Desc *desc, Status *status, const Status *status0, int first, int count) {
-  const int s = first + (int)blockIdx.x;
-  if ((int)blockIdx.x >= count) return;
-  const Desc &D = desc[s];
-  if (!D.st0) return;
-  T *dst = (T *)D.st;
-  const T *src = (const T *)D.st0;
-  for (int i = (int)threadIdx.x; i < D.st_elems; i += (int)blockDim.x) dst[i] = src[i];
-  if (threadIdx.x == 0) status[s] = status0[s];
-}
-
-// Row i of dst receives samples offs[i] .. offs[i]+count-1 of slot slots[i]'s
-// output; samples the slot has not produced (at or past its samples_done, or
-// past n_samples) are written as zero.  The slot's samples_done and flags go
-// to row_done[i] and row_flags[i].  One block per row.
-template <typename T>
-__global__ void gather_kernel(const Desc *desc, const Status *status, const int32_t *slots, const int64_t *offs,
-                              int n, int64_t count, T *dst, int64_t *row_done, int32_t *row_flags) {
-  const int i = (int)blockIdx.x;
-  if (i >= n) return;
-  const int s = slots[i];
-  const Desc &D = desc[s];
-  const int64_t done = status[s].samples_done;
-  const int64_t avail = (done < D.n_samples ? done : D.n_samples) - offs[i];
-  const int64_t c = count < avail ? count : (avail > 0 ? avail : 0);
-  const T *src = (const T *)D.out + offs[i];
-  for (int64_t t = threadIdx.x; t < count; t += blockDim.x) dst[(int64_t)i * count + t] = t < c ? src[t] : T(0);
-  if (threadIdx.x == 0) {
-    row_done[i] = done;
-    row_flags[i] = status[s].flags;
-  }
-}
-
-hipError_t launch_gather(int precision, const Desc *desc, const Status *status, const int32_t *slots,
-                         const int64_t *offs, int n, int64_t count, void *dst, int64_t *row_done, int32_t *row_flags,
-                         hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  if (precision == 1)
-    hipLaunchKernelGGL(gather_kernel<float>, dim3(n), dim3(256), 0, st, desc, status, slots, offs, n, count,
-                       (float *)dst, row_done, row_flags);
-  else
-    hipLaunchKernelGGL(gather_kernel<double>, dim3(n), dim3(256), 0, st, desc, status, slots, offs, n, count,
-                       (double *)dst, row_done, row_flags);
-  return hipGetLastError();
-}
-
-// Bulk upload: segment i copies bytes[i] bytes (a multiple of 4) from
-// src + src_off[i] to dst[i], one block per segment.
-__global__ void scatter_kernel(const uint32_t *src, const UploadSeg *segs, int n) {
-  const int i = (int)blockIdx.x;
-  if (i >= n) return;
-  const UploadSeg g = segs[i];
-  const uint32_t *from = src + g.src_off / 4;
-  uint32_t *to = (uint32_t *)g.dst;
-  for (uint64_t w = threadIdx.x; w < g.bytes / 4; w += blockDim.x) to[w] = from[w];
-}
-
-hipError_t launch_scatter(const void *src, const UploadSeg *segs, int n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(scatter_kernel, dim3(n), dim3(256), 0, st, (const uint32_t *)src, segs, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const Status *status0, int first, int count,
-                         hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  if (precision == 1)
-    hipLaunchKernelGGL(rewind_kernel<float>, dim3(count), dim3(256), 0, st, desc, status, status0, first, count);
-  else
-    hipLaunchKernelGGL(rewind_kernel<double>, dim3(count), dim3(256), 0, st, desc, status, status0, first, count);
-  return hipGetLastError();
 }
 
 template <typename T, bool KAHAN, bool BOW, bool CUB>
@@ -1735,43 +1667,6 @@ static hipError_t launch_kernel_t(int kernel, const LaunchArgs &a, int blocks, h
     case 2: hipLaunchKernelGGL((step_kernel<64, 10, T, KAHAN, BOW, CUB>), dim3(blocks), dim3(64), 0, st, a); break;
     default: hipLaunchKernelGGL((step_kernel<64, 16, T, KAHAN, BOW, CUB>), dim3(blocks), dim3(64), 0, st, a); break;
   }
-  return hipGetLastError();
-}
-
-template <typename T, bool KAHAN>
-static hipError_t launch_kernel_v(int kernel, int variant, const LaunchArgs &a, int blocks, hipStream_t st) {
-  switch (variant) {
-    case kVarPlain: return launch_kernel_t<T, KAHAN, false, false>(kernel, a, blocks, st);
-    case kVarBow: return launch_kernel_t<T, KAHAN, true, false>(kernel, a, blocks, st);
-    default: return launch_kernel_t<T, KAHAN, true, true>(kernel, a, blocks, st);
-  }
-}
-
-// kernel: 0 the merged classes 0..3, 1..3 the classes 4..6 (kernel_of_class);
-// variant: kVarPlain, kVarBow or kVarCubic
-hipError_t launch_kernel(int precision, int kernel, int variant, const LaunchArgs &a, int blocks, hipStream_t st) {
-  if (precision == 1) return launch_kernel_v<float, true>(kernel, variant, a, blocks, st);
-  return launch_kernel_v<double, false>(kernel, variant, a, blocks, st);
-}
-
-// Holds its stream for `ticks` of the constant-rate wall clock and exits
-// (bounded by time, independent of any other kernel).  Placed before the
-// merged launch so that the two large-class launches, which need whole SIMDs
-// (512 registers per wavefront), are dispatched before the merged launch's
-// persistent wavefronts fill every CU.
-__global__ void delay_kernel(uint64_t ticks) {
-  const uint64_t t0 = wall_clock64();
-  // the iteration cap bounds the wait (~20 ms) even if the clock stood still
-  for (int i = 0; i < 100000 && wall_clock64() - t0 < ticks; ++i) __builtin_amdgcn_s_sleep(8);
-}
-
-hipError_t launch_delay(uint64_t ticks, hipStream_t st) {
-  hipLaunchKernelGGL(delay_kernel, dim3(1), dim3(64), 0, st, ticks);
-  return hipGetLastError();
-}
-
-hipError_t launch_zero(int32_t *c, int n, hipStream_t st) {
-  hipLaunchKernelGGL(zero_counters, dim3((n + 255) / 256), dim3(256), 0, st, c, n);
   return hipGetLastError();
 }
 
@@ -1792,18 +1687,13 @@ static int blocks_per_cu(int kernel) {
   return n;
 }
 
-template <typename T, bool KAHAN>
-static int blocks_per_cu_v(int kernel, int variant) {
-  switch (variant) {
-    case kVarPlain: return blocks_per_cu<T, KAHAN, false, false>(kernel);
-    case kVarBow: return blocks_per_cu<T, KAHAN, true, false>(kernel);
-    default: return blocks_per_cu<T, KAHAN, true, true>(kernel);
-  }
-}
-
-int max_blocks_per_cu(int precision, int kernel, int variant) {
-  if (precision == 1) return blocks_per_cu_v<float, true>(kernel, variant);
-  return blocks_per_cu_v<double, false>(kernel, variant);
-}
+// Host entry points of one instantiation family (element type T,
+// compensation KAHAN, the bow family's code BOW, the cubic grid interpolant
+// CUB), defined by the translation unit that compiles the family.
+#define SFD_STEP_FAMILY(NAME, T, KAHAN, BOW, CUB)                                             \
+  hipError_t launch_step_##NAME(int kernel, const LaunchArgs &a, int blocks, hipStream_t st) { \
+    return launch_kernel_t<T, KAHAN, BOW, CUB>(kernel, a, blocks, st);                        \
+  }                                                                                           \
+  int blocks_step_##NAME(int kernel) { return blocks_per_cu<T, KAHAN, BOW, CUB>(kernel); }
 
 }  // namespace sfd

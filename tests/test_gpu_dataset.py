@@ -1,5 +1,12 @@
 """The dataset generator on the GPU: notes with several excitations each
-against the oracle's schedule."""
+against the oracle's schedule.
+
+Bowed notes can hold near-ties of the stick/slip decision: there a change of
+the string's parameters by a relative 1e-7 already flips a later step and
+moves the oracle's own output by O(1e-2) from then on.  In FP32 such notes
+are held to 3x the oracle's spread under those changes, and element by
+element to 1e-3 over the window in which the changed oracle runs still agree
+within 1e-4; every other note stays within the plain tolerance."""
 from __future__ import annotations
 
 import numpy as np
@@ -11,6 +18,19 @@ from paper_2311_18505_amd import binding, dataset
 pytestmark = pytest.mark.gpu
 
 
+def _rel_l2(y, ref):
+    return float(np.linalg.norm(np.asarray(y, np.float64) - ref) / np.linalg.norm(ref))
+
+
+def _agree_window(ref, others, tol):
+    """Samples from the start over which every run in `others` stays within
+    tol x max|ref| of ref, element by element."""
+    scale = np.max(np.abs(ref))
+    dev = np.max([np.abs(np.asarray(q, np.float64) - ref) for q in others], axis=0)
+    bad = np.nonzero(dev > tol * scale)[0]
+    return int(bad[0]) if len(bad) else len(ref)
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-3)])
 def test_dataset_notes_match_oracle(precision, tol):
     if not binding.device_available():
@@ -20,10 +40,31 @@ def test_dataset_notes_match_oracle(precision, tol):
           flush=True)
     audio = dataset.synthesize(notes, precision, capacity=16)
     refs = oracle.run_many([(x["params"], x["excitation"]) for x in notes])   # warm the oracle library
-    errs = []
+    assert len(refs) == len(notes)
+    errs, rsched = [], []
     for x, y in zip(notes, audio):
         ref = oracle.run(x["params"], x["excitation"], schedule=x["events"])["y_u"]
-        errs.append(float(np.linalg.norm(np.asarray(y, np.float64) - ref) / np.linalg.norm(ref)))
+        rsched.append(ref)
+        errs.append(_rel_l2(y, ref))
     print("[gpu] dataset %s: worst rel-L2 %.3e" % (precision, max(errs)), flush=True)
-    assert len(refs) == len(notes)
-    assert max(errs) <= tol
+    if precision == "fp64":
+        assert max(errs) <= tol
+        return
+    bowed = lambda x: x["excitation"].get("type") == 3 or any(e.get("type") == 3 for _, e in x["events"])
+    for i, x in enumerate(notes):
+        if errs[i] <= tol:
+            continue
+        assert bowed(x), (i, errs[i])
+        runs = []
+        for rel in (1e-7, -1e-7):
+            for key in ("f0", "B", "alpha"):
+                p = dict(x["params"], **{key: x["params"][key] * (1 + rel)})
+                runs.append(oracle.run(p, x["excitation"], schedule=x["events"])["y_u"])
+        spread = max(_rel_l2(q, rsched[i]) for q in runs)
+        n = _agree_window(rsched[i], runs, 1e-4)
+        scale = np.max(np.abs(rsched[i]))
+        d = float(np.max(np.abs(np.asarray(audio[i][:n], np.float64) - rsched[i][:n]))) / scale if n else 0.0
+        print("[gpu] dataset fp32c note %d (bowed): rel-L2 %.2e, oracle spread %.2e under 1e-7 changes, "
+              "element-wise %.1e over the first %d samples" % (i, errs[i], spread, d, n), flush=True)
+        assert errs[i] <= 3 * spread
+        assert n >= 480 and d <= 1e-3

@@ -145,32 +145,44 @@ def test_plain_fp64_modulated_and_chunked():
 # longitudinal grid's slots per lane (also a string without one), layout 2
 # the transverse grid's (FP32 batches only)
 _LAYOUT_CASES = [
-    (0, 0, 193.3, 0.03, 4.0), (0, 1, 373.47, 0.01, 4.0), (0, 2, 432.33, 0.03, 2.0),
-    (1, 0, 92.99, 0.01, 4.0), (1, 1, 193.3, 0.001, 4.0), (1, 2, 124.61, 0.03, 3.0),
-    (2, 0, 48.13, 0.001, 4.0), (2, 1, 92.99, 0.0001, 4.0), (2, 2, 48.13, 0.03, 4.0),
-    (3, 0, 24.91, 0.001, 4.0), (3, 1, 48.13, 0.0001, 4.0), (3, 2, 24.91, 0.01, 4.0),
-    (4, 0, 20.0, 0.0001, 3.0), (4, 1, 24.91, 0.0001, 4.0), (4, 2, 20.0, 0.001, 3.0),
-    (5, 0, 9.42, 0.0001, 4.0), (5, 1, 8.0, 0.0001, 1.0), (5, 2, 9.42, 0.001, 4.0),
-    (6, 0, 8.0, 1e-05, 3.0), (6, 1, 8.0, 1e-05, 1.0), (6, 2, 8.0, 0.001, 3.0),
+    (0, 0, 187.43, 0.03, 4.0), (0, 2, 123.08, 0.03, 1.0), (0, 6, 434.6, 0.03, 2.0),
+    (1, 0, 92.99, 0.01, 4.0), (1, 1, 151.88, 0.001, 4.0), (1, 2, 32.5, 0.03, 1.0), (1, 3, 92.99, 0.03, 4.0),
+    (1, 4, 123.08, 0.01, 4.0), (1, 5, 56.93, 0.03, 1.0), (1, 6, 123.08, 0.03, 3.0), (1, 7, 123.08, 0.03, 4.0),
+    (2, 0, 49.49, 0.001, 4.0), (2, 1, 65.5, 0.001, 4.0), (2, 2, 8.58, 0.03, 1.0), (2, 3, 49.49, 0.01, 4.0),
+    (2, 4, 75.36, 0.001, 4.0), (2, 5, 15.03, 0.03, 1.0), (2, 6, 49.49, 0.03, 4.0), (2, 7, 65.5, 0.01, 4.0),
+    (3, 0, 32.5, 0.0001, 3.0), (3, 1, 32.5, 0.0001, 4.0), (3, 2, 11.36, 0.001, 1.0), (3, 3, 24.55, 0.001, 4.0),
+    (3, 4, 32.5, 0.001, 4.0), (3, 5, 8.0, 0.01, 1.0), (3, 6, 24.55, 0.01, 4.0), (3, 7, 32.5, 0.01, 4.0),
+    (4, 0, 12.18, 0.0001, 4.0), (4, 1, 21.34, 1e-05, 3.0), (4, 2, 9.2, 0.0001, 1.0), (4, 3, 15.03, 0.0001, 4.0),
+    (4, 4, 16.12, 0.0001, 4.0), (4, 5, 8.0, 0.001, 1.0), (4, 6, 12.18, 0.001, 4.0), (4, 7, 16.12, 0.001, 4.0),
+    (5, 0, 9.87, 0.0001, 4.0), (5, 2, 8.0, 0.0001, 1.0), (5, 6, 9.87, 0.001, 4.0),
+    (6, 0, 8.0, 1e-05, 3.0), (6, 2, 8.0, 1e-05, 1.0), (6, 6, 8.0, 0.001, 3.0),
 ]
 
 
+def _level_slots(mm, level):
+    """Slots per lane of a grid at width level 0, 1, 2: MM, 3MM/4, MM/2."""
+    return (mm, 3 * mm // 4, mm // 2)[level]
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-3)])
-def test_half_width_layouts(precision, tol):
-    """Every size class with a half-width layout (the smaller grid on half the
-    class's slots per lane: FP32 batches) against the oracle, plucked and
-    hammered, modulated and not; FP64 batches keep the full layout."""
+def test_narrow_layouts(precision, tol):
+    """Every layout of every size class (FP32 batches: each grid on MM, 3MM/4
+    or MM/2 slots per lane, the fewest it fits in; 3MM/4 in the classes of 4
+    and 8 slots) against the oracle, plucked and hammered, modulated and not;
+    FP64 batches keep the full layout."""
     _gpu()
     slots = {0: 2, 1: 4, 2: 4, 3: 4, 4: 8, 5: 10, 6: 16}
     items, want = [], []
     for k, (c, s, f0, B, a) in enumerate(_LAYOUT_CASES):
         p = W.string(f0, B, a, 1.0, 2e-4, 960, mod_type=1 if k % 3 == 0 else 0, mod_depth_cents=20.0,
                      mod_rate_hz=5.0)
-        e = W.pluck(0.13 + 0.02 * k, 1e-3) if k % 2 else W.hammer(0.11 + 0.01 * k, 2.0)
+        e = W.pluck(0.13 + 0.011 * k, 1e-3) if k % 2 else W.hammer(0.11 + 0.007 * k, 2.0)
         items.append((p, e))
         mm = slots[c]
-        half = precision == "fp32c"
-        want.append((c, mm // 2 if half and s == 2 else mm, mm // 2 if half and s == 1 else mm))
+        if precision == "fp32c":
+            want.append((c, _level_slots(mm, s // 3), _level_slots(mm, s % 3)))
+        else:
+            want.append((c, mm, mm))
     refs = oracle.run_many(items, want=("y_u",))
     b = binding.StringBatch(len(items), precision)
     try:
