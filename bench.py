@@ -39,8 +39,8 @@ PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 2.4 GHz x 25
 # (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a
 # 512 MiB device copy (x2.000 and x1.000); profiles/hbm_traffic_uneven16384.md.
 # Valid only for the kernel sources it was measured on (kernel_source_hash).
-TRAFFIC = {"kernel": "step_kernel_small<float, true>", "source_sha256": "4eccdf9f8d64be40",
-           "fetch_bytes": 0.3231e9, "write_bytes": 6.799e9}
+TRAFFIC = {"kernel": "step_kernel_small<float, true>", "source_sha256": "cbef5d33dffa003d",
+           "fetch_bytes": 0.3033e9, "write_bytes": 6.805e9}
 
 # the kernels of the three launch units of a step (size classes 0..3 merged,
 # 4, then 5 and 6 on one stream)
@@ -445,9 +445,9 @@ def main():
                    "updates_per_step": updates, "audio_seconds_per_step": audio_s,
                    "precision": "FP32 with compensated state updates, FP64 energy monitor",
                    "launch": "three concurrent persistent launch units per step (size classes 0-3 merged, 4, "
-                             "then 5 and 6; forked onto their streams and joined), strings of classes 0-4 laid "
-                             "out with half the slots per lane on a grid that fits, blocks/CU autotuned; the "
-                             "same step replayed from a HIP graph is reported beside",
+                             "then 5 and 6; forked onto their streams and joined), each grid of a string laid out "
+                             "on the fewest of MM, 3MM/4 and MM/2 slots per lane it fits in, blocks/CU "
+                             "autotuned; the same step replayed from a HIP graph is reported beside",
                    "blocks_per_cu": tuned},
         "audio_s_per_s": audio_s / sec_per_step,
         "sweeps_per_step_mean": sweeps / max(1, sum(inf["n_samples"] - 2 for inf in infos)),
