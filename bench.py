@@ -61,6 +61,11 @@ def unknowns(info):
 
 KERNEL_SOURCES = ("step_kernel.h", "bow.h", "interp.h", "sfd_types.h")
 
+# the bow, clamped and dataset legs' accuracy samples: their first strings,
+# the opening samples of each (compared with the oracle in the cpu_baseline leg)
+SAMPLE_STRINGS = 16
+SAMPLE_CUT = 9600
+
 
 def kernel_source_hash() -> str:
     """sha256 prefix over the sources the stepping kernels are built from."""
@@ -138,6 +143,60 @@ def accuracy(outs, refs, fs):
             "partial_offset_cents_max": max(cts) if cts else None,
             "partial_offset_cents_median": float(np.median(cts)) if cts else None,
             "partials_compared": len(cts)}
+
+
+def cut_note(p, e, events, seconds_cap):
+    """A note cut to its first seconds_cap for the oracle so that it computes
+    the same samples as the first ones of the GPU's full-length run: both
+    grids pinned to the full note's, a glide and a moving bow keep their
+    rates (their spans scale with the cut), events past the cut dropped.
+    None for a note whose re-excitation moves a bow (its travel time follows
+    the note's length)."""
+    import oracle
+    ns_full = p["n_samples"]
+    ns = min(ns_full, int(seconds_cap * p["fs"]))
+    g = oracle.grid(p)
+    q = dict(p, n_samples=ns, grid_t=g["N_t"], grid_l=g["N_l"])
+    if p.get("mod_type", 0) == 2:
+        q["glide_semitones"] = p["glide_semitones"] * ns / ns_full
+    if e.get("type") == 3 and e.get("x_end", e["x"]) != e["x"]:
+        e = dict(e, x_end=e["x"] + (e["x_end"] - e["x"]) * ns / ns_full)
+    kept = [(st, x) for st, x in (events or []) if st + 1 < ns]
+    if any(x.get("type") == 3 and x.get("x_end", x["x"]) != x["x"] for _, x in kept):
+        return None
+    return q, e, kept
+
+
+def leg_accuracy(sample, seconds_cap, threads):
+    """accuracy() of a leg's sampled GPU outputs [(params, excitation, events,
+    output)] against the oracle on the same notes cut to seconds_cap."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    jobs, outs = [], []
+    for p, e, ev, y in sample:
+        c = cut_note(p, e, ev, seconds_cap)
+        if c is not None:
+            jobs.append(c)
+            outs.append(y)
+    run = lambda c: oracle.run(c[0], c[1], schedule=c[2] or None)["y_u"]
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        refs = list(ex.map(run, jobs))
+        rec = accuracy(outs, refs, 48000.0)
+        # a string above 1e-3 next to the oracle's own spread under a 1e-7
+        # relative change of f0 (either sign): bowed strings near a stick/slip
+        # tie move by O(1) under such changes, which bounds what any
+        # arithmetic can reproduce
+        rel = [float(np.linalg.norm(np.asarray(y, np.float64)[:len(r)] - r) / np.linalg.norm(r))
+               for y, r in zip(outs, refs)]
+        above = [i for i, x in enumerate(rel) if x > 1e-3]
+        nudged = [(dict(jobs[i][0], f0=jobs[i][0]["f0"] * (1 + d)), jobs[i][1], jobs[i][2])
+                  for i in above for d in (1e-7, -1e-7)]
+        spread_runs = list(ex.map(run, nudged))
+    rec["above_1e-3"] = [{"rel_l2": rel[i], "oracle_spread_1e-7_f0": max(
+        float(np.linalg.norm(q - refs[i]) / np.linalg.norm(refs[i])) for q in spread_runs[2 * k:2 * k + 2])}
+        for k, i in enumerate(above)]
+    rec["sample"] = "%d strings of the leg, each cut to its first %.2f s" % (len(jobs), seconds_cap)
+    return rec
 
 
 def cpu_model() -> str:
@@ -228,6 +287,9 @@ def bow_leg(W, binding, hiptime, n, seconds):
         ms = ev0.elapsed_ms(ev1)
         bad = sum(1 for i in range(n) if b.info(i)["flags"] != 0 or b.info(i)["samples_done"] != infos[i]["n_samples"])
         sweeps = sum(b.info(i)["total_sweeps"] for i in range(n))
+        if name == "bowed":
+            sample = [(items[i][0], excs[i], [], b.read_output(i, 0, min(items[i][0]["n_samples"], SAMPLE_CUT)))
+                      for i in range(min(n, SAMPLE_STRINGS))]
         b.close()
         upd = sum(unknowns(inf) * (inf["n_samples"] - 2) for inf in infos)
         res[name] = {"value": upd / (ms / 1e3), "ms": ms, "audio_s_per_s": n * seconds / (ms / 1e3),
@@ -238,7 +300,7 @@ def bow_leg(W, binding, hiptime, n, seconds):
             "sweeps_per_step_mean": res["bowed"]["sweeps_per_step_mean"],
             "strings_not_finished": res["bowed"]["strings_not_finished"],
             "plucked_same_strings": res["plucked"], "bowed_vs_plucked": res["bowed"]["value"] / res["plucked"]["value"],
-            "workload": "%d bowed nonlinear strings of %.1f s (seeded draws), FP32 compensated" % (n, seconds)}
+            "workload": "%d bowed nonlinear strings of %.1f s (seeded draws), FP32 compensated" % (n, seconds)}, sample
 
 
 def clamped_leg(W, binding, hiptime, n, seconds):
@@ -264,6 +326,10 @@ def clamped_leg(W, binding, hiptime, n, seconds):
         ev1.synchronize()
         ms = ev0.elapsed_ms(ev1)
         bad = sum(1 for i in range(n) if b.info(i)["flags"] != 0 or b.info(i)["samples_done"] != infos[i]["n_samples"])
+        if bnd == 1:
+            sample = [(dict(items[i][0], boundary=1), items[i][1], [],
+                       b.read_output(i, 0, min(items[i][0]["n_samples"], SAMPLE_CUT)))
+                      for i in range(min(n, SAMPLE_STRINGS))]
         b.close()
         upd = sum(unknowns(inf) * (inf["n_samples"] - 2) for inf in infos)
         res[name] = {"value": upd / (ms / 1e3), "ms": ms, "audio_s_per_s": n * seconds / (ms / 1e3),
@@ -274,7 +340,7 @@ def clamped_leg(W, binding, hiptime, n, seconds):
             "simply_supported_same_strings": res["simply_supported"],
             "clamped_vs_simply_supported": res["clamped"]["value"] / res["simply_supported"]["value"],
             "workload": "%d nonlinear strings of %.1f s (seeded draws, plucks and hammers), FP32 compensated"
-                        % (n, seconds)}
+                        % (n, seconds)}, sample
 
 
 def dataset_leg(hiptime, n, seconds):
@@ -291,12 +357,14 @@ def dataset_leg(hiptime, n, seconds):
     hiptime.synchronize()
     wall = time.perf_counter() - t0
     secs = sum(x["params"]["n_samples"] for x in notes) / 48000.0
+    sample = [(x["params"], x["excitation"], x["events"], a[:SAMPLE_CUT])
+              for x, a in zip(notes[:SAMPLE_STRINGS], audio[:SAMPLE_STRINGS]) if a is not None]
     return {"value": secs / wall, "unit": "audio-s/s", "notes_per_s": n / wall, "wall_s": wall,
             "notes": n, "events": sum(len(x["events"]) for x in notes),
             "finite": bool(all(np.isfinite(a).all() for a in audio if a is not None)),
             "flagged_notes": sum(1 for a in audio if a is None),
             "workload": "%d notes of U(%.1f, %.1f) s, pluck/hammer/bow, half re-excited mid-note once or twice, "
-                        "FP32 compensated" % (n, seconds[0], seconds[1])}
+                        "FP32 compensated" % (n, seconds[0], seconds[1])}, sample
 
 
 def serving_leg(W, serving, rate, seconds, capacity):
@@ -456,6 +524,7 @@ def main():
         "graph_replay_ms": graph_ms,
         "chunked_480_ms": chunked_ms,
     }
+    samples = {}   # leg -> [(params, excitation, events, GPU output)] for accuracy_vs_oracle
     if not args.no_plain:
         pl = plain_leg(W, binding, hiptime, args.plain_seconds)
         print("[bench] plain FP64: %.1f ms, %.3e updates/s" % (pl["ms"], pl["value"]), file=sys.stderr, flush=True)
@@ -466,17 +535,17 @@ def main():
         print("[bench] uniform 4096: %.1f ms, %.3e updates/s" % (un["ms"], un["value"]), file=sys.stderr, flush=True)
         out["uniform4096_fp32c"] = un
     if not args.no_bow:
-        bw = bow_leg(W, binding, hiptime, args.bow_strings, 1.0)
+        bw, samples["bow_fp32c"] = bow_leg(W, binding, hiptime, args.bow_strings, 1.0)
         print("[bench] bow: %.1f ms, %.3e updates/s (%.2f x the same strings plucked)"
               % (bw["ms"], bw["value"], bw["bowed_vs_plucked"]), file=sys.stderr, flush=True)
         out["bow_fp32c"] = bw
     if not args.no_clamped:
-        cl = clamped_leg(W, binding, hiptime, args.clamped_strings, 1.0)
+        cl, samples["clamped_fp32c"] = clamped_leg(W, binding, hiptime, args.clamped_strings, 1.0)
         print("[bench] clamped: %.1f ms, %.3e updates/s (%.2f x the same strings simply supported)"
               % (cl["ms"], cl["value"], cl["clamped_vs_simply_supported"]), file=sys.stderr, flush=True)
         out["clamped_fp32c"] = cl
     if not args.no_dataset:
-        ds = dataset_leg(hiptime, args.dataset_notes, (0.5, 2.0))
+        ds, samples["dataset_fp32c"] = dataset_leg(hiptime, args.dataset_notes, (0.5, 2.0))
         print("[bench] dataset: %d notes (%d re-excitations) in %.2f s, %.0f audio-s/s"
               % (ds["notes"], ds["events"], ds["wall_s"], ds["value"]), file=sys.stderr, flush=True)
         out["dataset_fp32c"] = ds
@@ -499,6 +568,13 @@ def main():
         out["accuracy_vs_oracle"] = dict(accuracy(gpu_sample, refs, 48000.0),
                                          sample=rec["sample"], precision="FP32 compensated vs FP64 oracle")
         print("[bench] accuracy vs oracle: %s" % json.dumps(out["accuracy_vs_oracle"]), file=sys.stderr, flush=True)
+        # the bow, clamped and dataset legs: their first strings' opening
+        # samples against the oracle
+        for leg, smp in samples.items():
+            out[leg]["accuracy_vs_oracle"] = dict(leg_accuracy(smp, SAMPLE_CUT / 48000.0, threads),
+                                                  precision="FP32 compensated vs FP64 oracle")
+            print("[bench] %s accuracy vs oracle: %s" % (leg, json.dumps(out[leg]["accuracy_vs_oracle"])),
+                  file=sys.stderr, flush=True)
         # roofline of each launch's kernel: the oracle's arithmetic per
         # grid-point update (banded elimination without pivoting's fill) times
         # the updates of that launch's strings, over the kernel's own duration
