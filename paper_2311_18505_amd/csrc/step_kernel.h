@@ -107,15 +107,18 @@ __device__ __forceinline__ double odd_rows(double x) {
   return __builtin_bit_cast(double, ((uint64_t)nhi << 32) | nlo);
 }
 
-// value of the previous / next lane of the same group (0 at the group edge)
+// value of the previous / next lane of the same group (0 at the group edge;
+// a group of 64 lanes has its edges at the wave's, where the move reads 0)
 template <int G, typename T>
 __device__ __forceinline__ T grp_prev(T x) {
   const T v = dpp<kWaveShr1>(x);
+  if (G == 64) return v;
   return (lane_id() & (G - 1)) == 0 ? T(0) : v;
 }
 template <int G, typename T>
 __device__ __forceinline__ T grp_next(T x) {
   const T v = dpp<kWaveShl1>(x);
+  if (G == 64) return v;
   return (lane_id() & (G - 1)) == G - 1 ? T(0) : v;
 }
 
@@ -130,23 +133,27 @@ __device__ __forceinline__ T grp_reduce(T x) {
   x = op(x, dpp<kRowShr8>(x));
   // lane 15 of a row now holds the row total
   if (G == 16) return dpp_rows<kRowNewBcast15, 0xf>(x);
-  // rows 1 and 3 add the totals of rows 0 and 2 (the other rows add 0):
-  // lanes 31 and 63 hold the totals of the two halves
-  x = op(x, dpp_rows<kRowBcast15, 0xa>(x));
+  // rows 1 and 3 add the totals of rows 0 and 2: lanes 31 and 63 hold the
+  // totals of the two halves (rows 0 and 2 take values no later step reads,
+  // so the moves need no row mask)
+  x = op(x, dpp<kRowBcast15>(x));
   // (groups of 32: each odd row spreads its lane 15 and lends it to its pair)
-  if (G == 32) return odd_rows(dpp_rows<kRowNewBcast15, 0xa>(x));
+  if (G == 32) return odd_rows(dpp<kRowNewBcast15>(x));
   // rows 2 and 3 add the first half's total: lane 63 holds the wave's
-  x = op(x, dpp_rows<kRowBcast31, 0xc>(x));
+  x = op(x, dpp<kRowBcast31>(x));
   return lane_read(x, 63);
 }
 
-// Powers of the lane-to-lane carry factor g used by the group scans.
+// Powers of the lane-to-lane carry factor g used by the group scans of G
+// lanes.  The cross-row carries move whole rows; a row that must not take a
+// carry (one of its own group: a value of another group is never scaled in)
+// has the factor 0 there.
 template <typename T>
 struct ScanPow {
   T g1, g2, g4, g8, g16;
-  T gl;   // g^{(lane & 15) + 1}
-  T gl2;  // g^{(lane & 31) + 1}
-  T gr;   // g^{16 - (lane & 15)}
+  T gl;   // g^{(lane & 15) + 1} (G = 64: 0 in rows 0 and 2)
+  T gl2;  // g^{(lane & 31) + 1} (0 in rows 0 and 1)
+  T gr;   // g^{16 - (lane & 15)}, 0 in rows 1 and 3
   T gr2;  // g^{32 - (lane & 31)}
 };
 
@@ -161,7 +168,7 @@ __device__ __forceinline__ T ipow(T g, int e) {   // 0 <= e <= 31
   return r;
 }
 
-template <typename T>
+template <int G, typename T>
 __device__ __forceinline__ ScanPow<T> scan_pow(T g) {
   ScanPow<T> p;
   p.g1 = g;
@@ -169,11 +176,12 @@ __device__ __forceinline__ ScanPow<T> scan_pow(T g) {
   p.g4 = p.g2 * p.g2;
   p.g8 = p.g4 * p.g4;
   p.g16 = p.g8 * p.g8;
-  const int j = lane_id() & 15;
-  p.gl = ipow(g, j + 1);
-  p.gl2 = (lane_id() & 16) ? p.gl * p.g16 : p.gl;
-  p.gr = ipow(g, 16 - j);
-  p.gr2 = (lane_id() & 16) ? p.gr : p.gr * p.g16;
+  const int j = lane_id() & 15, row = lane_id() >> 4;
+  const T gl = ipow(g, j + 1), gr = ipow(g, 16 - j);
+  p.gl = (G == 64 && !(row & 1)) ? T(0) : gl;
+  p.gl2 = row < 2 ? T(0) : ((row & 1) ? gl * p.g16 : gl);
+  p.gr = (row & 1) ? T(0) : gr;
+  p.gr2 = (row & 1) ? gr : gr * p.g16;
   return p;
 }
 
@@ -186,14 +194,30 @@ __device__ __forceinline__ T grp_scan_fwd(T e, const ScanPow<T> &p) {
   t = fma(p.g2, dpp<kRowShr2>(t), t);
   t = fma(p.g4, dpp<kRowShr4>(t), t);
   t = fma(p.g8, dpp<kRowShr8>(t), t);
-  if (G >= 32) {
-    // rows 1 and 3 carry in the last lane of rows 0 and 2 (rows 0 and 2 add 0)
+  if (G == 32) {
+    // rows 1 and 3 carry in the last lane of rows 0 and 2 (rows 0 and 2, the
+    // first rows of the groups, take nothing)
     t = fma(p.gl, dpp_rows<kRowBcast15, 0xa>(t), t);
   }
   if (G == 64) {
-    // rows 2 and 3 carry in lane 31, now the scan of the first half
-    t = fma(p.gl2, dpp_rows<kRowBcast31, 0xc>(t), t);
+    // the same within the one group (rows 0 and 2 scale what they read by 0),
+    // then rows 2 and 3 carry in lane 31, the scan of the first half
+    t = fma(p.gl, dpp<kRowBcast15>(t), t);
+    t = fma(p.gl2, dpp<kRowBcast31>(t), t);
   }
+  return t;
+}
+
+// The same with g = 1 (running sums).
+template <int G, typename T>
+__device__ __forceinline__ T grp_sum_fwd(T e) {
+  T t = e;
+  t += dpp<kRowShr1>(t);
+  t += dpp<kRowShr2>(t);
+  t += dpp<kRowShr4>(t);
+  t += dpp<kRowShr8>(t);
+  if (G >= 32) t += dpp_rows<kRowBcast15, 0xa>(t);
+  if (G == 64) t += dpp_rows<kRowBcast31, 0xc>(t);
   return t;
 }
 
@@ -206,8 +230,9 @@ __device__ __forceinline__ T grp_scan_bwd(T e, const ScanPow<T> &p) {
   t = fma(p.g4, dpp<kRowShl4>(t), t);
   t = fma(p.g8, dpp<kRowShl8>(t), t);
   if (G >= 32) {
-    // rows 0 and 2 carry in the first lane of rows 1 and 3 (rows 1 and 3 add 0)
-    t = fma(p.gr, dpp_rows<kRowNewBcast0, 0x5>(odd_rows(t)), t);
+    // rows 0 and 2 carry in the first lane of rows 1 and 3 (rows 1 and 3 read
+    // their own first lane and scale it by 0)
+    t = fma(p.gr, dpp<kRowNewBcast0>(odd_rows(t)), t);
   }
   if (G == 64) {
     // rows 0 and 1 carry in lane 32, now the scan of the second half
@@ -286,12 +311,10 @@ __device__ __forceinline__ void toeplitz_solve(T (&x)[MM], const T (&b)[MM], con
   for (int r = 0; r < MM; ++r) part = fma(wb[r], b[r], part);
   const T z0 = grp_reduce<G, false>(part);
   T z[MM];
-  T prev = T(0);
+  z[0] = b[0] * itk;
 #pragma unroll
-  for (int r = 0; r < MM; ++r) {
-    z[r] = fma(-rho, prev, b[r] * itk);
-    prev = z[r];
-  }
+  for (int r = 1; r < MM; ++r) z[r] = fma(-rho, z[r - 1], b[r] * itk);
+  T prev = z[MM - 1];
   const bool first = (lane_id() & (G - 1)) == 0;
   const T e = first ? fma(sp.g1, z0, prev) : prev;
   const T Z = grp_scan_fwd<G>(e, sp);
@@ -303,13 +326,10 @@ __device__ __forceinline__ void toeplitz_solve(T (&x)[MM], const T (&b)[MM], con
     z[r] = fma(pw, C, z[r]) * mask[r];
     pw = pw * (-rho);
   }
-  prev = T(0);
+  x[MM - 1] = z[MM - 1];
 #pragma unroll
-  for (int r = MM - 1; r >= 0; --r) {
-    x[r] = fma(-rho, prev, z[r]);
-    prev = x[r];
-  }
-  const T X = grp_scan_bwd<G>(prev, sp);
+  for (int r = MM - 2; r >= 0; --r) x[r] = fma(-rho, x[r + 1], z[r]);
+  const T X = grp_scan_bwd<G>(x[0], sp);
   const T Dn = grp_next<G>(X);
   pw = T(1);
 #pragma unroll
@@ -551,8 +571,7 @@ __device__ __forceinline__ void prefix_store(T *PA, T *PB, const T (&x)[MM], con
     pa[r] = ca;
     pb[r] = cb;
   }
-  const ScanPow<T> one = {T(1), T(1), T(1), T(1), T(1), T(1), T(1), T(1), T(1)};
-  const T oa = grp_scan_fwd<G>(grp_prev<G>(ca), one), ob = grp_scan_fwd<G>(grp_prev<G>(cb), one);
+  const T oa = grp_sum_fwd<G>(grp_prev<G>(ca)), ob = grp_sum_fwd<G>(grp_prev<G>(cb));
 #pragma unroll
   for (int r = 0; r < MM; ++r) {
     PA[tb + r + 1] = oa + pa[r];
@@ -908,8 +927,8 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   mask_l.init(lb, nl);
 
   const T rho_t = (T)D.rho_t, itk_t = (T)D.itk_t, rho_l = (T)D.rho_l, itk_l = (T)D.itk_l;
-  const ScanPow<T> spt = scan_pow<T>(ipow<T>(-rho_t, mt));
-  const ScanPow<T> spl = scan_pow<T>(ipow<T>(-rho_l, ml));
+  const ScanPow<T> spt = scan_pow<G, T>(ipow<T>(-rho_t, mt));
+  const ScanPow<T> spl = scan_pow<G, T>(ipow<T>(-rho_l, ml));
   const T Ntd = (T)D.Ntd, Nld = (T)D.Nld;
   const T cS = (T)D.cS, s0t2 = (T)(2.0 * D.s0k_t), s1t2 = (T)(2.0 * D.s1k_t);
   const T s0l2 = (T)(2.0 * D.s0k_l), s1l2 = (T)(2.0 * D.s1k_l);
