@@ -154,7 +154,7 @@ struct ScanPow {
   T gl;   // g^{(lane & 15) + 1} (G = 64: 0 in rows 0 and 2)
   T gl2;  // g^{(lane & 31) + 1} (0 in rows 0 and 1)
   T gr;   // g^{16 - (lane & 15)}, 0 in rows 1 and 3
-  T gr2;  // g^{32 - (lane & 31)}
+  T gr2;  // g^{32 - (lane & 31)}, 0 in rows 2 and 3
 };
 
 template <typename T>
@@ -181,7 +181,7 @@ __device__ __forceinline__ ScanPow<T> scan_pow(T g) {
   p.gl = (G == 64 && !(row & 1)) ? T(0) : gl;
   p.gl2 = row < 2 ? T(0) : ((row & 1) ? gl * p.g16 : gl);
   p.gr = (row & 1) ? T(0) : gr;
-  p.gr2 = (row & 1) ? gr : gr * p.g16;
+  p.gr2 = row >= 2 ? T(0) : ((row & 1) ? gr : gr * p.g16);
   return p;
 }
 
@@ -235,9 +235,9 @@ __device__ __forceinline__ T grp_scan_bwd(T e, const ScanPow<T> &p) {
     t = fma(p.gr, dpp<kRowNewBcast0>(odd_rows(t)), t);
   }
   if (G == 64) {
-    // rows 0 and 1 carry in lane 32, now the scan of the second half
-    const T c = lane_read(t, 32);
-    t = lane_id() < 32 ? fma(p.gr2, c, t) : t;
+    // rows 0 and 1 carry in lane 32, now the scan of the second half (rows 2
+    // and 3 scale it by 0)
+    t = fma(p.gr2, lane_read(t, 32), t);
   }
   return t;
 }
