@@ -576,7 +576,13 @@ struct WorkPlan {
 static int part_lanes(int part) { return kClassLanes[part / kNumShapes]; }
 
 static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPlan &wp) {
-  std::vector<std::pair<double, int>> parts[kNumVariants][kNumParts];
+  // per part: (steps, cost, slot) of each string
+  struct Item {
+    int64_t steps;
+    double cost;
+    int slot;
+  };
+  std::vector<Item> parts[kNumVariants][kNumParts];
   bool any = false;
   for (int i = first; i < first + count; ++i) {
     Slot &s = b->slots[i];
@@ -593,21 +599,25 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
     const bool cubic_hammer = d.ham_on && (d.hn2 || d.hn3);
     const int v = d.grid_interp == 3 ? kVarCubic
                                      : ((d.bow_on || d.clamped || d.zeta_out || cubic_hammer) ? kVarBow : kVarPlain);
-    parts[v][part].push_back({cost, i});
+    parts[v][part].push_back({st, cost, i});
   }
   if (!any) return fail(b, SB_ESTATE, "no excited slot");
   std::vector<int32_t> work;
   for (int v = 0; v < kNumVariants; ++v) {
     for (int q = 0; q < kNumParts; ++q) {
       auto &L = parts[v][q];
-      std::stable_sort(L.begin(), L.end(), [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
-        return x.first > y.first;
+      // longest first by steps: the strings of a part cost the same per
+      // step (one layout), and a wavefront steps as long as its longest
+      // group, so the groups of a task should have equal steps (the cost
+      // breaks ties and orders the plain path's one-string launches)
+      std::stable_sort(L.begin(), L.end(), [](const Item &x, const Item &y) {
+        return x.steps != y.steps ? x.steps > y.steps : x.cost > y.cost;
       });
       wp.off[v][q] = (int)work.size();
       const int groups = b->precision == SB_FP64_PLAIN ? 1 : kWave / part_lanes(q);
       for (size_t i = 0; i < L.size(); i += groups)
-        for (int g = 0; g < groups; ++g) work.push_back(i + g < L.size() ? L[i + g].second : -1);
-      for (auto &w : L) wp.members.push_back(w.second);
+        for (int g = 0; g < groups; ++g) work.push_back(i + g < L.size() ? L[i + g].slot : -1);
+      for (auto &w : L) wp.members.push_back(w.slot);
     }
     wp.off[v][kNumParts] = (int)work.size();
     if (b->precision != SB_FP64_PLAIN) {
