@@ -91,7 +91,7 @@ sb_excitation draw_excitation(int i) {
 
 int main(int argc, char **argv) {
   const int n = argc > 1 ? std::atoi(argv[1]) : 600;
-  int ok = 0, refused = 0, budget = 0, exc_ok = 0, exc_refused = 0, plain_ok = 0, plain_refused = 0;
+  int ok = 0, refused = 0, budget = 0, exc_ok = 0, exc_refused = 0, plain_ok = 0, plain_refused = 0, shaped = 0;
   double checksum = 0.0;
   for (int i = 0; i < n; ++i) {
     const sb_string_params p = draw_string(i);
@@ -99,7 +99,9 @@ int main(int argc, char **argv) {
     const int gst = string_plan_grid(&p, &nt, &nl);
     sfd::Plan P;
     std::string err;
-    const int st = sfd::plan_string(p, P, err);
+    // every other string is planned for an FP32 batch, with the narrow layouts
+    const bool shapes = i % 2 == 1;
+    const int st = sfd::plan_string(p, P, err, shapes);
     // string_plan_grid sizes the grid only; the per-string budget is the planner's
     if ((st == SB_EINVAL) != (gst == SB_EINVAL)) {
       std::printf("MISMATCH string %d: plan_string %d, string_plan_grid %d (%s)\n", i, st, gst, err.c_str());
@@ -115,6 +117,28 @@ int main(int argc, char **argv) {
     }
     ++ok;
     checksum += nt + nl;
+    {
+      // the layout: each grid on MM, 3MM/4 (classes of 4 and 8 slots) or
+      // MM/2 slots per lane, covering its points, the fewest in total, not
+      // both at MM/2; MM on both grids without shapes
+      const sfd::Desc &D = P.desc;
+      const int G = sfd::kClassLanes[D.cls], mm = sfd::kClassSlots[D.cls];
+      std::vector<int> levels = {mm, mm / 2};
+      if (mm == 4 || mm == 8) levels.push_back(3 * mm / 4);
+      int best = 1 << 30;
+      for (int mt : levels)
+        for (int ml : levels) {
+          if (mt == mm / 2 && ml == mm / 2) continue;
+          if (D.Nt <= G * mt && D.Nl <= G * ml && mt + ml < best) best = mt + ml;
+        }
+      const bool cover = D.Nt <= G * D.mt && D.Nl <= G * D.ml;
+      if (!cover || (shapes ? D.mt + D.ml != best : (D.mt != mm || D.ml != mm))) {
+        std::printf("LAYOUT string %d: class %d Nt %d Nl %d -> mt %d ml %d (fewest %d)\n", i, D.cls, D.Nt, D.Nl,
+                    D.mt, D.ml, best);
+        return 3;
+      }
+      shaped += (D.mt + D.ml < 2 * mm) ? 1 : 0;
+    }
     for (double v : P.tabf) checksum += std::isfinite(v) ? 1e-9 * v : 0.0;
     for (int k = 0; k < 2; ++k) {
       sfd::Plan Q = P;
@@ -140,7 +164,8 @@ int main(int argc, char **argv) {
       }
     }
   }
-  std::printf("strings %d ok %d refused %d budget %d excitations ok %d refused %d plain ok %d refused %d checksum %.6e\n",
-              n, ok, refused, budget, exc_ok, exc_refused, plain_ok, plain_refused, checksum);
+  std::printf("strings %d ok %d refused %d budget %d excitations ok %d refused %d plain ok %d refused %d "
+              "narrow layouts %d checksum %.6e\n",
+              n, ok, refused, budget, exc_ok, exc_refused, plain_ok, plain_refused, shaped, checksum);
   return 0;
 }

@@ -5,10 +5,11 @@
   -fsanitize=address,undefined and -fno-sanitize-recover=all; it must finish
   with no report, and its results must equal those of the uninstrumented
   liboracle on the same cases.
-* The library's host planner (grid sizing, coefficient and excitation
-  tables, the plain path's tables; tests/sanitize/planner_driver.cpp) over a
-  seeded sweep of valid and invalid parameters, built the same way with
-  hipcc (host code only: each -fsanitize goes to the host compiler).
+* The library's host planner (grid sizing, the layouts of FP32 batches,
+  coefficient and excitation tables, the plain path's tables;
+  tests/sanitize/planner_driver.cpp) over a seeded sweep of valid and
+  invalid parameters, built the same way with hipcc (host code only: each
+  -fsanitize goes to the host compiler).
 
 The kernels and the HIP runtime calls are outside these builds (no GPU
 sanitizer on the test machines); the GPU tests' bitwise determinism checks
@@ -115,9 +116,12 @@ def test_planner_under_asan_ubsan(tmp_path):
     res = subprocess.run([exe, "600"], capture_output=True, text=True, env=SAN_ENV, timeout=600)
     _clean(res)
     m = re.search(r"strings (\d+) ok (\d+) refused (\d+) budget (\d+) excitations ok (\d+) refused (\d+) "
-                  r"plain ok (\d+) refused (\d+)", res.stdout)
+                  r"plain ok (\d+) refused (\d+) narrow layouts (\d+)", res.stdout)
     assert m, res.stdout
-    n, ok, refused, budget, exc_ok, exc_refused, plain_ok, plain_refused = (int(x) for x in m.groups())
+    n, ok, refused, budget, exc_ok, exc_refused, plain_ok, plain_refused, narrow = (int(x) for x in m.groups())
+    # (the driver checks every planned layout: each grid covered, the fewest
+    # slots per lane among the class's width levels)
+    assert narrow > 50
     # the sweep reaches valid and invalid strings, excitations and plain-path plans
     assert n == 600 and ok > 200 and refused > 200 and budget >= 1
     assert exc_ok > 300 and exc_refused > 10 and plain_ok > 100 and plain_refused > 10
