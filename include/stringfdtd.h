@@ -137,8 +137,9 @@ typedef struct {
     int32_t size_class;        /* kernel size class 0..6 of the batched paths      */
     int32_t lanes;             /* lanes per string in that class (16, 32 or 64)   */
     int32_t slots_t, slots_l;  /* slots per lane of the transverse / longitudinal
-                                  grid in the string's layout (FP32 batches halve
-                                  a grid that fits; 0 on the plain path)         */
+                                  grid in the string's layout (FP32 batches: the
+                                  fewest of the class's MM, 3MM/4 and MM/2 the
+                                  grid fits in; FP64: MM; 0 on the plain path)   */
 } sb_string_info;
 
 /* Create a batch of `capacity` (>= 1) slots computing in `precision`
