@@ -199,3 +199,37 @@ def test_narrow_layouts(precision, tol):
     assert got == want
     assert all(inf["flags"] == 0 for inf in infos)
     assert max(errs) <= tol
+
+
+def test_narrow_layouts_bow_family():
+    """The same layouts in the instantiation that carries the bow family's
+    code (asking for the zeta channel routes a string there), FP32: both
+    channels against the oracle, every (class, layout) pair."""
+    _gpu()
+    slots = {0: 2, 1: 4, 2: 4, 3: 4, 4: 8, 5: 10, 6: 16}
+    items, want = [], []
+    for k, (c, s, f0, B, a) in enumerate(_LAYOUT_CASES):
+        p = W.string(f0, B, a, 1.0, 2e-4, 960, mod_type=2 if k % 4 == 0 else 0, glide_semitones=0.5)
+        p["readout_zeta"] = 1
+        e = W.hammer(0.11 + 0.007 * k, 2.0) if k % 2 else W.pluck(0.13 + 0.011 * k, 1e-3)
+        items.append((p, e))
+        want.append((c, _level_slots(slots[c], s // 3), _level_slots(slots[c], s % 3)))
+    refs = oracle.run_many(items, want=("y_u", "y_z"))
+    b = binding.StringBatch(len(items), "fp32c")
+    try:
+        b.set_params(0, [p for p, _ in items])
+        b.excite(0, [e for _, e in items])
+        b.step(960)
+        outs = [b.read_output(i) for i in range(len(items))]
+        outz = [b.read_output_zeta(i) for i in range(len(items))]
+        infos = [b.info(i) for i in range(len(items))]
+    finally:
+        b.close()
+    got = [(inf["size_class"], inf["slots_t"], inf["slots_l"]) for inf in infos]
+    errs = [rel_l2(y, r["y_u"]) for y, r in zip(outs, refs)]
+    errz = [rel_l2(y, r["y_z"]) for y, r in zip(outz, refs) if np.any(r["y_z"])]
+    print("[gpu] bow-family layouts: worst rel-L2 u %.3e, zeta %.3e (%d strings with a zeta grid)"
+          % (max(errs), max(errz), len(errz)), flush=True)
+    assert got == want
+    assert all(inf["flags"] == 0 for inf in infos)
+    assert max(errs) <= 1e-3 and max(errz) <= 1e-3
