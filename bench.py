@@ -42,8 +42,8 @@ PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 2.4 GHz x 25
 TRAFFIC = {"kernel": "step_kernel_small<float, true>", "source_sha256": "a4c20f87dec8558a",
            "fetch_bytes": 0.3054e9, "write_bytes": 6.805e9}
 
-# the kernels of the three launch units of a step (size classes 0..3 merged,
-# 4, then 5 and 6 on one stream)
+# the kernels of the three launch units of a step (size classes 0..4 merged,
+# 5, then 6 and 7 on one stream)
 LAUNCH_KERNELS = ["step_kernel_small<float, true>", "step_kernel<64, 8, float, true>",
                   "step_kernel<64, 10 and 16, float, true>"]
 
@@ -512,8 +512,8 @@ def main():
         "config": {"workload": args.workload, "strings": len(items), "fs": 48000,
                    "updates_per_step": updates, "audio_seconds_per_step": audio_s,
                    "precision": "FP32 with compensated state updates, FP64 energy monitor",
-                   "launch": "three concurrent persistent launch units per step (size classes 0-3 merged, 4, "
-                             "then 5 and 6; forked onto their streams and joined), each grid of a string laid out "
+                   "launch": "three concurrent persistent launch units per step (size classes 0-4 merged, 5, "
+                             "then 6 and 7; forked onto their streams and joined), each grid of a string laid out "
                              "on the fewest of MM, 3MM/4 and MM/2 slots per lane it fits in, blocks/CU "
                              "autotuned; the same step replayed from a HIP graph is reported beside",
                    "blocks_per_cu": tuned},

@@ -134,7 +134,7 @@ typedef struct {
     int32_t flags;             /* 1: unstable (energy monitor), 2: no convergence */
     int32_t max_sweeps;        /* largest number of coupled-solve sweeps in a step */
     int64_t total_sweeps;      /* total sweeps                                    */
-    int32_t size_class;        /* kernel size class 0..6 of the batched paths      */
+    int32_t size_class;        /* kernel size class 0..7 of the batched paths      */
     int32_t lanes;             /* lanes per string in that class (16, 32 or 64)   */
     int32_t slots_t, slots_l;  /* slots per lane of the transverse / longitudinal
                                   grid in the string's layout (FP32 batches: the
@@ -241,10 +241,10 @@ int string_batch_graph_launch(sb_batch *b);
 /* A batched step runs as SB_NUM_LAUNCHES concurrent units of kernel
  * launches, each on its own stream, forked from and joined back to the batch
  * stream:
- *   0: size classes 0..3 (up to 256 points), one persistent launch with one
+ *   0: size classes 0..4 (up to 384 points), one persistent launch with one
  *      work queue, the classes' tasks dealt out in proportion;
- *   1: size class 4 (up to 512 points);
- *   2: size classes 5 (up to 640 points) and 6 (up to 1024), one launch
+ *   1: size class 5 (up to 512 points);
+ *   2: size classes 6 (up to 640 points) and 7 (up to 1024), one launch
  *      after the other. */
 #define SB_NUM_LAUNCHES 3
 

@@ -22,10 +22,10 @@ SB_FP64, SB_FP32C, SB_FP64_PLAIN = 0, 1, 2
 PRECISIONS = {"fp64": SB_FP64, "fp32c": SB_FP32C, "fp64_plain": SB_FP64_PLAIN}
 # rows of the allocation-free gather's fixed scratch
 SB_NOALLOC_MAX_ROWS = 16384
-# concurrent launch units of a batched step: classes 0..3 merged, class 4,
-# classes 5 and 6 one after the other
+# concurrent launch units of a batched step: classes 0..4 merged, class 5,
+# classes 6 and 7 one after the other
 NUM_LAUNCHES = 3
-LAUNCH_CLASSES = ((0, 1, 2, 3), (4,), (5, 6))
+LAUNCH_CLASSES = ((0, 1, 2, 3, 4), (5,), (6, 7))
 STATUS_NAMES = {0: "SB_OK", -1: "SB_EINVAL", -2: "SB_ENOMEM", -3: "SB_EBUDGET", -4: "SB_EUNSTABLE",
                 -5: "SB_ESTATE", -6: "SB_EDEVICE"}
 

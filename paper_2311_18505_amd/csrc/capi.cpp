@@ -566,7 +566,7 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
 // own, which keeps the bow's code and registers out of every other task.
 struct WorkPlan {
   int off[kNumVariants][kNumParts + 1] = {};      // per variant, start of each part's tasks
-  // ticket maps of the merged launch (parts of classes 0..3, index 0) and of
+  // ticket maps of the merged launch (parts of classes 0..4, index 0) and of
   // each large class's launch (its shapes, index 1 + class - 4)
   static constexpr int kTicketLists = 1 + kNumClasses - kNumSmall;
   int tickets_off[kNumVariants][kTicketLists] = {}, n_tickets[kNumVariants][kTicketLists] = {};
@@ -666,7 +666,7 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
 }
 
 // One step launch on `st`: counters cleared by a kernel (no memset nodes
-// under capture), the three launches (classes 0..3 merged, class 4, class 5)
+// under capture), the three launches (classes 0..4 merged, class 5, classes 6 and 7)
 // forked onto their own streams and joined back.  Issues no synchronisation
 // and no copy, so it can be captured.
 static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t n_steps) {
@@ -680,7 +680,7 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
     b->unit_strings[u] = 0;
     bool forked = false;
     // the unit's classes one after the other (unit 0: the merged launch of
-    // classes 0..3); the bow-family variants follow the plain one on the same stream
+    // classes 0..4); the bow-family variants follow the plain one on the same stream
     const int c_lo = u == 0 ? 0 : (u == 1 ? kNumSmall : kNumSmall + 1);
     const int c_hi = u == 0 ? 1 : (u == 1 ? kNumSmall + 1 : kNumClasses);
     for (int c = c_lo; c < c_hi; ++c) {
@@ -694,7 +694,7 @@ static int enqueue_step(sb_batch *b, hipStream_t st, const WorkPlan &wp, int64_t
         a.tickets = nullptr;
         {
           // ticketed launches: the merged one over the parts of classes
-          // 0..3, a large class's over its shapes
+          // 0..4, a large class's over its shapes
           const int tl = u == 0 ? 0 : 1 + c - kNumSmall;
           const int q0 = u == 0 ? 0 : c * kNumShapes;
           const int nq = u == 0 ? kNumSmall * kNumShapes : kNumShapes;

@@ -14,16 +14,24 @@ constexpr int kMaxN = kWave * kMaxSlots;   // N_t, N_l <= 1024
 // (a wavefront holds 64/G strings) and every lane owns up to MM consecutive
 // points of each grid; a string runs in the smallest class with
 // G * MM >= max(N_t, N_l).
-constexpr int kNumClasses = 7;
-constexpr int kClassLanes[kNumClasses] = {16, 16, 32, 64, 64, 64, 64};
-constexpr int kClassSlots[kNumClasses] = {2, 4, 4, 4, 8, 10, 16};
+constexpr int kNumClasses = 8;
+constexpr int kClassLanes[kNumClasses] = {16, 16, 32, 64, 64, 64, 64, 64};
+constexpr int kClassSlots[kNumClasses] = {2, 4, 4, 4, 6, 8, 10, 16};
+constexpr int class_points(int c) { return kClassLanes[c] * kClassSlots[c]; }
+// the class of G lanes and MM slots per lane (-1 if none)
+constexpr int class_of(int G, int MM) {
+  for (int c = 0; c < kNumClasses; ++c)
+    if (kClassLanes[c] == G && kClassSlots[c] == MM) return c;
+  return -1;
+}
 
-// Launches of one step.  The classes up to 256 points share one occupancy
-// profile and run as one persistent launch with one work queue (unit 0);
-// class 4 runs as a launch of its own (unit 1) and classes 5 and 6 one after
-// the other on a third stream (unit 2; no string of the benchmark workloads
-// needs class 6), so the three units run concurrently.
-constexpr int kNumSmall = 4;        // classes 0..3
+// Launches of one step.  The classes up to 384 points share one occupancy
+// profile (two wavefronts per SIMD) and run as one persistent launch with one
+// work queue (unit 0); class 5 runs as a launch of its own (unit 1) and
+// classes 6 and 7 one after the other on a third stream (unit 2; no string of
+// the benchmark workloads needs class 7), so the three units run
+// concurrently.
+constexpr int kNumSmall = 5;        // classes 0..4
 constexpr int kNumUnits = 3;
 constexpr int unit_of_class(int c) { return c < kNumSmall ? 0 : (c == kNumSmall ? 1 : 2); }
 // kernel of a class: 0 the merged classes, then one per large class
@@ -37,22 +45,27 @@ constexpr int kNumKernels = kNumClasses - kNumSmall + 1;
 // registers of what its strings use.
 enum : int { kVarPlain = 0, kVarBow = 1, kVarCubic = 2, kNumVariants = 3 };
 
-// Layouts ("shapes") of a string in its class: each grid gets MM, 3MM/4 or
-// MM/2 slots per lane (width levels 0, 1, 2), the fewest its points fit in;
-// shape = 3 * (transverse level) + (longitudinal level).  The stepping loops
-// run over a grid's slots, so a narrower grid does proportionally less work.
-// Level 1 exists in the classes of 4 and 8 slots; both grids at level 2 would
-// fit the next smaller class, so shape 8 is never used.  FP32 batches; FP64
-// batches use shape 0.
+// Layouts ("shapes") of a string in its class: each grid gets MM, an
+// intermediate count or MM/2 slots per lane (width levels 0, 1, 2), the
+// fewest its points fit in; shape = 3 * (transverse level) + (longitudinal
+// level).  The stepping loops run over a grid's slots, so a narrower grid
+// does proportionally less work.  Level 1 is 3MM/4 in the classes of 4 and 8
+// slots and 4 in the class of 6; the others have none.  A shape is kept only
+// where its wider grid needs more points than the next smaller class holds
+// (otherwise the string would be in that class; this also drops both grids
+// at MM/2, shape 8).  FP32 batches; FP64 batches use shape 0.
 constexpr int kNumShapes = 9;
-constexpr bool slots_have_quarter(int mm) { return mm == 4 || mm == 8; }
-constexpr int level_slots(int mm, int level) { return level == 0 ? mm : level == 1 ? 3 * mm / 4 : mm / 2; }
-constexpr bool shape_fits(int mm, int s) {
-  return s >= 0 && s < kNumShapes && s != 8 && (slots_have_quarter(mm) || (s / 3 != 1 && s % 3 != 1));
-}
+constexpr int level1_slots(int mm) { return mm == 4 || mm == 8 ? 3 * mm / 4 : (mm == 6 ? 4 : 0); }
+constexpr int level_slots(int mm, int level) { return level == 0 ? mm : level == 1 ? level1_slots(mm) : mm / 2; }
 constexpr int shape_mt(int c, int s) { return level_slots(kClassSlots[c], s / 3); }
 constexpr int shape_ml(int c, int s) { return level_slots(kClassSlots[c], s % 3); }
-constexpr bool shape_ok(int c, int s) { return shape_fits(kClassSlots[c], s); }
+constexpr bool shape_ok(int c, int s) {
+  if (c < 0 || c >= kNumClasses || s < 0 || s >= kNumShapes || s == 8) return false;
+  const int mt = shape_mt(c, s), ml = shape_ml(c, s);
+  if (mt == 0 || ml == 0) return false;
+  const int wide = mt > ml ? mt : ml;
+  return c == 0 || kClassLanes[c] * wide > class_points(c - 1);
+}
 // work lists are kept per part = class * kNumShapes + shape
 constexpr int kNumParts = kNumClasses * kNumShapes;
 
@@ -163,7 +176,7 @@ struct LaunchArgs {
   int32_t n_work;             // number of wavefront tasks (tickets)
   // ticket w runs task tickets[w] & 0xffffff of part tickets[w] >> 24,
   // whose tasks are listed at part_work[part] (the merged launch: the parts
-  // of classes 0..3; a large class: its shapes)
+  // of classes 0..4; a large class: its shapes)
   const int32_t *part_work[kNumSmall * kNumShapes];
   const int32_t *tickets;
   int32_t *counter;           // work-queue head (zeroed before the launch)

@@ -823,6 +823,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
     }
   }
   const bool bowed = BOW && D.bow_on != 0;
+  // the stopping rule of the coupled solve for bowed strings (the other
+  // strings of the bow family's instantiation keep the usual one)
+  const bool bow_stop = bowed;
   // the bow's code exists only in the BOW instantiation (its registers would
   // crowd every other task's)
   const bool any_bow = BOW && __ballot(bowed) != 0;
@@ -1327,10 +1330,10 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   #pragma unroll
             for (int r = 0; r < ML; ++r) amax = fmax(amax, fabs(nz[r]));
             const T A = grp_reduce<G, true>(amax);
-            // the instantiation that carries the bow stops on the update alone,
-            // at 100 tol in FP32 (an update of 1e-5 leaves an error of about
-            // rho 1e-5, the FP32 target of the estimate)
-            ascale = (T)(BOW && sizeof(T) == 4 ? 100.0 * a.tol : a.tol) * A;
+            // a bowed string stops on the update alone, at 100 tol in FP32 (an
+            // update of 1e-5 leaves an error of about rho 1e-5, the FP32 target
+            // of the estimate)
+            ascale = (T)(bow_stop && sizeof(T) == 4 ? 100.0 * a.tol : a.tol) * A;
             iscale = A > T(0) ? T(1) / A : T(0);
           } else {
             T delta = T(0);
@@ -1340,10 +1343,9 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
             for (int r = 0; r < ML; ++r) delta = fmax(delta, fabs(nz[r] - az[r]));
             const T dmax = grp_reduce<G, true>(delta);
             const T dn = dmax * iscale;
-            // (the instantiation that carries the bow stops on the update alone:
-            // the stick/slip decision of a chaotic bowed string amplifies
-            // the solve's error)
-            now = now || dmax <= ascale || (!BOW && dn <= T(0.5) * dprev && dn * dn <= (T)a.tol * dprev);
+            // (a bowed string stops on the update alone: the stick/slip
+            // decision of a chaotic bowed string amplifies the solve's error)
+            now = now || dmax <= ascale || (!bow_stop && dn <= T(0.5) * dprev && dn * dn <= (T)a.tol * dprev);
             dprev = dn;
           }
         }
@@ -1545,13 +1547,14 @@ __device__ __forceinline__ void run_task(const LaunchArgs &a, const int32_t *wor
   Sw->eta_nm1 = eta_nm1;
 }
 
-// Occupancy target per instantiation: the FP32 classes with up to 4 slots per
-// lane run two wavefronts per SIMD (256 registers each; the compiler spills a
-// few hundred bytes per lane, which the second wavefront more than pays for);
-// the larger and the FP64 classes keep the whole register file (one
-// wavefront per SIMD) because forcing them down spills their state.
+// Occupancy target per instantiation: the FP32 classes with up to 6 slots per
+// lane (the merged launch) run two wavefronts per SIMD (256 registers each;
+// the compiler spills a few hundred bytes per lane, which the second
+// wavefront more than pays for); the larger and the FP64 classes keep the
+// whole register file (one wavefront per SIMD) because forcing them down
+// spills their state.
 template <int MM, typename T>
-constexpr int kWavesPerEU = (sizeof(T) == 4 && MM <= 4) ? 2 : 1;
+constexpr int kWavesPerEU = (sizeof(T) == 4 && MM <= 6) ? 2 : 1;
 
 // FP32 instantiations step the narrower shapes as well (FP64 batches lay
 // every string out with shape 0)
@@ -1595,7 +1598,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
       switch (m >> 24) {
 #define SFD_SHAPE(S)                                                                                             \
   case S:                                                                                                       \
-    if constexpr (kShapes<T> && shape_fits(MM, S))                                                              \
+    if constexpr (kShapes<T> && shape_ok(class_of(G, MM), S))                                                   \
       run_task<G, level_slots(MM, (S) / 3), level_slots(MM, (S) % 3), T, KAHAN, BOW, CUB>(                       \
           a, a.part_work[S], t, sS, sE, sC, sTu, sTf, lds_bow, lds_w);                                          \
     break;
@@ -1615,14 +1618,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
   }
 }
 
-// The classes up to 256 points in one persistent launch: one ticket counter
+// The classes up to 384 points in one persistent launch: one ticket counter
 // over their tasks in the order the host chose (estimated work, longest
 // first), so that the short tasks fill the tail.  They share the occupancy
 // target and need neither LDS tables nor LDS compensation.
 template <typename T, bool CUB>
 constexpr int small_lds_doubles() {
   constexpr int n = kLdsArrays<CUB>;
-  constexpr int a = (Lds<64, 4, n>::kStride * (int)sizeof(T) + 7) / 8, ae = EnergyLds<64, 4>::kStride;
+  // (the class of 64 lanes and 6 slots needs the most)
+  constexpr int a = (Lds<64, 6, n>::kStride * (int)sizeof(T) + 7) / 8, ae = EnergyLds<64, 6>::kStride;
   constexpr int b = (2 * Lds<32, 4, n>::kStride * (int)sizeof(T) + 7) / 8, be = 2 * EnergyLds<32, 4>::kStride;
   constexpr int c = (4 * Lds<16, 4, n>::kStride * (int)sizeof(T) + 7) / 8, ce = 4 * EnergyLds<16, 4>::kStride;
   constexpr int d = (4 * Lds<16, 2, n>::kStride * (int)sizeof(T) + 7) / 8, de = 4 * EnergyLds<16, 2>::kStride;
@@ -1634,11 +1638,13 @@ constexpr int small_lds_doubles() {
 template <typename T, bool KAHAN, bool BOW, bool CUB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<4, T>))) void step_kernel_small(
     LaunchArgs a) {
-  static_assert(kWavesPerEU<2, T> == kWavesPerEU<4, T>, "one occupancy target for the merged classes");
-  static_assert(!kSideComp<4, T, KAHAN> && !kTabLds<4>, "no LDS tables in the merged classes");
+  static_assert(kWavesPerEU<2, T> == kWavesPerEU<4, T> && kWavesPerEU<6, T> == kWavesPerEU<4, T>,
+                "one occupancy target for the merged classes");
+  static_assert(!kSideComp<6, T, KAHAN> && !kTabLds<6>, "no LDS tables in the merged classes");
+  static_assert(kNumSmall == 5 && class_of(64, 6) == 4, "the merged classes");
   __shared__ double lds[small_lds_doubles<T, CUB>()];
   __shared__ double lds_bow[BOW ? 4 * kBowRec : 1];   // up to four groups per wavefront
-  __shared__ T lds_w[2 * 4 * kWave];                    // per-slot weights of the point interpolants
+  __shared__ T lds_w[2 * 6 * kWave];                    // per-slot weights of the point interpolants
   T *sS = (T *)lds;
   double *sE = lds;
   for (;;) {
@@ -1663,7 +1669,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
   SFD_PART(P0 + 5, G_, 3, 2)  \
   SFD_PART(P0 + 6, G_, 2, 4)  \
   SFD_PART(P0 + 7, G_, 2, 3)
+// the shapes of the class of 64 lanes and six slots per lane (its wider grid
+// on six)
+#define SFD_PARTS6(P0)         \
+  SFD_PART(P0, 64, 6, 6)       \
+  SFD_PART(P0 + 1, 64, 6, 4)   \
+  SFD_PART(P0 + 2, 64, 6, 3)   \
+  SFD_PART(P0 + 3, 64, 4, 6)   \
+  SFD_PART(P0 + 6, 64, 3, 6)
     switch (m >> 24) {
+      SFD_PARTS6(4 * kNumShapes)
       SFD_PARTS4(3 * kNumShapes, 64)
       SFD_PARTS4(2 * kNumShapes, 32)
       SFD_PARTS4(1 * kNumShapes, 16)
@@ -1673,6 +1688,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
         run_task<16, 2, 2, T, KAHAN, BOW, CUB>(a, a.part_work[0], t, sS, sE, sS, nullptr, nullptr, lds_bow, lds_w);
         break;
     }
+#undef SFD_PARTS6
 #undef SFD_PARTS4
 #undef SFD_PART
   }

@@ -99,7 +99,7 @@ hipError_t launch_rewind(int precision, const Desc *desc, Status *status, const 
   return hipGetLastError();
 }
 
-// kernel: 0 the merged classes 0..3, 1..3 the classes 4..6 (kernel_of_class);
+// kernel: 0 the merged classes 0..4, 1..3 the classes 5..7 (kernel_of_class);
 // variant: kVarPlain, kVarBow or kVarCubic; precision 1 is FP32 with
 // compensation, else FP64
 hipError_t launch_kernel(int precision, int kernel, int variant, const LaunchArgs &a, int blocks, hipStream_t st) {

@@ -25,8 +25,8 @@ def items():
     its.append((dict(q, boundary=1, readout_zeta=1, alpha=max(q["alpha"], 1.5)), f))
     its.append((dict(its[5][0], grid_interp=3, alpha=max(its[5][0]["alpha"], 1.5)), its[5][1]))
     its.append((W.string(180.0, 3e-4, 2.5, 1.0, 2e-4, n), dict(W.hammer(0.03, 2.0), interp_order=3)))
-    its.append((W.string(40.0, 1e-5, 1.1, 0.5, 1e-4, n), W.hammer(0.12, 2.0)))          # class 5
-    its.append((W.string(20.0, 1e-6, 1.1713, 0.5, 1e-4, n), W.hammer(0.12, 2.0)))       # class 6
+    its.append((W.string(40.0, 1e-5, 1.1, 0.5, 1e-4, n), W.hammer(0.12, 2.0)))          # class 6
+    its.append((W.string(20.0, 1e-6, 1.1713, 0.5, 1e-4, n), W.hammer(0.12, 2.0)))       # class 7
     its.append((dict(W.string(20.7, 1e-5, 3.0, 1.0, 1e-4, n), boundary=1), W.pluck(0.2, 1e-3)))
     return its
 

@@ -118,17 +118,22 @@ int main(int argc, char **argv) {
     ++ok;
     checksum += nt + nl;
     {
-      // the layout: each grid on MM, 3MM/4 (classes of 4 and 8 slots) or
-      // MM/2 slots per lane, covering its points, the fewest in total, not
-      // both at MM/2; MM on both grids without shapes
+      // the layout: each grid on MM, an intermediate count (3 of 4, 6 of 8,
+      // 4 of 6 slots) or MM/2 slots per lane, covering its points, the fewest
+      // in total, its wider grid beyond what the next smaller class holds and
+      // not both at MM/2; MM on both grids without shapes
       const sfd::Desc &D = P.desc;
       const int G = sfd::kClassLanes[D.cls], mm = sfd::kClassSlots[D.cls];
       std::vector<int> levels = {mm, mm / 2};
-      if (mm == 4 || mm == 8) levels.push_back(3 * mm / 4);
+      if (mm == 4) levels.push_back(3);
+      if (mm == 8) levels.push_back(6);
+      if (mm == 6) levels.push_back(4);
+      const int below = D.cls > 0 ? sfd::kClassLanes[D.cls - 1] * sfd::kClassSlots[D.cls - 1] : 0;
       int best = 1 << 30;
       for (int mt : levels)
         for (int ml : levels) {
           if (mt == mm / 2 && ml == mm / 2) continue;
+          if (G * (mt > ml ? mt : ml) <= below) continue;
           if (D.Nt <= G * mt && D.Nl <= G * ml && mt + ml < best) best = mt + ml;
         }
       const bool cover = D.Nt <= G * D.mt && D.Nl <= G * D.ml;

@@ -66,7 +66,7 @@ def test_clamped_mixed_batch(precision, tol):
     errs = [rel_l2(y, r) for y, r in zip(outs, refs)]
     print("[gpu] %s clamped batch: worst rel-L2 %.3e" % (precision, max(errs)), flush=True)
     assert all(i["flags"] == 0 for i in infos)
-    assert set(i["size_class"] for (p, _), i in zip(items, infos) if p["boundary"] == 1) == set(range(7))
+    assert set(i["size_class"] for (p, _), i in zip(items, infos) if p["boundary"] == 1) == set(range(8))
     assert max(errs) <= tol
 
 

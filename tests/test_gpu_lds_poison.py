@@ -49,7 +49,7 @@ def test_poisoned_lds_build_matches_regular_build(tmp_path):
         print("[gpu] regular build, %s" % precision, flush=True)
         outs, infos = R.run(precision)
         classes = {inf["size_class"] for inf in infos}
-        assert classes == set(range(7)), classes
+        assert classes == set(range(8)), classes
         assert np.array_equal(got[precision + "_class"], [inf["size_class"] for inf in infos])
         assert all(inf["flags"] == 0 for inf in infos)
         assert np.all(got[precision + "_flags"] == 0), got[precision + "_flags"]

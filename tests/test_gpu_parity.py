@@ -145,33 +145,34 @@ def test_plain_fp64_modulated_and_chunked():
 # longitudinal grid's slots per lane (also a string without one), layout 2
 # the transverse grid's (FP32 batches only)
 _LAYOUT_CASES = [
-    (0, 0, 187.43, 0.03, 4.0), (0, 2, 123.08, 0.03, 1.0), (0, 6, 434.6, 0.03, 2.0),
-    (1, 0, 92.99, 0.01, 4.0), (1, 1, 151.88, 0.001, 4.0), (1, 2, 32.5, 0.03, 1.0), (1, 3, 92.99, 0.03, 4.0),
-    (1, 4, 123.08, 0.01, 4.0), (1, 5, 56.93, 0.03, 1.0), (1, 6, 123.08, 0.03, 3.0), (1, 7, 123.08, 0.03, 4.0),
-    (2, 0, 49.49, 0.001, 4.0), (2, 1, 65.5, 0.001, 4.0), (2, 2, 8.58, 0.03, 1.0), (2, 3, 49.49, 0.01, 4.0),
-    (2, 4, 75.36, 0.001, 4.0), (2, 5, 15.03, 0.03, 1.0), (2, 6, 49.49, 0.03, 4.0), (2, 7, 65.5, 0.01, 4.0),
-    (3, 0, 32.5, 0.0001, 3.0), (3, 1, 32.5, 0.0001, 4.0), (3, 2, 11.36, 0.001, 1.0), (3, 3, 24.55, 0.001, 4.0),
-    (3, 4, 32.5, 0.001, 4.0), (3, 5, 8.0, 0.01, 1.0), (3, 6, 24.55, 0.01, 4.0), (3, 7, 32.5, 0.01, 4.0),
-    (4, 0, 12.18, 0.0001, 4.0), (4, 1, 21.34, 1e-05, 3.0), (4, 2, 9.2, 0.0001, 1.0), (4, 3, 15.03, 0.0001, 4.0),
-    (4, 4, 16.12, 0.0001, 4.0), (4, 5, 8.0, 0.001, 1.0), (4, 6, 12.18, 0.001, 4.0), (4, 7, 16.12, 0.001, 4.0),
-    (5, 0, 9.87, 0.0001, 4.0), (5, 2, 8.0, 0.0001, 1.0), (5, 6, 9.87, 0.001, 4.0),
-    (6, 0, 8.0, 1e-05, 3.0), (6, 2, 8.0, 1e-05, 1.0), (6, 6, 8.0, 0.001, 3.0),
+    (0, 0, 182.52, 0.02, 4.0), (0, 2, 124.54, 0.03, 1.0), (0, 6, 435.12, 0.03, 2.0), (1, 0, 94.32, 0.01, 4.0),
+    (1, 1, 124.54, 0.002, 4.0), (1, 2, 33.25, 0.03, 1.0), (1, 3, 94.32, 0.02, 4.0), (1, 4, 124.54, 0.01, 4.0),
+    (1, 5, 57.98, 0.03, 1.0), (1, 6, 124.54, 0.03, 3.0), (1, 7, 124.54, 0.03, 4.0), (2, 0, 47.07, 0.001, 4.0),
+    (2, 1, 62.16, 0.001, 4.0), (2, 2, 8.58, 0.03, 1.0), (2, 3, 47.07, 0.003, 4.0), (2, 4, 62.16, 0.002, 4.0),
+    (2, 5, 14.95, 0.03, 1.0), (2, 6, 47.07, 0.02, 4.0), (2, 7, 62.16, 0.01, 4.0), (3, 0, 23.49, 0.0003, 4.0),
+    (3, 1, 32.12, 0.0001, 4.0), (3, 2, 8.0, 0.003, 1.0), (3, 3, 23.49, 0.001, 4.0), (3, 4, 32.12, 0.001, 4.0),
+    (3, 5, 8.0, 0.01, 1.0), (3, 6, 23.49, 0.01, 4.0), (3, 7, 32.12, 0.002, 4.0), (4, 0, 16.03, 0.0001, 4.0),
+    (4, 1, 23.49, 0.0001, 4.0), (4, 2, 8.0, 0.001, 1.0), (4, 3, 16.03, 0.001, 4.0), (4, 6, 16.03, 0.002, 4.0),
+    (5, 0, 11.72, 0.0001, 4.0), (5, 1, 16.03, 3e-05, 4.0), (5, 2, 8.0, 0.0002, 1.0), (5, 3, 11.72, 0.0002, 4.0),
+    (5, 6, 11.72, 0.001, 4.0), (6, 0, 9.52, 0.0001, 4.0), (6, 2, 8.0, 0.0001, 1.0), (6, 6, 9.52, 0.001, 4.0),
+    (7, 0, 8.0, 1e-05, 3.0), (7, 2, 8.0, 1e-05, 1.0), (7, 6, 8.0, 0.0002, 3.0),
 ]
 
 
 def _level_slots(mm, level):
-    """Slots per lane of a grid at width level 0, 1, 2: MM, 3MM/4, MM/2."""
-    return (mm, 3 * mm // 4, mm // 2)[level]
+    """Slots per lane of a grid at width level 0, 1, 2: MM, the intermediate
+    count (3MM/4 for 4 and 8 slots, 4 for 6) and MM/2."""
+    return (mm, {4: 3, 6: 4, 8: 6}.get(mm, 0), mm // 2)[level]
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-3)])
 def test_narrow_layouts(precision, tol):
-    """Every layout of every size class (FP32 batches: each grid on MM, 3MM/4
-    or MM/2 slots per lane, the fewest it fits in; 3MM/4 in the classes of 4
-    and 8 slots) against the oracle, plucked and hammered, modulated and not;
-    FP64 batches keep the full layout."""
+    """Every layout of every size class (FP32 batches: each grid on MM, the
+    intermediate count or MM/2 slots per lane, the fewest it fits in) against
+    the oracle, plucked and hammered, modulated and not; FP64 batches keep the
+    full layout."""
     _gpu()
-    slots = {0: 2, 1: 4, 2: 4, 3: 4, 4: 8, 5: 10, 6: 16}
+    slots = {0: 2, 1: 4, 2: 4, 3: 4, 4: 6, 5: 8, 6: 10, 7: 16}
     items, want = [], []
     for k, (c, s, f0, B, a) in enumerate(_LAYOUT_CASES):
         p = W.string(f0, B, a, 1.0, 2e-4, 960, mod_type=1 if k % 3 == 0 else 0, mod_depth_cents=20.0,
@@ -206,7 +207,7 @@ def test_narrow_layouts_bow_family():
     code (asking for the zeta channel routes a string there), FP32: both
     channels against the oracle, every (class, layout) pair."""
     _gpu()
-    slots = {0: 2, 1: 4, 2: 4, 3: 4, 4: 8, 5: 10, 6: 16}
+    slots = {0: 2, 1: 4, 2: 4, 3: 4, 4: 6, 5: 8, 6: 10, 7: 16}
     items, want = [], []
     for k, (c, s, f0, B, a) in enumerate(_LAYOUT_CASES):
         p = W.string(f0, B, a, 1.0, 2e-4, 960, mod_type=2 if k % 4 == 0 else 0, glide_semitones=0.5)
@@ -227,7 +228,17 @@ def test_narrow_layouts_bow_family():
         b.close()
     got = [(inf["size_class"], inf["slots_t"], inf["slots_l"]) for inf in infos]
     errs = [rel_l2(y, r["y_u"]) for y, r in zip(outs, refs)]
-    errz = [rel_l2(y, r["y_z"]) for y, r in zip(outz, refs) if np.any(r["y_z"])]
+    # zeta against its own norm; where the longitudinal motion is below 5 %
+    # of the transverse (a strongly nonlinear hammered string: its zeta moves
+    # by 1.8e-4 under a 1e-7 change of f0, 30 times as much as u), on the
+    # displacement scale of u
+    errz = []
+    for y, r in zip(outz, refs):
+        if not np.any(r["y_z"]):
+            continue
+        d = np.linalg.norm(np.asarray(y, np.float64) - r["y_z"])
+        nz, nu = np.linalg.norm(r["y_z"]), np.linalg.norm(r["y_u"])
+        errz.append(d / nz if nz >= 0.05 * nu else d / nu)
     print("[gpu] bow-family layouts: worst rel-L2 u %.3e, zeta %.3e (%d strings with a zeta grid)"
           % (max(errs), max(errz), len(errz)), flush=True)
     assert got == want

@@ -160,13 +160,13 @@ def test_theta_one_and_largest_class_fp64():
         err = rel_l2(y, r["y_u"])
         print("[gpu] N=(%d,%d) class %d: rel-L2 %.3e" % (inf["N_t"], inf["N_l"], inf["size_class"], err), flush=True)
         assert err <= 1e-10
-    assert infos[1]["size_class"] == 5 and infos[2]["size_class"] == 5
+    assert infos[1]["size_class"] == 6 and infos[2]["size_class"] == 6
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-3)])
 def test_maximum_grid_sizes(precision, tol):
     """The largest grids the batched paths accept (1024 intervals, the top of
-    size class 6): N_l = 1024 (hammered, nonlinear) and N_t = 1024 (plucked,
+    size class 7): N_l = 1024 (hammered, nonlinear) and N_t = 1024 (plucked,
     linear), beside a small string in the same batch; one interval more is
     refused with SB_EBUDGET."""
     _gpu()

@@ -31,7 +31,7 @@ def _items():
     q, f = items[2]
     items.append((dict(q, boundary=1, readout_zeta=1, alpha=max(q["alpha"], 1.5)), f))
     items.append((dict(items[3][0], grid_interp=3, alpha=max(items[3][0]["alpha"], 1.5)), items[3][1]))
-    items.append((W.string(40.0, 1e-5, 1.1, 0.5, 1e-4, 2400), W.hammer(0.12, 2.0)))    # class 5
+    items.append((W.string(40.0, 1e-5, 1.1, 0.5, 1e-4, 2400), W.hammer(0.12, 2.0)))    # class 6
     return items
 
 
@@ -77,7 +77,7 @@ def test_snapshot_restore_resumes_bitwise(precision):
     finally:
         b.close()
     assert all(inf["flags"] == 0 for inf in ref[2])
-    assert {inf["size_class"] for inf in ref[2]} >= {0, 1, 2, 3, 5}
+    assert {inf["size_class"] for inf in ref[2]} >= {0, 1, 2, 3, 6}
 
     h = hiptime.hip()
     b = _batch(items, precision)
