@@ -575,6 +575,17 @@ struct WorkPlan {
 
 static int part_lanes(int part) { return kClassLanes[part / kNumShapes]; }
 
+// Estimated cost of one step of a wavefront task of a part (VALU
+// instructions, roughly: the per-lane scans and bookkeeping plus the
+// per-slot work of both grids), for ordering tickets only.
+static double part_step_cost(int part) {
+  const int c = part / kNumShapes, s = part % kNumShapes;
+  return 300.0 + 60.0 * (shape_mt(c, s) + shape_ml(c, s));
+}
+// the most expensive part's tickets are dealt over the first 1 - kTailSpan of
+// the sequence, a part of no cost over all of it
+constexpr double kTailSpan = 0.6;
+
 static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPlan &wp) {
   // per part: (steps, cost, slot) of each string
   struct Item {
@@ -622,20 +633,28 @@ static int build_work(sb_batch *b, int first, int count, int64_t n_steps, WorkPl
     wp.off[v][kNumParts] = (int)work.size();
     if (b->precision != SB_FP64_PLAIN) {
       // tickets of the merged launch and of each large class's launch: the
-      // tasks of their parts dealt out in proportion to their counts (task t
-      // of a part of n tasks at t / n), each part longest first.  The mix of
-      // parts on the CUs then stays the same over the whole launch, which
-      // runs faster than one part after another (their bottlenecks differ),
-      // and the shortest tasks of every part fill the tail.  A ticket is
-      // part << 24 | task (a large class: its shape).
+      // tasks of their parts dealt out in proportion to their counts, each
+      // part longest first, over a span of the ticket sequence that shrinks
+      // with the part's cost per step (task t of a part of n tasks at
+      // (t / n) (1 - kTailSpan cost / largest cost)).  The mix of parts on
+      // the CUs stays broad over the launch, which runs faster than one part
+      // after another (their bottlenecks differ), while the tail holds the
+      // cheapest tasks (with chunked stepping every task has the same steps,
+      // and an expensive task started last would set the chunk's end).  A
+      // ticket is part << 24 | task (a large class: its shape).
       for (int u = 0; u < WorkPlan::kTicketLists; ++u) {
         const int q_lo = u == 0 ? 0 : (kNumSmall + u - 1) * kNumShapes;
         const int q_hi = u == 0 ? kNumSmall * kNumShapes : q_lo + kNumShapes;
         std::vector<std::pair<double, int32_t>> tk;
+        double cmax = 0.0;
+        for (int q = q_lo; q < q_hi; ++q)
+          if (!parts[v][q].empty()) cmax = std::max(cmax, part_step_cost(q));
         for (int q = q_lo; q < q_hi; ++q) {
           const int groups = kWave / part_lanes(q);
           const int nt = (int)((parts[v][q].size() + groups - 1) / groups);
-          for (int t = 0; t < nt; ++t) tk.push_back({-(double)t / (double)nt, (int32_t)(((q - q_lo) << 24) | t)});
+          const double span = 1.0 - kTailSpan * part_step_cost(q) / std::max(cmax, 1.0);
+          for (int t = 0; t < nt; ++t)
+            tk.push_back({-(double)t / (double)nt * span, (int32_t)(((q - q_lo) << 24) | t)});
         }
         std::stable_sort(tk.begin(), tk.end(), [](const std::pair<double, int32_t> &x, const std::pair<double, int32_t> &y) {
           return x.first > y.first;
