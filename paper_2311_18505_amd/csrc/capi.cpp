@@ -567,7 +567,7 @@ extern "C" int string_batch_excite(sb_batch *b, int first, int count, const sb_e
 struct WorkPlan {
   int off[kNumVariants][kNumParts + 1] = {};      // per variant, start of each part's tasks
   // ticket maps of the merged launch (parts of classes 0..4, index 0) and of
-  // each large class's launch (its shapes, index 1 + class - 4)
+  // each large class's launch (its shapes, index 1 + class - kNumSmall)
   static constexpr int kTicketLists = 1 + kNumClasses - kNumSmall;
   int tickets_off[kNumVariants][kTicketLists] = {}, n_tickets[kNumVariants][kTicketLists] = {};
   std::vector<int> members;   // slots stepped
