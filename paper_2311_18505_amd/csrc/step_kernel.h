@@ -475,7 +475,7 @@ struct TabLds {
 // uses (4 MM G values per group) instead of in registers: with 16 slots per
 // lane they would otherwise crowd the register file and spill the state.
 template <int MM, typename T, bool KAHAN>
-constexpr bool kSideComp = KAHAN && MM >= 10;
+constexpr bool kSideComp = KAHAN && MM >= 16;
 
 // array k of a group's side region holds S slots per lane (S = the larger
 // grid's slot count); x has the slots of its own grid
