@@ -39,8 +39,8 @@ PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 2.4 GHz x 25
 # (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a
 # 512 MiB device copy (x2.000 and x1.000); profiles/hbm_traffic_uneven16384.md.
 # Valid only for the kernel sources it was measured on (kernel_source_hash).
-TRAFFIC = {"kernel": "step_kernel_small<float, true>", "source_sha256": "cbd9e7493af29f75",
-           "fetch_bytes": 0.7656e9, "write_bytes": 8.622e9}
+TRAFFIC = {"kernel": "step_kernel_small<float, true>", "source_sha256": "32212cc91f09c9de",
+           "fetch_bytes": 0.7706e9, "write_bytes": 8.626e9}
 
 # the kernels of the three launch units of a step (size classes 0..4 merged,
 # 5, then 6 and 7 on one stream)
