@@ -12,9 +12,11 @@ JSON line: grid-point updates per second (the sum over strings of
 position of each launch's kernel (the one with the most updates reported as
 `roofline`), the FP64 CPU oracle timed on a sample of the same workload and
 the GPU output's error against it on that sample (rel-L2 and partial offsets
-in cents), the uniform 4096-string batch, the plain FP64 per-string method
-on the single nonlinear string, and a real-time serving run with Poisson
-arrivals (p50/p99 latencies).
+in cents), the uniform 4096-string batch, the bowed, clamped and dataset
+batches (each with the same error on 16 of its strings, and the oracle's own
+spread under a 1e-7 change of f0 for any string above 1e-3), the plain FP64
+per-string method on the single nonlinear string, and a real-time serving
+run with Poisson arrivals (p50/p99 latencies).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
